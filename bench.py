@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the GEE hot path on one MI355X.
+
+One step = one ``gee_embed`` call (class counts and label packing, projection
+weights, the edge pass and the split-row merge) over the paper-scale R-MAT: scale 27
+(n = 134,217,728), edge factor 14 (s = 1,879,048,192 records), (a, b, c) = (0.57, 0.19,
+0.19), unit weights, K = 50 planted classes with 1% unknown, adjacency version, all
+inputs resident in HBM. The symmetric CSR is built once beforehand (per-graph
+preprocessing, reported as ``csr_build_ms``). Prints one JSON line on stdout;
+progress goes to stderr.
+
+``value`` is GEdges/s = s / step time. ``roofline`` prices the edge-pass kernel
+(``k_pull``) against HBM: algorithmic bytes per launch = 4 nnz (col) + 8 (n + 1)
+(row_ptr) + n (one read of each packed label) + 4 n K (Z written once), divided by
+the kernel's mean duration measured with HIP events recorded around that launch on
+the stream it runs on. ``cpu_baseline`` times the FP64 oracle, single thread, on a
+prefix of the same record list.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "k_pull_rmat27_counters.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2402_04403_amd", "csrc", "embed.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--scale", type=int, default=27)
+    p.add_argument("--edge-factor", type=int, default=14)
+    p.add_argument("--K", type=int, default=50)
+    p.add_argument("--form", choices=["pull", "push"], default="pull")
+    p.add_argument("--seg-len", type=int, default=0)
+    p.add_argument("--rows-per-window", type=int, default=0)
+    p.add_argument("--push-steps", type=int, default=3, help="timed steps of the push form, reported beside")
+    p.add_argument("--cpu-records", type=int, default=20_000_000)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+def source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def counters_traffic(launch_bytes_alg):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it still
+    describes the current kernel source; else None."""
+    try:
+        with open(PROFILE_COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None, None
+    if c.get("kernel_source_sha256") != source_hash(KERNEL_SOURCE):
+        return None, c
+    return float(c["hbm_bytes_per_launch"]), c
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (the path shards by rows, "
+              "see DESIGN.md, but no multi-GPU run is part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2402_04403_amd as gee
+
+    dev = torch.device("cuda:0")
+    gee.load()
+    t0 = time.time()
+    wl = gen.rmat_paper_scale(scale=a.scale, edge_factor=a.edge_factor, K=a.K)
+    g = wl.graph
+    n, s, K = g.n, g.s, wl.K
+    log(f"generated {wl.name}: n={n} s={s} in {time.time() - t0:.1f}s")
+    cpu_src = g.src[: a.cpu_records].copy()
+    cpu_dst = g.dst[: a.cpu_records].copy()
+    coo = gee.to_device(n, g.src, g.dst, None, device=dev)
+    labels = torch.as_tensor(wl.labels).to(dev)
+    Y_host = wl.labels
+    del g, wl
+    torch.cuda.synchronize()
+    log(f"inputs on device {time.time() - t0:.1f}s")
+
+    # per-graph preprocessing: canonical symmetric CSR
+    e0, e1 = gee.HipEvent(), gee.HipEvent()
+    e0.record()
+    csr = gee.csr_build(coo, check=False)
+    e1.record()
+    e1.synchronize()
+    csr_ms = e0.elapsed_ms(e1)
+    torch.cuda.empty_cache()
+    nnz = csr.nnz
+    log(f"csr built nnz={nnz} in {csr_ms:.1f} ms")
+
+    # copy probe: attainable streaming bandwidth on this GPU
+    buf_a = torch.empty(1 << 32, dtype=torch.uint8, device=dev)
+    buf_b = torch.empty_like(buf_a)
+    gee.copy(buf_b, buf_a)
+    c0, c1 = gee.HipEvent(), gee.HipEvent()
+    c0.record()
+    for _ in range(5):
+        gee.copy(buf_b, buf_a)
+    c1.record()
+    c1.synchronize()
+    copy_gbps = 5 * 2 * buf_a.numel() / (c0.elapsed_ms(c1) * 1e-3) / 1e9
+    del buf_a, buf_b
+    torch.cuda.empty_cache()
+    log(f"copy probe {copy_gbps:.0f} GB/s")
+
+    use_csr = csr if a.form == "pull" else None
+    ws_bytes = gee.embed_workspace_bytes(K, coo=coo, csr=use_csr, seg_len=a.seg_len,
+                                         rows_per_window=a.rows_per_window)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    Z = torch.empty((n, K), dtype=torch.float32, device=dev)
+    err = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def step(events=None, form=a.form):
+        gee.embed(labels, K, coo=coo, csr=csr if form == "pull" else None, Z=Z, ws=ws, err=err,
+                  seg_len=a.seg_len, rows_per_window=a.rows_per_window, events=events, check=False)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    hot = [(gee.HipEvent(), gee.HipEvent()) for _ in range(a.steps)]
+    t_begin, t_end = gee.HipEvent(), gee.HipEvent()
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t_begin.record()
+    for i in range(a.steps):
+        step(events=hot[i])
+    t_end.record()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - w0) * 1e3
+    step_ms = t_begin.elapsed_ms(t_end) / a.steps
+    hot_ms = [b.elapsed_ms(e) for b, e in hot]
+    hot_avg = float(np.mean(hot_ms))
+    if int(err.item()) != 0:
+        raise SystemExit(f"gee_embed reported {int(err.item())}")
+    log(f"{a.form}: step {step_ms:.3f} ms (wall {wall_ms / a.steps:.3f}), hot kernel mean {hot_avg:.3f} ms "
+        f"min {min(hot_ms):.3f}")
+
+    # the other form, reported beside
+    other = "push" if a.form == "pull" else "pull"
+    other_ms = None
+    if a.push_steps > 0:
+        ws_o = gee.embed_workspace_bytes(K, coo=coo, csr=csr if other == "pull" else None)
+        if ws_o > ws.numel():
+            ws = torch.empty(ws_o, dtype=torch.uint8, device=dev)
+        step(form=other)
+        torch.cuda.synchronize()
+        o0, o1 = gee.HipEvent(), gee.HipEvent()
+        o0.record()
+        for _ in range(a.push_steps):
+            step(form=other)
+        o1.record()
+        o1.synchronize()
+        other_ms = o0.elapsed_ms(o1) / a.push_steps
+        log(f"{other}: step {other_ms:.3f} ms")
+
+    # roofline of the edge-pass kernel
+    lab_bytes = 1 if K <= 255 else 2
+    if a.form == "pull":
+        bytes_alg = 4 * nnz + 8 * (n + 1) + lab_bytes * n + 4 * n * K
+        kernel = "k_pull"
+    else:
+        bytes_alg = 8 * s + lab_bytes * n + 2 * 8 * s  # records once, labels once, two 8-byte atomic RMW
+        kernel = "k_push"
+    achieved = bytes_alg / (hot_avg * 1e-3) / 1e9
+    traffic, counters = counters_traffic(bytes_alg) if a.form == "pull" else (None, None)
+    step_bytes = bytes_alg + 4 * n + lab_bytes * n  # + the label read and pack of the counts kernel
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": kernel,
+                "bytes_alg_per_launch": int(bytes_alg), "kernel_ms": round(hot_avg, 4)}
+
+    cpu = None
+    if not a.no_cpu_baseline and a.cpu_records > 0:
+        import oracle
+
+        ns = int(cpu_src.shape[0])
+        log(f"cpu baseline: oracle on the first {ns} records ...")
+        c_t0 = time.perf_counter()
+        oracle.embed(n, cpu_src, cpu_dst, None, Y_host, K, False)
+        c_t = time.perf_counter() - c_t0
+        cpu = {"value": round(ns / c_t / 1e9, 6), "unit": "GEdges/s", "cores": 1, "kind": "oracle",
+               "seconds": round(c_t, 2),
+               "sample": f"first {ns:,} of {s:,} records of the same R-MAT list, all n={n:,} vertices and labels, "
+                         f"K={K}, adjacency; FP64 Algorithm 1, one thread, Z (n x K FP64) allocated zeroed "
+                         f"and first touched inside the timed call"}
+        log(f"cpu baseline {cpu['value']} GEdges/s in {c_t:.1f}s")
+
+    out = {
+        "metric": "GEdges/s",
+        "value": round(s / (step_ms * 1e-3) / 1e9, 3),
+        "unit": "GEdges/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"rmat-s{a.scale}-ef{a.edge_factor}-K{K}-unit-adjacency",
+            "n": n, "s": s, "nnz": nnz, "K": K, "form": "csr-pull" if a.form == "pull" else "edge-push",
+            "seg_len": a.seg_len or 4096, "rows_per_window": a.rows_per_window or "auto",
+            "csr_build_ms": round(csr_ms, 2),
+            "step_hbm_frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "copy_probe_GBps": round(copy_gbps, 1),
+            f"{other}_ms_per_step": None if other_ms is None else round(other_ms, 3),
+            "paper_context": "6.42 s for Friendster (1.8B edges) on a 24-core Xeon Platinum 8259CL, Table I",
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if counters is not None:
+        out["config"]["counters_file"] = os.path.relpath(PROFILE_COUNTERS, ROOT)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * gee.h — C ABI of the MI355X (gfx950) one-hot graph encoder embedding library.
+ *
+ * The operation is Algorithm 1 ("Semi-Supervised GEE") of Lubonja, Shen, Priebe
+ * and Burns, "Edge-Parallel Graph Encoder Embedding", Section II: given an edge
+ * list E of s records (u, v, w) and labels Y in {0..K}^n (0 = unknown class),
+ * build the projection W(v, k) = 1 / count(Y = k) for Y(v) = k, then in one pass
+ * over the records add W(v, Y(v)) * w to Z(u, Y(v)) and W(u, Y(u)) * w to
+ * Z(v, Y(u)). Section II calls this the formulation for weighted directed graphs;
+ * unweighted graphs use w = 1. The result is Z = (A + A^T) M with A[u][v] the sum
+ * of w over records (u, v) and M[v][k-1] = [Y(v) = k] / n_k.
+ *
+ * The Laplacian version, whose preprocessing Section II leaves out, scales each
+ * record's w by (d_u d_v)^-1/2 with d = (A + A^T) 1 the weighted degree:
+ * Z = D^-1/2 (A + A^T) D^-1/2 M, and a vertex of degree 0 gets factor 0.
+ *
+ * Conventions shared by every entry point:
+ *  - Vertex ids are 0-based int32 in [0, n), n <= 2^31 - 1.
+ *  - Labels are int32 in [0, K], 1 <= K <= 65535; class k in 1..K is column
+ *    k - 1 of Z; an update whose target class is 0 is skipped, the record's
+ *    other update still happens. Self-loops fire both updates, repeated records
+ *    add up.
+ *  - Z is FP32, n x K, row-major: Z[u * K + (k - 1)].
+ *  - Unless marked "host", every pointer is device memory on the current HIP
+ *    device, owned by the caller. The library allocates no device memory: the
+ *    calls that need scratch take a caller-provided workspace of the size the
+ *    matching *_workspace() query returns, aligned to 256 bytes.
+ *  - Every call is stream-ordered on `stream` and returns before the GPU work
+ *    finishes. Inputs must stay valid, and outputs untouched, until then.
+ *  - Calls are stateless and reentrant; calls on different streams with
+ *    disjoint outputs and workspaces are independent.
+ *
+ * Errors come in two classes:
+ *  - host-detectable ones (bad sizes, null pointers, short workspace) are
+ *    returned at once and nothing is launched;
+ *  - data-dependent ones (a label outside [0, K], a vertex id outside [0, n),
+ *    a negative weight in the Laplacian version) are found by the kernels that
+ *    already read the data. The offending item is skipped and the lowest code
+ *    seen is stored into the caller's device word `*err` by atomic minimum. The
+ *    library never resets `*err`: the caller zeroes it before the call and reads
+ *    it after synchronising. When `*err != 0` the outputs are unspecified.
+ */
+#ifndef GEE_H
+#define GEE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GEE_OK = 0,
+    GEE_EINVAL = -1,     /* bad argument: null pointer, size out of range, bad option */
+    GEE_ELABEL = -2,     /* a label outside [0, K] (data-dependent) */
+    GEE_EVERTEX = -3,    /* a vertex id outside [0, n) (data-dependent) */
+    GEE_ENEGW = -4,      /* a negative or NaN weight in the Laplacian version (data-dependent) */
+    GEE_EOVERFLOW = -5,  /* n * K or an index would overflow 64 bits / the supported range */
+    GEE_EWORKSPACE = -6, /* workspace null, misaligned or smaller than the query says */
+    GEE_EHIP = -7        /* a HIP launch or event call failed */
+} gee_status;
+
+/* Edge list of s records (src[i], dst[i], w[i]), i < s. w == NULL means unit
+ * weights. The struct itself is host memory; the arrays are device memory. */
+typedef struct gee_coo {
+    int64_t n;          /* vertex count, 1 <= n <= 2^31 - 1 */
+    int64_t s;          /* record count, s >= 0 */
+    const int32_t *src; /* [s] */
+    const int32_t *dst; /* [s] */
+    const float *w;     /* [s] or NULL */
+} gee_coo;
+
+/* Symmetric CSR of S = A + A^T (the per-vertex edge lists that the paper's
+ * edge-map walks, Section III): for record (u, v, w), row u holds (v, w) and row
+ * v holds (u, w); a self-loop appears twice in its row. row_ptr is
+ * non-decreasing with row_ptr[0] = 0 and row_ptr[n] = nnz. gee_csr_build writes
+ * rows sorted by (column, bit pattern of w), which makes the layout independent
+ * of record order; gee_embed accepts any valid layout. val == NULL means unit
+ * weights. The struct is host memory; the arrays are device memory. */
+typedef struct gee_csr {
+    int64_t n;              /* vertex count, as in gee_coo */
+    int64_t nnz;            /* entry count (2 s for a CSR built from s records) */
+    const int64_t *row_ptr; /* [n + 1] */
+    const int32_t *col;     /* [nnz] */
+    const float *val;       /* [nnz] or NULL */
+} gee_csr;
+
+/* Optional knobs of gee_embed (host struct; pass NULL for the defaults). */
+typedef struct gee_embed_opts {
+    /* CSR-pull form: work items (rows + entries) per wavefront segment; 0 picks
+     * the default (4096). Must be 0 or in [64, 2^24]. */
+    int32_t seg_len;
+    /* CSR-pull form: rows per LDS window; 0 picks the largest that fits the
+     * per-wavefront LDS budget (at most 64). Must be 0 or in [1, 64]. */
+    int32_t rows_per_window;
+    /* When non-NULL, recorded on `stream` right before and right after the launch
+     * of the edge-pass kernel (push or pull), so a caller can time that kernel
+     * alone. */
+    hipEvent_t hot_begin;
+    hipEvent_t hot_end;
+} gee_embed_opts;
+
+/* Class counts, Algorithm 1's count(Y = k): counts[k] = #{v : labels[v] = k} for
+ * k = 0..K (index 0 counts unknown labels). labels: [n] int32; counts: [K + 1]
+ * int64, overwritten. A label outside [0, K] is not counted and raises
+ * GEE_ELABEL in *err. */
+int gee_counts(const int32_t *labels, int64_t n, int32_t K, int64_t *counts, int32_t *err,
+               hipStream_t stream);
+
+/* Projection weights, Algorithm 1's W(idx, k) = 1 / count(Y = k), stored as one
+ * value per class: inv[0] = 0, inv[k] = 1 / counts[k] (IEEE-754 FP64 division,
+ * correctly rounded) or 0 when counts[k] = 0. W itself is never materialised:
+ * W(v, k) = [labels[v] = k] * inv[k]. counts: [K + 1] int64; inv: [K + 1] double. */
+int gee_weights(const int64_t *counts, int32_t K, double *inv, hipStream_t stream);
+
+/* Weighted degree d = (A + A^T) 1 (a self-loop adds 2 w), the preprocessing of
+ * the Laplacian version. With csr != NULL the rows of the CSR are summed, each in
+ * its stored order (deterministic); otherwise the records of g are accumulated
+ * with FP64 atomics (exact for unit weights, and for weights on a 2^-k grid
+ * whose sums stay below 2^(53-k)). deg: [n] double, overwritten. Exactly the
+ * graph given is read: g may be NULL when csr is not, and vice versa. */
+int gee_degrees(const gee_coo *g, const gee_csr *csr, double *deg, int32_t *err, hipStream_t stream);
+
+/* Workspace bytes gee_embed needs for this graph, K and variant (csr == NULL:
+ * edge-parallel push form; else CSR-pull form). Returns 0 on invalid input. */
+size_t gee_embed_workspace(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian,
+                           const gee_embed_opts *opts);
+
+/* The embedding Z (Algorithm 1; Laplacian version when laplacian != 0).
+ *  csr == NULL: edge-parallel push form. One thread per record gathers both
+ *    endpoints' labels and adds into Z with FP32 global atomics; class weights
+ *    and the row factor of the Laplacian are applied by a final scaling pass.
+ *    Needs g. Unit-weight adjacency sums are exact integers before the one
+ *    final rounding; other sums round in FP32 in an unspecified order.
+ *  csr != NULL: CSR-pull form. Rows are split into segments of equal work
+ *    (rows + entries); one wavefront per segment accumulates each row's K bins in
+ *    LDS and writes every row of Z exactly once; a row cut by segment boundaries
+ *    is summed from FP64 partials in segment order by a second pass. Bit-identical
+ *    from run to run. Needs csr (g unused, may be NULL); K <= 4096.
+ * Z: [n * K] float, overwritten (no zero-fill needed). ws: workspace of at least
+ * gee_embed_workspace() bytes. */
+int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32_t K, int laplacian,
+              float *Z, void *ws, size_t ws_bytes, int32_t *err, const gee_embed_opts *opts,
+              hipStream_t stream);
+
+/* Workspace bytes gee_csr_build needs (weighted != 0 when the records carry w). */
+size_t gee_csr_workspace(int64_t n, int64_t s, int weighted);
+
+/* Build the symmetric CSR of S = A + A^T from g: row_ptr [n + 1] int64, col [2 s]
+ * int32 and, when g->w != NULL, val [2 s] float (else val may be NULL). Rows come
+ * out sorted by (column, bit pattern of w): a stable LSD radix sort of the 2 s
+ * directed entries, so the result depends only on the multiset of records. */
+int gee_csr_build(const gee_coo *g, int64_t *row_ptr, int32_t *col, float *val, void *ws,
+                  size_t ws_bytes, int32_t *err, hipStream_t stream);
+
+/* Measurement probe: copy `bytes` bytes from src to dst with a plain streaming
+ * kernel (16-byte loads and stores). Used to calibrate memory-traffic counters
+ * and to measure the attainable copy bandwidth. Both pointers 16-byte aligned. */
+int gee_copy(void *dst, const void *src, size_t bytes, hipStream_t stream);
+
+/* Host: static description of a status code. */
+const char *gee_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEE_H */

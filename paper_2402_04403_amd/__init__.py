@@ -1,0 +1,329 @@
+"""MI355X-native one-hot graph encoder embedding (GEE).
+
+A thin ctypes binding over ``libgee.so`` (hand-written HIP for gfx950; C ABI in
+``include/gee.h``). PyTorch supplies device memory and the current stream; every step
+of the computation runs in the library's kernels. There is no CPU fallback: without a
+built library or a GPU every compute call raises.
+
+Functions mirror the C entry points:
+
+* :func:`counts`   — ``gee_counts``: class counts n_k (Algorithm 1's count(Y = k)).
+* :func:`weights`  — ``gee_weights``: inv[k] = 1 / n_k, the nonzeros of W.
+* :func:`degrees`  — ``gee_degrees``: weighted degree d = (A + A^T) 1.
+* :func:`csr_build` — ``gee_csr_build``: canonical symmetric CSR of A + A^T.
+* :func:`embed`    — ``gee_embed``: Z by the edge-parallel push form (COO) or the
+  deterministic CSR-pull form (CSR), adjacency or Laplacian version.
+* :func:`copy`     — ``gee_copy``: the streaming copy probe used for measurement.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # loads the HIP runtime libgee.so must share: import before the library
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgee.so")
+
+GEE_OK, GEE_EINVAL, GEE_ELABEL, GEE_EVERTEX, GEE_ENEGW, GEE_EOVERFLOW, GEE_EWORKSPACE, GEE_EHIP = 0, -1, -2, -3, -4, -5, -6, -7
+
+_c_i32p = ctypes.POINTER(ctypes.c_int32)
+
+
+class GeeError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        self.code = int(code)
+        msg = _lib_or_none().gee_strerror(self.code).decode() if _lib_or_none() else str(code)
+        super().__init__(f"{where}: {msg} ({self.code})" if where else f"{msg} ({self.code})")
+
+
+class Coo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("s", ctypes.c_int64), ("src", ctypes.c_void_p),
+                ("dst", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class EmbedOpts(ctypes.Structure):
+    _fields_ = [("seg_len", ctypes.c_int32), ("rows_per_window", ctypes.c_int32),
+                ("hot_begin", ctypes.c_void_p), ("hot_end", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def _lib_or_none():
+    return _lib
+
+
+def load():
+    """Load libgee.so (built in-tree by ``build.py``); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libgee.so not built at {LIB_PATH}; run paper_2402_04403_amd/build.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz, ci = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_int
+        CooP, CsrP, OptP = ctypes.POINTER(Coo), ctypes.POINTER(Csr), ctypes.POINTER(EmbedOpts)
+        lib.gee_strerror.restype = ctypes.c_char_p
+        lib.gee_strerror.argtypes = [ci]
+        lib.gee_counts.restype = ci
+        lib.gee_counts.argtypes = [vp, i64, i32, vp, vp, vp]
+        lib.gee_weights.restype = ci
+        lib.gee_weights.argtypes = [vp, i32, vp, vp]
+        lib.gee_degrees.restype = ci
+        lib.gee_degrees.argtypes = [CooP, CsrP, vp, vp, vp]
+        lib.gee_embed_workspace.restype = sz
+        lib.gee_embed_workspace.argtypes = [CooP, CsrP, i32, ci, OptP]
+        lib.gee_embed.restype = ci
+        lib.gee_embed.argtypes = [CooP, CsrP, vp, i32, ci, vp, vp, sz, vp, OptP, vp]
+        lib.gee_csr_workspace.restype = sz
+        lib.gee_csr_workspace.argtypes = [i64, i64, ci]
+        lib.gee_csr_build.restype = ci
+        lib.gee_csr_build.argtypes = [CooP, vp, vp, vp, vp, sz, vp, vp]
+        lib.gee_copy.restype = ci
+        lib.gee_copy.argtypes = [vp, vp, sz, vp]
+        _lib = lib
+    return _lib
+
+
+# ------------------------------------------------------------------ helpers --
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _need(t, dtype, numel, name, device):
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous {dtype} tensor")
+    if t.device.type != "cuda" or (device is not None and t.device != device):
+        raise ValueError(f"{name}: expected a tensor on {device or 'a GPU'}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+
+
+def _rc(code, where):
+    if code != GEE_OK:
+        raise GeeError(code, where)
+
+
+def _check_err(err: torch.Tensor, where: str):
+    code = int(err.item())  # synchronises the stream the call ran on
+    if code != GEE_OK:
+        raise GeeError(code, where)
+
+
+class HipEvent:
+    """A HIP event created through the HIP runtime torch uses (plumbing for timing)."""
+
+    _hip = None
+
+    def __init__(self):
+        if HipEvent._hip is None:
+            load()
+            hip = ctypes.CDLL("libamdhip64.so.7")  # resolves to the runtime already loaded
+            hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+            hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+            hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+            hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+            hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+            HipEvent._hip = hip
+        self.handle = ctypes.c_void_p()
+        if HipEvent._hip.hipEventCreate(ctypes.byref(self.handle)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+
+    def record(self, stream=None):
+        if HipEvent._hip.hipEventRecord(self.handle, ctypes.c_void_p(_stream(stream))) != 0:
+            raise RuntimeError("hipEventRecord failed")
+
+    def synchronize(self):
+        HipEvent._hip.hipEventSynchronize(self.handle)
+
+    def elapsed_ms(self, end: "HipEvent") -> float:
+        ms = ctypes.c_float()
+        if HipEvent._hip.hipEventElapsedTime(ctypes.byref(ms), self.handle, end.handle) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def __del__(self):
+        try:
+            if self.handle and HipEvent._hip is not None:
+                HipEvent._hip.hipEventDestroy(self.handle)
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ graphs --
+
+@dataclass
+class DeviceCoo:
+    n: int
+    src: torch.Tensor
+    dst: torch.Tensor
+    w: torch.Tensor | None = None
+
+    @property
+    def s(self) -> int:
+        return int(self.src.numel())
+
+    def struct(self) -> Coo:
+        dev = self.src.device
+        _need(self.src, torch.int32, None, "src", dev)
+        _need(self.dst, torch.int32, self.s, "dst", dev)
+        if self.w is not None:
+            _need(self.w, torch.float32, self.s, "w", dev)
+        return Coo(self.n, self.s, _ptr(self.src), _ptr(self.dst), _ptr(self.w))
+
+
+@dataclass
+class DeviceCsr:
+    n: int
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor | None = None
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    def struct(self) -> Csr:
+        dev = self.row_ptr.device
+        _need(self.row_ptr, torch.int64, self.n + 1, "row_ptr", dev)
+        _need(self.col, torch.int32, None, "col", dev)
+        if self.val is not None:
+            _need(self.val, torch.float32, self.nnz, "val", dev)
+        return Csr(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val))
+
+
+def to_device(n: int, src, dst, w=None, device="cuda") -> DeviceCoo:
+    """Copy a host edge list (NumPy or tensors) to the GPU as int32 / float32."""
+    def t(a, dt):
+        if a is None:
+            return None
+        a = torch.as_tensor(a)
+        return a.to(device=device, dtype=dt).contiguous()
+    return DeviceCoo(n, t(src, torch.int32), t(dst, torch.int32), t(w, torch.float32))
+
+
+# --------------------------------------------------------------- entry points --
+
+def counts(labels: torch.Tensor, K: int, stream=None, check: bool = True) -> torch.Tensor:
+    lib = load()
+    _need(labels, torch.int32, None, "labels", None)
+    out = torch.empty(K + 1, dtype=torch.int64, device=labels.device)
+    err = torch.zeros(1, dtype=torch.int32, device=labels.device)
+    _rc(lib.gee_counts(_ptr(labels), labels.numel(), K, _ptr(out), _ptr(err), _stream(stream)), "gee_counts")
+    if check:
+        _check_err(err, "gee_counts")
+    return out
+
+
+def weights(cnt: torch.Tensor, K: int, stream=None) -> torch.Tensor:
+    lib = load()
+    _need(cnt, torch.int64, K + 1, "counts", None)
+    inv = torch.empty(K + 1, dtype=torch.float64, device=cnt.device)
+    _rc(lib.gee_weights(_ptr(cnt), K, _ptr(inv), _stream(stream)), "gee_weights")
+    return inv
+
+
+def degrees(coo: DeviceCoo | None = None, csr: DeviceCsr | None = None, stream=None, check: bool = True):
+    lib = load()
+    g = coo if coo is not None else csr
+    if g is None:
+        raise ValueError("degrees: give coo or csr")
+    dev = (coo.src if coo is not None else csr.row_ptr).device
+    deg = torch.empty(g.n, dtype=torch.float64, device=dev)
+    err = torch.zeros(1, dtype=torch.int32, device=dev)
+    cs = ctypes.byref(coo.struct()) if coo is not None else None
+    rs = ctypes.byref(csr.struct()) if csr is not None else None
+    _rc(lib.gee_degrees(cs, rs, _ptr(deg), _ptr(err), _stream(stream)), "gee_degrees")
+    if check:
+        _check_err(err, "gee_degrees")
+    return deg
+
+
+def csr_build(coo: DeviceCoo, stream=None, check: bool = True) -> DeviceCsr:
+    lib = load()
+    st = coo.struct()
+    dev = coo.src.device
+    nnz = 2 * coo.s
+    row_ptr = torch.empty(coo.n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(nnz, dtype=torch.int32, device=dev)
+    val = torch.empty(nnz, dtype=torch.float32, device=dev) if coo.w is not None else None
+    wsb = lib.gee_csr_workspace(coo.n, coo.s, 1 if coo.w is not None else 0)
+    if wsb == 0:
+        raise GeeError(GEE_EINVAL, "gee_csr_workspace")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    err = torch.zeros(1, dtype=torch.int32, device=dev)
+    _rc(lib.gee_csr_build(ctypes.byref(st), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(ws), wsb, _ptr(err),
+                          _stream(stream)), "gee_csr_build")
+    if check:
+        _check_err(err, "gee_csr_build")
+    del ws
+    return DeviceCsr(coo.n, row_ptr, col, val)
+
+
+def _opts(seg_len=0, rows_per_window=0, events=None):
+    o = EmbedOpts(seg_len, rows_per_window, None, None)
+    if events is not None:
+        o.hot_begin, o.hot_end = events[0].handle, events[1].handle
+    return o
+
+
+def embed_workspace_bytes(K: int, coo: DeviceCoo | None = None, csr: DeviceCsr | None = None,
+                          laplacian: bool = False, seg_len: int = 0, rows_per_window: int = 0) -> int:
+    lib = load()
+    cs = ctypes.byref(coo.struct()) if coo is not None else None
+    rs = ctypes.byref(csr.struct()) if csr is not None else None
+    o = _opts(seg_len, rows_per_window)
+    return int(lib.gee_embed_workspace(cs, rs, K, 1 if laplacian else 0, ctypes.byref(o)))
+
+
+def embed(labels: torch.Tensor, K: int, coo: DeviceCoo | None = None, csr: DeviceCsr | None = None,
+          laplacian: bool = False, Z: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+          err: torch.Tensor | None = None, seg_len: int = 0, rows_per_window: int = 0, events=None,
+          stream=None, check: bool = True) -> torch.Tensor:
+    """GEE embedding Z [n, K] (FP32). ``csr`` selects the CSR-pull form, else the push form on ``coo``."""
+    lib = load()
+    g = csr if csr is not None else coo
+    if g is None:
+        raise ValueError("embed: give coo (push form) or csr (pull form)")
+    dev = (csr.row_ptr if csr is not None else coo.src).device
+    _need(labels, torch.int32, g.n, "labels", dev)
+    cs = ctypes.byref(coo.struct()) if (coo is not None and csr is None) else None
+    rs = ctypes.byref(csr.struct()) if csr is not None else None
+    o = _opts(seg_len, rows_per_window, events)
+    wsb = int(lib.gee_embed_workspace(cs, rs, K, 1 if laplacian else 0, ctypes.byref(o)))
+    if wsb == 0:
+        raise GeeError(GEE_EINVAL, "gee_embed_workspace")
+    if Z is None:
+        Z = torch.empty((g.n, K), dtype=torch.float32, device=dev)
+    _need(Z, torch.float32, g.n * K, "Z", dev)
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    if err is None:
+        err = torch.zeros(1, dtype=torch.int32, device=dev)
+    _rc(lib.gee_embed(cs, rs, _ptr(labels), K, 1 if laplacian else 0, _ptr(Z), _ptr(ws), ws.numel(), _ptr(err),
+                      ctypes.byref(o), _stream(stream)), "gee_embed")
+    if check:
+        _check_err(err, "gee_embed")
+    return Z
+
+
+def copy(dst: torch.Tensor, src: torch.Tensor, stream=None) -> None:
+    lib = load()
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("copy: destination too small")
+    _rc(lib.gee_copy(_ptr(dst), _ptr(src), nbytes, _stream(stream)), "gee_copy")

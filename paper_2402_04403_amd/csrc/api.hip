@@ -1,0 +1,246 @@
+// extern "C" entry points of libgee: argument checks, workspace layout and the
+// stream-ordered launch sequence of each call. Declarations and contracts are in
+// include/gee.h.
+
+#include <limits.h>
+
+#include "common.h"
+#include "launch.h"
+
+using namespace gee;
+
+namespace {
+
+constexpr int64_t kMaxN = INT32_MAX;
+constexpr int64_t kMaxRecords = (int64_t)1 << 40;
+constexpr int32_t kMaxK = 65535;
+constexpr int32_t kMaxKPull = 4096;
+constexpr int32_t kDefaultSegLen = 4096;
+constexpr size_t kWaveLdsBudget = 16384;
+
+inline bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+struct Plan {
+    bool pull = false;
+    int64_t n = 0, ns = 0, nnz = 0;
+    int32_t K = 0;
+    bool lap = false, weighted = false, wide = false;
+    Pack pack = Pack::U8;
+    int64_t L = 0, nseg = 0;
+    int rw = 0;
+    // workspace offsets
+    size_t o_counts = 0, o_inv = 0, o_lab = 0, o_deg = 0, o_segi = 0, o_sege = 0, o_part = 0, total = 0;
+};
+
+int check_coo(const gee_coo *g)
+{
+    if (!g) return GEE_EINVAL;
+    if (g->n < 1 || g->n > kMaxN || g->s < 0) return GEE_EINVAL;
+    if (g->s > kMaxRecords) return GEE_EOVERFLOW;
+    if (g->s > 0 && (!g->src || !g->dst)) return GEE_EINVAL;
+    return GEE_OK;
+}
+
+int check_csr(const gee_csr *c)
+{
+    if (!c) return GEE_EINVAL;
+    if (c->n < 1 || c->n > kMaxN || c->nnz < 0 || !c->row_ptr) return GEE_EINVAL;
+    if (c->nnz > 2 * kMaxRecords) return GEE_EOVERFLOW;
+    if (c->nnz > 0 && !c->col) return GEE_EINVAL;
+    return GEE_OK;
+}
+
+int make_plan(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian, const gee_embed_opts *o, Plan *p)
+{
+    if (K < 1 || K > kMaxK) return GEE_EINVAL;
+    Plan P;
+    P.pull = csr != nullptr;
+    P.K = K;
+    P.lap = laplacian != 0;
+    int rc;
+    if (P.pull) {
+        if ((rc = check_csr(csr)) != GEE_OK) return rc;
+        if (g && g->n != csr->n) return GEE_EINVAL;
+        if (K > kMaxKPull) return GEE_EINVAL;
+        P.n = csr->n;
+        P.nnz = csr->nnz;
+        P.weighted = csr->val != nullptr;
+    } else {
+        if ((rc = check_coo(g)) != GEE_OK) return rc;
+        P.n = g->n;
+        P.ns = g->s;
+        P.weighted = g->w != nullptr;
+    }
+    P.pack = P.lap ? Pack::LAP64 : (K <= 255 ? Pack::U8 : Pack::U16);
+    P.wide = P.lap || P.weighted;
+    if (o) {
+        if (o->seg_len != 0 && (o->seg_len < 64 || o->seg_len > (1 << 24))) return GEE_EINVAL;
+        if (o->rows_per_window < 0 || o->rows_per_window > 64) return GEE_EINVAL;
+    }
+    if (P.pull) {
+        P.L = (o && o->seg_len) ? o->seg_len : kDefaultSegLen;
+        P.nseg = (P.n + P.nnz + P.L - 1) / P.L;
+        if (o && o->rows_per_window) {
+            P.rw = o->rows_per_window;
+        } else {
+            P.rw = 64;
+            while (P.rw > 1 && pull_wave_bytes(K, P.wide, P.rw) > kWaveLdsBudget) --P.rw;
+        }
+        if (pull_wave_bytes(K, P.wide, P.rw) > 65536) return GEE_EINVAL;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = align_up(off, 256);
+        const size_t at = off;
+        off += bytes;
+        return at;
+    };
+    const size_t lab_bytes = P.pack == Pack::U8 ? 1 : (P.pack == Pack::U16 ? 2 : 8);
+    P.o_counts = take(8 * (size_t)(K + 1));
+    P.o_inv = take(8 * (size_t)(K + 1));
+    P.o_lab = take(lab_bytes * (size_t)P.n);
+    if (P.lap) P.o_deg = take(8 * (size_t)P.n);
+    if (P.pull) {
+        P.o_segi = take(4 * (size_t)(P.nseg + 1));
+        P.o_sege = take(8 * (size_t)(P.nseg + 1));
+        P.o_part = take(8 * 2 * (size_t)P.nseg * (size_t)K);
+    }
+    P.total = align_up(off, 256);
+    *p = P;
+    return GEE_OK;
+}
+
+inline int hip_rc(hipError_t e) { return e == hipSuccess ? GEE_OK : GEE_EHIP; }
+
+} // namespace
+
+extern "C" {
+
+const char *gee_strerror(int code)
+{
+    switch (code) {
+    case GEE_OK: return "success";
+    case GEE_EINVAL: return "invalid argument";
+    case GEE_ELABEL: return "label outside [0, K]";
+    case GEE_EVERTEX: return "vertex id outside [0, n)";
+    case GEE_ENEGW: return "negative or NaN weight in the Laplacian version";
+    case GEE_EOVERFLOW: return "size outside the supported range";
+    case GEE_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case GEE_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+int gee_counts(const int32_t *labels, int64_t n, int32_t K, int64_t *counts, int32_t *err, hipStream_t stream)
+{
+    if (!labels || !counts || n < 1 || n > kMaxN || K < 1 || K > kMaxK) return GEE_EINVAL;
+    return hip_rc(launch_counts(labels, n, K, reinterpret_cast<uint64_t *>(counts), nullptr, Pack::U8, err, stream));
+}
+
+int gee_weights(const int64_t *counts, int32_t K, double *inv, hipStream_t stream)
+{
+    if (!counts || !inv || K < 1 || K > kMaxK) return GEE_EINVAL;
+    return hip_rc(launch_weights(reinterpret_cast<const uint64_t *>(counts), K, inv, stream));
+}
+
+int gee_degrees(const gee_coo *g, const gee_csr *csr, double *deg, int32_t *err, hipStream_t stream)
+{
+    if (!deg) return GEE_EINVAL;
+    int rc;
+    if (csr) {
+        if ((rc = check_csr(csr)) != GEE_OK) return rc;
+        if (g && g->n != csr->n) return GEE_EINVAL;
+        return hip_rc(launch_degrees_csr(csr->n, csr->row_ptr, csr->val, csr->nnz, deg, false, err, stream));
+    }
+    if ((rc = check_coo(g)) != GEE_OK) return rc;
+    return hip_rc(launch_degrees_coo(g->n, g->s, g->src, g->dst, g->w, deg, false, err, stream));
+}
+
+size_t gee_embed_workspace(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian,
+                           const gee_embed_opts *opts)
+{
+    Plan p;
+    if (make_plan(g, csr, K, laplacian, opts, &p) != GEE_OK) return 0;
+    return p.total;
+}
+
+int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32_t K, int laplacian, float *Z,
+              void *ws, size_t ws_bytes, int32_t *err, const gee_embed_opts *opts, hipStream_t stream)
+{
+    Plan p;
+    int rc = make_plan(g, csr, K, laplacian, opts, &p);
+    if (rc != GEE_OK) return rc;
+    if (!labels || !Z) return GEE_EINVAL;
+    if (!ws || !aligned(ws, 256) || ws_bytes < p.total) return GEE_EWORKSPACE;
+    char *w = static_cast<char *>(ws);
+
+    EmbedArgs a;
+    a.n = p.n;
+    a.K = K;
+    a.laplacian = p.lap;
+    a.weighted = p.weighted;
+    a.pack = p.pack;
+    a.labels = labels;
+    a.err = err;
+    a.counts = reinterpret_cast<uint64_t *>(w + p.o_counts);
+    a.inv = reinterpret_cast<double *>(w + p.o_inv);
+    a.lab = w + p.o_lab;
+    a.deg = p.lap ? reinterpret_cast<double *>(w + p.o_deg) : nullptr;
+    a.Z = Z;
+
+    // class counts (+ packed labels for the adjacency version), then W
+    if ((rc = hip_rc(launch_counts(labels, p.n, K, a.counts, p.lap ? nullptr : a.lab, p.pack, err, stream))))
+        return rc;
+    if ((rc = hip_rc(launch_weights(a.counts, K, a.inv, stream)))) return rc;
+    if (p.lap) {
+        hipError_t e = p.pull ? launch_degrees_csr(p.n, csr->row_ptr, csr->val, p.nnz, a.deg, true, err, stream)
+                              : launch_degrees_coo(p.n, p.ns, g->src, g->dst, g->w, a.deg, true, err, stream);
+        if ((rc = hip_rc(e))) return rc;
+        if ((rc = hip_rc(launch_pack_lap(labels, p.n, K, a.deg, static_cast<uint64_t *>(a.lab), stream)))) return rc;
+    }
+    const bool timed = opts && opts->hot_begin && opts->hot_end;
+    if (!p.pull) {
+        if ((rc = hip_rc(launch_fill_f32(Z, p.n * K, 0.0f, stream)))) return rc;
+        if (timed && (rc = hip_rc(hipEventRecord(opts->hot_begin, stream)))) return rc;
+        if ((rc = hip_rc(launch_push(a, p.ns, g->src, g->dst, g->w, stream)))) return rc;
+        if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;
+        return hip_rc(launch_scale(a, stream));
+    }
+    int32_t *seg_i = reinterpret_cast<int32_t *>(w + p.o_segi);
+    int64_t *seg_e = reinterpret_cast<int64_t *>(w + p.o_sege);
+    double *part = reinterpret_cast<double *>(w + p.o_part);
+    if ((rc = hip_rc(launch_seg_bounds(p.n, p.nnz, csr->row_ptr, p.L, p.nseg, seg_i, seg_e, stream)))) return rc;
+    if (timed && (rc = hip_rc(hipEventRecord(opts->hot_begin, stream)))) return rc;
+    if ((rc = hip_rc(launch_pull(a, p.nnz, csr->row_ptr, csr->col, csr->val, seg_i, seg_e, p.nseg, p.rw, part,
+                                 stream))))
+        return rc;
+    if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;
+    return hip_rc(launch_merge(a, csr->row_ptr, seg_i, seg_e, p.nseg, part, stream));
+}
+
+size_t gee_csr_workspace(int64_t n, int64_t s, int weighted)
+{
+    if (n < 1 || n > kMaxN || s < 0 || s > kMaxRecords) return 0;
+    return csr_build_layout(n, s, weighted != 0, nullptr, nullptr);
+}
+
+int gee_csr_build(const gee_coo *g, int64_t *row_ptr, int32_t *col, float *val, void *ws, size_t ws_bytes,
+                  int32_t *err, hipStream_t stream)
+{
+    int rc = check_coo(g);
+    if (rc != GEE_OK) return rc;
+    if (!row_ptr || (g->s > 0 && !col) || (g->w && g->s > 0 && !val)) return GEE_EINVAL;
+    const size_t need = csr_build_layout(g->n, g->s, g->w != nullptr, nullptr, nullptr);
+    if (!ws || !aligned(ws, 256) || ws_bytes < need) return GEE_EWORKSPACE;
+    CsrBuildWs w;
+    csr_build_layout(g->n, g->s, g->w != nullptr, static_cast<char *>(ws), &w);
+    return hip_rc(launch_csr_build(g->n, g->s, g->src, g->dst, g->w, row_ptr, col, val, w, err, stream));
+}
+
+int gee_copy(void *dst, const void *src, size_t bytes, hipStream_t stream)
+{
+    if (!dst || !src || bytes % 16 || !aligned(dst, 16) || !aligned(src, 16)) return GEE_EINVAL;
+    return hip_rc(launch_copy(dst, src, bytes, stream));
+}
+
+} // extern "C"

@@ -1,0 +1,68 @@
+// Host-side launchers of the GEE kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gee {
+
+// Per-vertex label record used by the edge pass: 1 byte (K <= 255), 2 bytes
+// (K <= 65535) or 8 bytes (Laplacian: class + d^-1/2).
+enum class Pack { U8, U16, LAP64 };
+
+struct EmbedArgs {
+    int64_t n = 0;
+    int32_t K = 0;
+    bool laplacian = false;
+    bool weighted = false;
+    Pack pack = Pack::U8;
+    const int32_t *labels = nullptr;
+    int32_t *err = nullptr;
+    // workspace pieces
+    uint64_t *counts = nullptr;  // [K+1]
+    double *inv = nullptr;       // [K+1]
+    void *lab = nullptr;         // [n] packed records
+    double *deg = nullptr;       // [n] (Laplacian)
+    float *Z = nullptr;
+};
+
+hipError_t launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s);
+hipError_t launch_fill_f32(float *p, int64_t count, float value, hipStream_t s);
+hipError_t launch_counts(const int32_t *labels, int64_t n, int32_t K, uint64_t *counts, void *packed,
+                         Pack pack, int32_t *err, hipStream_t s);
+hipError_t launch_weights(const uint64_t *counts, int32_t K, double *inv, hipStream_t s);
+hipError_t launch_degrees_coo(int64_t n, int64_t ns, const int32_t *src, const int32_t *dst, const float *w,
+                              double *deg, bool check_neg, int32_t *err, hipStream_t s);
+hipError_t launch_degrees_csr(int64_t n, const int64_t *row_ptr, const float *val, int64_t nnz, double *deg,
+                              bool check_neg, int32_t *err, hipStream_t s);
+hipError_t launch_pack_lap(const int32_t *labels, int64_t n, int32_t K, const double *deg, uint64_t *lab,
+                           hipStream_t s);
+hipError_t launch_push(const EmbedArgs &a, int64_t ns, const int32_t *src, const int32_t *dst, const float *w,
+                       hipStream_t s);
+hipError_t launch_scale(const EmbedArgs &a, hipStream_t s);
+hipError_t launch_seg_bounds(int64_t n, int64_t nnz, const int64_t *row_ptr, int64_t L, int64_t nseg,
+                             int32_t *seg_i, int64_t *seg_e, hipStream_t s);
+// LDS bytes one wavefront of the pull kernel uses for `rw` rows of K bins.
+size_t pull_wave_bytes(int32_t K, bool wide_bins, int rw);
+hipError_t launch_pull(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                       const float *val, const int32_t *seg_i, const int64_t *seg_e, int64_t nseg, int rw,
+                       double *part, hipStream_t s);
+hipError_t launch_merge(const EmbedArgs &a, const int64_t *row_ptr, const int32_t *seg_i, const int64_t *seg_e,
+                        int64_t nseg, const double *part, hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// CSR build
+struct CsrBuildWs {
+    uint64_t *keys[2];
+    float *vals[2];
+    uint32_t *hist;     // [256 * nblocks]
+    int64_t *offs;      // [256 * nblocks]
+    int64_t *scan_part; // scan partials
+    int64_t *rowlast;   // [n]
+};
+size_t csr_build_layout(int64_t n, int64_t s, bool weighted, char *base, CsrBuildWs *out);
+hipError_t launch_csr_build(int64_t n, int64_t ns, const int32_t *src, const int32_t *dst, const float *w,
+                            int64_t *row_ptr, int32_t *col, float *val, const CsrBuildWs &ws, int32_t *err,
+                            hipStream_t s);
+
+} // namespace gee

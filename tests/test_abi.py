@@ -1,0 +1,112 @@
+"""The C ABI library loads, exports what include/gee.h declares, and rejects bad host
+arguments before launching anything (CPU only: no call here reaches a kernel)."""
+import ctypes
+import os
+import re
+
+import pytest
+import torch  # noqa: F401  (the HIP runtime libgee.so links against)
+
+import paper_2402_04403_amd as gee
+from paper_2402_04403_amd import build as hipbuild
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gee.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(gee.LIB_PATH):
+        hipbuild.build(force=True)
+    return gee.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(gee_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert {"gee_counts", "gee_weights", "gee_degrees", "gee_embed", "gee_embed_workspace", "gee_csr_build",
+            "gee_csr_workspace", "gee_copy", "gee_strerror"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in gee.h but not exported"
+
+
+def test_strerror(lib):
+    for code in range(-7, 1):
+        assert lib.gee_strerror(code)
+    assert lib.gee_strerror(-99) == b"unknown status"
+
+
+FAKE = 1 << 20  # an aligned non-null address; never dereferenced by these calls
+
+
+def test_host_argument_errors(lib):
+    assert lib.gee_counts(None, 10, 5, FAKE, FAKE, None) == gee.GEE_EINVAL
+    assert lib.gee_counts(FAKE, 0, 5, FAKE, FAKE, None) == gee.GEE_EINVAL
+    assert lib.gee_counts(FAKE, 10, 0, FAKE, FAKE, None) == gee.GEE_EINVAL
+    assert lib.gee_counts(FAKE, 10, 65536, FAKE, FAKE, None) == gee.GEE_EINVAL
+    assert lib.gee_weights(FAKE, 0, FAKE, None) == gee.GEE_EINVAL
+    assert lib.gee_degrees(None, None, FAKE, FAKE, None) == gee.GEE_EINVAL
+    assert lib.gee_copy(FAKE, FAKE + 4, 64, None) == gee.GEE_EINVAL
+    assert lib.gee_copy(FAKE, FAKE, 60, None) == gee.GEE_EINVAL
+
+
+def test_embed_argument_errors(lib):
+    coo = gee.Coo(100, 1000, FAKE, FAKE, None)
+    csr = gee.Csr(100, 2000, FAKE, FAKE, None)
+    o = gee.EmbedOpts(0, 0, None, None)
+    ws = lambda c, r, K, lap=0, opt=o: lib.gee_embed_workspace(c, r, K, lap, ctypes.byref(opt))
+    assert ws(ctypes.byref(coo), None, 5) > 0
+    assert ws(None, ctypes.byref(csr), 5) > 0
+    assert ws(None, None, 5) == 0
+    assert ws(ctypes.byref(coo), None, 0) == 0
+    assert ws(None, ctypes.byref(csr), 4097) == 0  # pull form: K <= 4096
+    assert ws(ctypes.byref(coo), None, 65535) > 0  # push form: up to 65535 (16-bit labels)
+    assert ws(None, ctypes.byref(csr), 5, 0, gee.EmbedOpts(10, 0, None, None)) == 0  # seg_len < 64
+    assert ws(None, ctypes.byref(csr), 5, 0, gee.EmbedOpts(0, 65, None, None)) == 0
+    bad_n = gee.Coo(0, 10, FAKE, FAKE, None)
+    assert ws(ctypes.byref(bad_n), None, 5) == 0
+    mismatch = gee.Coo(99, 10, FAKE, FAKE, None)
+    assert ws(ctypes.byref(mismatch), ctypes.byref(csr), 5) == 0
+    # workspace too small / misaligned / missing: rejected before any launch
+    need = ws(None, ctypes.byref(csr), 5)
+    call = lambda wsp, wsb: lib.gee_embed(None, ctypes.byref(csr), FAKE, 5, 0, FAKE, wsp, wsb, FAKE,
+                                          ctypes.byref(o), None)
+    assert call(FAKE, need - 1) == gee.GEE_EWORKSPACE
+    assert call(FAKE + 8, need) == gee.GEE_EWORKSPACE
+    assert call(None, need) == gee.GEE_EWORKSPACE
+    assert lib.gee_embed(None, ctypes.byref(csr), None, 5, 0, FAKE, FAKE, need, FAKE, ctypes.byref(o),
+                         None) == gee.GEE_EINVAL
+    big = gee.Coo(100, (1 << 40) + 1, FAKE, FAKE, None)
+    assert lib.gee_embed(ctypes.byref(big), None, FAKE, 5, 0, FAKE, FAKE, 1 << 30, FAKE, None,
+                         None) == gee.GEE_EOVERFLOW
+
+
+def test_workspace_sizes_scale(lib):
+    o = gee.EmbedOpts(0, 0, None, None)
+    small = gee.Csr(1000, 10_000, FAKE, FAKE, None)
+    large = gee.Csr(1000, 1_000_000, FAKE, FAKE, None)
+    a = lib.gee_embed_workspace(None, ctypes.byref(small), 50, 0, ctypes.byref(o))
+    b = lib.gee_embed_workspace(None, ctypes.byref(large), 50, 0, ctypes.byref(o))
+    assert b > a > 0 and a % 256 == 0 and b % 256 == 0
+    lap = lib.gee_embed_workspace(None, ctypes.byref(small), 50, 1, ctypes.byref(o))
+    assert lap > a  # 8-byte label records and FP64 degrees
+    assert lib.gee_csr_workspace(1000, 5000, 1) > lib.gee_csr_workspace(1000, 5000, 0) > 0
+    assert lib.gee_csr_workspace(0, 5000, 0) == 0
+
+
+def test_csr_build_argument_errors(lib):
+    coo = gee.Coo(100, 1000, FAKE, FAKE, FAKE)
+    need = lib.gee_csr_workspace(100, 1000, 1)
+    assert lib.gee_csr_build(ctypes.byref(coo), FAKE, FAKE, None, FAKE, need, FAKE, None) == gee.GEE_EINVAL
+    assert lib.gee_csr_build(ctypes.byref(coo), FAKE, FAKE, FAKE, FAKE, need - 1, FAKE, None) == gee.GEE_EWORKSPACE
+    assert lib.gee_csr_build(None, FAKE, FAKE, FAKE, FAKE, need, FAKE, None) == gee.GEE_EINVAL
+
+
+def test_python_binding_refuses_host_tensors(lib):
+    with pytest.raises(ValueError):
+        gee.counts(torch.zeros(4, dtype=torch.int32), 2)

@@ -1,0 +1,88 @@
+"""Parity at the workload sizes: the Erdős–Rényi weighted graph (n = 2^22, s = 2^26,
+K = 50) in full against the oracle, and the paper-scale R-MAT (scale 27, edge factor
+14, 1,879,048,192 records) on sampled rows, in the launch configuration the
+benchmark times (default segment length and window)."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+import paper_2402_04403_amd as gee
+from gpu_util import announce, assert_parity
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    announce(request.node.nodeid)
+    yield
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_er_weighted_full_parity():
+    t0 = time.time()
+    wl = gen.er_weighted()  # n = 2^22, s = 2^26, K = 50, 5% unknown
+    g = wl.graph
+    coo = gee.to_device(g.n, g.src, g.dst, g.w, device=DEV)
+    labels = torch.as_tensor(wl.labels).to(DEV)
+    csr = gee.csr_build(coo)
+    assert np.array_equal(gee.counts(labels, wl.K).cpu().numpy(), oracle.counts(wl.labels, wl.K))
+    d = gee.degrees(csr=csr).cpu().numpy()
+    assert np.array_equal(d, oracle.degrees(g.n, g.src, g.dst, g.w))
+    announce(f"  inputs ready {time.time() - t0:.1f}s")
+    for lap in (False, True):
+        Zo = oracle.embed(g.n, g.src, g.dst, g.w, wl.labels, wl.K, lap)
+        announce(f"  oracle lap={lap} {time.time() - t0:.1f}s")
+        Zp = gee.embed(labels, wl.K, csr=csr, laplacian=lap).cpu().numpy()
+        e_pull = assert_parity(Zp, Zo, what=f"pull lap={lap}")
+        Za = gee.embed(labels, wl.K, coo=coo, laplacian=lap).cpu().numpy()
+        e_push = assert_parity(Za, Zo, what=f"push lap={lap}")
+        announce(f"  lap={lap}: pull {e_pull:.2e} push {e_push:.2e}")
+        del Zo, Zp, Za
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_rmat_paper_scale_sampled_rows():
+    t0 = time.time()
+    wl = gen.rmat_paper_scale()  # scale 27, edge factor 14, K = 50, 1% unknown
+    g = wl.graph
+    announce(f"  generated s={g.s} {time.time() - t0:.1f}s")
+    coo = gee.to_device(g.n, g.src, g.dst, device=DEV)
+    labels = torch.as_tensor(wl.labels).to(DEV)
+    csr = gee.csr_build(coo)
+    torch.cuda.synchronize()
+    announce(f"  csr built nnz={csr.nnz} {time.time() - t0:.1f}s")
+    assert csr.nnz == 2 * g.s
+    assert np.array_equal(gee.counts(labels, wl.K).cpu().numpy(), oracle.counts(wl.labels, wl.K))
+    # rows to compare: uniform rows, the highest-degree rows (split across many
+    # segments), and isolated rows (must be exactly zero)
+    rng = np.random.default_rng(27)
+    deg = (csr.row_ptr[1:] - csr.row_ptr[:-1])
+    top = torch.topk(deg, 64).indices.cpu().numpy()
+    iso = torch.nonzero(deg == 0)[:64, 0].cpu().numpy()
+    rows = np.unique(np.r_[rng.choice(g.n, 3000, replace=False), top, iso]).astype(np.int64)
+    idx = torch.as_tensor(rows, device=DEV)
+    Zp = gee.embed(labels, wl.K, csr=csr)
+    pull_rows = Zp[idx].cpu().numpy()
+    del Zp
+    torch.cuda.empty_cache()
+    announce(f"  pull done {time.time() - t0:.1f}s")
+    Za = gee.embed(labels, wl.K, coo=coo)
+    push_rows = Za[idx].cpu().numpy()
+    del Za
+    announce(f"  push done {time.time() - t0:.1f}s")
+    Zo = oracle.embed_rows(g.n, g.src, g.dst, None, wl.labels, wl.K, False, rows)
+    announce(f"  oracle rows {time.time() - t0:.1f}s")
+    assert_parity(pull_rows, Zo, what="pull, sampled rows")
+    assert_parity(push_rows, Zo, what="push, sampled rows")
+    # unit weights: both forms hold exact integer sums, so they agree bit for bit
+    assert np.array_equal(pull_rows.view(np.uint32), push_rows.view(np.uint32))
+    assert not pull_rows[np.isin(rows, iso)].any()
