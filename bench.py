@@ -48,6 +48,7 @@ def parse():
     p.add_argument("--form", choices=["pull", "push"], default="pull")
     p.add_argument("--seg-len", type=int, default=0)
     p.add_argument("--rows-per-window", type=int, default=0)
+    p.add_argument("--hot-budget", type=int, default=-1, help="hot-vertex slots of the CSR (-1: library default)")
     p.add_argument("--push-steps", type=int, default=3, help="timed steps of the push form, reported beside")
     p.add_argument("--cpu-records", type=int, default=20_000_000)
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -104,7 +105,8 @@ def main():
     # per-graph preprocessing: canonical symmetric CSR
     e0, e1 = gee.HipEvent(), gee.HipEvent()
     e0.record()
-    csr = gee.csr_build(coo, check=False)
+    hot_budget = gee.DEFAULT_HOT_BUDGET if a.hot_budget < 0 else a.hot_budget
+    csr = gee.csr_build(coo, hot_budget=hot_budget, check=False)
     e1.record()
     e1.synchronize()
     csr_ms = e0.elapsed_ms(e1)
@@ -225,6 +227,7 @@ def main():
             "workload": f"rmat-s{a.scale}-ef{a.edge_factor}-K{K}-unit-adjacency",
             "n": n, "s": s, "nnz": nnz, "K": K, "form": "csr-pull" if a.form == "pull" else "edge-push",
             "seg_len": a.seg_len or 4096, "rows_per_window": a.rows_per_window or "auto",
+            "hot_slots": csr.n_hot,
             "csr_build_ms": round(csr_ms, 2),
             "step_hbm_frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "copy_probe_GBps": round(copy_gbps, 1),

@@ -79,19 +79,27 @@ typedef struct gee_coo {
  * non-decreasing with row_ptr[0] = 0 and row_ptr[n] = nnz. gee_csr_build writes
  * rows sorted by (column, bit pattern of w), which makes the layout independent
  * of record order; gee_embed accepts any valid layout. val == NULL means unit
- * weights. The struct is host memory; the arrays are device memory. */
+ * weights. The struct is host memory; the arrays are device memory.
+ *
+ * Hot-vertex slots (optional, n_hot > 0): a column value with bit 31 set names
+ * slot (col & 0x7fffffff) < n_hot, whose vertex is hot_ids[slot]. gee_csr_build
+ * gives the n_hot highest-degree vertices such slots so that gee_embed gathers
+ * their labels from a compact table that stays in cache. With n_hot == 0 every
+ * column is a plain vertex id and hot_ids is ignored. */
 typedef struct gee_csr {
     int64_t n;              /* vertex count, as in gee_coo */
     int64_t nnz;            /* entry count (2 s for a CSR built from s records) */
     const int64_t *row_ptr; /* [n + 1] */
     const int32_t *col;     /* [nnz] */
     const float *val;       /* [nnz] or NULL */
+    int64_t n_hot;          /* number of hot slots, 0 <= n_hot <= n */
+    const int32_t *hot_ids; /* [n_hot] vertex id of each slot, or NULL when n_hot == 0 */
 } gee_csr;
 
 /* Optional knobs of gee_embed (host struct; pass NULL for the defaults). */
 typedef struct gee_embed_opts {
     /* CSR-pull form: work items (rows + entries) per wavefront segment; 0 picks
-     * the default (4096). Must be 0 or in [64, 2^24]. */
+     * the default (4096). Must be 0 or in [64, 65535]. */
     int32_t seg_len;
     /* CSR-pull form: rows per LDS window; 0 picks the largest that fits the
      * per-wavefront LDS budget (at most 64). Must be 0 or in [1, 64]. */
@@ -146,15 +154,21 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
               float *Z, void *ws, size_t ws_bytes, int32_t *err, const gee_embed_opts *opts,
               hipStream_t stream);
 
-/* Workspace bytes gee_csr_build needs (weighted != 0 when the records carry w). */
-size_t gee_csr_workspace(int64_t n, int64_t s, int weighted);
+/* Workspace bytes gee_csr_build needs (weighted != 0 when the records carry w;
+ * hot_budget as passed to gee_csr_build). Returns 0 on invalid input. */
+size_t gee_csr_workspace(int64_t n, int64_t s, int weighted, int64_t hot_budget);
 
 /* Build the symmetric CSR of S = A + A^T from g: row_ptr [n + 1] int64, col [2 s]
  * int32 and, when g->w != NULL, val [2 s] float (else val may be NULL). Rows come
  * out sorted by (column, bit pattern of w): a stable LSD radix sort of the 2 s
- * directed entries, so the result depends only on the multiset of records. */
-int gee_csr_build(const gee_coo *g, int64_t *row_ptr, int32_t *col, float *val, void *ws,
-                  size_t ws_bytes, int32_t *err, hipStream_t stream);
+ * directed entries, so the result depends only on the multiset of records.
+ * With hot_budget > 0, the n_hot = min(hot_budget, n) vertices of highest degree
+ * (ties: smaller id first) get slots 0..n_hot-1 in id order: hot_ids [n_hot]
+ * receives their ids and each column naming one of them is stored as
+ * (slot | 0x80000000); the gee_csr passed to gee_embed then carries n_hot and
+ * hot_ids. The choice of slots depends only on the graph. */
+int gee_csr_build(const gee_coo *g, int64_t hot_budget, int64_t *row_ptr, int32_t *col, float *val,
+                  int32_t *hot_ids, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream);
 
 /* Measurement probe: copy `bytes` bytes from src to dst with a plain streaming
  * kernel (16-byte loads and stores). Used to calibrate memory-traffic counters

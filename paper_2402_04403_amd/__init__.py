@@ -28,7 +28,9 @@ LIB_PATH = os.path.join(_PKG, "libgee.so")
 
 GEE_OK, GEE_EINVAL, GEE_ELABEL, GEE_EVERTEX, GEE_ENEGW, GEE_EOVERFLOW, GEE_EWORKSPACE, GEE_EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
-_c_i32p = ctypes.POINTER(ctypes.c_int32)
+# Hot-vertex slots the benchmark configuration gives a CSR: a 2 MiB label table
+# (1-byte records) that fits in one XCD's 4 MiB L2 beside the streaming traffic.
+DEFAULT_HOT_BUDGET = 1 << 21
 
 
 class GeeError(RuntimeError):
@@ -45,7 +47,8 @@ class Coo(ctypes.Structure):
 
 class Csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
-                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p), ("n_hot", ctypes.c_int64),
+                ("hot_ids", ctypes.c_void_p)]
 
 
 class EmbedOpts(ctypes.Structure):
@@ -82,9 +85,9 @@ def load():
         lib.gee_embed.restype = ci
         lib.gee_embed.argtypes = [CooP, CsrP, vp, i32, ci, vp, vp, sz, vp, OptP, vp]
         lib.gee_csr_workspace.restype = sz
-        lib.gee_csr_workspace.argtypes = [i64, i64, ci]
+        lib.gee_csr_workspace.argtypes = [i64, i64, ci, i64]
         lib.gee_csr_build.restype = ci
-        lib.gee_csr_build.argtypes = [CooP, vp, vp, vp, vp, sz, vp, vp]
+        lib.gee_csr_build.argtypes = [CooP, i64, vp, vp, vp, vp, vp, sz, vp, vp]
         lib.gee_copy.restype = ci
         lib.gee_copy.argtypes = [vp, vp, sz, vp]
         _lib = lib
@@ -188,14 +191,22 @@ class DeviceCoo:
 
 @dataclass
 class DeviceCsr:
+    """Symmetric CSR on the GPU. With ``hot_ids`` set, a column with bit 31 set names
+    slot ``col & 0x7fffffff`` of ``hot_ids`` instead of a vertex."""
+
     n: int
     row_ptr: torch.Tensor
     col: torch.Tensor
     val: torch.Tensor | None = None
+    hot_ids: torch.Tensor | None = None
 
     @property
     def nnz(self) -> int:
         return int(self.col.numel())
+
+    @property
+    def n_hot(self) -> int:
+        return 0 if self.hot_ids is None else int(self.hot_ids.numel())
 
     def struct(self) -> Csr:
         dev = self.row_ptr.device
@@ -203,7 +214,18 @@ class DeviceCsr:
         _need(self.col, torch.int32, None, "col", dev)
         if self.val is not None:
             _need(self.val, torch.float32, self.nnz, "val", dev)
-        return Csr(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val))
+        if self.hot_ids is not None:
+            _need(self.hot_ids, torch.int32, None, "hot_ids", dev)
+        return Csr(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val), self.n_hot,
+                   _ptr(self.hot_ids))
+
+    def plain_col(self) -> torch.Tensor:
+        """Columns as vertex ids (hot slots resolved)."""
+        if self.hot_ids is None:
+            return self.col
+        hot = self.col < 0
+        slot = (self.col & 0x7FFFFFFF).long()
+        return torch.where(hot, self.hot_ids[slot.clamp(max=max(self.n_hot - 1, 0))], self.col)
 
 
 def to_device(n: int, src, dst, w=None, device="cuda") -> DeviceCoo:
@@ -253,25 +275,28 @@ def degrees(coo: DeviceCoo | None = None, csr: DeviceCsr | None = None, stream=N
     return deg
 
 
-def csr_build(coo: DeviceCoo, stream=None, check: bool = True) -> DeviceCsr:
+def csr_build(coo: DeviceCoo, hot_budget: int = 0, stream=None, check: bool = True) -> DeviceCsr:
+    """Canonical symmetric CSR; ``hot_budget > 0`` gives the highest-degree vertices hot slots."""
     lib = load()
     st = coo.struct()
     dev = coo.src.device
     nnz = 2 * coo.s
+    n_hot = min(int(hot_budget), coo.n)
     row_ptr = torch.empty(coo.n + 1, dtype=torch.int64, device=dev)
     col = torch.empty(nnz, dtype=torch.int32, device=dev)
     val = torch.empty(nnz, dtype=torch.float32, device=dev) if coo.w is not None else None
-    wsb = lib.gee_csr_workspace(coo.n, coo.s, 1 if coo.w is not None else 0)
+    hot_ids = torch.empty(n_hot, dtype=torch.int32, device=dev) if n_hot > 0 else None
+    wsb = lib.gee_csr_workspace(coo.n, coo.s, 1 if coo.w is not None else 0, n_hot)
     if wsb == 0:
         raise GeeError(GEE_EINVAL, "gee_csr_workspace")
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     err = torch.zeros(1, dtype=torch.int32, device=dev)
-    _rc(lib.gee_csr_build(ctypes.byref(st), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(ws), wsb, _ptr(err),
-                          _stream(stream)), "gee_csr_build")
+    _rc(lib.gee_csr_build(ctypes.byref(st), n_hot, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(hot_ids), _ptr(ws),
+                          wsb, _ptr(err), _stream(stream)), "gee_csr_build")
     if check:
         _check_err(err, "gee_csr_build")
     del ws
-    return DeviceCsr(coo.n, row_ptr, col, val)
+    return DeviceCsr(coo.n, row_ptr, col, val, hot_ids)
 
 
 def _opts(seg_len=0, rows_per_window=0, events=None):

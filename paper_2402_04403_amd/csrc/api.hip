@@ -16,6 +16,7 @@ constexpr int64_t kMaxRecords = (int64_t)1 << 40;
 constexpr int32_t kMaxK = 65535;
 constexpr int32_t kMaxKPull = 4096;
 constexpr int32_t kDefaultSegLen = 4096;
+constexpr int32_t kMaxSegLen = 65535; // 16-bit per-segment class counters
 constexpr size_t kWaveLdsBudget = 16384;
 
 inline bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -29,7 +30,8 @@ struct Plan {
     int64_t L = 0, nseg = 0;
     int rw = 0;
     // workspace offsets
-    size_t o_counts = 0, o_inv = 0, o_lab = 0, o_deg = 0, o_segi = 0, o_sege = 0, o_part = 0, total = 0;
+    int64_t n_hot = 0;
+    size_t o_counts = 0, o_inv = 0, o_lab = 0, o_deg = 0, o_hot = 0, o_segi = 0, o_sege = 0, o_part = 0, total = 0;
 };
 
 int check_coo(const gee_coo *g)
@@ -47,6 +49,7 @@ int check_csr(const gee_csr *c)
     if (c->n < 1 || c->n > kMaxN || c->nnz < 0 || !c->row_ptr) return GEE_EINVAL;
     if (c->nnz > 2 * kMaxRecords) return GEE_EOVERFLOW;
     if (c->nnz > 0 && !c->col) return GEE_EINVAL;
+    if (c->n_hot < 0 || c->n_hot > c->n || (c->n_hot > 0 && !c->hot_ids)) return GEE_EINVAL;
     return GEE_OK;
 }
 
@@ -65,6 +68,7 @@ int make_plan(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian, co
         P.n = csr->n;
         P.nnz = csr->nnz;
         P.weighted = csr->val != nullptr;
+        P.n_hot = csr->n_hot;
     } else {
         if ((rc = check_coo(g)) != GEE_OK) return rc;
         P.n = g->n;
@@ -74,7 +78,7 @@ int make_plan(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian, co
     P.pack = P.lap ? Pack::LAP64 : (K <= 255 ? Pack::U8 : Pack::U16);
     P.wide = P.lap || P.weighted;
     if (o) {
-        if (o->seg_len != 0 && (o->seg_len < 64 || o->seg_len > (1 << 24))) return GEE_EINVAL;
+        if (o->seg_len != 0 && (o->seg_len < 64 || o->seg_len > kMaxSegLen)) return GEE_EINVAL;
         if (o->rows_per_window < 0 || o->rows_per_window > 64) return GEE_EINVAL;
     }
     if (P.pull) {
@@ -101,6 +105,7 @@ int make_plan(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian, co
     P.o_lab = take(lab_bytes * (size_t)P.n);
     if (P.lap) P.o_deg = take(8 * (size_t)P.n);
     if (P.pull) {
+        P.o_hot = take(lab_bytes * (size_t)P.n_hot);
         P.o_segi = take(4 * (size_t)(P.nseg + 1));
         P.o_sege = take(8 * (size_t)(P.nseg + 1));
         P.o_part = take(8 * 2 * (size_t)P.nseg * (size_t)K);
@@ -198,6 +203,9 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
         if ((rc = hip_rc(e))) return rc;
         if ((rc = hip_rc(launch_pack_lap(labels, p.n, K, a.deg, static_cast<uint64_t *>(a.lab), stream)))) return rc;
     }
+    if (p.pull && p.n_hot > 0 &&
+        (rc = hip_rc(launch_pack_hot(a, csr->hot_ids, p.n_hot, w + p.o_hot, stream))))
+        return rc;
     const bool timed = opts && opts->hot_begin && opts->hot_end;
     if (!p.pull) {
         if ((rc = hip_rc(launch_fill_f32(Z, p.n * K, 0.0f, stream)))) return rc;
@@ -211,30 +219,33 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
     double *part = reinterpret_cast<double *>(w + p.o_part);
     if ((rc = hip_rc(launch_seg_bounds(p.n, p.nnz, csr->row_ptr, p.L, p.nseg, seg_i, seg_e, stream)))) return rc;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_begin, stream)))) return rc;
-    if ((rc = hip_rc(launch_pull(a, p.nnz, csr->row_ptr, csr->col, csr->val, seg_i, seg_e, p.nseg, p.rw, part,
-                                 stream))))
+    if ((rc = hip_rc(launch_pull(a, p.nnz, csr->row_ptr, csr->col, csr->val, w + p.o_hot, p.n_hot, seg_i, seg_e,
+                                 p.nseg, p.rw, part, stream))))
         return rc;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;
     return hip_rc(launch_merge(a, csr->row_ptr, seg_i, seg_e, p.nseg, part, stream));
 }
 
-size_t gee_csr_workspace(int64_t n, int64_t s, int weighted)
+size_t gee_csr_workspace(int64_t n, int64_t s, int weighted, int64_t hot_budget)
 {
-    if (n < 1 || n > kMaxN || s < 0 || s > kMaxRecords) return 0;
-    return csr_build_layout(n, s, weighted != 0, nullptr, nullptr);
+    if (n < 1 || n > kMaxN || s < 0 || s > kMaxRecords || hot_budget < 0) return 0;
+    return csr_build_layout(n, s, weighted != 0, hot_budget < n ? hot_budget : n, nullptr, nullptr);
 }
 
-int gee_csr_build(const gee_coo *g, int64_t *row_ptr, int32_t *col, float *val, void *ws, size_t ws_bytes,
-                  int32_t *err, hipStream_t stream)
+int gee_csr_build(const gee_coo *g, int64_t hot_budget, int64_t *row_ptr, int32_t *col, float *val,
+                  int32_t *hot_ids, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream)
 {
     int rc = check_coo(g);
     if (rc != GEE_OK) return rc;
-    if (!row_ptr || (g->s > 0 && !col) || (g->w && g->s > 0 && !val)) return GEE_EINVAL;
-    const size_t need = csr_build_layout(g->n, g->s, g->w != nullptr, nullptr, nullptr);
+    if (hot_budget < 0) return GEE_EINVAL;
+    const int64_t n_hot = hot_budget < g->n ? hot_budget : g->n;
+    if (!row_ptr || (g->s > 0 && !col) || (g->w && g->s > 0 && !val) || (n_hot > 0 && !hot_ids)) return GEE_EINVAL;
+    const size_t need = csr_build_layout(g->n, g->s, g->w != nullptr, n_hot, nullptr, nullptr);
     if (!ws || !aligned(ws, 256) || ws_bytes < need) return GEE_EWORKSPACE;
     CsrBuildWs w;
-    csr_build_layout(g->n, g->s, g->w != nullptr, static_cast<char *>(ws), &w);
-    return hip_rc(launch_csr_build(g->n, g->s, g->src, g->dst, g->w, row_ptr, col, val, w, err, stream));
+    csr_build_layout(g->n, g->s, g->w != nullptr, n_hot, static_cast<char *>(ws), &w);
+    return hip_rc(
+        launch_csr_build(g->n, g->s, g->src, g->dst, g->w, n_hot, row_ptr, col, val, hot_ids, w, err, stream));
 }
 
 int gee_copy(void *dst, const void *src, size_t bytes, hipStream_t stream)

@@ -309,6 +309,98 @@ k_finalize(const uint64_t *__restrict__ keys, const float *__restrict__ vin, int
     }
 }
 
+// -------------------------------------------------- hot-vertex selection ----
+//
+// The n_hot vertices of highest degree (ties broken by smaller id) get slots
+// 0..n_hot-1 in id order, and every CSR column naming one of them is rewritten
+// as (slot | 2^31). The pull pass then gathers these labels from a compact table
+// of n_hot records, small enough to stay in L2, instead of from the n-entry
+// label array. Degrees above kDegBins - 1 share the top bucket.
+
+constexpr int kDegBins = 4096;
+
+__device__ inline int deg_bucket(const int64_t *__restrict__ row_ptr, int64_t v)
+{
+    const int64_t d = row_ptr[v + 1] - row_ptr[v];
+    return d <= 0 ? 0 : (d >= kDegBins - 1 ? kDegBins - 1 : (int)d);
+}
+
+__global__ void __launch_bounds__(kT) k_deg_hist(int64_t n, const int64_t *__restrict__ row_ptr, int64_t *hist)
+{
+    __shared__ uint32_t h[kDegBins];
+    for (int b = threadIdx.x; b < kDegBins; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&h[deg_bucket(row_ptr, v)], 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < kDegBins; b += blockDim.x)
+        if (h[b]) atomicAdd((unsigned long long *)&hist[b], (unsigned long long)h[b]);
+}
+
+// par[0] = bucket T with #(bucket >= T) >= H > #(bucket > T); par[1] = how many
+// bucket-T vertices (the lowest ids) join the hot set.
+__global__ void k_hot_threshold(const int64_t *__restrict__ hist, int64_t H, int64_t *par)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t above = 0;
+    int T = 0;
+    int64_t quota = H;
+    for (int b = kDegBins - 1; b >= 0; --b) {
+        if (above + hist[b] >= H) {
+            T = b;
+            quota = H - above;
+            break;
+        }
+        above += hist[b];
+    }
+    par[0] = T;
+    par[1] = quota;
+}
+
+__global__ void __launch_bounds__(kT)
+k_hot_eq(int64_t n, const int64_t *__restrict__ row_ptr, const int64_t *__restrict__ par, int64_t *__restrict__ eq)
+{
+    const int T = (int)par[0];
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        eq[v] = deg_bucket(row_ptr, v) == T;
+}
+
+__global__ void __launch_bounds__(kT)
+k_hot_flag(int64_t n, const int64_t *__restrict__ row_ptr, const int64_t *__restrict__ par,
+           const int64_t *__restrict__ eqrank, int64_t *__restrict__ hot)
+{
+    const int T = (int)par[0];
+    const int64_t quota = par[1];
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int b = deg_bucket(row_ptr, v);
+        hot[v] = b > T || (b == T && eqrank[v] < quota);
+    }
+}
+
+// hot_ids[slot[v]] = v for hot v; map[v] becomes slot[v] (hot) or -1, in place of the flag.
+__global__ void __launch_bounds__(kT)
+k_hot_ids(int64_t n, int64_t n_hot, int64_t *__restrict__ flag_to_map, const int64_t *__restrict__ slot,
+          int32_t *__restrict__ hot_ids)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const bool hot = flag_to_map[v] != 0;
+        const int64_t sl = slot[v];
+        if (hot && sl < n_hot) hot_ids[sl] = (int32_t)v;
+        flag_to_map[v] = (hot && sl < n_hot) ? sl : -1;
+    }
+}
+
+__global__ void __launch_bounds__(kT)
+k_col_encode(int64_t N, int64_t n, int32_t *__restrict__ col, const int64_t *__restrict__ map)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = col[j];
+        if ((uint32_t)c >= (uint64_t)n) continue;
+        const int64_t sl = map[c];
+        if (sl >= 0) col[j] = (int32_t)((uint32_t)sl | 0x80000000u);
+    }
+}
+
 __global__ void k_fill_i64(int64_t *__restrict__ p, int64_t count, int64_t value)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
@@ -332,7 +424,7 @@ int key_bits(int64_t n)
 
 } // namespace
 
-size_t csr_build_layout(int64_t n, int64_t s, bool weighted, char *base, CsrBuildWs *out)
+size_t csr_build_layout(int64_t n, int64_t s, bool weighted, int64_t n_hot, char *base, CsrBuildWs *out)
 {
     const int64_t N = 2 * s;
     const int64_t nt = tiles(N > 0 ? N : 1);
@@ -354,13 +446,19 @@ size_t csr_build_layout(int64_t n, int64_t s, bool weighted, char *base, CsrBuil
     w.offs = (int64_t *)take((size_t)hist_len * 8);
     w.scan_part = (int64_t *)take((size_t)tiles(scan_len) * 8 + 8);
     w.rowlast = (int64_t *)take((size_t)n * 8);
+    if (n_hot > 0) {
+        w.vtmp[0] = (int64_t *)take((size_t)n * 8);
+        w.vtmp[1] = (int64_t *)take((size_t)n * 8);
+        w.hot_hist = (int64_t *)take((size_t)kDegBins * 8);
+        w.hot_par = (int64_t *)take(2 * 8);
+    }
     if (out) *out = w;
     return align_up(off, 256);
 }
 
 hipError_t launch_csr_build(int64_t n, int64_t ns, const int32_t *src, const int32_t *dst, const float *w,
-                            int64_t *row_ptr, int32_t *col, float *val, const CsrBuildWs &ws, int32_t *err,
-                            hipStream_t s)
+                            int64_t n_hot, int64_t *row_ptr, int32_t *col, float *val, int32_t *hot_ids,
+                            const CsrBuildWs &ws, int32_t *err, hipStream_t s)
 {
     const int64_t N = 2 * ns;
     const bool HV = w != nullptr;
@@ -424,7 +522,24 @@ hipError_t launch_csr_build(int64_t n, int64_t ns, const int32_t *src, const int
     // row_ptr[0] = 0; row_ptr[u + 1] = max over rows r <= u of rowlast[r]
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(1), 0, s, row_ptr, (int64_t)1, (int64_t)0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return scan(ws.rowlast, n, row_ptr + 1, ws.scan_part, MaxOp{}, true, s);
+    if ((e = scan(ws.rowlast, n, row_ptr + 1, ws.scan_part, MaxOp{}, true, s)) != hipSuccess) return e;
+    if (n_hot <= 0) return hipSuccess;
+
+    // hot-vertex slots and column encoding
+    const dim3 gv(grid_cap(n, kT * 4)), b(kT);
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_cap(kDegBins, kT)), b, 0, s, ws.hot_hist, (int64_t)kDegBins, (int64_t)0);
+    hipLaunchKernelGGL(k_deg_hist, dim3(grid_cap(n, kT * 16)), b, 0, s, n, (const int64_t *)row_ptr, ws.hot_hist);
+    hipLaunchKernelGGL(k_hot_threshold, dim3(1), dim3(64), 0, s, (const int64_t *)ws.hot_hist, n_hot, ws.hot_par);
+    hipLaunchKernelGGL(k_hot_eq, gv, b, 0, s, n, (const int64_t *)row_ptr, (const int64_t *)ws.hot_par, ws.vtmp[0]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan(ws.vtmp[0], n, ws.vtmp[1], ws.scan_part, SumOp{}, false, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hot_flag, gv, b, 0, s, n, (const int64_t *)row_ptr, (const int64_t *)ws.hot_par,
+                       (const int64_t *)ws.vtmp[1], ws.vtmp[0]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan(ws.vtmp[0], n, ws.vtmp[1], ws.scan_part, SumOp{}, false, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hot_ids, gv, b, 0, s, n, n_hot, ws.vtmp[0], (const int64_t *)ws.vtmp[1], hot_ids);
+    hipLaunchKernelGGL(k_col_encode, dim3(grid_cap(N, kT * 4)), b, 0, s, N, n, col, (const int64_t *)ws.vtmp[0]);
+    return hipGetLastError();
 }
 
 } // namespace gee

@@ -140,6 +140,20 @@ k_pack_lap(const int32_t *__restrict__ labels, int64_t n, int32_t K, const doubl
     }
 }
 
+// Compact label table of the hot vertices named by a CSR's hot slots.
+template <typename P>
+__global__ void __launch_bounds__(kBlock)
+k_pack_hot(const P *__restrict__ lab, int64_t n, const int32_t *__restrict__ hot_ids, int64_t n_hot,
+           P *__restrict__ hotlab, int32_t *err)
+{
+    for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_hot; h += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = hot_ids[h];
+        const bool ok = (uint32_t)v < (uint64_t)n;
+        if (!ok) flag_error(err, GEE_EVERTEX);
+        hotlab[h] = ok ? lab[v] : (P)0;
+    }
+}
+
 // -------------------------------------------------------- form (a): push --
 
 // One thread per record (four records per thread, strided for coalescing):
@@ -256,102 +270,252 @@ __device__ inline SegInfo seg_info(int64_t j, int64_t n, const int64_t *__restri
     return s;
 }
 
-template <typename B> __device__ inline void lds_add(B *p, B x);
-template <> __device__ inline void lds_add<uint32_t>(uint32_t *p, uint32_t x) { atomicAdd(p, x); }
-template <> __device__ inline void lds_add<double>(double *p, double x) { atomicAdd(p, x); }
-
-// One wavefront per segment. The segment's rows are walked in windows of RW
-// consecutive rows whose K bins live in this wavefront's LDS slice. Entries are
-// read 64 at a time (coalesced), each lane finds its entry's row by binary
-// search over the window's row starts, gathers the neighbour's label record and
-// adds into bin (row, class) with an LDS atomic. A window's rows are then
-// written to Z as one contiguous block (non-temporal stores); a row cut by a
-// segment boundary goes to the FP64 partials instead (head: continues from an
-// earlier segment; tail: continues into later ones).
-template <typename B, bool LAP, bool W, typename P>
-__global__ void __launch_bounds__(kBlock)
-k_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-       const float *__restrict__ val, const P *__restrict__ lab, const double *__restrict__ inv, int32_t K,
-       uint64_t kmagic32, const int32_t *__restrict__ seg_i, const int64_t *__restrict__ seg_e, int64_t nseg,
-       int RW, uint32_t wave_bytes, float *__restrict__ Z, double *__restrict__ part, int32_t *err)
+__device__ inline int wave_incl_max(int x)
 {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x = x > y ? x : y;
+    }
+    return x;
+}
+
+// Bin storage of the pull pass. Unit-weight adjacency counts two classes per
+// 32-bit word (16-bit counters; a segment holds at most 65535 entries, so they
+// cannot overflow); every other variant keeps one FP64 sum per class.
+template <bool PACKED> struct Bins;
+template <> struct Bins<true> {
+    using word = uint32_t;
+    __host__ __device__ static int words(int K) { return (K + 1) / 2; }
+    __device__ static void add(word *row, int k, double) { atomicAdd(&row[k >> 1], 1u << (16 * (k & 1))); }
+    __device__ static double get(const word *row, int k) { return (double)((row[k >> 1] >> (16 * (k & 1))) & 0xffffu); }
+};
+template <> struct Bins<false> {
+    using word = double;
+    __host__ __device__ static int words(int K) { return K; }
+    __device__ static void add(word *row, int k, double x) { atomicAdd(&row[k], x); }
+    __device__ static double get(const word *row, int k) { return row[k]; }
+};
+
+constexpr int kPass = 1024;              // entries whose row-start markers are mapped at once
+constexpr int kChunk = 2 * 4 * kWave;    // entries per inner step (two 16-byte loads per lane)
+constexpr int kFlatFlushMaxK = kWave;    // K up to this writes rows as flat aligned blocks
+
+// LDS of one wavefront: bins of RW rows, the row-start marker map of one pass,
+// and the class weights (K <= 64).
+__host__ __device__ inline size_t pull_bins_bytes(int32_t K, bool packed, int rw)
+{
+    return align_up((size_t)rw * (packed ? (K + 1) / 2 * 4 : (size_t)K * 8), 16);
+}
+__host__ __device__ inline size_t pull_lds_bytes(int32_t K, bool packed, int rw)
+{
+    return pull_bins_bytes(K, packed, rw) + kPass + (K <= kFlatFlushMaxK ? align_up((size_t)K * 8, 16) : 0);
+}
+
+// One wavefront per segment of seg_len work items (rows + entries).
+//  - The segment's rows are walked in windows of RW consecutive rows whose K bins
+//    live in this wavefront's LDS.
+//  - A window's entries are taken in passes of kPass entries; in each pass the
+//    rows starting inside it write their local index into a byte map at their
+//    first entry. An entry's row is the running maximum of the markers up to it:
+//    a max over the lane's own four entries plus a wavefront max-scan, carried
+//    from step to step.
+//  - Each step reads 512 entries (two 16-byte loads per lane). The neighbour label
+//    records of step i are gathered before the column loads of step i+1 are
+//    issued, so those loads stay in flight while step i adds into its bins with
+//    LDS atomics. A column value with bit 31 set names a slot of the compact
+//    hot-vertex label table instead of a vertex.
+//  - The window's rows are written to Z with non-temporal stores: for K <= 64 as
+//    one flat run of floats in aligned 64-float blocks (whole cache lines), else
+//    row by row with lanes over classes. A row cut by a segment boundary goes to
+//    the FP64 partials instead (head: continues from an earlier segment; tail:
+//    continues into later ones).
+template <bool PACKED, bool LAP, bool W, typename P>
+__global__ void __launch_bounds__(kBlock)
+k_pull(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+       const float *__restrict__ val, const P *__restrict__ lab, const P *__restrict__ hotlab, int64_t n_hot,
+       const double *__restrict__ inv, int32_t K, const int32_t *__restrict__ seg_i,
+       const int64_t *__restrict__ seg_e, int64_t nseg, int RW, uint32_t wave_bytes, bool vec_ok,
+       float *__restrict__ Z, double *__restrict__ part, int32_t *err)
+{
+    using BT = Bins<PACKED>;
+    using word = typename BT::word;
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (j >= nseg) return;
-    B *bins = (B *)(smem + (size_t)wave * wave_bytes);
-    int32_t *cs = (int32_t *)(smem + (size_t)wave * wave_bytes + align_up((size_t)RW * K * sizeof(B), 16));
+    unsigned char *my = smem + (size_t)wave * wave_bytes;
+    const int KW = BT::words(K);
+    word *bins = (word *)my;
+    int8_t *mark = (int8_t *)(my + pull_bins_bytes(K, PACKED, RW));
+    double *invt = (double *)(my + pull_bins_bytes(K, PACKED, RW) + kPass);
+    const bool flat = K <= kFlatFlushMaxK;
 
     const SegInfo sg = seg_info(j, n, row_ptr, seg_i, seg_e);
-    for (int b = lane; b < RW * K; b += kWave) bins[b] = (B)0;
+    for (int b = lane; b < RW * KW; b += kWave) bins[b] = (word)0;
+    for (int b = lane; b < kPass / 4; b += kWave) ((int32_t *)mark)[b] = -1;
+    if (flat && lane < K) invt[lane] = inv[lane + 1];
     bool bad = false;
 
     for (int64_t r = sg.i0; r < sg.rend; r += RW) {
         const int nr = (int)((sg.rend - r) < RW ? (sg.rend - r) : RW);
-        // clamped row starts of the window, relative to e0; cs[nr] ends the last row
-        for (int l = lane; l <= nr; l += kWave) {
-            int64_t p = row_ptr[r + l];
-            p = p < sg.e0 ? sg.e0 : (p > sg.e1 ? sg.e1 : p);
-            cs[l] = (int32_t)(p - sg.e0);
+        // lane l < nr: clamped start and end of row r + l, relative to e0
+        int32_t cs = 0, ce = 0;
+        if (lane < nr) {
+            int64_t p0 = row_ptr[r + lane], p1 = row_ptr[r + lane + 1];
+            p0 = p0 < sg.e0 ? sg.e0 : (p0 > sg.e1 ? sg.e1 : p0);
+            p1 = p1 < sg.e0 ? sg.e0 : (p1 > sg.e1 ? sg.e1 : p1);
+            cs = (int32_t)(p0 - sg.e0);
+            ce = (int32_t)(p1 - sg.e0);
         }
-        wave_sync();
-        const int32_t ws = cs[0], we = cs[nr];
-        constexpr int U = 4;
-        for (int32_t q0 = ws; q0 < we; q0 += U * kWave) {
-            int32_t q[U], c[U];
-#pragma unroll
-            for (int t = 0; t < U; ++t) {
-                q[t] = q0 + t * kWave + lane;
-                c[t] = q[t] < we ? col[sg.e0 + q[t]] : -1;
-            }
-            P pk[U];
-            float x[U];
-#pragma unroll
-            for (int t = 0; t < U; ++t) {
-                const bool in = q[t] < we;
-                const bool ok = in && (uint32_t)c[t] < (uint64_t)n;
-                bad |= in && !ok;
-                if (!ok) q[t] = -1;
-                pk[t] = ok ? lab[c[t]] : (P)0;
-                x[t] = (W && ok) ? val[sg.e0 + q[t]] : 1.0f;
-            }
-#pragma unroll
-            for (int t = 0; t < U; ++t) {
-                const int y = LabelRec<P>::cls(pk[t]);
-                if (q[t] < 0 || y == 0) continue;
-                int lo = 0, hi = nr; // cs[lo] <= q < cs[hi]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (cs[mid] <= q[t]) lo = mid;
-                    else hi = mid;
-                }
-                if (sizeof(B) == 4) {
-                    lds_add<B>(&bins[lo * K + (y - 1)], (B)1);
+        const int32_t ws = __shfl(cs, 0), we = __shfl(ce, nr - 1);
+        // 4-aligned (in absolute entry index) start of the window's steps
+        const int32_t base = (int32_t)(((sg.e0 + ws) & ~(int64_t)3) - sg.e0);
+        const bool nonempty = lane < nr && cs < ce;
+        int carry = -1;
+        for (int32_t p0 = base; p0 < we; p0 += kPass) {
+            const int32_t p1 = (p0 + kPass < we) ? p0 + kPass : we;
+            const bool mine = nonempty && cs >= p0 && cs < p0 + kPass;
+            if (mine) mark[cs - p0] = (int8_t)lane;
+            wave_sync();
+
+            // column (and weight) quads of one half-step: lane owns q .. q+3
+            auto load = [&](int32_t q, int32_t (&c)[4], float (&x)[4]) {
+                const int64_t a = sg.e0 + q;
+                const bool any = q < p1 && q + 3 >= ws;
+                if (any && vec_ok && a + 3 < nnz) {
+                    const int4 cq = *reinterpret_cast<const int4 *>(col + a);
+                    c[0] = cq.x, c[1] = cq.y, c[2] = cq.z, c[3] = cq.w;
+                    if (W) {
+                        const float4 vq = *reinterpret_cast<const float4 *>(val + a);
+                        x[0] = vq.x, x[1] = vq.y, x[2] = vq.z, x[3] = vq.w;
+                    }
                 } else {
-                    double cval = W ? (double)x[t] : 1.0;
-                    if (LAP) cval *= (double)LabelRec<P>::rsd(pk[t]);
-                    lds_add<B>(&bins[lo * K + (y - 1)], (B)cval);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const bool in = q + t >= ws && q + t < p1;
+                        c[t] = in ? col[a + t] : 0;
+                        if (W) x[t] = in ? val[a + t] : 0.0f;
+                    }
                 }
+            };
+            int32_t cc[2][4], cn[2][4] = {};
+            float xc[2][4], xn[2][4] = {};
+            load(p0 + 4 * lane, cc[0], xc[0]);
+            load(p0 + 4 * kWave + 4 * lane, cc[1], xc[1]);
+            for (int32_t q0 = p0; q0 < p1; q0 += kChunk) {
+                int m[2][4];
+                bool in[2][4];
+                P pk[2][4];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int32_t q = q0 + h * 4 * kWave + 4 * lane;
+                    const int32_t mw = (q < p1 && q + 3 >= ws) ? ((const int32_t *)mark)[(q - p0) >> 2] : -1;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        m[h][t] = (int)(int8_t)(mw >> (8 * t));
+                        in[h][t] = q + t >= ws && q + t < p1;
+                    }
+                    m[h][1] = m[h][1] > m[h][0] ? m[h][1] : m[h][0];
+                    m[h][2] = m[h][2] > m[h][1] ? m[h][2] : m[h][1];
+                    m[h][3] = m[h][3] > m[h][2] ? m[h][3] : m[h][2];
+                    const int incl = wave_incl_max(m[h][3]);
+                    const int prev = __shfl_up(incl, 1);
+                    const int excl = lane == 0 ? carry : (prev > carry ? prev : carry);
+                    const int last = __shfl(incl, kWave - 1);
+                    carry = last > carry ? last : carry;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) m[h][t] = m[h][t] > excl ? m[h][t] : excl;
+                    // label records: bit 31 selects the hot table
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int32_t c = cc[h][t];
+                        const bool hot = c < 0;
+                        const uint32_t idx = (uint32_t)c & 0x7fffffffu;
+                        const bool ok = in[h][t] && (hot ? (int64_t)idx < n_hot : (int64_t)idx < n);
+                        bad |= in[h][t] && !ok;
+                        in[h][t] = ok;
+                        pk[h][t] = ok ? (hot ? hotlab : lab)[idx] : (P)0;
+                    }
+                }
+                // next step's columns: issued after this step's gathers
+                const int32_t qn = q0 + kChunk;
+                if (qn < p1) {
+                    load(qn + 4 * lane, cn[0], xn[0]);
+                    load(qn + 4 * kWave + 4 * lane, cn[1], xn[1]);
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int y = LabelRec<P>::cls(pk[h][t]);
+                        if (!in[h][t] || y == 0 || m[h][t] < 0) continue;
+                        double add = 1.0;
+                        if (!PACKED) {
+                            if (W) add = (double)xc[h][t];
+                            if (LAP) add *= (double)LabelRec<P>::rsd(pk[h][t]);
+                        }
+                        BT::add(&bins[m[h][t] * KW], y - 1, add);
+                    }
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        cc[h][t] = cn[h][t];
+                        if (W) xc[h][t] = xn[h][t];
+                    }
+            }
+            wave_sync();
+            if (mine) mark[cs - p0] = -1;
+        }
+        wave_sync();
+
+        // ---- write the window's rows
+        const bool head_here = sg.carried && r == sg.i0;
+        const bool tail_here = sg.tail && sg.i1 >= r && sg.i1 < r + nr;
+        if (head_here)
+            for (int k = lane; k < K; k += kWave) part[(2 * j) * K + k] = BT::get(&bins[0], k);
+        if (tail_here)
+            for (int k = lane; k < K; k += kWave) part[(2 * j + 1) * K + k] = BT::get(&bins[(sg.i1 - r) * KW], k);
+        if (flat) {
+            // floats [r K, (r + nr) K) in 64-float blocks aligned to 256 bytes
+            const int64_t f_lo = r * K, f_hi = (r + nr) * K;
+            const int64_t f_start = f_lo & ~(int64_t)(kWave - 1);
+            int64_t f = f_start + lane;
+            const int rel = (int)(f - f_lo); // negative in the first block: floats of earlier rows
+            int l = rel >= 0 ? rel / K : -((-rel + K - 1) / K);
+            int k = rel - l * K;
+            const int dl = kWave / K, dk = kWave % K;
+            for (; f < f_hi; f += kWave) {
+                if (l >= 0) {
+                    const int64_t u = r + l;
+                    const bool skip = (head_here && l == 0) || (tail_here && u == sg.i1);
+                    if (!skip) {
+                        double sc = invt[k];
+                        if (LAP) sc *= (double)LabelRec<P>::rsd(lab[u]);
+                        __builtin_nontemporal_store((float)(BT::get(&bins[l * KW], k) * sc), &Z[f]);
+                    }
+                }
+                l += dl;
+                k += dk;
+                if (k >= K) {
+                    k -= K;
+                    ++l;
+                }
+            }
+        } else {
+            for (int l = 0; l < nr; ++l) {
+                const int64_t u = r + l;
+                if ((head_here && l == 0) || (tail_here && u == sg.i1)) continue;
+                const double ru = LAP ? (double)LabelRec<P>::rsd(lab[u]) : 1.0;
+                for (int k = lane; k < K; k += kWave)
+                    __builtin_nontemporal_store((float)(BT::get(&bins[l * KW], k) * (inv[k + 1] * ru)),
+                                                &Z[u * K + k]);
             }
         }
         wave_sync();
-        const int total = nr * K;
-        for (int idx = lane; idx < total; idx += kWave) {
-            const int l = (int)div_small((uint32_t)idx, kmagic32);
-            const int k = idx - l * K;
-            const int64_t u = r + l;
-            const B b = bins[idx];
-            bins[idx] = (B)0;
-            if (u == sg.i0 && sg.carried) {
-                part[(2 * j) * K + k] = (double)b;
-            } else if (u == sg.i1 && sg.tail) {
-                part[(2 * j + 1) * K + k] = (double)b;
-            } else {
-                double sc = inv[k + 1];
-                if (LAP) sc *= (double)LabelRec<P>::rsd(lab[u]);
-                __builtin_nontemporal_store((float)((double)b * sc), &Z[u * K + k]);
-            }
-        }
+        for (int b = lane; b < nr * KW; b += kWave) bins[b] = (word)0;
         wave_sync();
     }
     if (bad) flag_error(err, GEE_EVERTEX);
@@ -510,40 +674,34 @@ hipError_t launch_seg_bounds(int64_t n, int64_t nnz, const int64_t *row_ptr, int
     return hipGetLastError();
 }
 
-size_t pull_wave_bytes(int32_t K, bool wide_bins, int rw)
-{
-    return align_up((size_t)rw * K * (wide_bins ? 8 : 4), 16) + align_up((size_t)(rw + 1) * 4, 16);
-}
+size_t pull_wave_bytes(int32_t K, bool wide_bins, int rw) { return pull_lds_bytes(K, !wide_bins, rw); }
 
-template <typename B, bool LAP, bool W, typename P>
-static hipError_t pull_t(const EmbedArgs &a, const int64_t *row_ptr, const int32_t *col, const float *val,
-                         const int32_t *seg_i, const int64_t *seg_e, int64_t nseg, int rw, double *part,
-                         hipStream_t s)
+template <bool PACKED, bool LAP, bool W, typename P>
+static hipError_t pull_t(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                         const float *val, const void *hotlab, int64_t n_hot, const int32_t *seg_i,
+                         const int64_t *seg_e, int64_t nseg, int rw, double *part, hipStream_t s)
 {
-    const uint32_t wb = (uint32_t)pull_wave_bytes(a.K, sizeof(B) == 8, rw);
+    const uint32_t wb = (uint32_t)pull_lds_bytes(a.K, PACKED, rw);
     int wpb = (int)(65536 / wb);
     wpb = wpb > kWavesPerBlock ? kWavesPerBlock : (wpb < 1 ? 1 : wpb);
     const int64_t blocks = (nseg + wpb - 1) / wpb;
-    hipLaunchKernelGGL((k_pull<B, LAP, W, P>), dim3((unsigned)blocks), dim3(wpb * kWave), (size_t)wpb * wb, s, a.n,
-                       row_ptr, col, val, static_cast<const P *>(a.lab), a.inv, a.K, magic32(a.K), seg_i, seg_e,
-                       nseg, rw, wb, a.Z, part, a.err);
+    const bool vec_ok = ((uintptr_t)col % 16 == 0) && (!val || (uintptr_t)val % 16 == 0);
+    hipLaunchKernelGGL((k_pull<PACKED, LAP, W, P>), dim3((unsigned)blocks), dim3(wpb * kWave), (size_t)wpb * wb, s,
+                       a.n, nnz, row_ptr, col, val, static_cast<const P *>(a.lab), static_cast<const P *>(hotlab),
+                       n_hot, a.inv, a.K, seg_i, seg_e, nseg, rw, wb, vec_ok, a.Z, part, a.err);
     return hipGetLastError();
 }
 
 hipError_t launch_pull(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const float *val,
-                       const int32_t *seg_i, const int64_t *seg_e, int64_t nseg, int rw, double *part, hipStream_t s)
+                       const void *hotlab, int64_t n_hot, const int32_t *seg_i, const int64_t *seg_e, int64_t nseg,
+                       int rw, double *part, hipStream_t s)
 {
-    (void)nnz;
-    if (a.laplacian)
-        return val ? pull_t<double, true, true, uint64_t>(a, row_ptr, col, val, seg_i, seg_e, nseg, rw, part, s)
-                   : pull_t<double, true, false, uint64_t>(a, row_ptr, col, val, seg_i, seg_e, nseg, rw, part, s);
-    if (val)
-        return a.pack == Pack::U16
-                   ? pull_t<double, false, true, uint16_t>(a, row_ptr, col, val, seg_i, seg_e, nseg, rw, part, s)
-                   : pull_t<double, false, true, uint8_t>(a, row_ptr, col, val, seg_i, seg_e, nseg, rw, part, s);
-    return a.pack == Pack::U16
-               ? pull_t<uint32_t, false, false, uint16_t>(a, row_ptr, col, val, seg_i, seg_e, nseg, rw, part, s)
-               : pull_t<uint32_t, false, false, uint8_t>(a, row_ptr, col, val, seg_i, seg_e, nseg, rw, part, s);
+#define GEE_PULL(PK, LAP, W, P) \
+    pull_t<PK, LAP, W, P>(a, nnz, row_ptr, col, val, hotlab, n_hot, seg_i, seg_e, nseg, rw, part, s)
+    if (a.laplacian) return val ? GEE_PULL(false, true, true, uint64_t) : GEE_PULL(false, true, false, uint64_t);
+    if (val) return a.pack == Pack::U16 ? GEE_PULL(false, false, true, uint16_t) : GEE_PULL(false, false, true, uint8_t);
+    return a.pack == Pack::U16 ? GEE_PULL(true, false, false, uint16_t) : GEE_PULL(true, false, false, uint8_t);
+#undef GEE_PULL
 }
 
 hipError_t launch_merge(const EmbedArgs &a, const int64_t *row_ptr, const int32_t *seg_i, const int64_t *seg_e,
@@ -556,6 +714,22 @@ hipError_t launch_merge(const EmbedArgs &a, const int64_t *row_ptr, const int32_
     else
         hipLaunchKernelGGL((k_merge<false, uint8_t>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.n, row_ptr,
                            seg_i, seg_e, nseg, static_cast<const uint8_t *>(nullptr), a.inv, a.K, part, a.Z);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_hot(const EmbedArgs &a, const int32_t *hot_ids, int64_t n_hot, void *hotlab, hipStream_t s)
+{
+    if (n_hot <= 0) return hipSuccess;
+    const dim3 g(grid_for(n_hot, kBlock, 1 << 20)), b(kBlock);
+    if (a.pack == Pack::U8)
+        hipLaunchKernelGGL(k_pack_hot<uint8_t>, g, b, 0, s, static_cast<const uint8_t *>(a.lab), a.n, hot_ids, n_hot,
+                           static_cast<uint8_t *>(hotlab), a.err);
+    else if (a.pack == Pack::U16)
+        hipLaunchKernelGGL(k_pack_hot<uint16_t>, g, b, 0, s, static_cast<const uint16_t *>(a.lab), a.n, hot_ids,
+                           n_hot, static_cast<uint16_t *>(hotlab), a.err);
+    else
+        hipLaunchKernelGGL(k_pack_hot<uint64_t>, g, b, 0, s, static_cast<const uint64_t *>(a.lab), a.n, hot_ids,
+                           n_hot, static_cast<uint64_t *>(hotlab), a.err);
     return hipGetLastError();
 }
 

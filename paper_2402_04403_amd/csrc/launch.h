@@ -45,8 +45,9 @@ hipError_t launch_seg_bounds(int64_t n, int64_t nnz, const int64_t *row_ptr, int
 // LDS bytes one wavefront of the pull kernel uses for `rw` rows of K bins.
 size_t pull_wave_bytes(int32_t K, bool wide_bins, int rw);
 hipError_t launch_pull(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
-                       const float *val, const int32_t *seg_i, const int64_t *seg_e, int64_t nseg, int rw,
-                       double *part, hipStream_t s);
+                       const float *val, const void *hotlab, int64_t n_hot, const int32_t *seg_i,
+                       const int64_t *seg_e, int64_t nseg, int rw, double *part, hipStream_t s);
+hipError_t launch_pack_hot(const EmbedArgs &a, const int32_t *hot_ids, int64_t n_hot, void *hotlab, hipStream_t s);
 hipError_t launch_merge(const EmbedArgs &a, const int64_t *row_ptr, const int32_t *seg_i, const int64_t *seg_e,
                         int64_t nseg, const double *part, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
@@ -59,10 +60,13 @@ struct CsrBuildWs {
     int64_t *offs;      // [256 * nblocks]
     int64_t *scan_part; // scan partials
     int64_t *rowlast;   // [n]
+    int64_t *vtmp[2];   // [n] each: hot-vertex selection scratch
+    int64_t *hot_hist;  // degree histogram
+    int64_t *hot_par;   // threshold, quota
 };
-size_t csr_build_layout(int64_t n, int64_t s, bool weighted, char *base, CsrBuildWs *out);
+size_t csr_build_layout(int64_t n, int64_t s, bool weighted, int64_t n_hot, char *base, CsrBuildWs *out);
 hipError_t launch_csr_build(int64_t n, int64_t ns, const int32_t *src, const int32_t *dst, const float *w,
-                            int64_t *row_ptr, int32_t *col, float *val, const CsrBuildWs &ws, int32_t *err,
-                            hipStream_t s);
+                            int64_t n_hot, int64_t *row_ptr, int32_t *col, float *val, int32_t *hot_ids,
+                            const CsrBuildWs &ws, int32_t *err, hipStream_t s);
 
 } // namespace gee

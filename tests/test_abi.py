@@ -57,7 +57,7 @@ def test_host_argument_errors(lib):
 
 def test_embed_argument_errors(lib):
     coo = gee.Coo(100, 1000, FAKE, FAKE, None)
-    csr = gee.Csr(100, 2000, FAKE, FAKE, None)
+    csr = gee.Csr(100, 2000, FAKE, FAKE, None, 0, None)
     o = gee.EmbedOpts(0, 0, None, None)
     ws = lambda c, r, K, lap=0, opt=o: lib.gee_embed_workspace(c, r, K, lap, ctypes.byref(opt))
     assert ws(ctypes.byref(coo), None, 5) > 0
@@ -67,6 +67,7 @@ def test_embed_argument_errors(lib):
     assert ws(None, ctypes.byref(csr), 4097) == 0  # pull form: K <= 4096
     assert ws(ctypes.byref(coo), None, 65535) > 0  # push form: up to 65535 (16-bit labels)
     assert ws(None, ctypes.byref(csr), 5, 0, gee.EmbedOpts(10, 0, None, None)) == 0  # seg_len < 64
+    assert ws(None, ctypes.byref(csr), 5, 0, gee.EmbedOpts(65536, 0, None, None)) == 0  # 16-bit counters
     assert ws(None, ctypes.byref(csr), 5, 0, gee.EmbedOpts(0, 65, None, None)) == 0
     bad_n = gee.Coo(0, 10, FAKE, FAKE, None)
     assert ws(ctypes.byref(bad_n), None, 5) == 0
@@ -88,23 +89,35 @@ def test_embed_argument_errors(lib):
 
 def test_workspace_sizes_scale(lib):
     o = gee.EmbedOpts(0, 0, None, None)
-    small = gee.Csr(1000, 10_000, FAKE, FAKE, None)
-    large = gee.Csr(1000, 1_000_000, FAKE, FAKE, None)
+    small = gee.Csr(1000, 10_000, FAKE, FAKE, None, 0, None)
+    large = gee.Csr(1000, 1_000_000, FAKE, FAKE, None, 0, None)
     a = lib.gee_embed_workspace(None, ctypes.byref(small), 50, 0, ctypes.byref(o))
     b = lib.gee_embed_workspace(None, ctypes.byref(large), 50, 0, ctypes.byref(o))
     assert b > a > 0 and a % 256 == 0 and b % 256 == 0
     lap = lib.gee_embed_workspace(None, ctypes.byref(small), 50, 1, ctypes.byref(o))
     assert lap > a  # 8-byte label records and FP64 degrees
-    assert lib.gee_csr_workspace(1000, 5000, 1) > lib.gee_csr_workspace(1000, 5000, 0) > 0
-    assert lib.gee_csr_workspace(0, 5000, 0) == 0
+    assert lib.gee_csr_workspace(1000, 5000, 1, 0) > lib.gee_csr_workspace(1000, 5000, 0, 0) > 0
+    assert lib.gee_csr_workspace(1000, 5000, 0, 100) > lib.gee_csr_workspace(1000, 5000, 0, 0)
+    assert lib.gee_csr_workspace(0, 5000, 0, 0) == 0
+    assert lib.gee_csr_workspace(10, 5000, 0, -1) == 0
+    hot = gee.Csr(1000, 10_000, FAKE, FAKE, None, 50, FAKE)
+    assert lib.gee_embed_workspace(None, ctypes.byref(hot), 50, 0, ctypes.byref(o)) > a  # hot label table
+    bad_hot = gee.Csr(1000, 10_000, FAKE, FAKE, None, 50, None)
+    assert lib.gee_embed_workspace(None, ctypes.byref(bad_hot), 50, 0, ctypes.byref(o)) == 0
+    too_many = gee.Csr(1000, 10_000, FAKE, FAKE, None, 1001, FAKE)
+    assert lib.gee_embed_workspace(None, ctypes.byref(too_many), 50, 0, ctypes.byref(o)) == 0
 
 
 def test_csr_build_argument_errors(lib):
     coo = gee.Coo(100, 1000, FAKE, FAKE, FAKE)
-    need = lib.gee_csr_workspace(100, 1000, 1)
-    assert lib.gee_csr_build(ctypes.byref(coo), FAKE, FAKE, None, FAKE, need, FAKE, None) == gee.GEE_EINVAL
-    assert lib.gee_csr_build(ctypes.byref(coo), FAKE, FAKE, FAKE, FAKE, need - 1, FAKE, None) == gee.GEE_EWORKSPACE
-    assert lib.gee_csr_build(None, FAKE, FAKE, FAKE, FAKE, need, FAKE, None) == gee.GEE_EINVAL
+    need = lib.gee_csr_workspace(100, 1000, 1, 0)
+    build = lambda c, hb, val, hot, wsb: lib.gee_csr_build(c, hb, FAKE, FAKE, val, hot, FAKE, wsb, FAKE, None)
+    assert build(ctypes.byref(coo), 0, None, None, need) == gee.GEE_EINVAL  # weighted needs val
+    assert build(ctypes.byref(coo), 0, FAKE, None, need - 1) == gee.GEE_EWORKSPACE
+    assert build(None, 0, FAKE, None, need) == gee.GEE_EINVAL
+    assert build(ctypes.byref(coo), -1, FAKE, None, need) == gee.GEE_EINVAL
+    assert build(ctypes.byref(coo), 10, FAKE, None, need) == gee.GEE_EINVAL  # hot slots need hot_ids
+    assert build(ctypes.byref(coo), 10, FAKE, FAKE, need) == gee.GEE_EWORKSPACE  # hot selection scratch
 
 
 def test_python_binding_refuses_host_tensors(lib):

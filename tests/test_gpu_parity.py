@@ -46,6 +46,8 @@ def run_both_forms(n, src, dst, w, Y, K, lap, seg_lens=(0,), rws=(0,)):
         for rw in rws:
             Z = gee.embed(labels, K, csr=csr, laplacian=lap, seg_len=L, rows_per_window=rw)
             yield f"pull(L={L},rw={rw})", Z.cpu().numpy()
+    hot = gee.csr_build(coo, hot_budget=max(1, n // 10))
+    yield "pull(hot)", gee.embed(labels, K, csr=hot, laplacian=lap).cpu().numpy()
 
 
 # ---------------------------------------------------------------- W, counts --
@@ -102,6 +104,58 @@ def test_csr_build_rmat_skew():
     csr = gee.csr_build(gee.to_device(g.n, g.src, g.dst, device=DEV))
     assert np.array_equal(csr.row_ptr.cpu().numpy(), rp)
     assert np.array_equal(csr.col.cpu().numpy(), col)
+
+
+def _expected_hot(rp, H):
+    """Top-H vertices by (degree capped at 4095, descending; id ascending), in id order."""
+    deg = np.diff(rp)
+    bucket = np.minimum(deg, 4095)
+    order = np.lexsort((np.arange(deg.size), -bucket))
+    return np.sort(order[:H])
+
+
+@pytest.mark.parametrize("n,s,weighted,H", [(1, 3, False, 1), (500, 20_000, True, 37), (1 << 14, 1 << 18, False, 1000),
+                                            (5000, 100, False, 4999), (300, 4000, False, 300)])
+def test_csr_hot_slots(n, s, weighted, H):
+    rng = np.random.default_rng(n + H)
+    if n == 1 << 14:
+        g = gen.rmat(14, s, seed=31)
+        src, dst, w = g.src, g.dst, None
+    else:
+        src, dst, w = random_multigraph(rng, n, s, weighted)
+    rp, col, val = oracle.csr(n, src, dst, w)
+    csr = gee.csr_build(gee.to_device(n, src, dst, w, device=DEV), hot_budget=H)
+    hot_ids = csr.hot_ids.cpu().numpy()
+    assert np.array_equal(hot_ids, _expected_hot(rp, min(H, n)))
+    assert np.array_equal(csr.row_ptr.cpu().numpy(), rp)
+    c = csr.col.cpu().numpy()
+    assert np.array_equal(csr.plain_col().cpu().numpy(), col)
+    is_hot = np.zeros(n, bool)
+    is_hot[hot_ids] = True
+    assert np.array_equal(c < 0, is_hot[col])  # exactly the hot columns are encoded
+    if weighted:
+        assert np.array_equal(csr.val.cpu().numpy().view(np.uint32), val.view(np.uint32))
+
+
+@pytest.mark.parametrize("lap", [False, True])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_hot_slots_do_not_change_z(lap, weighted):
+    """The gather source is the only difference: Z is bit-identical with and without hot slots."""
+    rng = np.random.default_rng(41)
+    g = gen.rmat(15, 12 << 15, seed=42)
+    w = ((rng.integers(0, 1 << 24, g.s) + 1) * 2.0 ** -24).astype(np.float32) if weighted else None
+    Y = random_labels(rng, g.n, 50)
+    coo = gee.to_device(g.n, g.src, g.dst, w, device=DEV)
+    labels = dev(Y)
+    plain = gee.csr_build(coo)
+    Zo = oracle.embed(g.n, g.src, g.dst, w, Y, 50, lap)
+    for H in (1, 1000, 1 << 14, g.n):
+        hot = gee.csr_build(coo, hot_budget=H)
+        for L in (0, 256):
+            Za = gee.embed(labels, 50, csr=plain, laplacian=lap, seg_len=L)
+            Zb = gee.embed(labels, 50, csr=hot, laplacian=lap, seg_len=L)
+            assert torch.equal(Za.view(torch.int32), Zb.view(torch.int32)), (H, L)
+        assert_parity(Zb.cpu().numpy(), Zo, what=f"hot H={H}")
 
 
 # -------------------------------------------------------------- hand-worked --
