@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--rows-per-window", type=int, default=0)
     p.add_argument("--hot-budget", type=int, default=-1, help="hot-vertex slots of the CSR (-1: library default)")
     p.add_argument("--push-steps", type=int, default=3, help="timed steps of the push form, reported beside")
-    p.add_argument("--cpu-records", type=int, default=20_000_000)
+    p.add_argument("--cpu-records", type=int, default=400_000_000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     return p.parse_args()
 

@@ -163,10 +163,10 @@ size_t gee_csr_workspace(int64_t n, int64_t s, int weighted, int64_t hot_budget)
  * out sorted by (column, bit pattern of w): a stable LSD radix sort of the 2 s
  * directed entries, so the result depends only on the multiset of records.
  * With hot_budget > 0, the n_hot = min(hot_budget, n) vertices of highest degree
- * (ties: smaller id first) get slots 0..n_hot-1 in id order: hot_ids [n_hot]
- * receives their ids and each column naming one of them is stored as
- * (slot | 0x80000000); the gee_csr passed to gee_embed then carries n_hot and
- * hot_ids. The choice of slots depends only on the graph. */
+ * get slots 0..n_hot-1 in order of degree (capped at 4095), highest first, ties by
+ * smaller id: hot_ids [n_hot] receives their ids and each column naming one of
+ * them is stored as (slot | 0x80000000); the gee_csr passed to gee_embed then
+ * carries n_hot and hot_ids. The choice of slots depends only on the graph. */
 int gee_csr_build(const gee_coo *g, int64_t hot_budget, int64_t *row_ptr, int32_t *col, float *val,
                   int32_t *hot_ids, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream);
 

@@ -28,9 +28,10 @@ LIB_PATH = os.path.join(_PKG, "libgee.so")
 
 GEE_OK, GEE_EINVAL, GEE_ELABEL, GEE_EVERTEX, GEE_ENEGW, GEE_EOVERFLOW, GEE_EWORKSPACE, GEE_EHIP = 0, -1, -2, -3, -4, -5, -6, -7
 
-# Hot-vertex slots the benchmark configuration gives a CSR: a 2 MiB label table
-# (1-byte records) that fits in one XCD's 4 MiB L2 beside the streaming traffic.
-DEFAULT_HOT_BUDGET = 1 << 21
+# Hot-vertex slots the benchmark configuration gives a CSR: a 4 MiB table of 1-byte
+# label records in degree-rank order, so the hottest labels share the lines that stay
+# in one XCD's 4 MiB L2 beside the streaming traffic.
+DEFAULT_HOT_BUDGET = 1 << 22
 
 
 class GeeError(RuntimeError):

@@ -377,16 +377,32 @@ k_hot_flag(int64_t n, const int64_t *__restrict__ row_ptr, const int64_t *__rest
     }
 }
 
-// hot_ids[slot[v]] = v for hot v; map[v] becomes slot[v] (hot) or -1, in place of the flag.
+// Hot vertices in id order: hkeys[pos[v]] = ((kDegBins - 1 - bucket) << 32) | v, so
+// that a stable sort on the upper word orders them by degree bucket, highest first,
+// ties by id. The flag array becomes the slot map, reset to -1 here.
 __global__ void __launch_bounds__(kT)
-k_hot_ids(int64_t n, int64_t n_hot, int64_t *__restrict__ flag_to_map, const int64_t *__restrict__ slot,
-          int32_t *__restrict__ hot_ids)
+k_hot_compact(int64_t n, const int64_t *__restrict__ row_ptr, int64_t *__restrict__ flag_to_map,
+              const int64_t *__restrict__ pos, int64_t n_hot, uint64_t *__restrict__ hkeys)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const bool hot = flag_to_map[v] != 0;
-        const int64_t sl = slot[v];
-        if (hot && sl < n_hot) hot_ids[sl] = (int32_t)v;
-        flag_to_map[v] = (hot && sl < n_hot) ? sl : -1;
+        const int64_t p = pos[v];
+        if (hot && p < n_hot)
+            hkeys[p] = ((uint64_t)(kDegBins - 1 - deg_bucket(row_ptr, v)) << 32) | (uint64_t)(uint32_t)v;
+        flag_to_map[v] = -1;
+    }
+}
+
+// Slot = rank in (degree bucket desc, id asc): the hottest labels share the first
+// cache lines of the hot table.
+__global__ void __launch_bounds__(kT)
+k_hot_ids(int64_t n, int64_t n_hot, const uint64_t *__restrict__ hkeys, int64_t *__restrict__ map,
+          int32_t *__restrict__ hot_ids)
+{
+    for (int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < n_hot; sl += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = (uint32_t)hkeys[sl];
+        hot_ids[sl] = (int32_t)v;
+        if ((uint64_t)v < (uint64_t)n) map[v] = sl;
     }
 }
 
@@ -428,7 +444,8 @@ size_t csr_build_layout(int64_t n, int64_t s, bool weighted, int64_t n_hot, char
 {
     const int64_t N = 2 * s;
     const int64_t nt = tiles(N > 0 ? N : 1);
-    const int64_t hist_len = 256 * nt;
+    const int64_t nt_hot = tiles(n_hot > 0 ? n_hot : 1);
+    const int64_t hist_len = 256 * (nt > nt_hot ? nt : nt_hot);
     const int64_t scan_len = (hist_len > n ? hist_len : n);
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
@@ -449,6 +466,8 @@ size_t csr_build_layout(int64_t n, int64_t s, bool weighted, int64_t n_hot, char
     if (n_hot > 0) {
         w.vtmp[0] = (int64_t *)take((size_t)n * 8);
         w.vtmp[1] = (int64_t *)take((size_t)n * 8);
+        w.hkeys[0] = (uint64_t *)take((size_t)n_hot * 8);
+        w.hkeys[1] = (uint64_t *)take((size_t)n_hot * 8);
         w.hot_hist = (int64_t *)take((size_t)kDegBins * 8);
         w.hot_par = (int64_t *)take(2 * 8);
     }
@@ -537,7 +556,24 @@ hipError_t launch_csr_build(int64_t n, int64_t ns, const int32_t *src, const int
                        (const int64_t *)ws.vtmp[1], ws.vtmp[0]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = scan(ws.vtmp[0], n, ws.vtmp[1], ws.scan_part, SumOp{}, false, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_hot_ids, gv, b, 0, s, n, n_hot, ws.vtmp[0], (const int64_t *)ws.vtmp[1], hot_ids);
+    hipLaunchKernelGGL(k_hot_compact, gv, b, 0, s, n, (const int64_t *)row_ptr, ws.vtmp[0],
+                       (const int64_t *)ws.vtmp[1], n_hot, ws.hkeys[0]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // stable sort of the hot keys on the 12 bucket bits above bit 32
+    const int64_t ntk = tiles(n_hot);
+    int hc = 0;
+    for (int sh = 32; sh < 32 + 12; sh += 8) {
+        hipLaunchKernelGGL(k_radix_hist<false>, dim3((unsigned)ntk), b, 0, s, ws.hkeys[hc], (const float *)nullptr,
+                           n_hot, sh, false, ws.hist, ntk);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = scan(ws.hist, 256 * ntk, ws.offs, ws.scan_part, SumOp{}, false, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)ntk), b, 0, s, ws.hkeys[hc], (const float *)nullptr,
+                           ws.hkeys[hc ^ 1], (float *)nullptr, n_hot, sh, false, ws.offs, ntk);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hc ^= 1;
+    }
+    hipLaunchKernelGGL(k_hot_ids, dim3(grid_cap(n_hot, kT * 4)), b, 0, s, n, n_hot, (const uint64_t *)ws.hkeys[hc],
+                       ws.vtmp[0], hot_ids);
     hipLaunchKernelGGL(k_col_encode, dim3(grid_cap(N, kT * 4)), b, 0, s, N, n, col, (const int64_t *)ws.vtmp[0]);
     return hipGetLastError();
 }

@@ -9,6 +9,8 @@
 // written; the sums themselves add raw weights (times d_v^-1/2 for the
 // Laplacian). Unit-weight adjacency sums are therefore exact integers.
 
+#include <type_traits>
+
 #include "common.h"
 #include "launch.h"
 
@@ -270,47 +272,71 @@ __device__ inline SegInfo seg_info(int64_t j, int64_t n, const int64_t *__restri
     return s;
 }
 
+// Wavefront inclusive max-scan of values >= -1 with DPP lane moves (no LDS
+// traffic, so it never waits behind the LDS atomics in flight): shifts by 1, 2,
+// 4, 8 within each 16-lane row, then row broadcasts of lanes 15 and 31.
+__device__ inline int imax(int a, int b) { return a > b ? a : b; }
 __device__ inline int wave_incl_max(int x)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int y = __shfl_up(x, o);
-        if (lane >= o) x = x > y ? x : y;
-    }
+    x = imax(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false)); // row_shr:1
+    x = imax(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false)); // row_shr:2
+    x = imax(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false)); // row_shr:4
+    x = imax(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false)); // row_shr:8
+    x = imax(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false)); // row_bcast:15
+    x = imax(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false)); // row_bcast:31
     return x;
 }
+// Value of the previous lane (-1 for lane 0): DPP wave_shr:1.
+__device__ inline int wave_shr1(int x) { return __builtin_amdgcn_update_dpp(-1, x, 0x138, 0xf, 0xf, false); }
 
-// Bin storage of the pull pass. Unit-weight adjacency counts two classes per
-// 32-bit word (16-bit counters; a segment holds at most 65535 entries, so they
-// cannot overflow); every other variant keeps one FP64 sum per class.
-template <bool PACKED> struct Bins;
-template <> struct Bins<true> {
-    using word = uint32_t;
-    __host__ __device__ static int words(int K) { return (K + 1) / 2; }
-    __device__ static void add(word *row, int k, double) { atomicAdd(&row[k >> 1], 1u << (16 * (k & 1))); }
-    __device__ static double get(const word *row, int k) { return (double)((row[k >> 1] >> (16 * (k & 1))) & 0xffffu); }
-};
-template <> struct Bins<false> {
+// Bin storage of the pull pass, by kind:
+//  0: one FP64 sum per class (weighted or Laplacian);
+//  1: unit-weight counts, two classes per 32-bit word (16-bit counters; a segment
+//     holds at most 65535 entries, so they cannot overflow);
+//  2: unit-weight counts, one 32-bit counter per class.
+template <int BK> struct Bins;
+template <> struct Bins<0> {
     using word = double;
     __host__ __device__ static int words(int K) { return K; }
     __device__ static void add(word *row, int k, double x) { atomicAdd(&row[k], x); }
+    __device__ static void add_masked(word *row, int k, double x, bool use) { atomicAdd(&row[k], use ? x : 0.0); }
     __device__ static double get(const word *row, int k) { return row[k]; }
 };
+template <> struct Bins<1> {
+    using word = uint32_t;
+    __host__ __device__ static int words(int K) { return (K + 1) / 2; }
+    __device__ static void add(word *row, int k, double) { atomicAdd(&row[k >> 1], 1u << (16 * (k & 1))); }
+    __device__ static void add_masked(word *row, int k, double, bool use)
+    {
+        atomicAdd(&row[k >> 1], use ? 1u << (16 * (k & 1)) : 0u);
+    }
+    __device__ static double get(const word *row, int k) { return (double)((row[k >> 1] >> (16 * (k & 1))) & 0xffffu); }
+};
+template <> struct Bins<2> {
+    using word = uint32_t;
+    __host__ __device__ static int words(int K) { return K; }
+    __device__ static void add(word *row, int k, double) { atomicAdd(&row[k], 1u); }
+    __device__ static void add_masked(word *row, int k, double, bool use) { atomicAdd(&row[k], use ? 1u : 0u); }
+    __device__ static double get(const word *row, int k) { return (double)row[k]; }
+};
+// Bin kind of the unit-weight adjacency variant.
+constexpr int kUnitBins = 1;
 
 constexpr int kPass = 1024;              // entries whose row-start markers are mapped at once
 constexpr int kChunk = 2 * 4 * kWave;    // entries per inner step (two 16-byte loads per lane)
 constexpr int kFlatFlushMaxK = kWave;    // K up to this writes rows as flat aligned blocks
+constexpr int kSinkBytes = kWave * 8;    // one word per lane for masked bin updates
 
 // LDS of one wavefront: bins of RW rows, the row-start marker map of one pass,
 // and the class weights (K <= 64).
-__host__ __device__ inline size_t pull_bins_bytes(int32_t K, bool packed, int rw)
+__host__ __device__ inline size_t pull_bins_bytes(int32_t K, int bk, int rw)
 {
-    return align_up((size_t)rw * (packed ? (K + 1) / 2 * 4 : (size_t)K * 8), 16);
+    const size_t row = bk == 0 ? (size_t)K * 8 : (bk == 1 ? (size_t)(K + 1) / 2 * 4 : (size_t)K * 4);
+    return align_up((size_t)rw * row, 16);
 }
-__host__ __device__ inline size_t pull_lds_bytes(int32_t K, bool packed, int rw)
+__host__ __device__ inline size_t pull_lds_bytes(int32_t K, int bk, int rw)
 {
-    return pull_bins_bytes(K, packed, rw) + kPass + (K <= kFlatFlushMaxK ? align_up((size_t)K * 8, 16) : 0);
+    return pull_bins_bytes(K, bk, rw) + kPass + kSinkBytes + (K <= kFlatFlushMaxK ? align_up((size_t)K * 8, 16) : 0);
 }
 
 // One wavefront per segment of seg_len work items (rows + entries).
@@ -331,7 +357,7 @@ __host__ __device__ inline size_t pull_lds_bytes(int32_t K, bool packed, int rw)
 //    row by row with lanes over classes. A row cut by a segment boundary goes to
 //    the FP64 partials instead (head: continues from an earlier segment; tail:
 //    continues into later ones).
-template <bool PACKED, bool LAP, bool W, typename P>
+template <int BK, bool LAP, bool W, typename P>
 __global__ void __launch_bounds__(kBlock)
 k_pull(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
        const float *__restrict__ val, const P *__restrict__ lab, const P *__restrict__ hotlab, int64_t n_hot,
@@ -339,17 +365,18 @@ k_pull(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_
        const int64_t *__restrict__ seg_e, int64_t nseg, int RW, uint32_t wave_bytes, bool vec_ok,
        float *__restrict__ Z, double *__restrict__ part, int32_t *err)
 {
-    using BT = Bins<PACKED>;
+    using BT = Bins<BK>;
     using word = typename BT::word;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (j >= nseg) return;
     unsigned char *my = smem + (size_t)wave * wave_bytes;
     const int KW = BT::words(K);
     word *bins = (word *)my;
-    int8_t *mark = (int8_t *)(my + pull_bins_bytes(K, PACKED, RW));
-    double *invt = (double *)(my + pull_bins_bytes(K, PACKED, RW) + kPass);
+    int8_t *mark = (int8_t *)(my + pull_bins_bytes(K, BK, RW));
+    word *sink = (word *)(my + pull_bins_bytes(K, BK, RW) + kPass); // one per lane: target of masked adds
+    double *invt = (double *)(my + pull_bins_bytes(K, BK, RW) + kPass + kSinkBytes);
     const bool flat = K <= kFlatFlushMaxK;
 
     const SegInfo sg = seg_info(j, n, row_ptr, seg_i, seg_e);
@@ -357,6 +384,11 @@ k_pull(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_
     for (int b = lane; b < kPass / 4; b += kWave) ((int32_t *)mark)[b] = -1;
     if (flat && lane < K) invt[lane] = inv[lane + 1];
     bool bad = false;
+    // A segment whose last 16-byte column quad may pass the end of the array takes
+    // the guarded loads; every other segment runs branch-free steps, so the loads
+    // in flight can be counted statically and the next step's column loads stay
+    // outstanding while this step's atomics issue.
+    const bool tail_seg = !vec_ok || sg.e1 + 4 > nnz;
 
     for (int64_t r = sg.i0; r < sg.rend; r += RW) {
         const int nr = (int)((sg.rend - r) < RW ? (sg.rend - r) : RW);
@@ -369,7 +401,7 @@ k_pull(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_
             cs = (int32_t)(p0 - sg.e0);
             ce = (int32_t)(p1 - sg.e0);
         }
-        const int32_t ws = __shfl(cs, 0), we = __shfl(ce, nr - 1);
+        const int32_t ws = __builtin_amdgcn_readlane(cs, 0), we = __builtin_amdgcn_readlane(ce, nr - 1);
         // 4-aligned (in absolute entry index) start of the window's steps
         const int32_t base = (int32_t)(((sg.e0 + ws) & ~(int64_t)3) - sg.e0);
         const bool nonempty = lane < nr && cs < ce;
@@ -380,92 +412,113 @@ k_pull(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_
             if (mine) mark[cs - p0] = (int8_t)lane;
             wave_sync();
 
-            // column (and weight) quads of one half-step: lane owns q .. q+3
-            auto load = [&](int32_t q, int32_t (&c)[4], float (&x)[4]) {
-                const int64_t a = sg.e0 + q;
-                const bool any = q < p1 && q + 3 >= ws;
-                if (any && vec_ok && a + 3 < nnz) {
-                    const int4 cq = *reinterpret_cast<const int4 *>(col + a);
-                    c[0] = cq.x, c[1] = cq.y, c[2] = cq.z, c[3] = cq.w;
-                    if (W) {
-                        const float4 vq = *reinterpret_cast<const float4 *>(val + a);
-                        x[0] = vq.x, x[1] = vq.y, x[2] = vq.z, x[3] = vq.w;
-                    }
-                } else {
+            auto pass = [&](auto tail_tag) {
+                constexpr bool TAIL = decltype(tail_tag)::value;
+                // column (and weight) quad of a half-step: lane owns entries q .. q+3
+                auto load = [&](int32_t q, int32_t (&c)[4], float (&x)[4]) {
+                    const bool any = q < p1 && q + 3 >= ws;
+                    if (TAIL) {
+                        const int64_t a = sg.e0 + q;
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const bool in = q + t >= ws && q + t < p1;
-                        c[t] = in ? col[a + t] : 0;
-                        if (W) x[t] = in ? val[a + t] : 0.0f;
+                        for (int t = 0; t < 4; ++t) {
+                            const bool in = any && q + t >= ws && q + t < p1;
+                            c[t] = in ? col[a + t] : 0;
+                            if (W) x[t] = in ? val[a + t] : 0.0f;
+                        }
+                    } else {
+                        // lanes outside the pass read the window's first quad (in bounds)
+                        const int64_t a = sg.e0 + (any ? q : base);
+                        const int4 cq = *reinterpret_cast<const int4 *>(col + a);
+                        c[0] = cq.x, c[1] = cq.y, c[2] = cq.z, c[3] = cq.w;
+                        if (W) {
+                            const float4 vq = *reinterpret_cast<const float4 *>(val + a);
+                            x[0] = vq.x, x[1] = vq.y, x[2] = vq.z, x[3] = vq.w;
+                        }
+                    }
+                };
+                // row-start marker word of a half-step (-1 outside the pass)
+                auto marks = [&](int32_t q) -> int32_t {
+                    const bool any = q < p1 && q + 3 >= ws;
+                    int32_t wi = (q - p0) >> 2;
+                    wi = wi < 0 ? 0 : (wi >= kPass / 4 ? kPass / 4 - 1 : wi);
+                    const int32_t mw = ((const int32_t *)mark)[wi];
+                    return any ? mw : -1;
+                };
+                int32_t cc[2][4], cn[2][4] = {};
+                float xc[2][4] = {}, xn[2][4] = {};
+                int32_t mwc[2], mwn[2] = {-1, -1};
+                load(p0 + 4 * lane, cc[0], xc[0]);
+                load(p0 + 4 * kWave + 4 * lane, cc[1], xc[1]);
+                mwc[0] = marks(p0 + 4 * lane);
+                mwc[1] = marks(p0 + 4 * kWave + 4 * lane);
+                for (int32_t q0 = p0; q0 < p1; q0 += kChunk) {
+                    int m[2][4];
+                    bool in[2][4];
+                    P pk[2][4];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int32_t q = q0 + h * 4 * kWave + 4 * lane;
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            m[h][t] = (int)(int8_t)(mwc[h] >> (8 * t));
+                            in[h][t] = q + t >= ws && q + t < p1;
+                        }
+                        m[h][1] = imax(m[h][1], m[h][0]);
+                        m[h][2] = imax(m[h][2], m[h][1]);
+                        m[h][3] = imax(m[h][3], m[h][2]);
+                        const int incl = wave_incl_max(m[h][3]);
+                        const int excl = imax(wave_shr1(incl), carry);
+                        carry = imax(carry, __builtin_amdgcn_readlane(incl, kWave - 1));
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) m[h][t] = imax(m[h][t], excl);
+                        // label records, one gather per entry (masked lanes read lab[0]);
+                        // bit 31 of a column selects the hot table
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int32_t c = cc[h][t];
+                            const bool hot = c < 0;
+                            const uint32_t idx = (uint32_t)c & 0x7fffffffu;
+                            const bool ok = in[h][t] && (hot ? (int64_t)idx < n_hot : (int64_t)idx < n);
+                            bad |= in[h][t] && !ok;
+                            in[h][t] = ok;
+                            const P *tab = (ok && hot) ? hotlab : lab;
+                            pk[h][t] = tab[ok ? idx : 0u];
+                        }
+                    }
+                    // next step's columns (issued after this step's gathers) and markers
+                    // (read before this step's atomics enter the LDS queue)
+                    const int32_t qn = q0 + kChunk;
+                    load(qn + 4 * lane, cn[0], xn[0]);
+                    load(qn + 4 * kWave + 4 * lane, cn[1], xn[1]);
+                    mwn[0] = marks(qn + 4 * lane);
+                    mwn[1] = marks(qn + 4 * kWave + 4 * lane);
+                    // bin updates; masked entries add nothing to this lane's sink word
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int y = LabelRec<P>::cls(pk[h][t]);
+                            const bool use = in[h][t] && y > 0 && m[h][t] >= 0;
+                            double add = 1.0;
+                            if (BK == 0) {
+                                if (W) add = (double)xc[h][t];
+                                if (LAP) add *= (double)LabelRec<P>::rsd(pk[h][t]);
+                            }
+                            BT::add_masked(use ? &bins[m[h][t] * KW] : &sink[lane], use ? y - 1 : 0, add, use);
+                        }
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        mwc[h] = mwn[h];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            cc[h][t] = cn[h][t];
+                            if (W) xc[h][t] = xn[h][t];
+                        }
                     }
                 }
             };
-            int32_t cc[2][4], cn[2][4] = {};
-            float xc[2][4], xn[2][4] = {};
-            load(p0 + 4 * lane, cc[0], xc[0]);
-            load(p0 + 4 * kWave + 4 * lane, cc[1], xc[1]);
-            for (int32_t q0 = p0; q0 < p1; q0 += kChunk) {
-                int m[2][4];
-                bool in[2][4];
-                P pk[2][4];
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int32_t q = q0 + h * 4 * kWave + 4 * lane;
-                    const int32_t mw = (q < p1 && q + 3 >= ws) ? ((const int32_t *)mark)[(q - p0) >> 2] : -1;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        m[h][t] = (int)(int8_t)(mw >> (8 * t));
-                        in[h][t] = q + t >= ws && q + t < p1;
-                    }
-                    m[h][1] = m[h][1] > m[h][0] ? m[h][1] : m[h][0];
-                    m[h][2] = m[h][2] > m[h][1] ? m[h][2] : m[h][1];
-                    m[h][3] = m[h][3] > m[h][2] ? m[h][3] : m[h][2];
-                    const int incl = wave_incl_max(m[h][3]);
-                    const int prev = __shfl_up(incl, 1);
-                    const int excl = lane == 0 ? carry : (prev > carry ? prev : carry);
-                    const int last = __shfl(incl, kWave - 1);
-                    carry = last > carry ? last : carry;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) m[h][t] = m[h][t] > excl ? m[h][t] : excl;
-                    // label records: bit 31 selects the hot table
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int32_t c = cc[h][t];
-                        const bool hot = c < 0;
-                        const uint32_t idx = (uint32_t)c & 0x7fffffffu;
-                        const bool ok = in[h][t] && (hot ? (int64_t)idx < n_hot : (int64_t)idx < n);
-                        bad |= in[h][t] && !ok;
-                        in[h][t] = ok;
-                        pk[h][t] = ok ? (hot ? hotlab : lab)[idx] : (P)0;
-                    }
-                }
-                // next step's columns: issued after this step's gathers
-                const int32_t qn = q0 + kChunk;
-                if (qn < p1) {
-                    load(qn + 4 * lane, cn[0], xn[0]);
-                    load(qn + 4 * kWave + 4 * lane, cn[1], xn[1]);
-                }
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int y = LabelRec<P>::cls(pk[h][t]);
-                        if (!in[h][t] || y == 0 || m[h][t] < 0) continue;
-                        double add = 1.0;
-                        if (!PACKED) {
-                            if (W) add = (double)xc[h][t];
-                            if (LAP) add *= (double)LabelRec<P>::rsd(pk[h][t]);
-                        }
-                        BT::add(&bins[m[h][t] * KW], y - 1, add);
-                    }
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        cc[h][t] = cn[h][t];
-                        if (W) xc[h][t] = xn[h][t];
-                    }
-            }
+            if (tail_seg) pass(std::true_type{});
+            else pass(std::false_type{});
             wave_sync();
             if (mine) mark[cs - p0] = -1;
         }
@@ -530,7 +583,7 @@ k_merge(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restric
         const int64_t *__restrict__ seg_e, int64_t nseg, const P *__restrict__ lab, const double *__restrict__ inv,
         int32_t K, const double *__restrict__ part, float *__restrict__ Z)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t j = (int64_t)blockIdx.x * kWavesPerBlock + wave;
     if (j >= nseg) return;
     const SegInfo sg = seg_info(j, n, row_ptr, seg_i, seg_e);
@@ -674,19 +727,19 @@ hipError_t launch_seg_bounds(int64_t n, int64_t nnz, const int64_t *row_ptr, int
     return hipGetLastError();
 }
 
-size_t pull_wave_bytes(int32_t K, bool wide_bins, int rw) { return pull_lds_bytes(K, !wide_bins, rw); }
+size_t pull_wave_bytes(int32_t K, bool wide_bins, int rw) { return pull_lds_bytes(K, wide_bins ? 0 : kUnitBins, rw); }
 
-template <bool PACKED, bool LAP, bool W, typename P>
+template <int BK, bool LAP, bool W, typename P>
 static hipError_t pull_t(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
                          const float *val, const void *hotlab, int64_t n_hot, const int32_t *seg_i,
                          const int64_t *seg_e, int64_t nseg, int rw, double *part, hipStream_t s)
 {
-    const uint32_t wb = (uint32_t)pull_lds_bytes(a.K, PACKED, rw);
+    const uint32_t wb = (uint32_t)pull_lds_bytes(a.K, BK, rw);
     int wpb = (int)(65536 / wb);
     wpb = wpb > kWavesPerBlock ? kWavesPerBlock : (wpb < 1 ? 1 : wpb);
     const int64_t blocks = (nseg + wpb - 1) / wpb;
     const bool vec_ok = ((uintptr_t)col % 16 == 0) && (!val || (uintptr_t)val % 16 == 0);
-    hipLaunchKernelGGL((k_pull<PACKED, LAP, W, P>), dim3((unsigned)blocks), dim3(wpb * kWave), (size_t)wpb * wb, s,
+    hipLaunchKernelGGL((k_pull<BK, LAP, W, P>), dim3((unsigned)blocks), dim3(wpb * kWave), (size_t)wpb * wb, s,
                        a.n, nnz, row_ptr, col, val, static_cast<const P *>(a.lab), static_cast<const P *>(hotlab),
                        n_hot, a.inv, a.K, seg_i, seg_e, nseg, rw, wb, vec_ok, a.Z, part, a.err);
     return hipGetLastError();
@@ -698,9 +751,9 @@ hipError_t launch_pull(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr, 
 {
 #define GEE_PULL(PK, LAP, W, P) \
     pull_t<PK, LAP, W, P>(a, nnz, row_ptr, col, val, hotlab, n_hot, seg_i, seg_e, nseg, rw, part, s)
-    if (a.laplacian) return val ? GEE_PULL(false, true, true, uint64_t) : GEE_PULL(false, true, false, uint64_t);
-    if (val) return a.pack == Pack::U16 ? GEE_PULL(false, false, true, uint16_t) : GEE_PULL(false, false, true, uint8_t);
-    return a.pack == Pack::U16 ? GEE_PULL(true, false, false, uint16_t) : GEE_PULL(true, false, false, uint8_t);
+    if (a.laplacian) return val ? GEE_PULL(0, true, true, uint64_t) : GEE_PULL(0, true, false, uint64_t);
+    if (val) return a.pack == Pack::U16 ? GEE_PULL(0, false, true, uint16_t) : GEE_PULL(0, false, true, uint8_t);
+    return a.pack == Pack::U16 ? GEE_PULL(kUnitBins, false, false, uint16_t) : GEE_PULL(kUnitBins, false, false, uint8_t);
 #undef GEE_PULL
 }
 

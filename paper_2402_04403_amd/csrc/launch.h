@@ -61,6 +61,7 @@ struct CsrBuildWs {
     int64_t *scan_part; // scan partials
     int64_t *rowlast;   // [n]
     int64_t *vtmp[2];   // [n] each: hot-vertex selection scratch
+    uint64_t *hkeys[2]; // [n_hot] each: hot vertices keyed by degree bucket
     int64_t *hot_hist;  // degree histogram
     int64_t *hot_par;   // threshold, quota
 };
