@@ -226,7 +226,7 @@ def main():
         "config": {
             "workload": f"rmat-s{a.scale}-ef{a.edge_factor}-K{K}-unit-adjacency",
             "n": n, "s": s, "nnz": nnz, "K": K, "form": "csr-pull" if a.form == "pull" else "edge-push",
-            "seg_len": a.seg_len or 4096, "rows_per_window": a.rows_per_window or "auto",
+            "seg_len": a.seg_len or 16384, "rows_per_window": a.rows_per_window or "auto",
             "hot_slots": csr.n_hot,
             "csr_build_ms": round(csr_ms, 2),
             "step_hbm_frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),

@@ -15,7 +15,7 @@ constexpr int64_t kMaxN = INT32_MAX;
 constexpr int64_t kMaxRecords = (int64_t)1 << 40;
 constexpr int32_t kMaxK = 65535;
 constexpr int32_t kMaxKPull = 4096;
-constexpr int32_t kDefaultSegLen = 4096;
+constexpr int32_t kDefaultSegLen = 16384;
 constexpr int32_t kMaxSegLen = 65535; // 16-bit per-segment class counters
 constexpr size_t kWaveLdsBudget = 16384;
 
@@ -25,7 +25,7 @@ struct Plan {
     bool pull = false;
     int64_t n = 0, ns = 0, nnz = 0;
     int32_t K = 0;
-    bool lap = false, weighted = false, wide = false;
+    bool lap = false, weighted = false, wide = false, hot6 = false;
     Pack pack = Pack::U8;
     int64_t L = 0, nseg = 0;
     int rw = 0;
@@ -77,6 +77,7 @@ int make_plan(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian, co
     }
     P.pack = P.lap ? Pack::LAP64 : (K <= 255 ? Pack::U8 : Pack::U16);
     P.wide = P.lap || P.weighted;
+    P.hot6 = P.pull && P.n_hot > 0 && !P.wide && P.pack == Pack::U8 && K <= 63;
     if (o) {
         if (o->seg_len != 0 && (o->seg_len < 64 || o->seg_len > kMaxSegLen)) return GEE_EINVAL;
         if (o->rows_per_window < 0 || o->rows_per_window > 64) return GEE_EINVAL;
@@ -102,10 +103,10 @@ int make_plan(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian, co
     const size_t lab_bytes = P.pack == Pack::U8 ? 1 : (P.pack == Pack::U16 ? 2 : 8);
     P.o_counts = take(8 * (size_t)(K + 1));
     P.o_inv = take(8 * (size_t)(K + 1));
-    P.o_lab = take(lab_bytes * (size_t)P.n);
+    P.o_lab = take(lab_bytes * (size_t)P.n + 4); // + one word: 32-bit reads of the last labels
     if (P.lap) P.o_deg = take(8 * (size_t)P.n);
     if (P.pull) {
-        P.o_hot = take(lab_bytes * (size_t)P.n_hot);
+        P.o_hot = take(P.hot6 ? 4 * (size_t)((P.n_hot + 4) / 5) : lab_bytes * (size_t)P.n_hot);
         P.o_segi = take(4 * (size_t)(P.nseg + 1));
         P.o_sege = take(8 * (size_t)(P.nseg + 1));
         P.o_part = take(8 * 2 * (size_t)P.nseg * (size_t)K);
@@ -185,6 +186,7 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
     a.laplacian = p.lap;
     a.weighted = p.weighted;
     a.pack = p.pack;
+    a.hot6 = p.hot6;
     a.labels = labels;
     a.err = err;
     a.counts = reinterpret_cast<uint64_t *>(w + p.o_counts);

@@ -156,6 +156,26 @@ k_pack_hot(const P *__restrict__ lab, int64_t n, const int32_t *__restrict__ hot
     }
 }
 
+// Hot label table packed at 6 bits per class, five slots per 32-bit word (K <= 63).
+__global__ void __launch_bounds__(kBlock)
+k_pack_hot6(const uint8_t *__restrict__ lab, int64_t n, const int32_t *__restrict__ hot_ids, int64_t n_hot,
+            uint32_t *__restrict__ hot6, int32_t *err)
+{
+    const int64_t nw = (n_hot + 4) / 5;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t word = 0;
+        for (int i = 0; i < 5; ++i) {
+            const int64_t h = 5 * w + i;
+            if (h >= n_hot) break;
+            const int32_t v = hot_ids[h];
+            const bool ok = (uint32_t)v < (uint64_t)n;
+            if (!ok) flag_error(err, GEE_EVERTEX);
+            word |= (ok ? (uint32_t)(lab[v] & 63u) : 0u) << (6 * i);
+        }
+        hot6[w] = word;
+    }
+}
+
 // -------------------------------------------------------- form (a): push --
 
 // One thread per record (four records per thread, strided for coalescing):
@@ -357,7 +377,7 @@ __host__ __device__ inline size_t pull_lds_bytes(int32_t K, int bk, int rw)
 //    row by row with lanes over classes. A row cut by a segment boundary goes to
 //    the FP64 partials instead (head: continues from an earlier segment; tail:
 //    continues into later ones).
-template <int BK, bool LAP, bool W, typename P>
+template <int BK, bool LAP, bool W, typename P, bool H6>
 __global__ void __launch_bounds__(kBlock)
 k_pull(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
        const float *__restrict__ val, const P *__restrict__ lab, const P *__restrict__ hotlab, int64_t n_hot,
@@ -390,12 +410,23 @@ k_pull(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_
     // outstanding while this step's atomics issue.
     const bool tail_seg = !vec_ok || sg.e1 + 4 > nnz;
 
+    // row_ptr[rr + lane], row_ptr[rr + lane + 1], clamped into the array; the next
+    // window's pair is fetched when a window starts, so no window waits for it
+    auto fetch_rows = [&](int64_t rr, int64_t &a0, int64_t &a1) {
+        int64_t idx = rr + lane;
+        idx = idx < n - 1 ? idx : n - 1;
+        a0 = row_ptr[idx];
+        a1 = row_ptr[idx + 1];
+    };
+    int64_t rp0, rp1;
+    fetch_rows(sg.i0, rp0, rp1);
     for (int64_t r = sg.i0; r < sg.rend; r += RW) {
         const int nr = (int)((sg.rend - r) < RW ? (sg.rend - r) : RW);
+        int64_t p0 = rp0, p1 = rp1;
+        fetch_rows(r + RW, rp0, rp1);
         // lane l < nr: clamped start and end of row r + l, relative to e0
         int32_t cs = 0, ce = 0;
         if (lane < nr) {
-            int64_t p0 = row_ptr[r + lane], p1 = row_ptr[r + lane + 1];
             p0 = p0 < sg.e0 ? sg.e0 : (p0 > sg.e1 ? sg.e1 : p0);
             p1 = p1 < sg.e0 ? sg.e0 : (p1 > sg.e1 ? sg.e1 : p1);
             cs = (int32_t)(p0 - sg.e0);
@@ -481,8 +512,21 @@ k_pull(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_
                             const bool ok = in[h][t] && (hot ? (int64_t)idx < n_hot : (int64_t)idx < n);
                             bad |= in[h][t] && !ok;
                             in[h][t] = ok;
-                            const P *tab = (ok && hot) ? hotlab : lab;
-                            pk[h][t] = tab[ok ? idx : 0u];
+                            if (H6) {
+                                // one aligned 32-bit gather: a hot slot's 6-bit field in the
+                                // packed hot table, or the byte of a cold label in its word
+                                const uint32_t wq = __umulhi(idx, 0xCCCCCCCDu) >> 2; // idx / 5
+                                const uint32_t *src =
+                                    !ok ? reinterpret_cast<const uint32_t *>(lab)
+                                        : (hot ? reinterpret_cast<const uint32_t *>(hotlab) + wq
+                                               : reinterpret_cast<const uint32_t *>(lab + (idx & ~3u)));
+                                const uint32_t word = *src;
+                                const uint32_t sh = hot ? 6u * (idx - 5u * wq) : 8u * (idx & 3u);
+                                pk[h][t] = ok ? (P)((word >> sh) & (hot ? 63u : 255u)) : (P)0;
+                            } else {
+                                const P *tab = (ok && hot) ? hotlab : lab;
+                                pk[h][t] = tab[ok ? idx : 0u];
+                            }
                         }
                     }
                     // next step's columns (issued after this step's gathers) and markers
@@ -729,7 +773,7 @@ hipError_t launch_seg_bounds(int64_t n, int64_t nnz, const int64_t *row_ptr, int
 
 size_t pull_wave_bytes(int32_t K, bool wide_bins, int rw) { return pull_lds_bytes(K, wide_bins ? 0 : kUnitBins, rw); }
 
-template <int BK, bool LAP, bool W, typename P>
+template <int BK, bool LAP, bool W, typename P, bool H6 = false>
 static hipError_t pull_t(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
                          const float *val, const void *hotlab, int64_t n_hot, const int32_t *seg_i,
                          const int64_t *seg_e, int64_t nseg, int rw, double *part, hipStream_t s)
@@ -739,7 +783,7 @@ static hipError_t pull_t(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr
     wpb = wpb > kWavesPerBlock ? kWavesPerBlock : (wpb < 1 ? 1 : wpb);
     const int64_t blocks = (nseg + wpb - 1) / wpb;
     const bool vec_ok = ((uintptr_t)col % 16 == 0) && (!val || (uintptr_t)val % 16 == 0);
-    hipLaunchKernelGGL((k_pull<BK, LAP, W, P>), dim3((unsigned)blocks), dim3(wpb * kWave), (size_t)wpb * wb, s,
+    hipLaunchKernelGGL((k_pull<BK, LAP, W, P, H6>), dim3((unsigned)blocks), dim3(wpb * kWave), (size_t)wpb * wb, s,
                        a.n, nnz, row_ptr, col, val, static_cast<const P *>(a.lab), static_cast<const P *>(hotlab),
                        n_hot, a.inv, a.K, seg_i, seg_e, nseg, rw, wb, vec_ok, a.Z, part, a.err);
     return hipGetLastError();
@@ -753,7 +797,10 @@ hipError_t launch_pull(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr, 
     pull_t<PK, LAP, W, P>(a, nnz, row_ptr, col, val, hotlab, n_hot, seg_i, seg_e, nseg, rw, part, s)
     if (a.laplacian) return val ? GEE_PULL(0, true, true, uint64_t) : GEE_PULL(0, true, false, uint64_t);
     if (val) return a.pack == Pack::U16 ? GEE_PULL(0, false, true, uint16_t) : GEE_PULL(0, false, true, uint8_t);
-    return a.pack == Pack::U16 ? GEE_PULL(kUnitBins, false, false, uint16_t) : GEE_PULL(kUnitBins, false, false, uint8_t);
+    if (a.pack == Pack::U16) return GEE_PULL(kUnitBins, false, false, uint16_t);
+    return a.hot6 ? pull_t<kUnitBins, false, false, uint8_t, true>(a, nnz, row_ptr, col, val, hotlab, n_hot, seg_i,
+                                                                  seg_e, nseg, rw, part, s)
+                  : GEE_PULL(kUnitBins, false, false, uint8_t);
 #undef GEE_PULL
 }
 
@@ -774,7 +821,11 @@ hipError_t launch_pack_hot(const EmbedArgs &a, const int32_t *hot_ids, int64_t n
 {
     if (n_hot <= 0) return hipSuccess;
     const dim3 g(grid_for(n_hot, kBlock, 1 << 20)), b(kBlock);
-    if (a.pack == Pack::U8)
+    if (a.hot6)
+        hipLaunchKernelGGL(k_pack_hot6, dim3(grid_for((n_hot + 4) / 5, kBlock, 1 << 20)), b, 0, s,
+                           static_cast<const uint8_t *>(a.lab), a.n, hot_ids, n_hot, static_cast<uint32_t *>(hotlab),
+                           a.err);
+    else if (a.pack == Pack::U8)
         hipLaunchKernelGGL(k_pack_hot<uint8_t>, g, b, 0, s, static_cast<const uint8_t *>(a.lab), a.n, hot_ids, n_hot,
                            static_cast<uint8_t *>(hotlab), a.err);
     else if (a.pack == Pack::U16)
