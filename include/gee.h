@@ -154,6 +154,38 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
               float *Z, void *ws, size_t ws_bytes, int32_t *err, const gee_embed_opts *opts,
               hipStream_t stream);
 
+/* A batch of label vectors over one graph. Vector b has labels
+ * labels[b * n .. b * n + n) in [0, K[b]], the Laplacian version when laplacian[b]
+ * != 0, and its n x K[b] embedding block at Z[u * ldz + zoff[b] + (k - 1)]. The
+ * column blocks of different vectors must not overlap. Host struct; labels and Z
+ * are device memory, K, laplacian and zoff host arrays. */
+typedef struct gee_batch {
+    int32_t B;                /* number of vectors, 1 <= B <= 4096 */
+    const int32_t *labels;    /* [B * n] int32 */
+    const int32_t *K;         /* [B], 1 <= K[b] <= 4096 */
+    const int32_t *laplacian; /* [B] */
+    const int64_t *zoff;      /* [B] first column of each block, zoff[b] + K[b] <= ldz */
+    int64_t ldz;              /* floats per row of Z */
+    float *Z;                 /* [n * ldz] */
+} gee_batch;
+
+/* Workspace bytes gee_embed_batch needs for this graph and batch (0 on invalid input). */
+size_t gee_embed_batch_workspace(const gee_csr *csr, const gee_batch *batch, const gee_embed_opts *opts);
+
+/* Batched Algorithm 1: every vector of the batch embedded over one graph with one
+ * pass of the CSR per group of vectors. Consecutive vectors (in column order) of
+ * the same version whose blocks are contiguous form a group of up to 64; the
+ * group's labels are stored transposed, one row of 16-bit labels per vertex, so
+ * one gather of a neighbour's row serves the whole group, and each row of Z gets
+ * the group's columns written once. Vector b's block holds the values gee_embed
+ * returns for it (identical bits for unit-weight adjacency vectors; other sums may
+ * differ in rounding order). Laplacian vectors share one degree pass. Per-segment
+ * work follows opts->seg_len as in gee_embed; opts->hot_begin / hot_end bracket the
+ * group passes. Data errors as for gee_embed; columns of Z outside the blocks are
+ * not touched. */
+int gee_embed_batch(const gee_csr *csr, const gee_batch *batch, void *ws, size_t ws_bytes, int32_t *err,
+                    const gee_embed_opts *opts, hipStream_t stream);
+
 /* Workspace bytes gee_csr_build needs (weighted != 0 when the records carry w;
  * hot_budget as passed to gee_csr_build). Returns 0 on invalid input. */
 size_t gee_csr_workspace(int64_t n, int64_t s, int weighted, int64_t hot_budget);

@@ -13,6 +13,8 @@ Functions mirror the C entry points:
 * :func:`csr_build` — ``gee_csr_build``: canonical symmetric CSR of A + A^T.
 * :func:`embed`    — ``gee_embed``: Z by the edge-parallel push form (COO) or the
   deterministic CSR-pull form (CSR), adjacency or Laplacian version.
+* :func:`embed_batch` — ``gee_embed_batch``: many label vectors over one graph, one CSR
+  pass per group of up to 64 vectors.
 * :func:`copy`     — ``gee_copy``: the streaming copy probe used for measurement.
 """
 from __future__ import annotations
@@ -52,6 +54,12 @@ class Csr(ctypes.Structure):
                 ("hot_ids", ctypes.c_void_p)]
 
 
+class Batch(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int32), ("labels", ctypes.c_void_p), ("K", ctypes.POINTER(ctypes.c_int32)),
+                ("laplacian", ctypes.POINTER(ctypes.c_int32)), ("zoff", ctypes.POINTER(ctypes.c_int64)),
+                ("ldz", ctypes.c_int64), ("Z", ctypes.c_void_p)]
+
+
 class EmbedOpts(ctypes.Structure):
     _fields_ = [("seg_len", ctypes.c_int32), ("rows_per_window", ctypes.c_int32),
                 ("hot_begin", ctypes.c_void_p), ("hot_end", ctypes.c_void_p)]
@@ -89,6 +97,11 @@ def load():
         lib.gee_csr_workspace.argtypes = [i64, i64, ci, i64]
         lib.gee_csr_build.restype = ci
         lib.gee_csr_build.argtypes = [CooP, i64, vp, vp, vp, vp, vp, sz, vp, vp]
+        BatchP = ctypes.POINTER(Batch)
+        lib.gee_embed_batch_workspace.restype = sz
+        lib.gee_embed_batch_workspace.argtypes = [CsrP, BatchP, OptP]
+        lib.gee_embed_batch.restype = ci
+        lib.gee_embed_batch.argtypes = [CsrP, BatchP, vp, sz, vp, OptP, vp]
         lib.gee_copy.restype = ci
         lib.gee_copy.argtypes = [vp, vp, sz, vp]
         _lib = lib
@@ -345,6 +358,69 @@ def embed(labels: torch.Tensor, K: int, coo: DeviceCoo | None = None, csr: Devic
     if check:
         _check_err(err, "gee_embed")
     return Z
+
+
+def _batch_struct(labels, Ks, laps, zoff, ldz, Z):
+    B = len(Ks)
+    K_arr = (ctypes.c_int32 * B)(*[int(k) for k in Ks])
+    L_arr = (ctypes.c_int32 * B)(*[1 if x else 0 for x in laps])
+    Z_arr = (ctypes.c_int64 * B)(*[int(z) for z in zoff])
+    st = Batch(B, _ptr(labels), ctypes.cast(K_arr, ctypes.POINTER(ctypes.c_int32)),
+               ctypes.cast(L_arr, ctypes.POINTER(ctypes.c_int32)), ctypes.cast(Z_arr, ctypes.POINTER(ctypes.c_int64)),
+               int(ldz), _ptr(Z))
+    return st, (K_arr, L_arr, Z_arr)
+
+
+def embed_batch(labels: torch.Tensor, Ks, laplacian, csr: DeviceCsr, Z: torch.Tensor | None = None, zoff=None,
+                ws: torch.Tensor | None = None, err: torch.Tensor | None = None, seg_len: int = 0, events=None,
+                stream=None, check: bool = True):
+    """Embed B label vectors (``labels`` [B, n] int32) over one graph in one pass per group.
+
+    ``Ks[b]`` and ``laplacian[b]`` give each vector's classes and version. By default the blocks
+    are packed side by side: Z is [n, sum(Ks)] and vector b owns columns zoff[b] .. zoff[b]+Ks[b].
+    Returns (Z, zoff)."""
+    lib = load()
+    B = len(Ks)
+    dev = csr.row_ptr.device
+    _need(labels, torch.int32, B * csr.n, "labels", dev)
+    if zoff is None:
+        zoff, acc = [], 0
+        for k in Ks:
+            zoff.append(acc)
+            acc += int(k)
+    if Z is None:
+        Z = torch.empty((csr.n, int(max(z + k for z, k in zip(zoff, Ks)))), dtype=torch.float32, device=dev)
+    if Z.dim() != 2 or Z.shape[0] != csr.n or not Z.is_contiguous() or Z.dtype != torch.float32:
+        raise ValueError("Z: expected a contiguous float32 [n, ldz] tensor")
+    st, keep = _batch_struct(labels, Ks, laplacian, zoff, Z.shape[1], Z)
+    rs = csr.struct()
+    o = _opts(seg_len, 0, events)
+    wsb = int(lib.gee_embed_batch_workspace(ctypes.byref(rs), ctypes.byref(st), ctypes.byref(o)))
+    if wsb == 0:
+        raise GeeError(GEE_EINVAL, "gee_embed_batch_workspace")
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    if err is None:
+        err = torch.zeros(1, dtype=torch.int32, device=dev)
+    _rc(lib.gee_embed_batch(ctypes.byref(rs), ctypes.byref(st), _ptr(ws), ws.numel(), _ptr(err), ctypes.byref(o),
+                            _stream(stream)), "gee_embed_batch")
+    del keep
+    if check:
+        _check_err(err, "gee_embed_batch")
+    return Z, list(zoff)
+
+
+def embed_batch_workspace_bytes(n: int, Ks, laplacian, csr: DeviceCsr, seg_len: int = 0, zoff=None, ldz=None) -> int:
+    lib = load()
+    if zoff is None:
+        zoff, acc = [], 0
+        for k in Ks:
+            zoff.append(acc)
+            acc += int(k)
+    ldz = ldz or int(max(z + k for z, k in zip(zoff, Ks)))
+    st, keep = _batch_struct(None, Ks, laplacian, zoff, ldz, None)
+    o = _opts(seg_len, 0, None)
+    return int(lib.gee_embed_batch_workspace(ctypes.byref(csr.struct()), ctypes.byref(st), ctypes.byref(o)))
 
 
 def copy(dst: torch.Tensor, src: torch.Tensor, stream=None) -> None:

@@ -4,6 +4,10 @@
 
 #include <limits.h>
 
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
 #include "common.h"
 #include "launch.h"
 
@@ -118,6 +122,110 @@ int make_plan(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian, co
 
 inline int hip_rc(hipError_t e) { return e == hipSuccess ? GEE_OK : GEE_EHIP; }
 
+constexpr int32_t kMaxBatch = 4096;
+constexpr int32_t kMaxBatchK = 4096;
+
+struct BatchPlan {
+    int64_t n = 0, nnz = 0, L = 0, nseg = 0;
+    bool any_lap = false, weighted = false;
+    std::vector<GroupDesc> groups;
+    std::vector<int64_t> zcol;  // first column of each group
+    std::vector<bool> lap;      // version of each group
+    std::vector<int> rw;        // rows per window of each group
+    std::vector<int64_t> cnt_off; // per vector: offset of its counts / inv tables
+    int64_t cnt_total = 0;
+    int Gs_max = 0, KT_max = 0;
+    size_t o_cnt = 0, o_inv = 0, o_lab = 0, o_scale = 0, o_segi = 0, o_sege = 0, o_part = 0, o_deg = 0, o_rsd = 0,
+           total = 0;
+};
+
+int make_batch_plan(const gee_csr *csr, const gee_batch *bt, const gee_embed_opts *o, BatchPlan *out)
+{
+    int rc;
+    if ((rc = check_csr(csr)) != GEE_OK) return rc;
+    if (!bt || bt->B < 1 || bt->B > kMaxBatch || !bt->K || !bt->laplacian || !bt->zoff || bt->ldz < 1)
+        return GEE_EINVAL;
+    if (o && o->seg_len != 0 && (o->seg_len < 64 || o->seg_len > kMaxSegLen)) return GEE_EINVAL;
+    BatchPlan P;
+    P.n = csr->n;
+    P.nnz = csr->nnz;
+    P.weighted = csr->val != nullptr;
+    if (bt->ldz > ((int64_t)1 << 62) / P.n) return GEE_EOVERFLOW;
+    const int B = bt->B;
+    for (int b = 0; b < B; ++b) {
+        if (bt->K[b] < 1 || bt->K[b] > kMaxBatchK || bt->zoff[b] < 0 || bt->zoff[b] + bt->K[b] > bt->ldz)
+            return GEE_EINVAL;
+        P.any_lap |= bt->laplacian[b] != 0;
+    }
+    // vectors in column order; blocks must not overlap
+    std::vector<int> ord(B);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return bt->zoff[a] < bt->zoff[c]; });
+    for (int i = 1; i < B; ++i)
+        if (bt->zoff[ord[i]] < bt->zoff[ord[i - 1]] + bt->K[ord[i - 1]]) return GEE_EINVAL;
+    P.cnt_off.resize(B);
+    for (int b = 0; b < B; ++b) {
+        P.cnt_off[b] = P.cnt_total;
+        P.cnt_total += bt->K[b] + 1;
+    }
+    // groups: runs of same-version vectors with contiguous blocks, <= 64, bins fitting LDS
+    for (int i = 0; i < B;) {
+        GroupDesc d{};
+        const int b0 = ord[i];
+        const bool lap = bt->laplacian[b0] != 0;
+        const bool wide = lap || P.weighted;
+        d.G = 0;
+        d.KT = 0;
+        int64_t next_col = bt->zoff[b0];
+        while (i < B && d.G < kGroupMax) {
+            const int b = ord[i];
+            if ((bt->laplacian[b] != 0) != lap || bt->zoff[b] != next_col) break;
+            if (batch_rows_per_window(d.KT + bt->K[b], wide) == 0) {
+                if (d.G == 0) return GEE_EINVAL; // one vector's bins alone do not fit
+                break;
+            }
+            d.vec[d.G] = b;
+            d.K[d.G] = bt->K[b];
+            d.coff[d.G] = d.KT;
+            d.inv_off[d.G] = P.cnt_off[b];
+            d.KT += bt->K[b];
+            next_col += bt->K[b];
+            ++d.G;
+            ++i;
+        }
+        d.Gs = (d.G + 7) / 8 * 8;
+        P.groups.push_back(d);
+        P.zcol.push_back(bt->zoff[b0]);
+        P.lap.push_back(lap);
+        P.rw.push_back(batch_rows_per_window(d.KT, wide));
+        P.Gs_max = std::max(P.Gs_max, d.Gs);
+        P.KT_max = std::max(P.KT_max, d.KT);
+    }
+    P.L = (o && o->seg_len) ? o->seg_len : kDefaultSegLen;
+    P.nseg = (P.n + P.nnz + P.L - 1) / P.L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = align_up(off, 256);
+        const size_t at = off;
+        off += bytes;
+        return at;
+    };
+    P.o_cnt = take(8 * (size_t)P.cnt_total);
+    P.o_inv = take(8 * (size_t)P.cnt_total);
+    P.o_lab = take(2 * (size_t)P.n * (size_t)P.Gs_max);
+    P.o_scale = take(8 * (size_t)P.KT_max);
+    P.o_segi = take(4 * (size_t)(P.nseg + 1));
+    P.o_sege = take(8 * (size_t)(P.nseg + 1));
+    P.o_part = take(8 * 2 * (size_t)P.nseg * (size_t)P.KT_max);
+    if (P.any_lap) {
+        P.o_deg = take(8 * (size_t)P.n);
+        P.o_rsd = take(4 * (size_t)P.n);
+    }
+    P.total = align_up(off, 256);
+    *out = std::move(P);
+    return GEE_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -226,6 +334,77 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
         return rc;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;
     return hip_rc(launch_merge(a, csr->row_ptr, seg_i, seg_e, p.nseg, part, stream));
+}
+
+size_t gee_embed_batch_workspace(const gee_csr *csr, const gee_batch *batch, const gee_embed_opts *opts)
+{
+    BatchPlan p;
+    if (make_batch_plan(csr, batch, opts, &p) != GEE_OK) return 0;
+    return p.total;
+}
+
+int gee_embed_batch(const gee_csr *csr, const gee_batch *batch, void *ws, size_t ws_bytes, int32_t *err,
+                    const gee_embed_opts *opts, hipStream_t stream)
+{
+    BatchPlan p;
+    int rc = make_batch_plan(csr, batch, opts, &p);
+    if (rc != GEE_OK) return rc;
+    if (!batch->labels || !batch->Z) return GEE_EINVAL;
+    if (!ws || !aligned(ws, 256) || ws_bytes < p.total) return GEE_EWORKSPACE;
+    char *w = static_cast<char *>(ws);
+    uint64_t *cnt = reinterpret_cast<uint64_t *>(w + p.o_cnt);
+    double *inv = reinterpret_cast<double *>(w + p.o_inv);
+    int32_t *seg_i = reinterpret_cast<int32_t *>(w + p.o_segi);
+    int64_t *seg_e = reinterpret_cast<int64_t *>(w + p.o_sege);
+    float *rsd = p.any_lap ? reinterpret_cast<float *>(w + p.o_rsd) : nullptr;
+
+    // class counts and weights of every vector
+    for (int b = 0; b < batch->B; ++b) {
+        const int32_t *lb = batch->labels + (int64_t)b * p.n;
+        if ((rc = hip_rc(launch_counts(lb, p.n, batch->K[b], cnt + p.cnt_off[b], nullptr, Pack::U8, err, stream))))
+            return rc;
+        if ((rc = hip_rc(launch_weights(cnt + p.cnt_off[b], batch->K[b], inv + p.cnt_off[b], stream)))) return rc;
+    }
+    // one degree pass shared by the Laplacian vectors
+    if (p.any_lap) {
+        double *deg = reinterpret_cast<double *>(w + p.o_deg);
+        if ((rc = hip_rc(launch_degrees_csr(p.n, csr->row_ptr, csr->val, p.nnz, deg, true, err, stream)))) return rc;
+        if ((rc = hip_rc(launch_rsd(deg, p.n, rsd, stream)))) return rc;
+    }
+    if ((rc = hip_rc(launch_seg_bounds(p.n, p.nnz, csr->row_ptr, p.L, p.nseg, seg_i, seg_e, stream)))) return rc;
+    const bool timed = opts && opts->hot_begin && opts->hot_end;
+    if (timed && (rc = hip_rc(hipEventRecord(opts->hot_begin, stream)))) return rc;
+    for (size_t gi = 0; gi < p.groups.size(); ++gi) {
+        GroupArgs g;
+        g.n = p.n;
+        g.nnz = p.nnz;
+        g.row_ptr = csr->row_ptr;
+        g.col = csr->col;
+        g.val = csr->val;
+        g.hot_ids = csr->hot_ids;
+        g.n_hot = csr->n_hot;
+        g.labmat = reinterpret_cast<const uint16_t *>(w + p.o_lab);
+        g.d = p.groups[gi];
+        g.scale = reinterpret_cast<const double *>(w + p.o_scale);
+        g.rsd = rsd;
+        g.seg_i = seg_i;
+        g.seg_e = seg_e;
+        g.nseg = p.nseg;
+        g.rw = p.rw[gi];
+        g.Z = batch->Z;
+        g.ldz = batch->ldz;
+        g.zcol = p.zcol[gi];
+        g.part = reinterpret_cast<double *>(w + p.o_part);
+        g.err = err;
+        g.lap = p.lap[gi];
+        if ((rc = hip_rc(launch_pack_group(batch->labels, p.n, g.d, reinterpret_cast<uint16_t *>(w + p.o_lab), err,
+                                           stream))))
+            return rc;
+        if ((rc = hip_rc(launch_group_scale(inv, g.d, reinterpret_cast<double *>(w + p.o_scale), stream)))) return rc;
+        if ((rc = hip_rc(launch_pull_group(g, stream)))) return rc;
+    }
+    if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;
+    return GEE_OK;
 }
 
 size_t gee_csr_workspace(int64_t n, int64_t s, int weighted, int64_t hot_budget)

@@ -123,3 +123,24 @@ def test_csr_build_argument_errors(lib):
 def test_python_binding_refuses_host_tensors(lib):
     with pytest.raises(ValueError):
         gee.counts(torch.zeros(4, dtype=torch.int32), 2)
+
+
+def test_batch_argument_errors(lib):
+    csr = gee.Csr(1000, 10_000, FAKE, FAKE, None, 0, None)
+    o = gee.EmbedOpts(0, 0, None, None)
+
+    def ws(Ks, laps, zoff, ldz):
+        st, keep = gee._batch_struct(None, Ks, laps, zoff, ldz, None)
+        return lib.gee_embed_batch_workspace(ctypes.byref(csr), ctypes.byref(st), ctypes.byref(o))
+
+    assert ws([5, 7, 3], [0, 1, 0], [0, 5, 12], 15) > 0
+    assert ws([5, 7], [0, 0], [0, 5], 11) == 0  # block past ldz
+    assert ws([5, 7], [0, 0], [0, 4], 20) == 0  # overlapping blocks
+    assert ws([0, 7], [0, 0], [0, 5], 20) == 0  # K < 1
+    assert ws([4097], [0], [0], 5000) == 0  # K above the batched limit
+    assert ws([5, 7], [0, 0], [7, 0], 20) > 0  # any column order
+    big = ws([50] * 64, [0] * 64, [50 * i for i in range(64)], 3200)
+    lap = ws([50] * 64, [1] * 64, [50 * i for i in range(64)], 3200)
+    assert big > 0 and lap > big  # degrees and d^-1/2 for the Laplacian vectors
+    st, keep = gee._batch_struct(None, [5], [0], [0], 5, None)
+    assert lib.gee_embed_batch(ctypes.byref(csr), ctypes.byref(st), FAKE, 1 << 30, FAKE, None, None) == gee.GEE_EINVAL

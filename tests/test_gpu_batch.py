@@ -1,0 +1,122 @@
+"""Batched GEE on the GPU: every vector's block equals the single-vector call and the
+FP64 oracle; groups, layouts, split rows and errors."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+import paper_2402_04403_amd as gee
+from gpu_util import announce, assert_parity, random_labels
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    announce(request.node.nodeid)
+    yield
+    torch.cuda.synchronize()
+
+
+def _graph(weighted, seed=51, scale=13, ef=10, hub=3000):
+    rng = np.random.default_rng(seed)
+    g = gen.rmat(scale, ef << scale, seed=seed)
+    src = np.r_[g.src, np.zeros(hub, np.int32)].astype(np.int32)  # a hub that spans many segments
+    dst = np.r_[g.dst, rng.integers(0, g.n, hub).astype(np.int32)]
+    w = ((rng.integers(0, 1 << 24, src.size) + 1) * 2.0 ** -24).astype(np.float32) if weighted else None
+    return g.n, src, dst, w
+
+
+def _labels(rng, n, Ks):
+    return np.stack([random_labels(rng, n, k, unknown=rng.uniform(0, 0.5)) for k in Ks]).astype(np.int32)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("seg_len", [0, 256])
+def test_batch_blocks_match_single_calls_and_oracle(weighted, seg_len):
+    n, src, dst, w = _graph(weighted)
+    rng = np.random.default_rng(7)
+    Ks = [1, 2, 3, 7, 50, 100, 255, 256, 300, 1000, 5, 64]
+    laps = [b % 3 == 1 for b in range(len(Ks))]
+    Y = _labels(rng, n, Ks)
+    coo = gee.to_device(n, src, dst, w, device=DEV)
+    csr = gee.csr_build(coo)
+    Z, zoff = gee.embed_batch(torch.as_tensor(Y).to(DEV), Ks, laps, csr, seg_len=seg_len)
+    Zh = Z.cpu().numpy()
+    for b, (K, lap) in enumerate(zip(Ks, laps)):
+        blk = Zh[:, zoff[b]:zoff[b] + K]
+        Zs = gee.embed(torch.as_tensor(Y[b]).to(DEV), K, csr=csr, laplacian=lap, seg_len=seg_len).cpu().numpy()
+        if not lap and not weighted:  # exact integer sums: identical bits
+            assert np.array_equal(blk.view(np.uint32), Zs.view(np.uint32)), b
+        Zo = oracle.embed(n, src, dst, w, Y[b], K, lap)
+        assert_parity(blk, Zo, what=f"vector {b} K={K} lap={lap}")
+
+
+def test_many_groups_interleaved_layout_and_gaps():
+    """100 vectors alternating versions (groups of one), blocks in reverse order with gaps:
+    gap columns stay untouched."""
+    n, src, dst, w = _graph(False, seed=52, scale=12, ef=8)
+    rng = np.random.default_rng(8)
+    B = 100
+    Ks = [int(k) for k in rng.integers(2, 40, B)]
+    laps = [b % 2 == 1 for b in range(B)]
+    zoff, acc = [0] * B, 0
+    for b in reversed(range(B)):  # reverse column order, one spare column after each block
+        zoff[b] = acc
+        acc += Ks[b] + 1
+    Y = _labels(rng, n, Ks)
+    csr = gee.csr_build(gee.to_device(n, src, dst, w, device=DEV))
+    Z = torch.full((n, acc), float("nan"), dtype=torch.float32, device=DEV)
+    gee.embed_batch(torch.as_tensor(Y).to(DEV), Ks, laps, csr, Z=Z, zoff=zoff)
+    Zh = Z.cpu().numpy()
+    gaps = np.array([zoff[b] + Ks[b] for b in range(B)])
+    assert np.all(np.isnan(Zh[:, gaps]))
+    for b in range(0, B, 9):
+        Zo = oracle.embed(n, src, dst, w, Y[b], Ks[b], laps[b])
+        assert_parity(Zh[:, zoff[b]:zoff[b] + Ks[b]], Zo, what=f"vector {b}")
+
+
+def test_large_group_of_64_and_hot_slot_csr():
+    n, src, dst, w = _graph(False, seed=53, scale=14, ef=12)
+    rng = np.random.default_rng(9)
+    Ks = [int(np.floor(np.exp(rng.uniform(np.log(2), np.log(257))))) for _ in range(70)]
+    laps = [False] * 70
+    Y = _labels(rng, n, Ks)
+    coo = gee.to_device(n, src, dst, w, device=DEV)
+    plain = gee.csr_build(coo)
+    hot = gee.csr_build(coo, hot_budget=2000)
+    Zp, zoff = gee.embed_batch(torch.as_tensor(Y).to(DEV), Ks, laps, plain)
+    Zh, _ = gee.embed_batch(torch.as_tensor(Y).to(DEV), Ks, laps, hot)
+    assert torch.equal(Zp.view(torch.int32), Zh.view(torch.int32))
+    Zn = Zp.cpu().numpy()
+    for b in (0, 31, 63, 64, 69):
+        Zo = oracle.embed(n, src, dst, w, Y[b], Ks[b], False)
+        assert_parity(Zn[:, zoff[b]:zoff[b] + Ks[b]], Zo, what=f"vector {b}")
+
+
+def test_batch_is_bit_reproducible():
+    n, src, dst, w = _graph(True, seed=54)
+    rng = np.random.default_rng(10)
+    Ks = [5, 17, 50, 3]
+    laps = [False, True, False, True]
+    Y = torch.as_tensor(_labels(rng, n, Ks)).to(DEV)
+    csr = gee.csr_build(gee.to_device(n, src, dst, w, device=DEV))
+    Z1, _ = gee.embed_batch(Y, Ks, laps, csr, seg_len=512)
+    Z2, _ = gee.embed_batch(Y, Ks, laps, csr, seg_len=512)
+    assert torch.equal(Z1.view(torch.int32), Z2.view(torch.int32))
+
+
+def test_batch_errors():
+    n, src, dst, w = _graph(False, seed=55, scale=10, ef=4, hub=10)
+    csr = gee.csr_build(gee.to_device(n, src, dst, w, device=DEV))
+    Y = np.ones((2, n), np.int32)
+    Y[1, 5] = 9  # K = 4
+    with pytest.raises(gee.GeeError) as e:
+        gee.embed_batch(torch.as_tensor(Y).to(DEV), [4, 4], [False, False], csr)
+    assert e.value.code == gee.GEE_ELABEL
+    with pytest.raises(gee.GeeError) as e:
+        gee.embed_batch(torch.as_tensor(Y).to(DEV), [4, 4], [False, False], csr, zoff=[0, 2],
+                        Z=torch.empty((n, 8), device=DEV))
+    assert e.value.code == gee.GEE_EINVAL
