@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "k_pull_rmat27_counters.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2402_04403_amd", "csrc", "embed.hip")
+PROFILE_COUNTERS_BATCH = os.path.join(ROOT, "profiles", "k_pull_group_rmat24_b64_counters.json")
+KERNEL_SOURCE_BATCH = os.path.join(ROOT, "paper_2402_04403_amd", "csrc", "batch.hip")
 
 
 def log(msg):
@@ -40,10 +42,16 @@ def log(msg):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--workload", choices=["rmat27", "batched"], default="rmat27",
+                   help="rmat27: one label vector on the paper-scale R-MAT (the headline line); "
+                        "batched: 64 label vectors on an R-MAT of scale 24, edge factor 16")
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--scale", type=int, default=27)
-    p.add_argument("--edge-factor", type=int, default=14)
+    p.add_argument("--scale", type=int, default=None)
+    p.add_argument("--edge-factor", type=int, default=None)
+    p.add_argument("--batch", type=int, default=64, help="label vectors of the batched workload")
+    p.add_argument("--plain-steps", type=int, default=1,
+                   help="batched workload: timed rounds of one plain call per vector, reported beside")
     p.add_argument("--K", type=int, default=50)
     p.add_argument("--form", choices=["pull", "push"], default="pull")
     p.add_argument("--seg-len", type=int, default=0)
@@ -52,7 +60,12 @@ def parse():
     p.add_argument("--push-steps", type=int, default=3, help="timed steps of the push form, reported beside")
     p.add_argument("--cpu-records", type=int, default=400_000_000)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    return p.parse_args()
+    a = p.parse_args()
+    if a.scale is None:
+        a.scale = 27 if a.workload == "rmat27" else 24
+    if a.edge_factor is None:
+        a.edge_factor = 14 if a.workload == "rmat27" else 16
+    return a
 
 
 def source_hash(path):
@@ -60,15 +73,15 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def counters_traffic(launch_bytes_alg):
+def counters_traffic(launch_bytes_alg, path=PROFILE_COUNTERS, source=KERNEL_SOURCE):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it still
     describes the current kernel source; else None."""
     try:
-        with open(PROFILE_COUNTERS) as f:
+        with open(path) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None, None
-    if c.get("kernel_source_sha256") != source_hash(KERNEL_SOURCE):
+    if c.get("kernel_source_sha256") != source_hash(source):
         return None, c
     return float(c["hbm_bytes_per_launch"]), c
 
@@ -79,6 +92,8 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (the path shards by rows, "
               "see DESIGN.md, but no multi-GPU run is part of this build)", file=sys.stderr)
         sys.exit(2)
+    if a.workload == "batched":
+        return main_batched(a)
 
     import numpy as np
     import torch
@@ -239,6 +254,163 @@ def main():
     }
     if counters is not None:
         out["config"]["counters_file"] = os.path.relpath(PROFILE_COUNTERS, ROOT)
+    print(json.dumps(out), flush=True)
+
+
+def main_batched(a):
+    """Many label vectors on one graph: one ``gee_embed_batch`` call per step.
+
+    Workload: R-MAT (0.57, 0.19, 0.19, 0.05) of scale 24, edge factor 16 (268,435,456
+    records), unit weights, 64 label vectors with K_b log-uniform on [2, 256], unknown
+    fraction f_b ~ U[0, 0.5), even b adjacency and odd b Laplacian. Z is one row-major
+    FP32 buffer [n, sum K_b] with the blocks side by side in vector order (a group
+    holds up to 64 vectors of either version). ``value`` is label-edge throughput =
+    s * B / step time. The roofline prices the group loop
+    (label packing, edge pass and split-row merge of every group, between the two HIP
+    events the call records) against one read of the labels, the CSR and one write of
+    Z. Beside it: one plain ``gee_embed`` call per vector (same CSR, same seg_len)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2402_04403_amd as gee
+
+    dev = torch.device("cuda:0")
+    gee.load()
+    t0 = time.time()
+    wl = gen.rmat_batched(scale=a.scale, edge_factor=a.edge_factor, B=a.batch)
+    g = wl.graph
+    n, s = g.n, g.s
+    B, Ks, laps = len(wl.Ks), wl.Ks, wl.laps
+    KS = int(sum(Ks))
+    log(f"generated {wl.name}: n={n} s={s} B={B} sum K={KS} in {time.time() - t0:.1f}s")
+    cpu_n = min(a.cpu_records, s) if not a.no_cpu_baseline else 0
+    cpu_src, cpu_dst = g.src[:cpu_n].copy(), g.dst[:cpu_n].copy()
+    cpu_Y = [wl.labels[0].copy(), wl.labels[1].copy()] if cpu_n else None
+    coo = gee.to_device(n, g.src, g.dst, None, device=dev)
+    labels = torch.as_tensor(wl.labels).to(dev)
+    del g, wl
+    hot_budget = gee.DEFAULT_HOT_BUDGET if a.hot_budget < 0 else a.hot_budget
+    e0, e1 = gee.HipEvent(), gee.HipEvent()
+    e0.record()
+    csr = gee.csr_build(coo, hot_budget=hot_budget, check=False)
+    e1.record()
+    e1.synchronize()
+    csr_ms = e0.elapsed_ms(e1)
+    nnz = csr.nnz
+    del coo
+    torch.cuda.empty_cache()
+    log(f"csr built nnz={nnz} hot={csr.n_hot} in {csr_ms:.1f} ms")
+
+    zoff, acc = [0] * B, 0
+    for b in range(B):
+        zoff[b] = acc
+        acc += Ks[b]
+    Z = torch.empty((n, KS), dtype=torch.float32, device=dev)
+    wsb = gee.embed_batch_workspace_bytes(n, Ks, laps, csr, seg_len=a.seg_len, zoff=zoff, ldz=KS)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    err = torch.zeros(1, dtype=torch.int32, device=dev)
+    log(f"Z {n * KS * 4 / 1e9:.1f} GB, workspace {wsb / 1e9:.2f} GB")
+
+    def step(events=None):
+        gee.embed_batch(labels, Ks, laps, csr, Z=Z, zoff=zoff, ws=ws, err=err, seg_len=a.seg_len,
+                        events=events, check=False)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    hot = [(gee.HipEvent(), gee.HipEvent()) for _ in range(a.steps)]
+    t_begin, t_end = gee.HipEvent(), gee.HipEvent()
+    w0 = time.perf_counter()
+    t_begin.record()
+    for i in range(a.steps):
+        step(events=hot[i])
+    t_end.record()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - w0) * 1e3
+    step_ms = t_begin.elapsed_ms(t_end) / a.steps
+    hot_ms = [b_.elapsed_ms(e_) for b_, e_ in hot]
+    hot_avg = float(np.mean(hot_ms))
+    if int(err.item()) != 0:
+        raise SystemExit(f"gee_embed_batch reported {int(err.item())}")
+    log(f"batched: step {step_ms:.3f} ms (wall {wall_ms / a.steps:.3f}), group loop {hot_avg:.3f} ms")
+
+    # one plain call per vector, into one reused [n, max K] buffer
+    plain_ms = None
+    if a.plain_steps > 0:
+        del Z
+        torch.cuda.empty_cache()
+        Zp = torch.empty(n * max(Ks), dtype=torch.float32, device=dev)
+        wsp = torch.empty(max(gee.embed_workspace_bytes(k, csr=csr, seg_len=a.seg_len, laplacian=l)
+                              for k, l in zip(Ks, laps)), dtype=torch.uint8, device=dev)
+
+        def plain():
+            for b in range(B):
+                gee.embed(labels[b], Ks[b], csr=csr, laplacian=laps[b], Z=Zp[: n * Ks[b]].view(n, Ks[b]), ws=wsp,
+                          err=err, seg_len=a.seg_len, check=False)
+
+        plain()
+        torch.cuda.synchronize()
+        p0, p1 = gee.HipEvent(), gee.HipEvent()
+        p0.record()
+        for _ in range(a.plain_steps):
+            plain()
+        p1.record()
+        p1.synchronize()
+        plain_ms = p0.elapsed_ms(p1) / a.plain_steps
+        if int(err.item()) != 0:
+            raise SystemExit(f"gee_embed reported {int(err.item())}")
+        log(f"plain: {B} calls {plain_ms:.3f} ms")
+
+    bytes_alg = 4 * n * B + 4 * nnz + 8 * (n + 1) + 4 * n * KS
+    achieved = bytes_alg / (hot_avg * 1e-3) / 1e9
+    traffic, counters = counters_traffic(bytes_alg, PROFILE_COUNTERS_BATCH, KERNEL_SOURCE_BATCH)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": "k_pack_group + k_pull_group + k_merge_group (every group)",
+                "bytes_alg_per_launch": int(bytes_alg), "kernel_ms": round(hot_avg, 4)}
+
+    cpu = None
+    if cpu_n:
+        import oracle
+
+        log(f"cpu baseline: oracle on the first {cpu_n} records, vectors 0 and 1 ...")
+        c_t0 = time.perf_counter()
+        for b in (0, 1):
+            oracle.embed(n, cpu_src, cpu_dst, None, cpu_Y[b], Ks[b], laps[b])
+        c_t = time.perf_counter() - c_t0
+        cpu = {"value": round(2 * cpu_n / c_t / 1e9, 6), "unit": "G label-edges/s", "cores": 1, "kind": "oracle",
+               "seconds": round(c_t, 2),
+               "sample": f"first {cpu_n:,} of {s:,} records, vectors 0 (K={Ks[0]}, adjacency) and 1 (K={Ks[1]}, "
+                         f"Laplacian) over all n={n:,} vertices; FP64 Algorithm 1, one thread, one call per vector"}
+        log(f"cpu baseline {cpu['value']} G label-edges/s in {c_t:.1f}s")
+
+    out = {
+        "metric": "G label-edges/s",
+        "value": round(s * B / (step_ms * 1e-3) / 1e9, 3),
+        "unit": "G label-edges/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"rmat-s{a.scale}-ef{a.edge_factor}-B{B}-batched",
+            "n": n, "s": s, "nnz": nnz, "B": B, "sum_K": KS, "Ks": Ks,
+            "versions": "even b adjacency, odd b Laplacian", "layout": "blocks side by side in vector order",
+            "seg_len": a.seg_len or 16384, "hot_slots": csr.n_hot, "csr_build_ms": round(csr_ms, 2),
+            "Z_GB": round(n * KS * 4 / 1e9, 2),
+            "plain_ms_per_batch": None if plain_ms is None else round(plain_ms, 3),
+            "plain_value": None if plain_ms is None else round(s * B / (plain_ms * 1e-3) / 1e9, 3),
+            "speedup_vs_plain": None if plain_ms is None else round(plain_ms / step_ms, 3),
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
     print(json.dumps(out), flush=True)
 
 

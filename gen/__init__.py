@@ -16,6 +16,11 @@ here; these synthetic graphs stand in with comparable shapes):
 * ``rmat_paper_scale`` — R-MAT (0.57, 0.19, 0.19, 0.05), scale 27, edge factor 14
   (1,879,048,192 records, about Friendster's 1.8B edges of Table I), unit weights,
   ids scrambled by a seeded bijection, labels 1 + hash mod 50 with 1% set to 0.
+* ``rmat_batched`` — R-MAT scale 24, edge factor 16 (268,435,456 records), unit
+  weights, and 64 label vectors on it: K_b = floor(exp(U[ln 2, ln 257))) in
+  [2, 256], unknown fraction f_b ~ U[0, 0.5) (Bernoulli per vertex), even b the
+  adjacency version and odd b the Laplacian version (many label vectors sharing
+  one graph, as in the paper's repeated-label experiments of Section IV).
 
 The paper's label protocol (Section IV) draws labels uniformly at random; here the
 class of a labelled vertex is uniform over 1..K and a fixed fraction is unknown (0).
@@ -199,3 +204,49 @@ def rmat_paper_scale(seed: int = 3, scale: int = 27, edge_factor: int = 14, K: i
     Y = labels_uniform(n, K, seed)
     unlabel_bernoulli(Y, unlabeled, seed)
     return Workload(f"rmat-s{scale}-ef{edge_factor}-K{K}", g, Y, K)
+
+
+BATCH_PARAM_STREAM = 13  # counter stream of the per-vector (K_b, f_b) draws
+
+
+def _unit(seed: int, stream: int, ctr: int) -> float:
+    return (rng_at(seed, stream, ctr) >> 11) * 2.0 ** -53
+
+
+def batch_params(B: int, seed: int, k_lo: int = 2, k_hi: int = 256):
+    """Per-vector (K_b, f_b, laplacian_b): K log-uniform on [k_lo, k_hi], f ~ U[0, 0.5), odd b Laplacian."""
+    Ks, fs, laps = [], [], []
+    lo, hi = np.log(k_lo), np.log(k_hi + 1)
+    for b in range(B):
+        K = int(np.floor(np.exp(lo + _unit(seed, BATCH_PARAM_STREAM, 2 * b) * (hi - lo))))
+        Ks.append(min(max(K, k_lo), k_hi))
+        fs.append(0.5 * _unit(seed, BATCH_PARAM_STREAM, 2 * b + 1))
+        laps.append(b % 2 == 1)
+    return Ks, fs, laps
+
+
+@dataclass
+class BatchWorkload:
+    name: str
+    graph: Graph
+    labels: np.ndarray  # [B, n] int32
+    Ks: list
+    fs: list
+    laps: list
+
+
+def batch_labels(n: int, Ks, fs, seed: int) -> np.ndarray:
+    Y = np.empty((len(Ks), n), np.int32)
+    for b, (K, f) in enumerate(zip(Ks, fs)):
+        sb = seed * 1_000_003 + b
+        Y[b] = labels_uniform(n, K, sb)
+        unlabel_bernoulli(Y[b], f, sb)
+    return Y
+
+
+def rmat_batched(seed: int = 4, scale: int = 24, edge_factor: int = 16, B: int = 64) -> BatchWorkload:
+    """R-MAT (0.57,0.19,0.19,0.05) 2^scale vertices, edge_factor*2^scale records; B label vectors."""
+    n = 1 << scale
+    g = rmat(scale, edge_factor * n, seed)
+    Ks, fs, laps = batch_params(B, seed)
+    return BatchWorkload(f"rmat-s{scale}-ef{edge_factor}-B{B}", g, batch_labels(n, Ks, fs, seed), Ks, fs, laps)

@@ -173,16 +173,18 @@ typedef struct gee_batch {
 size_t gee_embed_batch_workspace(const gee_csr *csr, const gee_batch *batch, const gee_embed_opts *opts);
 
 /* Batched Algorithm 1: every vector of the batch embedded over one graph with one
- * pass of the CSR per group of vectors. Consecutive vectors (in column order) of
- * the same version whose blocks are contiguous form a group of up to 64; the
- * group's labels are stored transposed, one row of 16-bit labels per vertex, so
- * one gather of a neighbour's row serves the whole group, and each row of Z gets
- * the group's columns written once. Vector b's block holds the values gee_embed
- * returns for it (identical bits for unit-weight adjacency vectors; other sums may
- * differ in rounding order). Laplacian vectors share one degree pass. Per-segment
- * work follows opts->seg_len as in gee_embed; opts->hot_begin / hot_end bracket the
- * group passes. Data errors as for gee_embed; columns of Z outside the blocks are
- * not touched. */
+ * pass of the CSR per group of vectors. Vectors taken in column order whose blocks
+ * are contiguous form groups of up to 64 with at most 4096 classes in total, any
+ * mix of adjacency and Laplacian vectors; the group's labels are stored transposed, one row of 16-bit
+ * labels per vertex, so one gather of a neighbour's row serves the whole group, and
+ * each row of Z gets the group's columns written once. Every bin is an FP64 sum
+ * taken in CSR order, so results are bit-reproducible. Vector b's block holds the
+ * values gee_embed returns for it (identical bits for unit-weight adjacency
+ * vectors; other sums may differ in rounding order). Laplacian vectors share one
+ * degree pass. Per-segment work follows opts->seg_len as in gee_embed;
+ * opts->hot_begin / hot_end bracket the group passes (label packing, edge pass and
+ * split-row merge of every group). Data errors as for gee_embed; columns of Z
+ * outside the blocks are not touched. GEE_EINVAL also when ldz > 2^31 - 1. */
 int gee_embed_batch(const gee_csr *csr, const gee_batch *batch, void *ws, size_t ws_bytes, int32_t *err,
                     const gee_embed_opts *opts, hipStream_t stream);
 

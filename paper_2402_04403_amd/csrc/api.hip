@@ -123,20 +123,18 @@ int make_plan(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian, co
 inline int hip_rc(hipError_t e) { return e == hipSuccess ? GEE_OK : GEE_EHIP; }
 
 constexpr int32_t kMaxBatch = 4096;
-constexpr int32_t kMaxBatchK = 4096;
+constexpr int32_t kMaxBatchK = kBatchMaxKT; // one vector's classes must fit one group
 
 struct BatchPlan {
-    int64_t n = 0, nnz = 0, L = 0, nseg = 0;
+    int64_t n = 0, nnz = 0, L = 0, nseg = 0, n_hot = 0;
     bool any_lap = false, weighted = false;
     std::vector<GroupDesc> groups;
-    std::vector<int64_t> zcol;  // first column of each group
-    std::vector<bool> lap;      // version of each group
-    std::vector<int> rw;        // rows per window of each group
+    std::vector<bool> lap;        // the group holds Laplacian vectors
     std::vector<int64_t> cnt_off; // per vector: offset of its counts / inv tables
     int64_t cnt_total = 0;
     int Gs_max = 0, KT_max = 0;
-    size_t o_cnt = 0, o_inv = 0, o_lab = 0, o_scale = 0, o_segi = 0, o_sege = 0, o_part = 0, o_deg = 0, o_rsd = 0,
-           total = 0;
+    size_t o_cnt = 0, o_inv = 0, o_lab = 0, o_labhot = 0, o_rsdhot = 0, o_cscale = 0, o_vmeta = 0,
+           o_segi = 0, o_sege = 0, o_part = 0, o_deg = 0, o_rsd = 0, total = 0;
 };
 
 int make_batch_plan(const gee_csr *csr, const gee_batch *bt, const gee_embed_opts *o, BatchPlan *out)
@@ -146,9 +144,11 @@ int make_batch_plan(const gee_csr *csr, const gee_batch *bt, const gee_embed_opt
     if (!bt || bt->B < 1 || bt->B > kMaxBatch || !bt->K || !bt->laplacian || !bt->zoff || bt->ldz < 1)
         return GEE_EINVAL;
     if (o && o->seg_len != 0 && (o->seg_len < 64 || o->seg_len > kMaxSegLen)) return GEE_EINVAL;
+    if (bt->ldz > INT32_MAX) return GEE_EINVAL; // Z column ids are 32-bit in the edge pass
     BatchPlan P;
     P.n = csr->n;
     P.nnz = csr->nnz;
+    P.n_hot = csr->n_hot;
     P.weighted = csr->val != nullptr;
     if (bt->ldz > ((int64_t)1 << 62) / P.n) return GEE_EOVERFLOW;
     const int B = bt->B;
@@ -168,36 +168,28 @@ int make_batch_plan(const gee_csr *csr, const gee_batch *bt, const gee_embed_opt
         P.cnt_off[b] = P.cnt_total;
         P.cnt_total += bt->K[b] + 1;
     }
-    // groups: runs of same-version vectors with contiguous blocks, <= 64, bins fitting LDS
+    // groups: runs of vectors whose blocks are contiguous in Z (in column order), up
+    // to 64 vectors and kBatchMaxKT classes per group, any mix of versions
     for (int i = 0; i < B;) {
         GroupDesc d{};
-        const int b0 = ord[i];
-        const bool lap = bt->laplacian[b0] != 0;
-        const bool wide = lap || P.weighted;
-        d.G = 0;
-        d.KT = 0;
-        int64_t next_col = bt->zoff[b0];
+        bool lap = false;
         while (i < B && d.G < kGroupMax) {
             const int b = ord[i];
-            if ((bt->laplacian[b] != 0) != lap || bt->zoff[b] != next_col) break;
-            if (batch_rows_per_window(d.KT + bt->K[b], wide) == 0) {
-                if (d.G == 0) return GEE_EINVAL; // one vector's bins alone do not fit
-                break;
-            }
+            if (d.G > 0 && (d.KT + bt->K[b] > kBatchMaxKT || bt->zoff[b] != d.zoff[0] + d.KT)) break;
             d.vec[d.G] = b;
             d.K[d.G] = bt->K[b];
             d.coff[d.G] = d.KT;
+            d.zoff[d.G] = bt->zoff[b];
             d.inv_off[d.G] = P.cnt_off[b];
+            d.lap[d.G] = bt->laplacian[b] != 0;
+            lap |= bt->laplacian[b] != 0;
             d.KT += bt->K[b];
-            next_col += bt->K[b];
             ++d.G;
             ++i;
         }
         d.Gs = (d.G + 7) / 8 * 8;
         P.groups.push_back(d);
-        P.zcol.push_back(bt->zoff[b0]);
         P.lap.push_back(lap);
-        P.rw.push_back(batch_rows_per_window(d.KT, wide));
         P.Gs_max = std::max(P.Gs_max, d.Gs);
         P.KT_max = std::max(P.KT_max, d.KT);
     }
@@ -212,14 +204,17 @@ int make_batch_plan(const gee_csr *csr, const gee_batch *bt, const gee_embed_opt
     };
     P.o_cnt = take(8 * (size_t)P.cnt_total);
     P.o_inv = take(8 * (size_t)P.cnt_total);
-    P.o_lab = take(2 * (size_t)P.n * (size_t)P.Gs_max);
-    P.o_scale = take(8 * (size_t)P.KT_max);
+    P.o_lab = take(2 * (size_t)(P.n + 1) * (size_t)P.Gs_max);
+    P.o_labhot = take(2 * (size_t)P.n_hot * (size_t)P.Gs_max);
+    P.o_cscale = take(8 * (size_t)P.KT_max);
+    P.o_vmeta = take(4 * (size_t)kGroupMax);
     P.o_segi = take(4 * (size_t)(P.nseg + 1));
     P.o_sege = take(8 * (size_t)(P.nseg + 1));
     P.o_part = take(8 * 2 * (size_t)P.nseg * (size_t)P.KT_max);
     if (P.any_lap) {
         P.o_deg = take(8 * (size_t)P.n);
         P.o_rsd = take(4 * (size_t)P.n);
+        P.o_rsdhot = take(4 * (size_t)P.n_hot);
     }
     P.total = align_up(off, 256);
     *out = std::move(P);
@@ -374,33 +369,41 @@ int gee_embed_batch(const gee_csr *csr, const gee_batch *batch, void *ws, size_t
     if ((rc = hip_rc(launch_seg_bounds(p.n, p.nnz, csr->row_ptr, p.L, p.nseg, seg_i, seg_e, stream)))) return rc;
     const bool timed = opts && opts->hot_begin && opts->hot_end;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_begin, stream)))) return rc;
+    uint16_t *labmat = reinterpret_cast<uint16_t *>(w + p.o_lab);
+    uint16_t *labhot = reinterpret_cast<uint16_t *>(w + p.o_labhot);
+    float *rsdhot = p.any_lap ? reinterpret_cast<float *>(w + p.o_rsdhot) : nullptr;
+    double *cscale = reinterpret_cast<double *>(w + p.o_cscale);
+    uint32_t *vmeta = reinterpret_cast<uint32_t *>(w + p.o_vmeta);
     for (size_t gi = 0; gi < p.groups.size(); ++gi) {
+        const GroupDesc &d = p.groups[gi];
         GroupArgs g;
         g.n = p.n;
-        g.nnz = p.nnz;
         g.row_ptr = csr->row_ptr;
         g.col = csr->col;
         g.val = csr->val;
-        g.hot_ids = csr->hot_ids;
-        g.n_hot = csr->n_hot;
-        g.labmat = reinterpret_cast<const uint16_t *>(w + p.o_lab);
-        g.d = p.groups[gi];
-        g.scale = reinterpret_cast<const double *>(w + p.o_scale);
-        g.rsd = rsd;
+        g.n_hot = p.n_hot;
+        g.labmat = labmat;
+        g.labhot = labhot;
+        g.Gs = d.Gs;
+        g.KT = d.KT;
+        g.lap = p.lap[gi];
+        g.rsd = g.lap ? rsd : nullptr;
+        g.rsdhot = g.lap ? rsdhot : nullptr;
+        g.vmeta = vmeta;
+        g.cscale = cscale;
         g.seg_i = seg_i;
         g.seg_e = seg_e;
         g.nseg = p.nseg;
-        g.rw = p.rw[gi];
         g.Z = batch->Z;
         g.ldz = batch->ldz;
-        g.zcol = p.zcol[gi];
+        g.zcol = d.zoff[0];
         g.part = reinterpret_cast<double *>(w + p.o_part);
         g.err = err;
-        g.lap = p.lap[gi];
-        if ((rc = hip_rc(launch_pack_group(batch->labels, p.n, g.d, reinterpret_cast<uint16_t *>(w + p.o_lab), err,
-                                           stream))))
+        if ((rc = hip_rc(launch_pack_group(batch->labels, p.n, d, labmat, err, stream)))) return rc;
+        if ((rc = hip_rc(launch_pack_group_hot(csr->hot_ids, p.n_hot, p.n, d.Gs, labmat, labhot, g.rsd, g.lap ? rsdhot : nullptr, err,
+                                               stream))))
             return rc;
-        if ((rc = hip_rc(launch_group_scale(inv, g.d, reinterpret_cast<double *>(w + p.o_scale), stream)))) return rc;
+        if ((rc = hip_rc(launch_group_cols(inv, d, cscale, vmeta, stream)))) return rc;
         if ((rc = hip_rc(launch_pull_group(g, stream)))) return rc;
     }
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;

@@ -2,14 +2,21 @@
 // of the CSR.
 //
 // Algorithm 1 (Section II of the paper) is a single pass over the edges for one
-// label vector. For B vectors on the same graph the pass is shared: the vectors
-// of a group (up to 64, all adjacency or all Laplacian) are stored transposed, one
-// row of 16-bit labels per vertex, so one gather of a neighbour's label row (one
-// 128-byte line for 64 vectors) serves every vector of the group. A block of 256
-// threads owns a segment of the merge-path split (rows + entries), accumulates the
-// bins of a window of rows for all vectors of the group in LDS, and writes each
-// row's group columns of Z once. Rows cut by segment boundaries are summed from
-// FP64 partials in segment order, as in the single-vector pull pass.
+// label vector. For B vectors on the same graph the pass is shared. The vectors of
+// a group (up to 64, any mix of adjacency and Laplacian) are stored transposed: one
+// row of 16-bit labels per vertex, so one 128-byte line holds a vertex's labels in
+// all 64 vectors. Hot vertices (the CSR's hot slots) get a compact copy of their
+// rows, addressed by slot, so an entry whose column is a slot needs no id lookup.
+//
+// One wavefront owns a segment of the merge-path split (rows + entries). Lane b is
+// vector b: for every entry (u, v) of a row the wave reads v's label row with one
+// coalesced load and lane b adds the entry's weight into its own bin
+// (u, coff_b + Y_b(v) - 1) in LDS. The bins of different lanes are disjoint, so the
+// adds need no atomicity, and every bin receives its terms in CSR order: the FP64
+// sums are deterministic. A finished row is scaled and written to Z once. Rows cut
+// by segment boundaries are summed from FP64 partials in segment order.
+
+#include <type_traits>
 
 #include "common.h"
 #include "launch.h"
@@ -18,9 +25,11 @@ namespace gee {
 
 namespace {
 
-constexpr int kBT = 256;               // threads per block
-constexpr int kMaxGroup = 64;          // vectors per group
-constexpr size_t kBatchLds = 48 * 1024; // bins of a window (per block)
+constexpr int kBT = 256;      // threads per block of the helper kernels
+constexpr int kCW = 32;       // entries per chunk (a chunk never spans two rows)
+constexpr int kMaxWavesPerBlock = 8;
+constexpr uint32_t kNoVec = 0xffffffffu;
+typedef __attribute__((address_space(1))) const uint16_t global_u16;
 
 inline int grid_cap(int64_t items, int per_block)
 {
@@ -31,8 +40,9 @@ inline int grid_cap(int64_t items, int per_block)
 }
 
 // labmat[v * Gs + b] = label of vertex v in vector b of the group (0 for a label
-// outside [0, K_b] and for the padding columns b >= G). A 64 x 64 tile goes
-// through LDS so both the read (along v) and the write (along b) are coalesced.
+// outside [0, K_b] and for the padding columns b >= G); row n is all zeros and is
+// where invalid column ids point. A 64 x 64 tile goes through LDS so both the read
+// (along v) and the write (along b) are coalesced.
 __global__ void __launch_bounds__(kBT)
 k_pack_group(const int32_t *__restrict__ labels, int64_t n, GroupDesc d, uint16_t *__restrict__ labmat, int32_t *err)
 {
@@ -56,15 +66,52 @@ k_pack_group(const int32_t *__restrict__ labels, int64_t n, GroupDesc d, uint16_
         const int64_t v = v0 + r;
         if (v < n && tx < d.Gs) labmat[v * d.Gs + tx] = tile[r][tx];
     }
+    if (blockIdx.x == 0 && threadIdx.x < d.Gs) labmat[n * d.Gs + threadIdx.x] = 0;
     if (bad) flag_error(err, GEE_ELABEL);
 }
 
-// scale[coff_b + k] = 1 / n_{b,k+1} for the group's columns (inv tables of each vector).
-__global__ void k_group_scale(const double *__restrict__ inv_all, GroupDesc d, double *__restrict__ scale)
+// Hot rows in slot order: labhot[s] = labmat[hot_ids[s]] (8 labels per thread), and
+// for a group with Laplacian vectors rsdhot[s] = d^-1/2 of that vertex.
+__global__ void __launch_bounds__(kBT)
+k_pack_group_hot(const int32_t *__restrict__ hot_ids, int64_t n_hot, int64_t n, int Gs,
+                 const uint16_t *__restrict__ labmat, uint16_t *__restrict__ labhot, const float *__restrict__ rsd,
+                 float *__restrict__ rsdhot, int32_t *err)
+{
+    const int pieces = Gs / 8;
+    const int64_t total = n_hot * pieces;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = i / pieces;
+        const int p = (int)(i - s * pieces);
+        int64_t v = hot_ids[s];
+        if ((uint64_t)v >= (uint64_t)n) {
+            bad = true;
+            v = n; // the zero row
+        }
+        const uint4 q = *reinterpret_cast<const uint4 *>(labmat + v * Gs + p * 8);
+        *reinterpret_cast<uint4 *>(labhot + s * Gs + p * 8) = q;
+        if (rsdhot && p == 0) rsdhot[s] = v < n ? rsd[v] : 0.0f;
+    }
+    if (bad) flag_error(err, GEE_EVERTEX);
+}
+
+// Per column f of the group: cscale[f] = 1 / n_{b,k+1}, negated (sign bit set, also
+// for a zero) when vector b is a Laplacian one. Per lane: vmeta[b] = coff_b |
+// (Laplacian << 31), kNoVec for the lanes b >= G.
+__global__ void k_group_cols(const double *__restrict__ inv_all, GroupDesc d, double *__restrict__ cscale,
+                             uint32_t *__restrict__ vmeta)
 {
     const int b = blockIdx.x;
-    if (b >= d.G) return;
-    for (int k = threadIdx.x; k < d.K[b]; k += blockDim.x) scale[d.coff[b] + k] = inv_all[d.inv_off[b] + k + 1];
+    if (b == d.G) {
+        for (int t = d.G + threadIdx.x; t < kGroupMax; t += blockDim.x) vmeta[t] = kNoVec;
+        return;
+    }
+    const bool lap = d.lap[b] != 0;
+    for (int k = threadIdx.x; k < d.K[b]; k += blockDim.x) {
+        const double inv = inv_all[d.inv_off[b] + k + 1];
+        cscale[d.coff[b] + k] = lap ? -inv : inv;
+    }
+    if (threadIdx.x == 0) vmeta[b] = (uint32_t)d.coff[b] | (lap ? 0x80000000u : 0u);
 }
 
 struct BatchSeg {
@@ -88,106 +135,258 @@ __device__ inline BatchSeg batch_seg(int64_t j, int64_t n, const int64_t *__rest
     return s;
 }
 
-template <bool WIDE> struct GBins;
-template <> struct GBins<false> { // unit-weight adjacency: integer counts
-    using word = uint32_t;
-    __device__ static void add(word *p, double) { atomicAdd(p, 1u); }
-};
-template <> struct GBins<true> { // weighted or Laplacian: FP64 sums
-    using word = double;
-    __device__ static void add(word *p, double x) { atomicAdd(p, x); }
+__device__ inline int64_t readlane64(int64_t x, int l)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)x >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ inline float readlanef(float x, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// Factor of a bin in Z: 1 / n_k, times the row's d^-1/2 for a Laplacian column
+// (sign bit of the stored scale). Same expression, x * (inv * r_u), as the
+// single-vector pass, with r_u = 1 for adjacency columns.
+__device__ inline double column_scale(double s, double ru)
+{
+    return __double_as_longlong(s) < 0 ? (-s) * ru : s * 1.0;
+}
+
+// The chunk iterator and the row window are scalar (wave-uniform) state.
+struct Chunk {
+    int64_t u = 0, e = 0; // row, first entry
+    int m = 0;            // entries (1..kCW)
+    bool last = false;    // the chunk ends the row's entries in this segment
 };
 
-// One block per segment. The window's rows have bins [RW][KT] in LDS (KT = sum of
-// K_b over the group). Each thread takes one entry at a time: it finds the entry's
-// row by a binary search over the window's row starts, gathers the neighbour's
-// label row (G 16-bit labels, 16 bytes per load) and adds 1 (or w, times the
-// neighbour's d^-1/2 for a Laplacian group) into bin (row, col_off[b] + y_b - 1)
-// for every vector b with y_b > 0.
-template <bool WIDE, bool LAP, bool W>
-__global__ void __launch_bounds__(kBT)
-k_pull_group(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-             const float *__restrict__ val, const int32_t *__restrict__ hot_ids, int64_t n_hot,
-             const uint16_t *__restrict__ labmat, GroupDesc d, const double *__restrict__ scale, const float *__restrict__ rsd, const int32_t *__restrict__ seg_i,
-             const int64_t *__restrict__ seg_e, int64_t nseg, int RW, float *__restrict__ Z, int64_t ldz,
-             int64_t zcol, double *__restrict__ part, int32_t *err)
+// One wavefront per segment. Lane b accumulates vector b's bins of the current row
+// (bins[coff_b .. coff_b + K_b), FP64, private to the lane). Entries are taken in
+// chunks of up to kCW entries of one row; the labels of chunk k+1 and the column
+// ids of chunk k+2 are in flight while chunk k is added and its row written. The
+// row writes read nothing from global memory (column scales sit in LDS, shared by
+// the block's wavefronts; row ends and d^-1/2 in a 64-row register window), so they
+// never wait on those loads.
+template <bool W, bool LAP>
+__global__ void __launch_bounds__(kWave * kMaxWavesPerBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_batch_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+             const float *__restrict__ val, int64_t n_hot, const uint16_t *__restrict__ labmat,
+             const uint16_t *__restrict__ labhot, int Gs, const float *__restrict__ rsd,
+             const float *__restrict__ rsdhot, const uint32_t *__restrict__ vmeta, const double *__restrict__ cscale,
+             int KT, const int32_t *__restrict__ seg_i, const int64_t *__restrict__ seg_e, int64_t nseg,
+             float *__restrict__ Z, int64_t ldz, int64_t zcol, double *__restrict__ part, int32_t *err)
 {
-    using word = typename GBins<WIDE>::word;
-    extern __shared__ __align__(16) unsigned char smem[];
-    word *bins = (word *)smem;
-    const int KT = d.KT, G = d.G;
-    int32_t *cs = (int32_t *)(smem + align_up((size_t)RW * KT * sizeof(word), 16));
-    int32_t *coff = cs + (kMaxGroup + 2);
-    const int t = threadIdx.x;
-    const int64_t j = blockIdx.x;
+    extern __shared__ __align__(16) double smem_d[];
+    double *tab = smem_d; // [KT] column scales
+    const int nw = blockDim.x / kWave;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); // uniform per wavefront
+    const int lane = threadIdx.x % kWave;
+    // per wavefront: KT bins, then one sink bin per lane (target of unknown labels)
+    double *bins = smem_d + (size_t)KT + (size_t)(KT + kWave) * wid;
+    for (int f = threadIdx.x; f < KT; f += blockDim.x) tab[f] = cscale[f];
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * nw + wid;
     if (j >= nseg) return;
     const BatchSeg sg = batch_seg(j, n, row_ptr, seg_i, seg_e);
-    for (int b = t; b < G; b += kBT) coff[b] = d.coff[b];
-    for (int i = t; i < RW * KT; i += kBT) bins[i] = (word)0;
-    __syncthreads();
+    const uint32_t vm = vmeta[lane];
+    const bool vvalid = vm != kNoVec;
+    const int boff = (int)(vm & 0x7fffffffu) - 1; // bin of class y is boff + y
+    const bool vlap = LAP && vvalid && (vm >> 31) != 0;
+    const int lsrc = lane < Gs ? lane : Gs - 1;
+    for (int f = lane; f < KT + kWave; f += kWave) bins[f] = 0.0;
+    const int sink = KT + lane;
     bool bad = false;
 
-    for (int64_t r = sg.i0; r < sg.rend; r += RW) {
-        const int nr = (int)((sg.rend - r) < RW ? (sg.rend - r) : RW);
-        if (t <= nr) {
-            int64_t p = row_ptr[r + t];
-            p = p < sg.e0 ? sg.e0 : (p > sg.e1 ? sg.e1 : p);
-            cs[t] = (int32_t)(p - sg.e0);
+    // row window: lane i holds the end of row wb + i
+    int64_t cu = sg.i0, ce = sg.e0, wb = sg.i0;
+    int64_t win;
+    auto load_window = [&]() __attribute__((always_inline)) {
+        const int64_t r = wb + lane + 1;
+        win = row_ptr[r < n ? r : n];
+    };
+    load_window();
+    auto next_chunk = [&](Chunk &c) __attribute__((always_inline)) -> bool {
+        while (cu < sg.rend) {
+            if (cu - wb >= kWave) {
+                wb = cu;
+                load_window();
+            }
+            int64_t re = readlane64(win, (int)(cu - wb));
+            re = re < sg.e1 ? re : sg.e1;
+            if (ce < re) {
+                const int64_t left = re - ce;
+                c.u = cu;
+                c.e = ce;
+                c.m = (int)(left < kCW ? left : kCW);
+                c.last = c.m == left;
+                ce += c.m;
+                return true;
+            }
+            ++cu;
         }
-        __syncthreads();
-        const int32_t ws = cs[0], we = cs[nr];
-        for (int32_t q = ws + t; q < we; q += kBT) {
-            int lo = 0, hi = nr; // cs[lo] <= q < cs[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (cs[mid] <= q) lo = mid;
-                else hi = mid;
-            }
-            const int64_t e = sg.e0 + q;
-            int32_t c = col[e];
-            if (c < 0) {
-                const int64_t slot = (int64_t)((uint32_t)c & 0x7fffffffu);
-                c = slot < n_hot ? hot_ids[slot] : -1;
-            }
-            if ((uint32_t)c >= (uint64_t)n) {
-                bad = true;
-                continue;
-            }
-            double inc = W ? (double)val[e] : 1.0;
-            if (LAP) inc *= (double)rsd[c];
-            word *rowbins = bins + (size_t)lo * KT;
-            const uint16_t *lr = labmat + (int64_t)c * d.Gs;
-            for (int b0 = 0; b0 < G; b0 += 8) {
-                // eight 16-bit labels per 16-byte load (rows padded to a multiple of 8 labels)
-                const uint4 q4 = *reinterpret_cast<const uint4 *>(lr + b0);
-                const uint32_t wv[4] = {q4.x, q4.y, q4.z, q4.w};
+        return false;
+    };
+    // column id (and weight) of entry c.e + lane, lanes past the chunk repeating its
+    // last entry; before them (Laplacian) the d^-1/2 of the chunk's row
+    // (the row factor is a vector load: a scalar load would make every later LDS read
+    // wait for it, since scalar loads complete out of order on the same counter)
+    int32_t vzero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+    auto load_cols = [&](const Chunk &c, int32_t &cv, float &wv, float &rq) __attribute__((always_inline)) {
+        if (LAP) rq = rsd[c.u + vzero];
+        const int64_t e = c.e + (lane < c.m ? lane : c.m - 1);
+        cv = col[e];
+        if (W) wv = val[e];
+    };
+    // label row of every entry of the chunk (lane b: vector b); per entry (lane j) its
+    // weight and the neighbour's d^-1/2
+    auto issue_labels = [&](int32_t cv, int m, float wv, float rq, uint16_t (&lab)[kCW], float &ia, float &rv,
+                            float &ru) __attribute__((always_inline)) {
+        if (W) ia = wv;
+        if (LAP) ru = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rq)));
+        const bool hot = cv < 0;
+        const int64_t slot = (int64_t)((uint32_t)cv & 0x7fffffffu);
+        const bool ok = hot ? slot < n_hot : cv < n;
+        bad |= !ok;
+        const int32_t c = ok ? cv : (int32_t)n; // the zero row
+        if (LAP) {
+            const float *rp = !ok ? rsd : (hot ? rsdhot + slot : rsd + c); // one load on every path
+            const float r = *rp;
+            rv = ok ? r : 0.0f;
+        }
+        // row address per entry (lane j), then per entry one scalar address and one
+        // coalesced load; in groups of 8 under a wave-uniform guard (all of them are
+        // complete by the time the next step's wait for its column ids returns)
+        const uint16_t *rowp = hot && ok ? labhot + slot * Gs : labmat + (int64_t)c * Gs;
+        const uint32_t ralo = (uint32_t)(uintptr_t)rowp, rahi = (uint32_t)((uintptr_t)rowp >> 32);
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int b = b0 + i;
-                    const uint32_t y = (wv[i >> 1] >> (16 * (i & 1))) & 0xffffu;
-                    if (b < G && y > 0) GBins<WIDE>::add(&rowbins[coff[b] + (int)y - 1], inc);
+        for (int q0 = 0; q0 < kCW; q0 += 8) {
+            if (q0 < m) {
+#pragma unroll
+                for (int q = q0; q < q0 + 8; ++q) {
+                    const uint64_t sa = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(rahi, q) << 32) |
+                                        (uint64_t)(uint32_t)__builtin_amdgcn_readlane(ralo, q);
+                    lab[q] = reinterpret_cast<const global_u16 *>(sa)[lsrc]; // global, not flat
                 }
+            } else {
+#pragma unroll
+                for (int q = q0; q < q0 + 8; ++q) lab[q] = 0;
             }
         }
-        __syncthreads();
-        // write the window's rows: group columns [zcol, zcol + KT) of each row
-        const bool head_here = sg.carried && r == sg.i0;
-        const bool tail_here = sg.tail && sg.i1 >= r && sg.i1 < r + nr;
-        for (int l = 0; l < nr; ++l) {
-            const int64_t u = r + l;
-            const bool head = head_here && l == 0, tail = tail_here && u == sg.i1;
-            const double ru = LAP ? (double)rsd[u] : 1.0;
-            for (int f = t; f < KT; f += kBT) {
-                const double x = (double)bins[(size_t)l * KT + f];
-                if (head) part[(2 * j) * KT + f] = x;
-                else if (tail) part[(2 * j + 1) * KT + f] = x;
-                else __builtin_nontemporal_store((float)(x * (scale[f] * ru)), &Z[u * ldz + zcol + f]);
+    };
+    auto consume = [&](const Chunk &c, const uint16_t (&lab)[kCW], float ia, float rv) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < kCW; ++q) {
+            if (q < c.m) {
+                double inc = 1.0;
+                if (W) inc = (double)readlanef(ia, q);
+                if (LAP) {
+                    const double il = inc * (double)readlanef(rv, q);
+                    inc = vlap ? il : inc;
+                }
+                const uint32_t y = lab[q];
+                const int at = (vvalid && y != 0) ? boff + (int)y : sink; // no branch, no exec change
+                atomicAdd(&bins[at], inc);
             }
         }
-        __syncthreads();
-        for (int i = t; i < nr * KT; i += kBT) bins[i] = (word)0;
-        __syncthreads();
+    };
+    // row u's bins scaled by 1 / n_k (and, Laplacian columns, the row's d^-1/2 ru);
+    // rows without entries hold zeros and take ru = 1
+    auto flush = [&](int64_t u, double ru) __attribute__((always_inline)) {
+        const bool head = sg.carried && u == sg.i0;
+        const bool tail = sg.tail && u == sg.i1;
+        if (head || tail) { // a split row: its FP64 partial, merged later in segment order
+            double *pr = part + (2 * j + (tail ? 1 : 0)) * KT;
+            for (int f = lane; f < KT; f += kWave) {
+                pr[f] = bins[f];
+                bins[f] = 0.0;
+            }
+            return;
+        }
+        float *zr = Z + u * ldz + zcol;
+        constexpr int U = 4; // columns per lane per pass
+        int f0 = lane;
+        for (; f0 + (U - 1) * kWave < KT; f0 += U * kWave) {
+            double x[U], t[U];
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                x[i] = bins[f0 + i * kWave];
+                t[i] = tab[f0 + i * kWave];
+            }
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                bins[f0 + i * kWave] = 0.0;
+                __builtin_nontemporal_store((float)(x[i] * column_scale(t[i], ru)), zr + f0 + i * kWave);
+            }
+        }
+        for (; f0 < KT; f0 += kWave) {
+            const double x = bins[f0];
+            bins[f0] = 0.0;
+            __builtin_nontemporal_store((float)(x * column_scale(tab[f0], ru)), zr + f0);
+        }
+    };
+    // a row with no entries in this segment: zeros, without touching its bins
+    auto flush_empty = [&](int64_t u) __attribute__((always_inline)) {
+        const bool head = sg.carried && u == sg.i0;
+        const bool tail = sg.tail && u == sg.i1;
+        if (head || tail) {
+            flush(u, 1.0);
+            return;
+        }
+        float *zr = Z + u * ldz + zcol;
+        int f = lane;
+        for (; f + 3 * kWave < KT; f += 4 * kWave) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) __builtin_nontemporal_store(0.0f, zr + f + i * kWave);
+        }
+        for (; f < KT; f += kWave) __builtin_nontemporal_store(0.0f, zr + f);
+    };
+
+    int64_t fr = sg.i0; // next row to write
+    Chunk ck;
+    bool have = next_chunk(ck);
+    // Loads are issued unconditionally (a missing next chunk repeats the current
+    // one) so the number of loads in flight is the same on every path, and loaded
+    // registers are never copied (a copy would wait for the load): the two register
+    // slots alternate between chunk k (being added) and chunk k + 1 (in flight).
+    Chunk cn = ck;
+    bool haven = have && next_chunk(cn);
+    int32_t cv[2];
+    float wv[2] = {0.f, 0.f}, rq[2] = {0.f, 0.f}, ia[2] = {0.f, 0.f}, rv[2] = {0.f, 0.f}, ru[2] = {1.f, 1.f};
+    uint16_t lab[2][kCW];
+    if (have) {
+        load_cols(ck, cv[0], wv[0], rq[0]);
+        issue_labels(cv[0], ck.m, wv[0], rq[0], lab[0], ia[0], rv[0], ru[0]);
+        load_cols(cn, cv[1], wv[1], rq[1]);
     }
+    // Chunk k sits in slot S (labels in lab[S]), chunk k + 1's column ids in cv[T]:
+    // issue chunk k + 1's labels, then chunk k + 2's column ids into the free slot,
+    // then add chunk k and write finished rows while both are in flight.
+    auto step = [&](auto slot) __attribute__((always_inline)) {
+        constexpr int S = decltype(slot)::value, T = 1 - S;
+        issue_labels(cv[T], cn.m, wv[T], rq[T], lab[T], ia[T], rv[T], ru[T]);
+        Chunk cnn = cn;
+        const bool havenn = haven && next_chunk(cnn);
+        load_cols(cnn, cv[S], wv[S], rq[S]); // chunk k + 2
+        for (; fr < ck.u; ++fr) flush_empty(fr); // rows without entries in this segment
+        consume(ck, lab[S], ia[S], rv[S]);
+        if (ck.last) {
+            flush(ck.u, (double)ru[S]);
+            fr = ck.u + 1;
+        }
+        ck = cn;
+        have = haven;
+        cn = cnn;
+        haven = havenn;
+    };
+    while (have) {
+        step(std::integral_constant<int, 0>());
+        if (!have) break;
+        step(std::integral_constant<int, 1>());
+    }
+    for (; fr < sg.rend; ++fr) flush_empty(fr);
     if (bad) flag_error(err, GEE_EVERTEX);
 }
 
@@ -196,7 +395,7 @@ k_pull_group(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const 
 template <bool LAP>
 __global__ void __launch_bounds__(kBT)
 k_merge_group(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ seg_i,
-              const int64_t *__restrict__ seg_e, int64_t nseg, int KT, const double *__restrict__ scale,
+              const int64_t *__restrict__ seg_e, int64_t nseg, int KT, const double *__restrict__ cscale,
               const float *__restrict__ rsd, const double *__restrict__ part, float *__restrict__ Z, int64_t ldz,
               int64_t zcol)
 {
@@ -212,7 +411,7 @@ k_merge_group(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__r
             acc += part[(2 * jj) * KT + f];
             if (seg_i[jj + 1] > u) break;
         }
-        Z[u * ldz + zcol + f] = (float)(acc * (scale[f] * ru));
+        Z[u * ldz + zcol + f] = (float)(acc * column_scale(cscale[f], ru));
     }
 }
 
@@ -226,17 +425,14 @@ __global__ void k_rsd(const double *__restrict__ deg, int64_t n, float *__restri
 
 } // namespace
 
-size_t batch_window_bytes(int KT, bool wide, int rw)
+int batch_waves_per_block(int KT)
 {
-    return align_up((size_t)rw * KT * (wide ? 8 : 4), 16) + (size_t)(2 * kMaxGroup + 4) * 4;
+    // one scale table of KT doubles, then KT bins + one sink per lane for each wavefront
+    const int fit = (int)((kBatchLdsBytes / sizeof(double) - (size_t)KT) / (size_t)(KT + kWave));
+    return fit < 1 ? 0 : (fit < kMaxWavesPerBlock ? fit : kMaxWavesPerBlock);
 }
 
-int batch_rows_per_window(int KT, bool wide)
-{
-    int rw = 64;
-    while (rw > 1 && batch_window_bytes(KT, wide, rw) > kBatchLds) --rw;
-    return batch_window_bytes(KT, wide, rw) <= 65536 ? rw : 0;
-}
+size_t batch_lds_bytes(int KT, int nw) { return sizeof(double) * ((size_t)KT + (size_t)(KT + kWave) * (size_t)nw); }
 
 hipError_t launch_pack_group(const int32_t *labels, int64_t n, const GroupDesc &d, uint16_t *labmat, int32_t *err,
                              hipStream_t s)
@@ -245,9 +441,19 @@ hipError_t launch_pack_group(const int32_t *labels, int64_t n, const GroupDesc &
     return hipGetLastError();
 }
 
-hipError_t launch_group_scale(const double *inv_all, const GroupDesc &d, double *scale, hipStream_t s)
+hipError_t launch_pack_group_hot(const int32_t *hot_ids, int64_t n_hot, int64_t n, int Gs, const uint16_t *labmat,
+                                 uint16_t *labhot, const float *rsd, float *rsdhot, int32_t *err, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_group_scale, dim3(d.G), dim3(256), 0, s, inv_all, d, scale);
+    if (n_hot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_group_hot, dim3(grid_cap(n_hot * (Gs / 8), kBT * 4)), dim3(kBT), 0, s, hot_ids, n_hot,
+                       n, Gs, labmat, labhot, rsd, rsdhot, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_cols(const double *inv_all, const GroupDesc &d, double *cscale, uint32_t *vmeta,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_group_cols, dim3(d.G + 1), dim3(256), 0, s, inv_all, d, cscale, vmeta);
     return hipGetLastError();
 }
 
@@ -259,28 +465,30 @@ hipError_t launch_rsd(const double *deg, int64_t n, float *rsd, hipStream_t s)
 
 hipError_t launch_pull_group(const GroupArgs &g, hipStream_t s)
 {
-    const bool wide = g.lap || g.val;
-    const size_t lds = batch_window_bytes(g.d.KT, wide, g.rw);
-#define GEE_GROUP(WIDE, LAP, W)                                                                                      \
-    hipLaunchKernelGGL((k_pull_group<WIDE, LAP, W>), dim3((unsigned)g.nseg), dim3(kBT), lds, s, g.n, g.nnz, g.row_ptr, \
-                       g.col, g.val, g.hot_ids, g.n_hot, g.labmat, g.d, g.scale, g.rsd, g.seg_i, g.seg_e, g.nseg,    \
-                       g.rw, g.Z, g.ldz, g.zcol, g.part, g.err)
+    const int nw = batch_waves_per_block(g.KT);
+    if (nw < 1) return hipErrorInvalidValue;
+    const size_t lds = batch_lds_bytes(g.KT, nw);
+    const unsigned blocks = (unsigned)((g.nseg + nw - 1) / nw);
+#define GEE_GROUP(W, LAP)                                                                                            \
+    hipLaunchKernelGGL((k_batch_pull<W, LAP>), dim3(blocks), dim3(kWave * nw), lds, s, g.n, g.row_ptr, g.col,        \
+                       g.val, g.n_hot, g.labmat, g.labhot, g.Gs, g.rsd, g.rsdhot, g.vmeta, g.cscale, g.KT, g.seg_i,  \
+                       g.seg_e, g.nseg, g.Z, g.ldz, g.zcol, g.part, g.err)
     if (g.lap) {
-        if (g.val) GEE_GROUP(true, true, true);
-        else GEE_GROUP(true, true, false);
+        if (g.val) GEE_GROUP(true, true);
+        else GEE_GROUP(false, true);
     } else {
-        if (g.val) GEE_GROUP(true, false, true);
-        else GEE_GROUP(false, false, false);
+        if (g.val) GEE_GROUP(true, false);
+        else GEE_GROUP(false, false);
     }
 #undef GEE_GROUP
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (g.lap)
         hipLaunchKernelGGL(k_merge_group<true>, dim3((unsigned)g.nseg), dim3(kBT), 0, s, g.n, g.row_ptr, g.seg_i,
-                           g.seg_e, g.nseg, g.d.KT, g.scale, g.rsd, g.part, g.Z, g.ldz, g.zcol);
+                           g.seg_e, g.nseg, g.KT, g.cscale, g.rsd, g.part, g.Z, g.ldz, g.zcol);
     else
         hipLaunchKernelGGL(k_merge_group<false>, dim3((unsigned)g.nseg), dim3(kBT), 0, s, g.n, g.row_ptr, g.seg_i,
-                           g.seg_e, g.nseg, g.d.KT, g.scale, g.rsd, g.part, g.Z, g.ldz, g.zcol);
+                           g.seg_e, g.nseg, g.KT, g.cscale, g.rsd, g.part, g.Z, g.ldz, g.zcol);
     return hipGetLastError();
 }
 

@@ -53,44 +53,54 @@ hipError_t launch_merge(const EmbedArgs &a, const int64_t *row_ptr, const int32_
                         int64_t nseg, const double *part, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 
-// Batched pull: one group of up to 64 label vectors of the same variant whose
-// column blocks tile the contiguous columns [zcol, zcol + KT) of Z.
+// Batched pull: one group of up to 64 label vectors (any mix of adjacency and
+// Laplacian) whose column blocks are contiguous in Z, embedded in one pass of the
+// CSR. Group column f in [0, KT) is class f - coff_b + 1 of the vector b with
+// coff_b <= f < coff_b + K_b, and Z column zcol + f.
 constexpr int kGroupMax = 64;
+constexpr int kBatchMaxKT = 4096;               // classes of one group: KT FP64 bins per wavefront
+constexpr size_t kBatchLdsBytes = 160 * 1024;   // LDS of one block: column scales + bins of each wavefront
 struct GroupDesc {
     int G = 0;                  // vectors in the group
     int Gs = 0;                 // label-matrix row stride (G rounded up to 8)
     int KT = 0;                 // sum of K over the group
     int32_t vec[kGroupMax];     // index of each vector in the caller's batch
     int32_t K[kGroupMax];       // classes of each vector
-    int32_t coff[kGroupMax];    // first column of each vector, relative to zcol
+    int32_t coff[kGroupMax];    // first group column of each vector
+    int64_t zoff[kGroupMax];    // first Z column of each vector
     int64_t inv_off[kGroupMax]; // offset of each vector's inv table in the batch's inv array
+    uint8_t lap[kGroupMax];     // 1: Laplacian version
 };
 struct GroupArgs {
-    int64_t n = 0, nnz = 0;
+    int64_t n = 0;
     const int64_t *row_ptr = nullptr;
     const int32_t *col = nullptr;
     const float *val = nullptr;
-    const int32_t *hot_ids = nullptr;
     int64_t n_hot = 0;
-    const uint16_t *labmat = nullptr;
-    GroupDesc d;
-    const double *scale = nullptr;
-    const float *rsd = nullptr;
+    const uint16_t *labmat = nullptr; // [(n + 1) * Gs]
+    const uint16_t *labhot = nullptr; // [n_hot * Gs]
+    int Gs = 0, KT = 0;
+    const float *rsd = nullptr;       // [n], Laplacian groups
+    const float *rsdhot = nullptr;    // [n_hot], Laplacian groups
+    const uint32_t *vmeta = nullptr;  // [64]
+    const double *cscale = nullptr;   // [KT]
     const int32_t *seg_i = nullptr;
     const int64_t *seg_e = nullptr;
     int64_t nseg = 0;
-    int rw = 0;
     float *Z = nullptr;
     int64_t ldz = 0, zcol = 0;
     double *part = nullptr;
     int32_t *err = nullptr;
-    bool lap = false;
+    bool lap = false; // the group holds Laplacian vectors
 };
-size_t batch_window_bytes(int KT, bool wide, int rw);
-int batch_rows_per_window(int KT, bool wide); // 0: the group's bins do not fit
+int batch_waves_per_block(int KT); // wavefronts whose bins fit one block's LDS beside the scale table
+size_t batch_lds_bytes(int KT, int nw);
 hipError_t launch_pack_group(const int32_t *labels, int64_t n, const GroupDesc &d, uint16_t *labmat, int32_t *err,
                              hipStream_t s);
-hipError_t launch_group_scale(const double *inv_all, const GroupDesc &d, double *scale, hipStream_t s);
+hipError_t launch_pack_group_hot(const int32_t *hot_ids, int64_t n_hot, int64_t n, int Gs, const uint16_t *labmat,
+                                 uint16_t *labhot, const float *rsd, float *rsdhot, int32_t *err, hipStream_t s);
+hipError_t launch_group_cols(const double *inv_all, const GroupDesc &d, double *cscale, uint32_t *vmeta,
+                             hipStream_t s);
 hipError_t launch_rsd(const double *deg, int64_t n, float *rsd, hipStream_t s);
 hipError_t launch_pull_group(const GroupArgs &g, hipStream_t s);
 

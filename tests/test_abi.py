@@ -137,7 +137,9 @@ def test_batch_argument_errors(lib):
     assert ws([5, 7], [0, 0], [0, 5], 11) == 0  # block past ldz
     assert ws([5, 7], [0, 0], [0, 4], 20) == 0  # overlapping blocks
     assert ws([0, 7], [0, 0], [0, 5], 20) == 0  # K < 1
-    assert ws([4097], [0], [0], 5000) == 0  # K above the batched limit
+    assert ws([4097], [0], [0], 5000) == 0  # K above the batched limit (one group's classes)
+    assert ws([4096], [1], [0], 4096) > 0
+    assert ws([5], [0], [0], 1 << 31) == 0  # Z column ids must fit 32 bits
     assert ws([5, 7], [0, 0], [7, 0], 20) > 0  # any column order
     big = ws([50] * 64, [0] * 64, [50 * i for i in range(64)], 3200)
     lap = ws([50] * 64, [1] * 64, [50 * i for i in range(64)], 3200)

@@ -120,3 +120,21 @@ def test_batch_errors():
         gee.embed_batch(torch.as_tensor(Y).to(DEV), [4, 4], [False, False], csr, zoff=[0, 2],
                         Z=torch.empty((n, 8), device=DEV))
     assert e.value.code == gee.GEE_EINVAL
+
+
+def test_group_at_the_class_limit():
+    """4096 classes in one group (the LDS limit of a group): two mixed-version vectors,
+    then one vector alone; blocks equal the single calls / oracle."""
+    n, src, dst, w = _graph(False, seed=56, scale=12, ef=6, hub=500)
+    rng = np.random.default_rng(11)
+    csr = gee.csr_build(gee.to_device(n, src, dst, w, device=DEV), hot_budget=300)
+    for Ks, laps in (([2000, 2096], [True, False]), ([4096], [False])):
+        Y = _labels(rng, n, Ks)
+        Z, zoff = gee.embed_batch(torch.as_tensor(Y).to(DEV), Ks, laps, csr, seg_len=512)
+        Zh = Z.cpu().numpy()
+        for b, (K, lap) in enumerate(zip(Ks, laps)):
+            blk = Zh[:, zoff[b]:zoff[b] + K]
+            if not lap:
+                Zs = gee.embed(torch.as_tensor(Y[b]).to(DEV), K, csr=csr, seg_len=512).cpu().numpy()
+                assert np.array_equal(blk.view(np.uint32), Zs.view(np.uint32)), b
+            assert_parity(blk, oracle.embed(n, src, dst, w, Y[b], K, lap), what=f"K={K} lap={lap}")
