@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "k_pull_rmat27_counters.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2402_04403_amd", "csrc", "embed.hip")
-PROFILE_COUNTERS_BATCH = os.path.join(ROOT, "profiles", "k_pull_group_rmat24_b64_counters.json")
+PROFILE_COUNTERS_BATCH = os.path.join(ROOT, "profiles", "k_batch_pull_rmat24_b64_counters.json")
 KERNEL_SOURCE_BATCH = os.path.join(ROOT, "paper_2402_04403_amd", "csrc", "batch.hip")
 
 
@@ -86,6 +86,23 @@ def counters_traffic(launch_bytes_alg, path=PROFILE_COUNTERS, source=KERNEL_SOUR
     return float(c["hbm_bytes_per_launch"]), c
 
 
+def copy_probe(gee, torch, dev):
+    """Attainable streaming bandwidth on this GPU: 5 copies of 4 GiB (read + write bytes / s)."""
+    buf_a = torch.empty(1 << 32, dtype=torch.uint8, device=dev)
+    buf_b = torch.empty_like(buf_a)
+    gee.copy(buf_b, buf_a)
+    c0, c1 = gee.HipEvent(), gee.HipEvent()
+    c0.record()
+    for _ in range(5):
+        gee.copy(buf_b, buf_a)
+    c1.record()
+    c1.synchronize()
+    gbps = 5 * 2 * buf_a.numel() / (c0.elapsed_ms(c1) * 1e-3) / 1e9
+    del buf_a, buf_b
+    torch.cuda.empty_cache()
+    return gbps
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -129,19 +146,7 @@ def main():
     nnz = csr.nnz
     log(f"csr built nnz={nnz} in {csr_ms:.1f} ms")
 
-    # copy probe: attainable streaming bandwidth on this GPU
-    buf_a = torch.empty(1 << 32, dtype=torch.uint8, device=dev)
-    buf_b = torch.empty_like(buf_a)
-    gee.copy(buf_b, buf_a)
-    c0, c1 = gee.HipEvent(), gee.HipEvent()
-    c0.record()
-    for _ in range(5):
-        gee.copy(buf_b, buf_a)
-    c1.record()
-    c1.synchronize()
-    copy_gbps = 5 * 2 * buf_a.numel() / (c0.elapsed_ms(c1) * 1e-3) / 1e9
-    del buf_a, buf_b
-    torch.cuda.empty_cache()
+    copy_gbps = copy_probe(gee, torch, dev)
     log(f"copy probe {copy_gbps:.0f} GB/s")
 
     use_csr = csr if a.form == "pull" else None
@@ -301,6 +306,8 @@ def main_batched(a):
     del coo
     torch.cuda.empty_cache()
     log(f"csr built nnz={nnz} hot={csr.n_hot} in {csr_ms:.1f} ms")
+    copy_gbps = copy_probe(gee, torch, dev)
+    log(f"copy probe {copy_gbps:.0f} GB/s")
 
     zoff, acc = [0] * B, 0
     for b in range(B):
@@ -367,7 +374,7 @@ def main_batched(a):
     traffic, counters = counters_traffic(bytes_alg, PROFILE_COUNTERS_BATCH, KERNEL_SOURCE_BATCH)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "k_pack_group + k_pull_group + k_merge_group (every group)",
+                "kernel": "k_pack_group + k_pack_group_hot + k_group_cols + k_batch_pull + k_merge_group (every group)",
                 "bytes_alg_per_launch": int(bytes_alg), "kernel_ms": round(hot_avg, 4)}
 
     cpu = None
@@ -403,7 +410,7 @@ def main_batched(a):
             "n": n, "s": s, "nnz": nnz, "B": B, "sum_K": KS, "Ks": Ks,
             "versions": "even b adjacency, odd b Laplacian", "layout": "blocks side by side in vector order",
             "seg_len": a.seg_len or 16384, "hot_slots": csr.n_hot, "csr_build_ms": round(csr_ms, 2),
-            "Z_GB": round(n * KS * 4 / 1e9, 2),
+            "Z_GB": round(n * KS * 4 / 1e9, 2), "copy_probe_GBps": round(copy_gbps, 1),
             "plain_ms_per_batch": None if plain_ms is None else round(plain_ms, 3),
             "plain_value": None if plain_ms is None else round(s * B / (plain_ms * 1e-3) / 1e9, 3),
             "speedup_vs_plain": None if plain_ms is None else round(plain_ms / step_ms, 3),
@@ -411,6 +418,8 @@ def main_batched(a):
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if counters is not None:
+        out["config"]["counters_file"] = os.path.relpath(PROFILE_COUNTERS_BATCH, ROOT)
     print(json.dumps(out), flush=True)
 
 

@@ -179,12 +179,13 @@ k_batch_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__re
              float *__restrict__ Z, int64_t ldz, int64_t zcol, double *__restrict__ part, int32_t *err)
 {
     extern __shared__ __align__(16) double smem_d[];
+    const int KTp = (KT + 1) & ~1; // even, so 16-byte LDS accesses of column pairs stay aligned
     double *tab = smem_d; // [KT] column scales
     const int nw = blockDim.x / kWave;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); // uniform per wavefront
     const int lane = threadIdx.x % kWave;
-    // per wavefront: KT bins, then one sink bin per lane (target of unknown labels)
-    double *bins = smem_d + (size_t)KT + (size_t)(KT + kWave) * wid;
+    // per wavefront: KTp bins, then one sink bin per lane (target of unknown labels)
+    double *bins = smem_d + (size_t)KTp + (size_t)(KTp + kWave) * wid;
     for (int f = threadIdx.x; f < KT; f += blockDim.x) tab[f] = cscale[f];
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * nw + wid;
@@ -195,8 +196,8 @@ k_batch_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__re
     const int boff = (int)(vm & 0x7fffffffu) - 1; // bin of class y is boff + y
     const bool vlap = LAP && vvalid && (vm >> 31) != 0;
     const int lsrc = lane < Gs ? lane : Gs - 1;
-    for (int f = lane; f < KT + kWave; f += kWave) bins[f] = 0.0;
-    const int sink = KT + lane;
+    for (int f = lane; f < KTp + kWave; f += kWave) bins[f] = 0.0;
+    const int sink = KTp + lane;
     bool bad = false;
 
     // row window: lane i holds the end of row wb + i
@@ -306,25 +307,34 @@ k_batch_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__re
             return;
         }
         float *zr = Z + u * ldz + zcol;
-        constexpr int U = 4; // columns per lane per pass
-        int f0 = lane;
-        for (; f0 + (U - 1) * kWave < KT; f0 += U * kWave) {
-            double x[U], t[U];
+        // lane l takes column pairs (2l, 2l + 1) + 128 i: one 16-byte LDS read of bins,
+        // one of scales and one 16-byte zeroing write per pair
+        int f0 = 2 * lane;
+        for (; f0 + 1 + kWave * 2 < KT; f0 += 2 * kWave * 2) {
+            double2 x[2], t[2];
 #pragma unroll
-            for (int i = 0; i < U; ++i) {
-                x[i] = bins[f0 + i * kWave];
-                t[i] = tab[f0 + i * kWave];
+            for (int i = 0; i < 2; ++i) {
+                x[i] = *reinterpret_cast<const double2 *>(bins + f0 + i * 2 * kWave);
+                t[i] = *reinterpret_cast<const double2 *>(tab + f0 + i * 2 * kWave);
             }
 #pragma unroll
-            for (int i = 0; i < U; ++i) {
-                bins[f0 + i * kWave] = 0.0;
-                __builtin_nontemporal_store((float)(x[i] * column_scale(t[i], ru)), zr + f0 + i * kWave);
+            for (int i = 0; i < 2; ++i) {
+                const int f = f0 + i * 2 * kWave;
+                *reinterpret_cast<double2 *>(bins + f) = make_double2(0.0, 0.0);
+                __builtin_nontemporal_store((float)(x[i].x * column_scale(t[i].x, ru)), zr + f);
+                __builtin_nontemporal_store((float)(x[i].y * column_scale(t[i].y, ru)), zr + f + 1);
             }
         }
-        for (; f0 < KT; f0 += kWave) {
-            const double x = bins[f0];
-            bins[f0] = 0.0;
-            __builtin_nontemporal_store((float)(x * column_scale(tab[f0], ru)), zr + f0);
+        for (; f0 < KT; f0 += 2 * kWave) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int f = f0 + i;
+                if (f < KT) {
+                    const double x = bins[f];
+                    bins[f] = 0.0;
+                    __builtin_nontemporal_store((float)(x * column_scale(tab[f], ru)), zr + f);
+                }
+            }
         }
     };
     // a row with no entries in this segment: zeros, without touching its bins
@@ -427,12 +437,17 @@ __global__ void k_rsd(const double *__restrict__ deg, int64_t n, float *__restri
 
 int batch_waves_per_block(int KT)
 {
-    // one scale table of KT doubles, then KT bins + one sink per lane for each wavefront
-    const int fit = (int)((kBatchLdsBytes / sizeof(double) - (size_t)KT) / (size_t)(KT + kWave));
+    // one scale table, then bins + one sink per lane for each wavefront (KT rounded up to even)
+    const size_t KTp = (size_t)((KT + 1) & ~1);
+    const int fit = (int)((kBatchLdsBytes / sizeof(double) - KTp) / (KTp + kWave));
     return fit < 1 ? 0 : (fit < kMaxWavesPerBlock ? fit : kMaxWavesPerBlock);
 }
 
-size_t batch_lds_bytes(int KT, int nw) { return sizeof(double) * ((size_t)KT + (size_t)(KT + kWave) * (size_t)nw); }
+size_t batch_lds_bytes(int KT, int nw)
+{
+    const size_t KTp = (size_t)((KT + 1) & ~1);
+    return sizeof(double) * (KTp + (KTp + kWave) * (size_t)nw);
+}
 
 hipError_t launch_pack_group(const int32_t *labels, int64_t n, const GroupDesc &d, uint16_t *labmat, int32_t *err,
                              hipStream_t s)
