@@ -20,7 +20,7 @@ here; these synthetic graphs stand in with comparable shapes):
   weights, and 64 label vectors on it: K_b = floor(exp(U[ln 2, ln 257))) in
   [2, 256], unknown fraction f_b ~ U[0, 0.5) (Bernoulli per vertex), even b the
   adjacency version and odd b the Laplacian version (many label vectors sharing
-  one graph, as in the paper's repeated-label experiments of Section IV).
+  one graph: labels from ground truth or from clusterings, Section II).
 
 The paper's label protocol (Section IV) draws labels uniformly at random; here the
 class of a labelled vertex is uniform over 1..K and a fixed fraction is unknown (0).
