@@ -42,9 +42,12 @@ def log(msg):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--workload", choices=["rmat27", "batched"], default="rmat27",
+    p.add_argument("--workload", choices=["rmat27", "batched", "er-sweep"], default="rmat27",
                    help="rmat27: one label vector on the paper-scale R-MAT (the headline line); "
-                        "batched: 64 label vectors on an R-MAT of scale 24, edge factor 16")
+                        "batched: 64 label vectors on an R-MAT of scale 24, edge factor 16; "
+                        "er-sweep: Erdos-Renyi graphs of growing size (the paper's Fig. 4 family)")
+    p.add_argument("--sweep", default="20,22,24,26,28,30", help="er-sweep: log2 of the record counts")
+    p.add_argument("--sweep-records-per-vertex", type=int, default=16)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--scale", type=int, default=None)
@@ -111,6 +114,8 @@ def main():
         sys.exit(2)
     if a.workload == "batched":
         return main_batched(a)
+    if a.workload == "er-sweep":
+        return main_sweep(a)
 
     import numpy as np
     import torch
@@ -420,6 +425,126 @@ def main_batched(a):
     }
     if counters is not None:
         out["config"]["counters_file"] = os.path.relpath(PROFILE_COUNTERS_BATCH, ROOT)
+    print(json.dumps(out), flush=True)
+
+
+def main_sweep(a):
+    """Erdős–Rényi graphs of growing size (Section IV, Fig. 4: runtime against the number of
+    edges). For each s = 2^k (k in --sweep), n = s / records-per-vertex, grid weights in
+    (0, 1], K = 50 uniform classes with exactly 5% unknown (the er_weighted family). Per size:
+    CSR build, the pull form (adjacency), the push form with atomics, and the push form's
+    atomics-off diagnostic (plain racing updates; wrong results by design, it prices the
+    atomics as the paper's unsafe run did). ``value`` is the pull form's GEdges/s at the
+    largest size; ``config.sweep`` holds every size and ``config.fit`` the least-squares line
+    of pull step time against s."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2402_04403_amd as gee
+
+    dev = torch.device("cuda:0")
+    gee.load()
+    K = 50
+    rows, cpu = [], None
+    for k in [int(x) for x in a.sweep.split(",")]:
+        s = 1 << k
+        n = max(s // a.sweep_records_per_vertex, 1)
+        log2n = n.bit_length() - 1
+        t0 = time.time()
+        wl = gen.er_weighted(log2n=log2n, log2s=k, K=K)
+        g = wl.graph
+        log(f"er 2^{k}: n={g.n} s={g.s} generated in {time.time() - t0:.1f}s")
+        if cpu is None and a.cpu_records > 0 and not a.no_cpu_baseline and k >= 24:
+            import oracle
+
+            c0 = time.perf_counter()
+            oracle.embed(g.n, g.src, g.dst, g.w, wl.labels, K, False)
+            ct = time.perf_counter() - c0
+            cpu = {"value": round(g.s / ct / 1e9, 6), "unit": "GEdges/s", "cores": 1, "kind": "oracle",
+                   "seconds": round(ct, 2),
+                   "sample": f"the whole 2^{k}-record ER graph of the sweep (n = 2^{log2n}, weighted, K = {K}); "
+                             f"FP64 Algorithm 1, one thread"}
+        coo = gee.to_device(g.n, g.src, g.dst, g.w, device=dev)
+        labels = torch.as_tensor(wl.labels).to(dev)
+        del g, wl
+        e0, e1 = gee.HipEvent(), gee.HipEvent()
+        e0.record()
+        csr = gee.csr_build(coo, hot_budget=0, check=False)
+        e1.record()
+        e1.synchronize()
+        csr_ms = e0.elapsed_ms(e1)
+        Z = torch.empty((n, K), dtype=torch.float32, device=dev)
+        err = torch.zeros(1, dtype=torch.int32, device=dev)
+        ws = torch.empty(max(gee.embed_workspace_bytes(K, csr=csr), gee.embed_workspace_bytes(K, coo=coo)),
+                         dtype=torch.uint8, device=dev)
+
+        def timed(fn, steps):
+            fn(None)
+            torch.cuda.synchronize()
+            hot = [(gee.HipEvent(), gee.HipEvent()) for _ in range(steps)]
+            b0, b1 = gee.HipEvent(), gee.HipEvent()
+            b0.record()
+            for i in range(steps):
+                fn(hot[i])
+            b1.record()
+            b1.synchronize()
+            return b0.elapsed_ms(b1) / steps, float(np.mean([x.elapsed_ms(y) for x, y in hot]))
+
+        pull = timed(lambda ev: gee.embed(labels, K, csr=csr, Z=Z, ws=ws, err=err, events=ev, check=False), a.steps)
+        push = timed(lambda ev: gee.embed(labels, K, coo=coo, Z=Z, ws=ws, err=err, events=ev, check=False),
+                     max(a.push_steps, 1))
+        plain = timed(lambda ev: gee.embed_push_nonatomic(labels, K, coo, Z=Z, ws=ws, err=err, events=ev,
+                                                          check=False), max(a.push_steps, 1))
+        if int(err.item()) != 0:
+            raise SystemExit(f"reported error {int(err.item())}")
+        nnz = csr.nnz
+        bytes_alg = 8 * nnz + 8 * (n + 1) + n + 4 * n * K  # col + val per entry, row_ptr, labels, Z
+        rows.append({"log2s": k, "s": s, "n": n, "nnz": nnz, "csr_build_ms": round(csr_ms, 3),
+                     "pull_ms": round(pull[0], 4), "pull_kernel_ms": round(pull[1], 4),
+                     "pull_GEdges_s": round(s / (pull[0] * 1e-3) / 1e9, 3),
+                     "pull_kernel_GBps": round(bytes_alg / (pull[1] * 1e-3) / 1e9, 1),
+                     "push_ms": round(push[0], 4), "push_kernel_ms": round(push[1], 4),
+                     "push_nonatomic_kernel_ms": round(plain[1], 4),
+                     "atomic_cost": round(push[1] / plain[1], 3) if plain[1] > 0 else None,
+                     "bytes_alg_pull": int(bytes_alg)})
+        log(f"  csr {csr_ms:.1f} ms, pull {pull[0]:.3f} ms ({rows[-1]['pull_GEdges_s']} GE/s), push {push[0]:.3f} ms, "
+            f"push kernel {push[1]:.3f} ms vs non-atomic {plain[1]:.3f} ms")
+        del coo, labels, csr, Z, ws, err
+        torch.cuda.empty_cache()
+
+    xs = np.array([r["s"] for r in rows], dtype=np.float64)
+    fit = {}
+    for key in ("pull_ms", "push_ms", "csr_build_ms"):
+        ys = np.array([r[key] for r in rows], dtype=np.float64)
+        b, c = np.polyfit(xs, ys, 1)
+        pred = b * xs + c
+        ss_res = float(((ys - pred) ** 2).sum())
+        ss_tot = float(((ys - ys.mean()) ** 2).sum())
+        fit[key] = {"ns_per_record": round(b * 1e6, 5), "intercept_ms": round(c, 4),
+                    "r2": round(1 - ss_res / ss_tot, 6) if ss_tot > 0 else None}
+    big = rows[-1]
+    achieved = big["bytes_alg_pull"] / (big["pull_kernel_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "GEdges/s",
+        "value": big["pull_GEdges_s"],
+        "unit": "GEdges/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": 1,
+        "ms_per_step": big["pull_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"er-sweep-2^{rows[0]['log2s']}..2^{big['log2s']}-records-{a.sweep_records_per_vertex}-per-vertex-K50-weighted",
+                   "form": "csr-pull (value); push and push-nonatomic beside", "sweep": rows, "fit": fit},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "k_pull",
+                     "bytes_alg_per_launch": big["bytes_alg_pull"], "kernel_ms": big["pull_kernel_ms"]},
+        "cpu_baseline": cpu,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -154,6 +154,17 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
               float *Z, void *ws, size_t ws_bytes, int32_t *err, const gee_embed_opts *opts,
               hipStream_t stream);
 
+/* DIAGNOSTIC, NOT THE EMBEDDING: the push form of gee_embed (g required, csr not
+ * used) with every update of Z a plain read-modify-write instead of an atomic add.
+ * Concurrent updates of one element race and can be lost, so Z is wrong whenever
+ * two records of the list update the same element (it is exact when none do, and
+ * for non-negative contributions never above the true value). It reproduces the
+ * paper's atomics-off run (Section IV: the program run with unsafe updates to
+ * measure what the atomics cost) and exists only for that measurement. Arguments,
+ * workspace (gee_embed_workspace with csr = NULL) and errors as for gee_embed. */
+int gee_embed_push_nonatomic(const gee_coo *g, const int32_t *labels, int32_t K, int laplacian, float *Z, void *ws,
+                             size_t ws_bytes, int32_t *err, const gee_embed_opts *opts, hipStream_t stream);
+
 /* A batch of label vectors over one graph. Vector b has labels
  * labels[b * n .. b * n + n) in [0, K[b]], the Laplacian version when laplacian[b]
  * != 0, and its n x K[b] embedding block at Z[u * ldz + zoff[b] + (k - 1)]. The

@@ -93,6 +93,8 @@ def load():
         lib.gee_embed_workspace.argtypes = [CooP, CsrP, i32, ci, OptP]
         lib.gee_embed.restype = ci
         lib.gee_embed.argtypes = [CooP, CsrP, vp, i32, ci, vp, vp, sz, vp, OptP, vp]
+        lib.gee_embed_push_nonatomic.restype = ci
+        lib.gee_embed_push_nonatomic.argtypes = [CooP, vp, i32, ci, vp, vp, sz, vp, OptP, vp]
         lib.gee_csr_workspace.restype = sz
         lib.gee_csr_workspace.argtypes = [i64, i64, ci, i64]
         lib.gee_csr_build.restype = ci
@@ -357,6 +359,33 @@ def embed(labels: torch.Tensor, K: int, coo: DeviceCoo | None = None, csr: Devic
                       ctypes.byref(o), _stream(stream)), "gee_embed")
     if check:
         _check_err(err, "gee_embed")
+    return Z
+
+
+def embed_push_nonatomic(labels: torch.Tensor, K: int, coo: DeviceCoo, laplacian: bool = False,
+                         Z: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                         err: torch.Tensor | None = None, events=None, stream=None, check: bool = True) -> torch.Tensor:
+    """Diagnostic only, not the embedding: the push form with plain (racing) updates of Z,
+    the paper's atomics-off measurement. Z is wrong wherever two records update one element."""
+    lib = load()
+    dev = coo.src.device
+    _need(labels, torch.int32, coo.n, "labels", dev)
+    cs = ctypes.byref(coo.struct())
+    o = _opts(0, 0, events)
+    wsb = int(lib.gee_embed_workspace(cs, None, K, 1 if laplacian else 0, ctypes.byref(o)))
+    if wsb == 0:
+        raise GeeError(GEE_EINVAL, "gee_embed_workspace")
+    if Z is None:
+        Z = torch.empty((coo.n, K), dtype=torch.float32, device=dev)
+    _need(Z, torch.float32, coo.n * K, "Z", dev)
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    if err is None:
+        err = torch.zeros(1, dtype=torch.int32, device=dev)
+    _rc(lib.gee_embed_push_nonatomic(cs, _ptr(labels), K, 1 if laplacian else 0, _ptr(Z), _ptr(ws), ws.numel(),
+                                     _ptr(err), ctypes.byref(o), _stream(stream)), "gee_embed_push_nonatomic")
+    if check:
+        _check_err(err, "gee_embed_push_nonatomic")
     return Z
 
 

@@ -273,8 +273,13 @@ size_t gee_embed_workspace(const gee_coo *g, const gee_csr *csr, int32_t K, int 
     return p.total;
 }
 
-int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32_t K, int laplacian, float *Z,
-              void *ws, size_t ws_bytes, int32_t *err, const gee_embed_opts *opts, hipStream_t stream)
+} // extern "C"
+
+namespace {
+
+int embed_impl(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32_t K, int laplacian, float *Z,
+               void *ws, size_t ws_bytes, int32_t *err, const gee_embed_opts *opts, hipStream_t stream,
+               bool atomic_updates)
 {
     Plan p;
     int rc = make_plan(g, csr, K, laplacian, opts, &p);
@@ -290,6 +295,7 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
     a.weighted = p.weighted;
     a.pack = p.pack;
     a.hot6 = p.hot6;
+    a.atomic_updates = atomic_updates;
     a.labels = labels;
     a.err = err;
     a.counts = reinterpret_cast<uint64_t *>(w + p.o_counts);
@@ -329,6 +335,23 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
         return rc;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;
     return hip_rc(launch_merge(a, csr->row_ptr, seg_i, seg_e, p.nseg, part, stream));
+}
+
+} // namespace
+
+extern "C" {
+
+int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32_t K, int laplacian, float *Z,
+              void *ws, size_t ws_bytes, int32_t *err, const gee_embed_opts *opts, hipStream_t stream)
+{
+    return embed_impl(g, csr, labels, K, laplacian, Z, ws, ws_bytes, err, opts, stream, true);
+}
+
+int gee_embed_push_nonatomic(const gee_coo *g, const int32_t *labels, int32_t K, int laplacian, float *Z, void *ws,
+                             size_t ws_bytes, int32_t *err, const gee_embed_opts *opts, hipStream_t stream)
+{
+    if (!g) return GEE_EINVAL;
+    return embed_impl(g, nullptr, labels, K, laplacian, Z, ws, ws_bytes, err, opts, stream, false);
 }
 
 size_t gee_embed_batch_workspace(const gee_csr *csr, const gee_batch *batch, const gee_embed_opts *opts)

@@ -181,7 +181,9 @@ k_pack_hot6(const uint8_t *__restrict__ lab, int64_t n, const int32_t *__restric
 // One thread per record (four records per thread, strided for coalescing):
 // gather both endpoints' label records and add the raw contribution into Z
 // with FP32 global atomics. Class weights and the row factor come later.
-template <bool LAP, bool W, typename P>
+// ATOMIC = false is the diagnostic of the paper's atomics-off run (Section IV):
+// plain read-modify-write, so concurrent updates of one element can be lost.
+template <bool LAP, bool W, typename P, bool ATOMIC>
 __global__ void __launch_bounds__(kBlock)
 k_push(int64_t n, int64_t ns, const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
        const float *__restrict__ w, const P *__restrict__ lab, int32_t K, float *__restrict__ Z, int32_t *err)
@@ -219,11 +221,15 @@ k_push(int64_t n, int64_t ns, const int32_t *__restrict__ src, const int32_t *__
         const int yu = LabelRec<P>::cls(pu[r]), yv = LabelRec<P>::cls(pv[r]);
         if (yv > 0) {
             const float c = LAP ? x[r] * LabelRec<P>::rsd(pv[r]) : x[r];
-            atomicAdd(&Z[(int64_t)u[r] * K + (yv - 1)], c);
+            float *z = &Z[(int64_t)u[r] * K + (yv - 1)];
+            if (ATOMIC) atomicAdd(z, c);
+            else *z += c;
         }
         if (yu > 0) {
             const float c = LAP ? x[r] * LabelRec<P>::rsd(pu[r]) : x[r];
-            atomicAdd(&Z[(int64_t)v[r] * K + (yu - 1)], c);
+            float *z = &Z[(int64_t)v[r] * K + (yu - 1)];
+            if (ATOMIC) atomicAdd(z, c);
+            else *z += c;
         }
     }
     if (bad) flag_error(err, GEE_EVERTEX);
@@ -729,8 +735,12 @@ static hipError_t push_t(const EmbedArgs &a, int64_t ns, const int32_t *src, con
 {
     const int64_t blocks = (ns + kBlock * 4 - 1) / (kBlock * 4);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_push<LAP, W, P>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.n, ns, src, dst, w,
-                       static_cast<const P *>(a.lab), a.K, a.Z, a.err);
+    if (a.atomic_updates)
+        hipLaunchKernelGGL((k_push<LAP, W, P, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.n, ns, src, dst, w,
+                           static_cast<const P *>(a.lab), a.K, a.Z, a.err);
+    else
+        hipLaunchKernelGGL((k_push<LAP, W, P, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.n, ns, src, dst,
+                           w, static_cast<const P *>(a.lab), a.K, a.Z, a.err);
     return hipGetLastError();
 }
 

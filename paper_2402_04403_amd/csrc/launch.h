@@ -17,6 +17,7 @@ struct EmbedArgs {
     bool weighted = false;
     Pack pack = Pack::U8;
     bool hot6 = false; // hot label table at 6 bits per slot (unit adjacency, 8-bit labels, K <= 63)
+    bool atomic_updates = true; // push form: false = plain read-modify-write (diagnostic only)
     const int32_t *labels = nullptr;
     int32_t *err = nullptr;
     // workspace pieces

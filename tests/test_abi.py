@@ -146,3 +146,10 @@ def test_batch_argument_errors(lib):
     assert big > 0 and lap > big  # degrees and d^-1/2 for the Laplacian vectors
     st, keep = gee._batch_struct(None, [5], [0], [0], 5, None)
     assert lib.gee_embed_batch(ctypes.byref(csr), ctypes.byref(st), FAKE, 1 << 30, FAKE, None, None) == gee.GEE_EINVAL
+
+
+def test_push_nonatomic_argument_errors(lib):
+    """The atomics-off diagnostic needs the edge list (its push form has no CSR input)."""
+    o = gee.EmbedOpts(0, 0, None, None)
+    assert lib.gee_embed_push_nonatomic(None, FAKE, 5, 0, FAKE, FAKE, 1 << 30, FAKE, ctypes.byref(o), None) == \
+        gee.GEE_EINVAL
