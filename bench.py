@@ -1,20 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the GEE hot path on one MI355X.
 
-One step = one ``gee_embed`` call (class counts and label packing, projection
-weights, the edge pass and the split-row merge) over the paper-scale R-MAT: scale 27
-(n = 134,217,728), edge factor 14 (s = 1,879,048,192 records), (a, b, c) = (0.57, 0.19,
-0.19), unit weights, K = 50 planted classes with 1% unknown, adjacency version, all
-inputs resident in HBM. The symmetric CSR is built once beforehand (per-graph
-preprocessing, reported as ``csr_build_ms``). Prints one JSON line on stdout;
-progress goes to stderr.
+One step = one embedding call over the paper-scale R-MAT: scale 27 (n = 134,217,728),
+edge factor 14 (s = 1,879,048,192 records), (a, b, c) = (0.57, 0.19, 0.19), unit
+weights, K = 50 planted classes with 1% unknown, adjacency version, all inputs resident
+in HBM. By default the call is ``gee_embed`` on the CSR (class counts and label
+packing, projection weights, the edge pass and the split-row merge); ``--form pb``
+times ``gee_embed_pb`` over the propagation-blocked layout (label gather and row
+counts) and ``--form push`` the edge-parallel form; the other forms are timed beside. The symmetric CSR and the layout are built
+once beforehand (per-graph preprocessing, reported as ``csr_build_ms`` and
+``pb_build_ms``). Prints one JSON line on stdout; progress goes to stderr.
 
-``value`` is GEdges/s = s / step time. ``roofline`` prices the edge-pass kernel
-(``k_pull``) against HBM: algorithmic bytes per launch = 4 nnz (col) + 8 (n + 1)
-(row_ptr) + n (one read of each packed label) + 4 n K (Z written once), divided by
-the kernel's mean duration measured with HIP events recorded around that launch on
-the stream it runs on. ``cpu_baseline`` times the FP64 oracle, single thread, on a
-prefix of the same record list.
+``value`` is GEdges/s = s / step time. ``roofline`` prices the edge pass against HBM:
+algorithmic bytes per launch = 4 nnz (col) + 8 (n + 1) (row_ptr) + n (one read of each
+packed label) + 4 n K (Z written once), divided by the pass's mean duration measured
+with HIP events recorded around its kernels on the stream they run on. ``cpu_baseline``
+times the FP64 oracle, single thread, on a prefix of the same record list.
 """
 from __future__ import annotations
 
@@ -32,6 +33,8 @@ HBM_PEAK_GBPS = 8000.0
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "k_pull_rmat27_counters.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2402_04403_amd", "csrc", "embed.hip")
 PROFILE_COUNTERS_BATCH = os.path.join(ROOT, "profiles", "k_batch_pull_rmat24_b64_counters.json")
+PROFILE_COUNTERS_PB = os.path.join(ROOT, "profiles", "k_pb_rmat27_counters.json")
+KERNEL_SOURCE_PB = os.path.join(ROOT, "paper_2402_04403_amd", "csrc", "pb.hip")
 KERNEL_SOURCE_BATCH = os.path.join(ROOT, "paper_2402_04403_amd", "csrc", "batch.hip")
 
 
@@ -48,6 +51,8 @@ def parse():
                         "er-sweep: Erdos-Renyi graphs of growing size (the paper's Fig. 4 family)")
     p.add_argument("--sweep", default="20,22,24,26,28,30", help="er-sweep: log2 of the record counts")
     p.add_argument("--sweep-records-per-vertex", type=int, default=16)
+    p.add_argument("--sweep-weighted", action="store_true",
+                   help="er-sweep: grid weights (no propagation-blocked form then)")
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--scale", type=int, default=None)
@@ -56,11 +61,13 @@ def parse():
     p.add_argument("--plain-steps", type=int, default=1,
                    help="batched workload: timed rounds of one plain call per vector, reported beside")
     p.add_argument("--K", type=int, default=50)
-    p.add_argument("--form", choices=["pull", "push"], default="pull")
+    p.add_argument("--form", choices=["pb", "pull", "push"], default="pull",
+                   help="rmat27: pb = pull over the propagation-blocked layout (unit weights), pull = CSR pull, "
+                        "push = edge-parallel atomics")
     p.add_argument("--seg-len", type=int, default=0)
     p.add_argument("--rows-per-window", type=int, default=0)
     p.add_argument("--hot-budget", type=int, default=-1, help="hot-vertex slots of the CSR (-1: library default)")
-    p.add_argument("--push-steps", type=int, default=3, help="timed steps of the push form, reported beside")
+    p.add_argument("--push-steps", type=int, default=3, help="timed steps of each other form, reported beside")
     p.add_argument("--cpu-records", type=int, default=400_000_000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     a = p.parse_args()
@@ -154,16 +161,32 @@ def main():
     copy_gbps = copy_probe(gee, torch, dev)
     log(f"copy probe {copy_gbps:.0f} GB/s")
 
-    use_csr = csr if a.form == "pull" else None
-    ws_bytes = gee.embed_workspace_bytes(K, coo=coo, csr=use_csr, seg_len=a.seg_len,
-                                         rows_per_window=a.rows_per_window)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    pb, pb_ms = None, None
+    if a.form == "pb" or a.push_steps > 0:
+        p0, p1 = gee.HipEvent(), gee.HipEvent()
+        p0.record()
+        pb = gee.pb_build(csr, check=False)
+        p1.record()
+        p1.synchronize()
+        pb_ms = p0.elapsed_ms(p1)
+        torch.cuda.empty_cache()
+        log(f"propagation-blocked layout built in {pb_ms:.1f} ms")
+
     Z = torch.empty((n, K), dtype=torch.float32, device=dev)
     err = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = {"pull": torch.empty(gee.embed_workspace_bytes(K, csr=csr, seg_len=a.seg_len,
+                                                        rows_per_window=a.rows_per_window),
+                              dtype=torch.uint8, device=dev),
+          "push": torch.empty(gee.embed_workspace_bytes(K, coo=coo), dtype=torch.uint8, device=dev)}
+    if pb is not None:
+        ws["pb"] = torch.empty(gee.embed_pb_workspace_bytes(pb, K), dtype=torch.uint8, device=dev)
 
     def step(events=None, form=a.form):
-        gee.embed(labels, K, coo=coo, csr=csr if form == "pull" else None, Z=Z, ws=ws, err=err,
-                  seg_len=a.seg_len, rows_per_window=a.rows_per_window, events=events, check=False)
+        if form == "pb":
+            gee.embed_pb(labels, K, pb, Z=Z, ws=ws["pb"], err=err, events=events, check=False)
+        else:
+            gee.embed(labels, K, coo=coo, csr=csr if form == "pull" else None, Z=Z, ws=ws[form], err=err,
+                      seg_len=a.seg_len, rows_per_window=a.rows_per_window, events=events, check=False)
 
     for _ in range(a.warmup):
         step()
@@ -182,17 +205,15 @@ def main():
     hot_ms = [b.elapsed_ms(e) for b, e in hot]
     hot_avg = float(np.mean(hot_ms))
     if int(err.item()) != 0:
-        raise SystemExit(f"gee_embed reported {int(err.item())}")
-    log(f"{a.form}: step {step_ms:.3f} ms (wall {wall_ms / a.steps:.3f}), hot kernel mean {hot_avg:.3f} ms "
+        raise SystemExit(f"embedding reported {int(err.item())}")
+    log(f"{a.form}: step {step_ms:.3f} ms (wall {wall_ms / a.steps:.3f}), edge pass mean {hot_avg:.3f} ms "
         f"min {min(hot_ms):.3f}")
 
-    # the other form, reported beside
-    other = "push" if a.form == "pull" else "pull"
-    other_ms = None
-    if a.push_steps > 0:
-        ws_o = gee.embed_workspace_bytes(K, coo=coo, csr=csr if other == "pull" else None)
-        if ws_o > ws.numel():
-            ws = torch.empty(ws_o, dtype=torch.uint8, device=dev)
+    # the other forms, reported beside
+    beside = {}
+    for other in ("pb", "pull", "push"):
+        if other == a.form or a.push_steps <= 0 or (other == "pb" and pb is None):
+            continue
         step(form=other)
         torch.cuda.synchronize()
         o0, o1 = gee.HipEvent(), gee.HipEvent()
@@ -201,19 +222,22 @@ def main():
             step(form=other)
         o1.record()
         o1.synchronize()
-        other_ms = o0.elapsed_ms(o1) / a.push_steps
-        log(f"{other}: step {other_ms:.3f} ms")
+        beside[other] = o0.elapsed_ms(o1) / a.push_steps
+        log(f"{other}: step {beside[other]:.3f} ms")
 
-    # roofline of the edge-pass kernel
+    # roofline of the edge pass: the embedding's algorithmic bytes (every CSR entry once,
+    # row_ptr, one read of each packed label, Z written once) over the measured pass
     lab_bytes = 1 if K <= 255 else 2
-    if a.form == "pull":
+    if a.form in ("pull", "pb"):
         bytes_alg = 4 * nnz + 8 * (n + 1) + lab_bytes * n + 4 * n * K
-        kernel = "k_pull"
+        kernel = "k_pull" if a.form == "pull" else "k_pb_gather + k_pb_rows"
+        traffic, counters = (counters_traffic(bytes_alg) if a.form == "pull"
+                             else counters_traffic(bytes_alg, PROFILE_COUNTERS_PB, KERNEL_SOURCE_PB))
     else:
         bytes_alg = 8 * s + lab_bytes * n + 2 * 8 * s  # records once, labels once, two 8-byte atomic RMW
         kernel = "k_push"
+        traffic, counters = None, None
     achieved = bytes_alg / (hot_avg * 1e-3) / 1e9
-    traffic, counters = counters_traffic(bytes_alg) if a.form == "pull" else (None, None)
     step_bytes = bytes_alg + 4 * n + lab_bytes * n  # + the label read and pack of the counts kernel
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": kernel,
@@ -250,20 +274,23 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"rmat-s{a.scale}-ef{a.edge_factor}-K{K}-unit-adjacency",
-            "n": n, "s": s, "nnz": nnz, "K": K, "form": "csr-pull" if a.form == "pull" else "edge-push",
+            "n": n, "s": s, "nnz": nnz, "K": K,
+            "form": {"pb": "propagation-blocked pull", "pull": "csr-pull", "push": "edge-push"}[a.form],
             "seg_len": a.seg_len or 16384, "rows_per_window": a.rows_per_window or "auto",
             "hot_slots": csr.n_hot,
             "csr_build_ms": round(csr_ms, 2),
+            "pb_build_ms": None if pb_ms is None else round(pb_ms, 2),
             "step_hbm_frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "copy_probe_GBps": round(copy_gbps, 1),
-            f"{other}_ms_per_step": None if other_ms is None else round(other_ms, 3),
+            **{f"{k}_ms_per_step": round(v, 3) for k, v in beside.items()},
             "paper_context": "6.42 s for Friendster (1.8B edges) on a 24-core Xeon Platinum 8259CL, Table I",
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     if counters is not None:
-        out["config"]["counters_file"] = os.path.relpath(PROFILE_COUNTERS, ROOT)
+        out["config"]["counters_file"] = os.path.relpath(PROFILE_COUNTERS if a.form == "pull" else PROFILE_COUNTERS_PB,
+                                                         ROOT)
     print(json.dumps(out), flush=True)
 
 
@@ -430,13 +457,14 @@ def main_batched(a):
 
 def main_sweep(a):
     """Erdős–Rényi graphs of growing size (Section IV, Fig. 4: runtime against the number of
-    edges). For each s = 2^k (k in --sweep), n = s / records-per-vertex, grid weights in
-    (0, 1], K = 50 uniform classes with exactly 5% unknown (the er_weighted family). Per size:
-    CSR build, the pull form (adjacency), the push form with atomics, and the push form's
+    edges). For each s = 2^k (k in --sweep), n = s / records-per-vertex, unit weights
+    (grid weights in (0, 1] with --sweep-weighted), K = 50 uniform classes with exactly 5%
+    unknown. Per size: CSR build and propagation-blocked layout, the pull form and the
+    propagation-blocked form (adjacency), the push form with atomics, and the push form's
     atomics-off diagnostic (plain racing updates; wrong results by design, it prices the
-    atomics as the paper's unsafe run did). ``value`` is the pull form's GEdges/s at the
-    largest size; ``config.sweep`` holds every size and ``config.fit`` the least-squares line
-    of pull step time against s."""
+    atomics as the paper's unsafe run did). ``value`` is the propagation-blocked form's
+    GEdges/s at the largest size (the pull form's with weights); ``config.sweep`` holds every
+    size and ``config.fit`` least-squares lines of step time against s."""
     import numpy as np
     import torch
 
@@ -452,7 +480,10 @@ def main_sweep(a):
         n = max(s // a.sweep_records_per_vertex, 1)
         log2n = n.bit_length() - 1
         t0 = time.time()
-        wl = gen.er_weighted(log2n=log2n, log2s=k, K=K)
+        if a.sweep_weighted:
+            wl = gen.er_weighted(log2n=log2n, log2s=k, K=K)
+        else:
+            wl = gen.er_unit(log2n=log2n, log2s=k, K=K)
         g = wl.graph
         log(f"er 2^{k}: n={g.n} s={g.s} generated in {time.time() - t0:.1f}s")
         if cpu is None and a.cpu_records > 0 and not a.no_cpu_baseline and k >= 24:
@@ -474,9 +505,17 @@ def main_sweep(a):
         e1.record()
         e1.synchronize()
         csr_ms = e0.elapsed_ms(e1)
+        pb, pb_ms = None, None
+        if not a.sweep_weighted:
+            e0.record()
+            pb = gee.pb_build(csr, check=False)
+            e1.record()
+            e1.synchronize()
+            pb_ms = e0.elapsed_ms(e1)
         Z = torch.empty((n, K), dtype=torch.float32, device=dev)
         err = torch.zeros(1, dtype=torch.int32, device=dev)
-        ws = torch.empty(max(gee.embed_workspace_bytes(K, csr=csr), gee.embed_workspace_bytes(K, coo=coo)),
+        ws = torch.empty(max(gee.embed_workspace_bytes(K, csr=csr), gee.embed_workspace_bytes(K, coo=coo),
+                             gee.embed_pb_workspace_bytes(pb, K) if pb is not None else 0),
                          dtype=torch.uint8, device=dev)
 
         def timed(fn, steps):
@@ -492,6 +531,8 @@ def main_sweep(a):
             return b0.elapsed_ms(b1) / steps, float(np.mean([x.elapsed_ms(y) for x, y in hot]))
 
         pull = timed(lambda ev: gee.embed(labels, K, csr=csr, Z=Z, ws=ws, err=err, events=ev, check=False), a.steps)
+        pbt = (timed(lambda ev: gee.embed_pb(labels, K, pb, Z=Z, ws=ws, err=err, events=ev, check=False), a.steps)
+               if pb is not None else None)
         push = timed(lambda ev: gee.embed(labels, K, coo=coo, Z=Z, ws=ws, err=err, events=ev, check=False),
                      max(a.push_steps, 1))
         plain = timed(lambda ev: gee.embed_push_nonatomic(labels, K, coo, Z=Z, ws=ws, err=err, events=ev,
@@ -499,8 +540,13 @@ def main_sweep(a):
         if int(err.item()) != 0:
             raise SystemExit(f"reported error {int(err.item())}")
         nnz = csr.nnz
-        bytes_alg = 8 * nnz + 8 * (n + 1) + n + 4 * n * K  # col + val per entry, row_ptr, labels, Z
+        per_entry = 8 if a.sweep_weighted else 4  # col (+ val)
+        bytes_alg = per_entry * nnz + 8 * (n + 1) + n + 4 * n * K  # entries, row_ptr, labels, Z
         rows.append({"log2s": k, "s": s, "n": n, "nnz": nnz, "csr_build_ms": round(csr_ms, 3),
+                     "pb_build_ms": None if pb_ms is None else round(pb_ms, 3),
+                     "pb_ms": None if pbt is None else round(pbt[0], 4),
+                     "pb_kernel_ms": None if pbt is None else round(pbt[1], 4),
+                     "pb_GEdges_s": None if pbt is None else round(s / (pbt[0] * 1e-3) / 1e9, 3),
                      "pull_ms": round(pull[0], 4), "pull_kernel_ms": round(pull[1], 4),
                      "pull_GEdges_s": round(s / (pull[0] * 1e-3) / 1e9, 3),
                      "pull_kernel_GBps": round(bytes_alg / (pull[1] * 1e-3) / 1e9, 1),
@@ -508,14 +554,17 @@ def main_sweep(a):
                      "push_nonatomic_kernel_ms": round(plain[1], 4),
                      "atomic_cost": round(push[1] / plain[1], 3) if plain[1] > 0 else None,
                      "bytes_alg_pull": int(bytes_alg)})
-        log(f"  csr {csr_ms:.1f} ms, pull {pull[0]:.3f} ms ({rows[-1]['pull_GEdges_s']} GE/s), push {push[0]:.3f} ms, "
+        log(f"  csr {csr_ms:.1f} ms, pull {pull[0]:.3f} ms ({rows[-1]['pull_GEdges_s']} GE/s), "
+            f"pb {rows[-1]['pb_ms']} ms ({rows[-1]['pb_GEdges_s']} GE/s), push {push[0]:.3f} ms, "
             f"push kernel {push[1]:.3f} ms vs non-atomic {plain[1]:.3f} ms")
-        del coo, labels, csr, Z, ws, err
+        del coo, labels, csr, pb, Z, ws, err
         torch.cuda.empty_cache()
 
     xs = np.array([r["s"] for r in rows], dtype=np.float64)
     fit = {}
-    for key in ("pull_ms", "push_ms", "csr_build_ms"):
+    for key in ("pull_ms", "pb_ms", "push_ms", "csr_build_ms"):
+        if rows[0].get(key) is None:
+            continue
         ys = np.array([r[key] for r in rows], dtype=np.float64)
         b, c = np.polyfit(xs, ys, 1)
         pred = b * xs + c
@@ -524,25 +573,31 @@ def main_sweep(a):
         fit[key] = {"ns_per_record": round(b * 1e6, 5), "intercept_ms": round(c, 4),
                     "r2": round(1 - ss_res / ss_tot, 6) if ss_tot > 0 else None}
     big = rows[-1]
-    achieved = big["bytes_alg_pull"] / (big["pull_kernel_ms"] * 1e-3) / 1e9
+    use_pb = big.get("pb_ms") is not None
+    kms = big["pb_kernel_ms"] if use_pb else big["pull_kernel_ms"]
+    achieved = big["bytes_alg_pull"] / (kms * 1e-3) / 1e9
     out = {
         "metric": "GEdges/s",
-        "value": big["pull_GEdges_s"],
+        "value": big["pb_GEdges_s"] if use_pb else big["pull_GEdges_s"],
         "unit": "GEdges/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": 1,
-        "ms_per_step": big["pull_ms"],
+        "ms_per_step": big["pb_ms"] if use_pb else big["pull_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"er-sweep-2^{rows[0]['log2s']}..2^{big['log2s']}-records-{a.sweep_records_per_vertex}-per-vertex-K50-weighted",
-                   "form": "csr-pull (value); push and push-nonatomic beside", "sweep": rows, "fit": fit},
+        "config": {"workload": f"er-sweep-2^{rows[0]['log2s']}..2^{big['log2s']}-records-"
+                               f"{a.sweep_records_per_vertex}-per-vertex-K50-{'weighted' if a.sweep_weighted else 'unit'}",
+                   "form": ("propagation-blocked pull (value); csr-pull, push and push-nonatomic beside" if use_pb
+                            else "csr-pull (value); push and push-nonatomic beside"),
+                   "sweep": rows, "fit": fit},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "k_pull",
-                     "bytes_alg_per_launch": big["bytes_alg_pull"], "kernel_ms": big["pull_kernel_ms"]},
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "k_pb_gather + k_pb_rows" if use_pb else "k_pull",
+                     "bytes_alg_per_launch": big["bytes_alg_pull"], "kernel_ms": kms},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -196,6 +196,15 @@ def er_weighted(seed: int = 2, log2n: int = 22, log2s: int = 26, K: int = 50) ->
     return Workload(f"er-n2^{log2n}-s2^{log2s}-K{K}-weighted", g, Y, K)
 
 
+def er_unit(seed: int = 2, log2n: int = 22, log2s: int = 26, K: int = 50) -> Workload:
+    """Erdős–Rényi n=2^log2n, s=2^log2s, unit weights, K uniform classes, 5% unknown."""
+    n, s = 1 << log2n, 1 << log2s
+    g = er(n, s, seed, weighted=False)
+    Y = labels_uniform(n, K, seed)
+    unlabel_exact(Y, (5 * n) // 100, seed)
+    return Workload(f"er-n2^{log2n}-s2^{log2s}-K{K}-unit", g, Y, K)
+
+
 def rmat_paper_scale(seed: int = 3, scale: int = 27, edge_factor: int = 14, K: int = 50,
                      unlabeled: float = 0.01) -> Workload:
     """R-MAT (0.57,0.19,0.19,0.05), 2^scale vertices, edge_factor*2^scale records, unit weights."""

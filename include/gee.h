@@ -154,6 +154,56 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
               float *Z, void *ws, size_t ws_bytes, int32_t *err, const gee_embed_opts *opts,
               hipStream_t stream);
 
+/* ------------------------------------------------------------------------------
+ * Propagation-blocked layout of a unit-weight CSR, and the pull pass over it.
+ *
+ * The pull pass of Algorithm 1 (Section II; Section III's per-vertex edge lists)
+ * reads the label of every entry's column at a random address. For unit weights
+ * the pass only needs, per entry, its row and the label of its column, so the
+ * entries can be re-laid out once per graph: sorted stably by column block (2^21
+ * vertices), each entry keeping its column and its row within a block of 256 rows.
+ * Per call, one streaming pass writes every entry's label in that order (a column
+ * block's labels stay in L2) and a second pass counts, per 256-row block, the
+ * (row, class) pairs of the block's cells in LDS and writes those rows of Z once.
+ * Counts are integers: Z is bit-identical to gee_embed on the same CSR.
+ *
+ * Cell (rb, cb) of the layout is the run of column block cb's entries whose rows
+ * lie in [256 rb, 256 rb + 256); cell_start[rb * n_cb + cb] is its first index in
+ * col/ul and cell_count[...] its length. n_rb = ceil(n / 256), n_cb = ceil(n / 2^21).
+ * ------------------------------------------------------------------------------ */
+typedef struct gee_pb {
+    int64_t n, nnz;            /* vertices, entries (as in the CSR) */
+    int64_t n_rb;              /* row blocks */
+    int32_t n_cb;              /* column blocks */
+    const int32_t *col;        /* [nnz] column of every entry, layout order; 16-byte aligned */
+    const uint8_t *ul;         /* [nnz] row within its 256-row block */
+    const int64_t *cell_start; /* [n_rb * n_cb] */
+    const uint32_t *cell_count; /* [n_rb * n_cb] */
+} gee_pb;
+
+/* n_rb * n_cb for n vertices (0 on invalid n). */
+int64_t gee_pb_cells(int64_t n);
+
+/* Scratch bytes gee_pb_build needs (0 on invalid input or a weighted CSR). */
+size_t gee_pb_build_workspace(const gee_csr *csr);
+
+/* Builds the layout of a unit-weight CSR (csr->val must be NULL; hot-slot columns
+ * are decoded through hot_ids). Outputs are caller device buffers: col [nnz]
+ * (16-byte aligned), ul [nnz], cell_start and cell_count [gee_pb_cells(n)]. A
+ * column id outside [0, n) stores GEE_EVERTEX in *err. */
+int gee_pb_build(const gee_csr *csr, int32_t *col, uint8_t *ul, int64_t *cell_start, uint32_t *cell_count, void *ws,
+                 size_t ws_bytes, int32_t *err, hipStream_t stream);
+
+/* Workspace bytes of gee_embed_pb (0 on invalid input); 1 <= K <= 128. */
+size_t gee_embed_pb_workspace(const gee_pb *pb, int32_t K);
+
+/* Algorithm 1, adjacency version, unit weights, over the layout: labels [n] in
+ * [0, K] (K <= 128), Z [n * K] FP32 overwritten. Same results and data errors as
+ * gee_embed on the CSR the layout was built from. opts->hot_begin / hot_end
+ * bracket the two passes (label gather and row counts); seg_len is unused. */
+int gee_embed_pb(const gee_pb *pb, const int32_t *labels, int32_t K, float *Z, void *ws, size_t ws_bytes,
+                 int32_t *err, const gee_embed_opts *opts, hipStream_t stream);
+
 /* DIAGNOSTIC, NOT THE EMBEDDING: the push form of gee_embed (g required, csr not
  * used) with every update of Z a plain read-modify-write instead of an atomic add.
  * Concurrent updates of one element race and can be lost, so Z is wrong whenever

@@ -54,6 +54,12 @@ class Csr(ctypes.Structure):
                 ("hot_ids", ctypes.c_void_p)]
 
 
+class Pb(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_rb", ctypes.c_int64), ("n_cb", ctypes.c_int32),
+                ("col", ctypes.c_void_p), ("ul", ctypes.c_void_p), ("cell_start", ctypes.c_void_p),
+                ("cell_count", ctypes.c_void_p)]
+
+
 class Batch(ctypes.Structure):
     _fields_ = [("B", ctypes.c_int32), ("labels", ctypes.c_void_p), ("K", ctypes.POINTER(ctypes.c_int32)),
                 ("laplacian", ctypes.POINTER(ctypes.c_int32)), ("zoff", ctypes.POINTER(ctypes.c_int64)),
@@ -93,6 +99,17 @@ def load():
         lib.gee_embed_workspace.argtypes = [CooP, CsrP, i32, ci, OptP]
         lib.gee_embed.restype = ci
         lib.gee_embed.argtypes = [CooP, CsrP, vp, i32, ci, vp, vp, sz, vp, OptP, vp]
+        PbP = ctypes.POINTER(Pb)
+        lib.gee_pb_cells.restype = i64
+        lib.gee_pb_cells.argtypes = [i64]
+        lib.gee_pb_build_workspace.restype = sz
+        lib.gee_pb_build_workspace.argtypes = [CsrP]
+        lib.gee_pb_build.restype = ci
+        lib.gee_pb_build.argtypes = [CsrP, vp, vp, vp, vp, vp, sz, vp, vp]
+        lib.gee_embed_pb_workspace.restype = sz
+        lib.gee_embed_pb_workspace.argtypes = [PbP, i32]
+        lib.gee_embed_pb.restype = ci
+        lib.gee_embed_pb.argtypes = [PbP, vp, i32, vp, vp, sz, vp, OptP, vp]
         lib.gee_embed_push_nonatomic.restype = ci
         lib.gee_embed_push_nonatomic.argtypes = [CooP, vp, i32, ci, vp, vp, sz, vp, OptP, vp]
         lib.gee_csr_workspace.restype = sz
@@ -313,6 +330,90 @@ def csr_build(coo: DeviceCoo, hot_budget: int = 0, stream=None, check: bool = Tr
         _check_err(err, "gee_csr_build")
     del ws
     return DeviceCsr(coo.n, row_ptr, col, val, hot_ids)
+
+
+PB_ROWS = 256
+PB_COLS = 1 << 21
+
+
+@dataclass
+class DevicePb:
+    """Propagation-blocked layout of a unit-weight CSR (entries by 2^21-vertex column
+    block; cells of 256-row blocks)."""
+
+    n: int
+    col: torch.Tensor
+    ul: torch.Tensor
+    cell_start: torch.Tensor
+    cell_count: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @property
+    def n_rb(self) -> int:
+        return (self.n + PB_ROWS - 1) // PB_ROWS
+
+    @property
+    def n_cb(self) -> int:
+        return max((self.n + PB_COLS - 1) // PB_COLS, 1)
+
+    def struct(self) -> Pb:
+        return Pb(self.n, self.nnz, self.n_rb, self.n_cb, _ptr(self.col), _ptr(self.ul), _ptr(self.cell_start),
+                  _ptr(self.cell_count))
+
+
+def pb_build(csr: DeviceCsr, stream=None, check: bool = True) -> DevicePb:
+    """Layout for gee_embed_pb from a unit-weight CSR (per-graph preprocessing)."""
+    lib = load()
+    rs = csr.struct()
+    dev = csr.row_ptr.device
+    cells = int(lib.gee_pb_cells(csr.n))
+    wsb = int(lib.gee_pb_build_workspace(ctypes.byref(rs)))
+    if wsb == 0 or cells == 0:
+        raise GeeError(GEE_EINVAL, "gee_pb_build_workspace")
+    col = torch.empty(max(csr.nnz, 1), dtype=torch.int32, device=dev)[: csr.nnz]
+    ul = torch.empty(max(csr.nnz, 1), dtype=torch.uint8, device=dev)[: csr.nnz]
+    cell_start = torch.empty(cells, dtype=torch.int64, device=dev)
+    cell_count = torch.empty(cells, dtype=torch.int32, device=dev)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    err = torch.zeros(1, dtype=torch.int32, device=dev)
+    _rc(lib.gee_pb_build(ctypes.byref(rs), _ptr(col), _ptr(ul), _ptr(cell_start), _ptr(cell_count), _ptr(ws), wsb,
+                         _ptr(err), _stream(stream)), "gee_pb_build")
+    if check:
+        _check_err(err, "gee_pb_build")
+    del ws
+    return DevicePb(csr.n, col, ul, cell_start, cell_count)
+
+
+def embed_pb_workspace_bytes(pb: DevicePb, K: int) -> int:
+    return int(load().gee_embed_pb_workspace(ctypes.byref(pb.struct()), K))
+
+
+def embed_pb(labels: torch.Tensor, K: int, pb: DevicePb, Z: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+             err: torch.Tensor | None = None, events=None, stream=None, check: bool = True) -> torch.Tensor:
+    """Adjacency-version Z [n, K] of a unit-weight graph from its propagation-blocked layout."""
+    lib = load()
+    dev = pb.cell_start.device
+    _need(labels, torch.int32, pb.n, "labels", dev)
+    st = pb.struct()
+    wsb = int(lib.gee_embed_pb_workspace(ctypes.byref(st), K))
+    if wsb == 0:
+        raise GeeError(GEE_EINVAL, "gee_embed_pb_workspace")
+    if Z is None:
+        Z = torch.empty((pb.n, K), dtype=torch.float32, device=dev)
+    _need(Z, torch.float32, pb.n * K, "Z", dev)
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    if err is None:
+        err = torch.zeros(1, dtype=torch.int32, device=dev)
+    o = _opts(0, 0, events)
+    _rc(lib.gee_embed_pb(ctypes.byref(st), _ptr(labels), K, _ptr(Z), _ptr(ws), ws.numel(), _ptr(err),
+                         ctypes.byref(o), _stream(stream)), "gee_embed_pb")
+    if check:
+        _check_err(err, "gee_embed_pb")
+    return Z
 
 
 def _opts(seg_len=0, rows_per_window=0, events=None):

@@ -433,6 +433,102 @@ int gee_embed_batch(const gee_csr *csr, const gee_batch *batch, void *ws, size_t
     return GEE_OK;
 }
 
+int64_t gee_pb_cells(int64_t n)
+{
+    if (n < 1 || n > kMaxN) return 0;
+    return pb_layout(n).cells;
+}
+
+size_t gee_pb_build_workspace(const gee_csr *csr)
+{
+    if (check_csr(csr) != GEE_OK || csr->val) return 0;
+    return pb_build_scratch(csr->n, csr->nnz);
+}
+
+int gee_pb_build(const gee_csr *csr, int32_t *col, uint8_t *ul, int64_t *cell_start, uint32_t *cell_count, void *ws,
+                 size_t ws_bytes, int32_t *err, hipStream_t stream)
+{
+    int rc;
+    if ((rc = check_csr(csr)) != GEE_OK) return rc;
+    if (csr->val) return GEE_EINVAL; // the layout serves unit-weight graphs
+    if ((csr->nnz > 0 && (!col || !ul)) || !cell_start || !cell_count || !aligned(col, 16)) return GEE_EINVAL;
+    const size_t need = pb_build_scratch(csr->n, csr->nnz);
+    if (!ws || !aligned(ws, 256) || ws_bytes < need) return GEE_EWORKSPACE;
+    return hip_rc(launch_pb_build(csr->n, csr->nnz, csr->row_ptr, csr->col, csr->hot_ids, csr->n_hot, col, ul,
+                                  cell_start, cell_count, ws, err, stream));
+}
+
+} // extern "C"
+
+namespace {
+
+int check_pb(const gee_pb *pb)
+{
+    if (!pb || pb->n < 1 || pb->n > kMaxN || pb->nnz < 0) return GEE_EINVAL;
+    const PbLayout L = pb_layout(pb->n);
+    if (pb->n_rb != L.n_rb || pb->n_cb != L.n_cb) return GEE_EINVAL;
+    if ((pb->nnz > 0 && (!pb->col || !pb->ul)) || !pb->cell_start || !pb->cell_count || !aligned(pb->col, 16))
+        return GEE_EINVAL;
+    return GEE_OK;
+}
+
+struct PbPlan {
+    size_t o_counts = 0, o_inv = 0, o_lab = 0, o_yv = 0, total = 0;
+};
+
+PbPlan pb_plan(const gee_pb *pb, int32_t K)
+{
+    PbPlan P;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = align_up(off, 256);
+        const size_t at = off;
+        off += bytes;
+        return at;
+    };
+    P.o_counts = take(8 * (size_t)(K + 1));
+    P.o_inv = take(8 * (size_t)(K + 1));
+    P.o_lab = take((size_t)pb->n);
+    P.o_yv = take((size_t)pb->nnz + 16);
+    P.total = align_up(off, 256);
+    return P;
+}
+
+} // namespace
+
+extern "C" {
+
+size_t gee_embed_pb_workspace(const gee_pb *pb, int32_t K)
+{
+    if (check_pb(pb) != GEE_OK || K < 1 || K > kPbMaxK) return 0;
+    return pb_plan(pb, K).total;
+}
+
+int gee_embed_pb(const gee_pb *pb, const int32_t *labels, int32_t K, float *Z, void *ws, size_t ws_bytes,
+                 int32_t *err, const gee_embed_opts *opts, hipStream_t stream)
+{
+    int rc;
+    if ((rc = check_pb(pb)) != GEE_OK) return rc;
+    if (K < 1 || K > kPbMaxK || !labels || !Z) return GEE_EINVAL;
+    const PbPlan p = pb_plan(pb, K);
+    if (!ws || !aligned(ws, 256) || ws_bytes < p.total) return GEE_EWORKSPACE;
+    char *w = static_cast<char *>(ws);
+    uint64_t *counts = reinterpret_cast<uint64_t *>(w + p.o_counts);
+    double *inv = reinterpret_cast<double *>(w + p.o_inv);
+    uint8_t *lab = reinterpret_cast<uint8_t *>(w + p.o_lab);
+    uint8_t *yv = reinterpret_cast<uint8_t *>(w + p.o_yv);
+    if ((rc = hip_rc(launch_counts(labels, pb->n, K, counts, lab, Pack::U8, err, stream)))) return rc;
+    if ((rc = hip_rc(launch_weights(counts, K, inv, stream)))) return rc;
+    const bool timed = opts && opts->hot_begin && opts->hot_end;
+    if (timed && (rc = hip_rc(hipEventRecord(opts->hot_begin, stream)))) return rc;
+    if ((rc = hip_rc(launch_pb_gather(pb->nnz, pb->col, lab, yv, stream)))) return rc;
+    const PbLayout L = pb_layout(pb->n);
+    if ((rc = hip_rc(launch_pb_rows(pb->n, K, L, pb->cell_start, pb->cell_count, pb->ul, yv, inv, Z, stream))))
+        return rc;
+    if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;
+    return GEE_OK;
+}
+
 size_t gee_csr_workspace(int64_t n, int64_t s, int weighted, int64_t hot_budget)
 {
     if (n < 1 || n > kMaxN || s < 0 || s > kMaxRecords || hot_budget < 0) return 0;

@@ -475,6 +475,50 @@ size_t csr_build_layout(int64_t n, int64_t s, bool weighted, int64_t n_hot, char
     return align_up(off, 256);
 }
 
+size_t radix_scratch_bytes(int64_t N, int64_t scan_n, size_t *hist_bytes, size_t *offs_bytes, size_t *part_bytes)
+{
+    const int64_t nt = tiles(N > 0 ? N : 1);
+    const int64_t hist_len = 256 * nt;
+    const int64_t scan_len = hist_len > scan_n ? hist_len : scan_n;
+    *hist_bytes = (size_t)hist_len * 4;
+    *offs_bytes = (size_t)hist_len * 8;
+    *part_bytes = (size_t)tiles(scan_len) * 8 + 8;
+    return *hist_bytes + *offs_bytes + *part_bytes;
+}
+
+hipError_t radix_sort_bits(uint64_t *keys0, uint64_t *keys1, int64_t N, int lo, int hi, uint32_t *hist,
+                           int64_t *offs, int64_t *scan_part, uint64_t **result, hipStream_t s)
+{
+    uint64_t *buf[2] = {keys0, keys1};
+    int cur = 0;
+    const int64_t nt = tiles(N);
+    hipError_t e;
+    for (int sh = lo; N > 0 && sh < hi; sh += 8) {
+        hipLaunchKernelGGL(k_radix_hist<false>, dim3((unsigned)nt), dim3(kT), 0, s, buf[cur], (const float *)nullptr,
+                           N, sh, false, hist, nt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = scan(hist, 256 * nt, offs, scan_part, SumOp{}, false, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nt), dim3(kT), 0, s, buf[cur], (const float *)nullptr,
+                           buf[cur ^ 1], (float *)nullptr, N, sh, false, offs, nt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        cur ^= 1;
+    }
+    *result = buf[cur];
+    return hipSuccess;
+}
+
+hipError_t max_scan_i64(const int64_t *in, int64_t N, int64_t *out, int64_t *scan_part, hipStream_t s)
+{
+    return scan(in, N, out, scan_part, MaxOp{}, true, s);
+}
+
+hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t value, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_cap(count, kT * 4)), dim3(kT), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
 hipError_t launch_csr_build(int64_t n, int64_t ns, const int32_t *src, const int32_t *dst, const float *w,
                             int64_t n_hot, int64_t *row_ptr, int32_t *col, float *val, int32_t *hot_ids,
                             const CsrBuildWs &ws, int32_t *err, hipStream_t s)

@@ -105,6 +105,35 @@ hipError_t launch_group_cols(const double *inv_all, const GroupDesc &d, double *
 hipError_t launch_rsd(const double *deg, int64_t n, float *rsd, hipStream_t s);
 hipError_t launch_pull_group(const GroupArgs &g, hipStream_t s);
 
+// Sorting and scanning pieces of the CSR build, shared by the propagation-blocked layout
+size_t radix_scratch_bytes(int64_t N, int64_t scan_n, size_t *hist_bytes, size_t *offs_bytes, size_t *part_bytes);
+// Stable LSD sort of N keys on bits [lo, hi) in 8-bit digits, ping-ponging between the two
+// buffers; *result is the buffer that holds the sorted keys.
+hipError_t radix_sort_bits(uint64_t *keys0, uint64_t *keys1, int64_t N, int lo, int hi, uint32_t *hist,
+                           int64_t *offs, int64_t *scan_part, uint64_t **result, hipStream_t s);
+hipError_t max_scan_i64(const int64_t *in, int64_t N, int64_t *out, int64_t *scan_part, hipStream_t s); // inclusive
+hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t value, hipStream_t s);
+
+// Propagation-blocked pull (unit-weight adjacency): entries of the CSR in column-block
+// order, 256-row blocks, 2^21-vertex column blocks.
+constexpr int kPbRowBits = 8;
+constexpr int kPbColBits = 21;
+constexpr int kPbMaxK = 128; // bins of a row block: 256 x K uint32 in LDS
+struct PbLayout {
+    int64_t n_rb = 0;
+    int32_t n_cb = 0;
+    int64_t cells = 0;
+};
+PbLayout pb_layout(int64_t n);
+size_t pb_build_scratch(int64_t n, int64_t nnz);
+hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const int32_t *hot_ids,
+                           int64_t n_hot, int32_t *colc, uint8_t *ul, int64_t *cell_start, uint32_t *cell_count,
+                           void *ws, int32_t *err, hipStream_t s);
+hipError_t launch_pb_gather(int64_t nnz, const int32_t *colc, const uint8_t *lab, uint8_t *yv, hipStream_t s);
+hipError_t launch_pb_rows(int64_t n, int32_t K, const PbLayout &L, const int64_t *cell_start,
+                          const uint32_t *cell_count, const uint8_t *ul, const uint8_t *yv, const double *inv, float *Z,
+                          hipStream_t s);
+
 // CSR build
 struct CsrBuildWs {
     uint64_t *keys[2];

@@ -153,3 +153,27 @@ def test_push_nonatomic_argument_errors(lib):
     o = gee.EmbedOpts(0, 0, None, None)
     assert lib.gee_embed_push_nonatomic(None, FAKE, 5, 0, FAKE, FAKE, 1 << 30, FAKE, ctypes.byref(o), None) == \
         gee.GEE_EINVAL
+
+
+def test_pb_argument_errors(lib):
+    """Layout sizes and the checks done before anything launches."""
+    assert lib.gee_pb_cells(0) == 0
+    assert lib.gee_pb_cells(256) == 1
+    assert lib.gee_pb_cells(257) == 2
+    assert lib.gee_pb_cells((1 << 21) + 1) == 2 * ((((1 << 21) + 1) + 255) // 256)
+    plain = gee.Csr(1000, 10_000, FAKE, FAKE, None, 0, None)
+    weighted = gee.Csr(1000, 10_000, FAKE, FAKE, FAKE, 0, None)
+    assert lib.gee_pb_build_workspace(ctypes.byref(plain)) > 10_000 * 16
+    assert lib.gee_pb_build_workspace(ctypes.byref(weighted)) == 0  # unit weights only
+    pb = gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE)
+    assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 128) > 10_000
+    assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 129) == 0
+    assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 0) == 0
+    bad = gee.Pb(1000, 10_000, 5, 1, FAKE, FAKE, FAKE, FAKE)  # n_rb does not match n
+    assert lib.gee_embed_pb_workspace(ctypes.byref(bad), 8) == 0
+    o = gee.EmbedOpts(0, 0, None, None)
+    assert lib.gee_embed_pb(ctypes.byref(bad), FAKE, 8, FAKE, FAKE, 1 << 30, FAKE, ctypes.byref(o), None) == \
+        gee.GEE_EINVAL
+    unaligned = gee.Pb(1000, 10_000, 4, 1, FAKE + 4, FAKE, FAKE, FAKE)
+    assert lib.gee_embed_pb(ctypes.byref(unaligned), FAKE, 8, FAKE, FAKE, 1 << 30, FAKE, ctypes.byref(o), None) == \
+        gee.GEE_EINVAL

@@ -1,0 +1,116 @@
+"""Propagation-blocked pull (unit-weight adjacency): the layout holds exactly the CSR's
+entries, and Z is bit-identical to the pull form (integer counts) on every shape."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+import paper_2402_04403_amd as gee
+from gpu_util import announce, assert_parity, random_labels
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    announce(request.node.nodeid)
+    yield
+    torch.cuda.synchronize()
+
+
+def _same_bits(a, b):
+    assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+def _check_layout(csr, pb):
+    """Every (row, column) entry of the CSR appears once in the layout, cells ordered by column block."""
+    rp = csr.row_ptr.cpu().numpy()
+    cols = csr.plain_col().cpu().numpy()
+    rows = np.repeat(np.arange(csr.n, dtype=np.int64), np.diff(rp))
+    start = pb.cell_start.cpu().numpy().reshape(pb.n_rb, pb.n_cb)
+    count = pb.cell_count.cpu().numpy().reshape(pb.n_rb, pb.n_cb).astype(np.int64)
+    assert count.sum() == csr.nnz
+    # column-block-major order: cells (cb, rb) are consecutive
+    order = np.argsort(start.T.reshape(-1), kind="stable")
+    flat_start, flat_count = start.T.reshape(-1)[order], count.T.reshape(-1)[order]
+    assert np.all(flat_start[1:] == (flat_start + flat_count)[:-1])
+    pcol = pb.col.cpu().numpy().astype(np.int64)
+    pul = pb.ul.cpu().numpy().astype(np.int64)
+    rb_of = np.repeat(np.repeat(np.arange(pb.n_rb), pb.n_cb), count.reshape(-1))
+    idx = np.concatenate([np.arange(a, a + c) for a, c in zip(start.reshape(-1), count.reshape(-1)) if c]) \
+        if csr.nnz else np.zeros(0, np.int64)
+    prow = rb_of * 256 + pul[idx]
+    assert np.all(pcol[idx] >> 21 == np.repeat(np.tile(np.arange(pb.n_cb), pb.n_rb), count.reshape(-1)))
+    a = np.lexsort((cols, rows))
+    b = np.lexsort((pcol[idx], prow))
+    assert np.array_equal(rows[a], prow[b]) and np.array_equal(cols[a], pcol[idx][b])
+
+
+def test_small_graph_matches_pull_and_oracle():
+    wl = gen.sbm_small()
+    g = wl.graph
+    coo = gee.to_device(g.n, g.src, g.dst, None, device=DEV)
+    csr = gee.csr_build(coo)
+    pb = gee.pb_build(csr)
+    _check_layout(csr, pb)
+    Y = torch.as_tensor(wl.labels).to(DEV)
+    Zb = gee.embed_pb(Y, wl.K, pb)
+    _same_bits(Zb, gee.embed(Y, wl.K, csr=csr))
+    assert_parity(Zb.cpu().numpy(), oracle.embed(g.n, g.src, g.dst, None, wl.labels, wl.K, False), what="sbm")
+
+
+@pytest.mark.parametrize("hot", [0, 5000])
+@pytest.mark.parametrize("K", [1, 7, 50, 128])
+def test_several_column_blocks(hot, K):
+    """n = 2^21 + 1000 vertices: two column blocks and a partial last row block; R-MAT hubs."""
+    n = (1 << 21) + 1000
+    rng = np.random.default_rng(K + hot)
+    g = gen.rmat(21, 6 << 21, seed=5)
+    src = np.r_[g.src, rng.integers(0, n, 200_000).astype(np.int32), np.full(50_000, n - 1, np.int32)]
+    dst = np.r_[g.dst, rng.integers(0, n, 200_000).astype(np.int32), rng.integers(0, n, 50_000).astype(np.int32)]
+    coo = gee.to_device(n, src, dst, None, device=DEV)
+    csr = gee.csr_build(coo, hot_budget=hot)
+    pb = gee.pb_build(csr)
+    assert pb.n_cb == 2
+    Y = torch.as_tensor(random_labels(rng, n, K, unknown=0.3)).to(DEV)
+    _same_bits(gee.embed_pb(Y, K, pb), gee.embed(Y, K, csr=csr))
+
+
+def test_layout_of_two_column_blocks():
+    n = (1 << 21) + 300
+    rng = np.random.default_rng(2)
+    src = rng.integers(0, n, 400_000).astype(np.int32)
+    dst = rng.integers(0, n, 400_000).astype(np.int32)
+    csr = gee.csr_build(gee.to_device(n, src, dst, None, device=DEV), hot_budget=1000)
+    _check_layout(csr, gee.pb_build(csr))
+
+
+def test_all_unknown_and_empty_graph():
+    rng = np.random.default_rng(3)
+    n = 5000
+    g = gen.rmat(12, 20_000, seed=3)
+    csr = gee.csr_build(gee.to_device(g.n, g.src, g.dst, None, device=DEV))
+    pb = gee.pb_build(csr)
+    Z = gee.embed_pb(torch.zeros(g.n, dtype=torch.int32, device=DEV), 4, pb)
+    assert torch.count_nonzero(Z) == 0
+    empty = gee.csr_build(gee.to_device(n, np.zeros(0, np.int32), np.zeros(0, np.int32), None, device=DEV))
+    pe = gee.pb_build(empty)
+    Z = gee.embed_pb(torch.as_tensor(random_labels(rng, n, 3)).to(DEV), 3, pe)
+    assert torch.count_nonzero(Z) == 0
+
+
+def test_errors():
+    g = gen.rmat(10, 4000, seed=4)
+    csr = gee.csr_build(gee.to_device(g.n, g.src, g.dst, None, device=DEV))
+    pb = gee.pb_build(csr)
+    Y = torch.ones(g.n, dtype=torch.int32, device=DEV)
+    Y[7] = 6
+    with pytest.raises(gee.GeeError) as e:
+        gee.embed_pb(Y, 5, pb)
+    assert e.value.code == gee.GEE_ELABEL
+    w = np.ones(g.s, np.float32)
+    wcsr = gee.csr_build(gee.to_device(g.n, g.src, g.dst, w, device=DEV))
+    with pytest.raises(gee.GeeError):
+        gee.pb_build(wcsr)

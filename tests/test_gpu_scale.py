@@ -1,7 +1,8 @@
 """Parity at the workload sizes: the Erdős–Rényi weighted graph (n = 2^22, s = 2^26,
 K = 50) in full against the oracle, and the paper-scale R-MAT (scale 27, edge factor
 14, 1,879,048,192 records) on sampled rows, in the launch configuration the
-benchmark times (default segment length and window)."""
+benchmark times (default segment length and window), with the propagation-blocked
+pass compared in full against the pull pass."""
 import time
 
 import numpy as np
@@ -72,9 +73,14 @@ def test_rmat_paper_scale_sampled_rows():
     idx = torch.as_tensor(rows, device=DEV)
     Zp = gee.embed(labels, wl.K, csr=csr)
     pull_rows = Zp[idx].cpu().numpy()
-    del Zp
-    torch.cuda.empty_cache()
     announce(f"  pull done {time.time() - t0:.1f}s")
+    # propagation-blocked layout of the same CSR: all of Z, bit for bit
+    pb = gee.pb_build(csr)
+    Zb = gee.embed_pb(labels, wl.K, pb)
+    assert torch.equal(Zb.view(torch.int32), Zp.view(torch.int32))
+    del Zp, Zb, pb
+    torch.cuda.empty_cache()
+    announce(f"  propagation-blocked pass equal in full {time.time() - t0:.1f}s")
     Za = gee.embed(labels, wl.K, coo=coo)
     push_rows = Za[idx].cpu().numpy()
     del Za
