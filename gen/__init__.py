@@ -72,6 +72,8 @@ def _load():
         lib.gen_rmat.argtypes = [ctypes.c_int, i64, f64, f64, f64, u64, ctypes.c_int, I32P, I32P]
         lib.gen_sbm.restype = i64
         lib.gen_sbm.argtypes = [i64, i64, f64, f64, u64, i64, I32P, I32P]
+        lib.gen_sbm_records.restype = None
+        lib.gen_sbm_records.argtypes = [i64, i64, f64, i64, u64, I32P, I32P]
         lib.gen_labels_uniform.restype = None
         lib.gen_labels_uniform.argtypes = [i64, i32, u64, I32P]
         lib.gen_unlabel_exact.restype = ctypes.c_int
@@ -142,6 +144,19 @@ def sbm(n: int, nb: int, p_in: float, p_out: float, seed: int) -> Graph:
     if s < 0:
         raise RuntimeError("sbm: record count exceeded capacity")
     return Graph(n, src[:s].copy(), dst[:s].copy(), None)
+
+
+def sbm_records(n: int, nb: int, ratio: float, s: int, seed: int) -> Graph:
+    """SBM with nb equal blocks by record sampling: s records, density inside blocks
+    ratio times the density between them (repeats possible)."""
+    sizes = np.diff((np.arange(nb + 1, dtype=np.int64) * n + nb - 1) // nb)
+    W = float((sizes * (sizes - 1) // 2).sum())
+    B = n * (n - 1) / 2 - W
+    p_within = ratio * W / (ratio * W + B) if (ratio * W + B) > 0 else 1.0
+    src = np.empty(s, np.int32)
+    dst = np.empty(s, np.int32)
+    _load().gen_sbm_records(n, nb, p_within, s, seed, _p(src, I32P), _p(dst, I32P))
+    return Graph(n, src, dst, None)
 
 
 def labels_uniform(n: int, K: int, seed: int) -> np.ndarray:
@@ -259,3 +274,86 @@ def rmat_batched(seed: int = 4, scale: int = 24, edge_factor: int = 16, B: int =
     g = rmat(scale, edge_factor * n, seed)
     Ks, fs, laps = batch_params(B, seed)
     return BatchWorkload(f"rmat-s{scale}-ef{edge_factor}-B{B}", g, batch_labels(n, Ks, fs, seed), Ks, fs, laps)
+
+
+# ----------------------------------------------------------- serving mix ----
+
+SERVE_STREAM = 17  # counter stream of the serving mix draws
+
+
+def _normal(seed: int, stream: int, ctr: int) -> float:
+    u1 = max(_unit(seed, stream, 2 * ctr), 2.0 ** -53)
+    u2 = _unit(seed, stream, 2 * ctr + 1)
+    return float(np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2))
+
+
+@dataclass
+class PoolGraph:
+    gid: int
+    kind: str  # "sbm" or "rmat"
+    n: int
+    s: int
+    seed: int
+
+    def make(self) -> Graph:
+        if self.kind == "sbm":
+            return sbm_records(self.n, 10, 10.0, self.s, self.seed)
+        return rmat(int(self.n).bit_length() - 1, self.s, self.seed)
+
+
+@dataclass
+class Job:
+    jid: int
+    gid: int
+    Ks: list
+    fs: list
+    laplacian: bool
+    seed: int
+
+    def labels(self, n: int) -> np.ndarray:
+        return batch_labels(n, self.Ks, self.fs, self.seed)
+
+
+def serve_pool(seed: int = 5, graphs: int = 100, mu: float = 12.32, sigma: float = 1.80,
+               s_min: int = 1_000, s_max: int = 50_000_000):
+    """Graphs of uneven size: s ~ log-normal(mu, sigma) truncated to [s_min, s_max]; even ids
+    SBM (10 blocks, inside/between density 10, mean degree 16: n = s / 8), odd ids R-MAT
+    (edge factor 16: n = the power of two nearest s / 16)."""
+    pool = []
+    for g in range(graphs):
+        x = int(round(np.exp(mu + sigma * _normal(seed, SERVE_STREAM, g))))
+        s = min(max(x, s_min), s_max)
+        if g % 2 == 0:
+            pool.append(PoolGraph(g, "sbm", max(s // 8, 16), s, seed * 1_000 + g))
+        else:
+            scale = max(int(round(np.log2(max(s / 16, 2)))), 4)
+            pool.append(PoolGraph(g, "rmat", 1 << scale, s, seed * 1_000 + g))
+    return pool
+
+
+def serve_jobs(pool, seed: int = 6, jobs: int = 2000, zipf: float = 1.1, k_lo: int = 2, k_hi: int = 128):
+    """Jobs on the pool: graph by Zipf(zipf) over the pool ids (id 0 most popular), 1..8
+    vectors, K log-uniform on [k_lo, k_hi], unknown fraction U[0, 0.5), version
+    Bernoulli(1/2) per job."""
+    w = 1.0 / np.arange(1, len(pool) + 1, dtype=np.float64) ** zipf
+    cdf = np.cumsum(w / w.sum())
+    out = []
+    lo, hi = np.log(k_lo), np.log(k_hi + 1)
+    for j in range(jobs):
+        g = int(np.searchsorted(cdf, _unit(seed, SERVE_STREAM + 1, 4 * j), side="right"))
+        g = min(g, len(pool) - 1)
+        B = 1 + int(_unit(seed, SERVE_STREAM + 1, 4 * j + 1) * 8)
+        lap = _unit(seed, SERVE_STREAM + 1, 4 * j + 2) < 0.5
+        Ks, fs = [], []
+        for b in range(B):
+            c = (j * 8 + b) * 2
+            Ks.append(min(max(int(np.floor(np.exp(lo + _unit(seed, SERVE_STREAM + 2, c) * (hi - lo)))), k_lo), k_hi))
+            fs.append(0.5 * _unit(seed, SERVE_STREAM + 2, c + 1))
+        out.append(Job(j, g, Ks, fs, lap, seed * 1_000_003 + j))
+    return out
+
+
+def poisson_arrivals(rate: float, jobs: int, seed: int = 7) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of the given rate."""
+    gaps = np.array([-np.log(max(1.0 - _unit(seed, SERVE_STREAM + 3, j), 2.0 ** -53)) / rate for j in range(jobs)])
+    return np.cumsum(gaps)

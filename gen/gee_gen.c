@@ -34,6 +34,10 @@ enum {
     STREAM_SCRAMBLE = 10,
     STREAM_SBM_FLIP = 11,
     STREAM_WEIGHT = 12,
+    /* 13: per-vector batch parameters (drawn from Python) */
+    STREAM_SBMR_TYPE = 14,
+    STREAM_SBMR_U = 15,
+    STREAM_SBMR_V = 16,
 };
 
 static inline uint64_t mix64(uint64_t z)
@@ -181,6 +185,31 @@ static inline int64_t sbm_block(int64_t v, int64_t n, int64_t nb) { return (v * 
  * stored once, oriented at random, and the records are then shuffled by a
  * seeded Fisher-Yates pass. Returns the record count, or -1 if it would
  * exceed `cap` (nothing useful is written then). */
+/* SBM by record sampling, for graphs too large for pair enumeration: s records, each a
+ * within-block pair with probability p_within and a between-block pair otherwise, both
+ * endpoints uniform under that constraint (repeats and self-loops possible). With
+ * p_within = r W / (r W + B) for W within-block and B between-block vertex pairs, the
+ * expected density inside blocks is r times that between them. */
+void gen_sbm_records(int64_t n, int64_t nb, double p_within, int64_t s, uint64_t seed, int32_t *src, int32_t *dst)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < s; ++i) {
+        const int64_t u = (int64_t)bounded32(rng_at(seed, STREAM_SBMR_U, (uint64_t)i), (uint64_t)n);
+        const int64_t bu = sbm_block(u, n, nb);
+        const int64_t b0 = (bu * n + nb - 1) / nb, b1 = ((bu + 1) * n + nb - 1) / nb; /* block bu = [b0, b1) */
+        const uint64_t rv = rng_at(seed, STREAM_SBMR_V, (uint64_t)i);
+        int64_t v;
+        if (u01(rng_at(seed, STREAM_SBMR_TYPE, (uint64_t)i)) < p_within || b1 - b0 == n) {
+            v = b0 + (int64_t)bounded32(rv, (uint64_t)(b1 - b0));
+        } else {
+            v = (int64_t)bounded32(rv, (uint64_t)(n - (b1 - b0)));
+            if (v >= b0) v += b1 - b0;
+        }
+        src[i] = (int32_t)u;
+        dst[i] = (int32_t)v;
+    }
+}
+
 int64_t gen_sbm(int64_t n, int64_t nb, double p_in, double p_out, uint64_t seed, int64_t cap,
                 int32_t *src, int32_t *dst)
 {

@@ -174,6 +174,7 @@ class HipEvent:
             hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
             hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
             hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+            hip.hipEventQuery.argtypes = [ctypes.c_void_p]
             HipEvent._hip = hip
         self.handle = ctypes.c_void_p()
         if HipEvent._hip.hipEventCreate(ctypes.byref(self.handle)) != 0:
@@ -185,6 +186,13 @@ class HipEvent:
 
     def synchronize(self):
         HipEvent._hip.hipEventSynchronize(self.handle)
+
+    def done(self) -> bool:
+        """True once the work recorded before the event has completed (hipEventQuery)."""
+        rc = HipEvent._hip.hipEventQuery(self.handle)
+        if rc not in (0, 600):  # hipSuccess, hipErrorNotReady
+            raise RuntimeError(f"hipEventQuery failed ({rc})")
+        return rc == 0
 
     def elapsed_ms(self, end: "HipEvent") -> float:
         ms = ctypes.c_float()

@@ -89,3 +89,24 @@ def test_output_independent_of_thread_count():
         env = dict(os.environ, OMP_NUM_THREADS=t)
         outs.append(subprocess.check_output([sys.executable, "-c", code], env=env).strip())
     assert outs[0] == outs[1]
+
+
+def test_serving_mix_recipe():
+    """Pool sizes within the truncation, both graph kinds, Zipf-skewed job placement,
+    K and vector counts in range, reproducible draws."""
+    pool = gen.serve_pool()
+    assert len(pool) == 100 and {p.kind for p in pool} == {"sbm", "rmat"}
+    assert all(1_000 <= p.s <= 50_000_000 for p in pool)
+    jobs = gen.serve_jobs(pool, jobs=500)
+    assert all(1 <= len(j.Ks) <= 8 and all(2 <= k <= 128 for k in j.Ks) for j in jobs)
+    assert all(0.0 <= f < 0.5 for j in jobs for f in j.fs)
+    counts = np.bincount([j.gid for j in jobs], minlength=100)
+    assert counts[0] == counts.max() and counts[0] > 3 * counts[10]
+    again = gen.serve_jobs(gen.serve_pool(), jobs=500)
+    assert [(j.gid, j.Ks, j.laplacian) for j in jobs] == [(j.gid, j.Ks, j.laplacian) for j in again]
+    g = gen.sbm_records(10_000, 10, 10.0, 200_000, seed=3)
+    blk_u, blk_v = g.src * 10 // 10_000, g.dst * 10 // 10_000
+    within = np.mean(blk_u == blk_v)
+    assert abs(within - 10 * 0.1 / (10 * 0.1 + 0.9)) < 0.01  # inside/between density ratio 10
+    t = gen.poisson_arrivals(100.0, 2000)
+    assert np.all(np.diff(t) > 0) and abs(t[-1] / 2000 - 0.01) < 0.001

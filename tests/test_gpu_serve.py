@@ -1,0 +1,98 @@
+"""Serving loop: a job's Z is the same alone and in the mix (bit for bit), plain and batched
+modes agree, graphs are evicted and rebuilt under a small HBM budget, and a job that can
+never fit is refused."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+import paper_2402_04403_amd as gee
+from gpu_util import announce, assert_parity
+from paper_2402_04403_amd.serve import Request, Server
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    announce(request.node.nodeid)
+    yield
+    torch.cuda.synchronize()
+
+
+def _pool():
+    pool = [gen.PoolGraph(0, "sbm", 20_000, 160_000, 11), gen.PoolGraph(1, "rmat", 1 << 14, 1 << 18, 12),
+            gen.PoolGraph(2, "sbm", 3_000, 24_000, 13)]
+    graphs = {}
+    for p in pool:
+        g = p.make()
+        graphs[p.gid] = (p.n, g.src, g.dst)
+    jobs = [j for j in gen.serve_jobs(pool, seed=21, jobs=40, k_hi=64)]
+    return pool, graphs, jobs
+
+
+def _reqs(graphs, jobs, t=0.0):
+    return [Request(j.jid, j.gid, j.Ks, [j.laplacian] * len(j.Ks),
+                    torch.from_numpy(j.labels(graphs[j.gid][0])).pin_memory(), t) for j in jobs]
+
+
+def _run(server, reqs):
+    for r in reqs:
+        r.arrival = time.perf_counter()
+        server.submit(r)
+    return {d.jid: d for d in server.drain()}
+
+
+def test_alone_equals_in_the_mix():
+    pool, graphs, jobs = _pool()
+    mix = _run(Server(graphs, 8 << 30, streams=3, keep_results=True), _reqs(graphs, jobs))
+    assert len(mix) == len(jobs) and all(d.error == 0 for d in mix.values())
+    for j in jobs[::3]:
+        alone = _run(Server(graphs, 8 << 30, streams=1, keep_results=True), _reqs(graphs, [j]))
+        assert torch.equal(alone[j.jid].Z.view(torch.int32), mix[j.jid].Z.view(torch.int32)), j.jid
+
+
+def test_plain_matches_batched_and_oracle():
+    pool, graphs, jobs = _pool()
+    jobs = jobs[:12]
+    b = _run(Server(graphs, 8 << 30, keep_results=True), _reqs(graphs, jobs))
+    p = _run(Server(graphs, 8 << 30, mode="plain", keep_results=True), _reqs(graphs, jobs))
+    for j in jobs:
+        zb, zp = b[j.jid].Z.cpu().numpy(), p[j.jid].Z.cpu().numpy()
+        n, src, dst = graphs[j.gid]
+        Y = j.labels(n)
+        col = 0
+        for k, y in zip(j.Ks, Y):
+            if not j.laplacian:  # integer sums: identical bits
+                assert np.array_equal(zb[:, col:col + k].view(np.uint32), zp[:, col:col + k].view(np.uint32))
+            else:
+                assert_parity(zp[:, col:col + k], zb[:, col:col + k], what=f"job {j.jid}")
+            col += k
+        if j.jid % 4 == 0:
+            assert_parity(zb[:, :j.Ks[0]], oracle.embed(n, src, dst, None, Y[0], j.Ks[0], j.laplacian),
+                          what=f"job {j.jid} vs oracle")
+
+
+def test_small_budget_evicts_and_refuses():
+    """Two graphs of equal size and jobs of equal shape alternating between them, under a
+    budget that holds one graph and one launch but not both graphs: every switch evicts."""
+    pool = [gen.PoolGraph(0, "sbm", 12_000, 96_000, 31), gen.PoolGraph(1, "sbm", 12_000, 96_000, 32)]
+    graphs = {p.gid: (p.n, p.make().src, p.make().dst) for p in pool}
+    jobs = [gen.Job(i, i % 2, [16, 8], [0.1, 0.3], i % 3 == 0, 900 + i) for i in range(8)]
+    probe = Server(graphs, 8 << 30, hot_budget=0)
+    g = probe._resident(0)
+    G, L = g.bytes, probe._launch_bytes(g, [16, 8], [True, True])
+    srv = Server(graphs, G + L + G // 2, streams=2, keep_results=True, hot_budget=0)
+    got = _run(srv, _reqs(graphs, jobs))
+    assert len(got) == len(jobs) and srv.evictions > 0
+    assert srv.used == sum(x.bytes for x in srv.resident.values())
+    ref = _run(Server(graphs, 8 << 30, keep_results=True, hot_budget=0), _reqs(graphs, jobs))
+    for j in jobs:
+        assert torch.equal(got[j.jid].Z.view(torch.int32), ref[j.jid].Z.view(torch.int32))
+    tiny = Server(graphs, G + L // 2, hot_budget=0)
+    tiny.submit(_reqs(graphs, jobs[:1])[0])
+    with pytest.raises(ValueError):
+        tiny.drain()
