@@ -162,37 +162,60 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
  * the pass only needs, per entry, its row and the label of its column, so the
  * entries can be re-laid out once per graph: sorted stably by column block (2^21
  * vertices), each entry keeping its column and its row within a block of 256 rows.
- * Per call, one streaming pass writes every entry's label in that order (a column
- * block's labels stay in L2) and a second pass counts, per 256-row block, the
- * (row, class) pairs of the block's cells in LDS and writes those rows of Z once.
- * Counts are integers: Z is bit-identical to gee_embed on the same CSR.
+ * Entries whose column is one of the CSR's first n_lds hot slots (its highest-degree
+ * vertices, n_lds <= 2^22) go instead to "tier slices" of 2^17 slots each, one extra
+ * column block per slice after the vertex blocks, and keep their slot within the
+ * slice. Per call, one streaming pass writes every entry's label in that order (a
+ * vertex block's labels stay in L2; a slice's labels, 128 KB, are read from LDS) and
+ * a second pass counts, per 256-row block, the (row, class) pairs of the block's
+ * cells in LDS and writes those rows of Z once. Counts are integers: Z is
+ * bit-identical to gee_embed on the same CSR.
  *
  * Cell (rb, cb) of the layout is the run of column block cb's entries whose rows
  * lie in [256 rb, 256 rb + 256); cell_start[rb * n_cb + cb] is its first index in
- * col/ul and cell_count[...] its length. n_rb = ceil(n / 256), n_cb = ceil(n / 2^21).
+ * col/ul and cell_count[...] its length. n_rb = ceil(n / 256),
+ * n_cb = ceil(n / 2^21) + ceil(n_lds / 2^17). The layout holds at most 2^32 - 65
+ * entries (GEE_EOVERFLOW beyond).
  * ------------------------------------------------------------------------------ */
+#define GEE_PB_SLICE 131072        /* hot slots per tier slice */
+#define GEE_PB_MAX_TIER 4194304    /* at most 32 slices */
+
 typedef struct gee_pb {
     int64_t n, nnz;            /* vertices, entries (as in the CSR) */
     int64_t n_rb;              /* row blocks */
-    int32_t n_cb;              /* column blocks */
-    const int32_t *col;        /* [nnz] column of every entry, layout order; 16-byte aligned */
-    const uint8_t *ul;         /* [nnz] row within its 256-row block */
+    int32_t n_cb;              /* column blocks: vertex blocks, then tier slices */
+    const int32_t *col;        /* [nnz] column (slot within the slice for tier entries), layout order; 16-byte aligned */
+    const uint8_t *ul;         /* [nnz rounded up to 16] row within its 256-row block; 16-byte aligned */
     const int64_t *cell_start; /* [n_rb * n_cb] */
     const uint32_t *cell_count; /* [n_rb * n_cb] */
+    int64_t n_lds;             /* tier slots the layout was built with (0 to GEE_PB_MAX_TIER) */
+    const int32_t *lds_ids;    /* [n_lds] vertex of each tier slot (written by gee_pb_build) */
 } gee_pb;
 
-/* n_rb * n_cb for n vertices (0 on invalid n). */
-int64_t gee_pb_cells(int64_t n);
+/* n_rb * n_cb for n vertices and n_lds tier slots (0 on invalid input). */
+int64_t gee_pb_cells(int64_t n, int64_t n_lds);
 
-/* Scratch bytes gee_pb_build needs (0 on invalid input or a weighted CSR). */
-size_t gee_pb_build_workspace(const gee_csr *csr);
+/* A tier size for the layout of csr: the hot slots of the longest run of leading
+ * slices (at most 32, of min(n_hot, GEE_PB_MAX_TIER) slots) whose entries average at
+ * least min_per_row_block per 256-row block, since each slice adds one cell to every
+ * row block. Counts each slice's entries on the GPU (row lengths of its vertices) in
+ * ws (device, 256-byte aligned, at least 256 bytes) and SYNCHRONIZES the stream.
+ * Returns the slot count (0 for no tier) or a negative status. */
+int64_t gee_pb_tier_slots(const gee_csr *csr, int64_t min_per_row_block, void *ws, size_t ws_bytes,
+                          hipStream_t stream);
 
-/* Builds the layout of a unit-weight CSR (csr->val must be NULL; hot-slot columns
- * are decoded through hot_ids). Outputs are caller device buffers: col [nnz]
- * (16-byte aligned), ul [nnz], cell_start and cell_count [gee_pb_cells(n)]. A
- * column id outside [0, n) stores GEE_EVERTEX in *err. */
-int gee_pb_build(const gee_csr *csr, int32_t *col, uint8_t *ul, int64_t *cell_start, uint32_t *cell_count, void *ws,
-                 size_t ws_bytes, int32_t *err, hipStream_t stream);
+/* Scratch bytes gee_pb_build needs (0 on invalid input, a weighted CSR, more than
+ * 2^32 - 65 entries, or n_lds above min(n_hot, GEE_PB_MAX_TIER)). */
+size_t gee_pb_build_workspace(const gee_csr *csr, int64_t n_lds);
+
+/* Builds the layout of a unit-weight CSR (csr->val must be NULL) with the first n_lds
+ * hot slots (0 <= n_lds <= min(n_hot, GEE_PB_MAX_TIER)) in the tier; other hot-slot
+ * columns are decoded through hot_ids. Outputs are caller device buffers: col [nnz]
+ * (16-byte aligned), ul [nnz rounded up to 16] (16-byte aligned), cell_start and
+ * cell_count [gee_pb_cells(n, n_lds)], lds_ids [n_lds] (may be NULL when n_lds = 0).
+ * A column id outside [0, n) stores GEE_EVERTEX in *err. */
+int gee_pb_build(const gee_csr *csr, int64_t n_lds, int32_t *col, uint8_t *ul, int64_t *cell_start,
+                 uint32_t *cell_count, int32_t *lds_ids, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream);
 
 /* Workspace bytes of gee_embed_pb (0 on invalid input); 1 <= K <= 128. */
 size_t gee_embed_pb_workspace(const gee_pb *pb, int32_t K);
@@ -200,7 +223,7 @@ size_t gee_embed_pb_workspace(const gee_pb *pb, int32_t K);
 /* Algorithm 1, adjacency version, unit weights, over the layout: labels [n] in
  * [0, K] (K <= 128), Z [n * K] FP32 overwritten. Same results and data errors as
  * gee_embed on the CSR the layout was built from. opts->hot_begin / hot_end
- * bracket the two passes (label gather and row counts); seg_len is unused. */
+ * bracket the two passes (label gathers and row counts); seg_len is unused. */
 int gee_embed_pb(const gee_pb *pb, const int32_t *labels, int32_t K, float *Z, void *ws, size_t ws_bytes,
                  int32_t *err, const gee_embed_opts *opts, hipStream_t stream);
 

@@ -57,7 +57,7 @@ class Csr(ctypes.Structure):
 class Pb(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_rb", ctypes.c_int64), ("n_cb", ctypes.c_int32),
                 ("col", ctypes.c_void_p), ("ul", ctypes.c_void_p), ("cell_start", ctypes.c_void_p),
-                ("cell_count", ctypes.c_void_p)]
+                ("cell_count", ctypes.c_void_p), ("n_lds", ctypes.c_int64), ("lds_ids", ctypes.c_void_p)]
 
 
 class Batch(ctypes.Structure):
@@ -101,11 +101,13 @@ def load():
         lib.gee_embed.argtypes = [CooP, CsrP, vp, i32, ci, vp, vp, sz, vp, OptP, vp]
         PbP = ctypes.POINTER(Pb)
         lib.gee_pb_cells.restype = i64
-        lib.gee_pb_cells.argtypes = [i64]
+        lib.gee_pb_cells.argtypes = [i64, i64]
+        lib.gee_pb_tier_slots.restype = i64
+        lib.gee_pb_tier_slots.argtypes = [CsrP, i64, vp, sz, vp]
         lib.gee_pb_build_workspace.restype = sz
-        lib.gee_pb_build_workspace.argtypes = [CsrP]
+        lib.gee_pb_build_workspace.argtypes = [CsrP, i64]
         lib.gee_pb_build.restype = ci
-        lib.gee_pb_build.argtypes = [CsrP, vp, vp, vp, vp, vp, sz, vp, vp]
+        lib.gee_pb_build.argtypes = [CsrP, i64, vp, vp, vp, vp, vp, vp, sz, vp, vp]
         lib.gee_embed_pb_workspace.restype = sz
         lib.gee_embed_pb_workspace.argtypes = [PbP, i32]
         lib.gee_embed_pb.restype = ci
@@ -342,18 +344,21 @@ def csr_build(coo: DeviceCoo, hot_budget: int = 0, stream=None, check: bool = Tr
 
 PB_ROWS = 256
 PB_COLS = 1 << 21
+PB_SLICE = 1 << 17
+PB_MAX_TIER = 1 << 22
 
 
 @dataclass
 class DevicePb:
     """Propagation-blocked layout of a unit-weight CSR (entries by 2^21-vertex column
-    block; cells of 256-row blocks)."""
+    block, then by tier slice of 2^17 hot slots; cells of 256-row blocks)."""
 
     n: int
     col: torch.Tensor
-    ul: torch.Tensor
+    ul: torch.Tensor          # [nnz rounded up to 16]
     cell_start: torch.Tensor
     cell_count: torch.Tensor
+    lds_ids: torch.Tensor     # [n_lds]
 
     @property
     def nnz(self) -> int:
@@ -365,34 +370,53 @@ class DevicePb:
 
     @property
     def n_cb(self) -> int:
-        return max((self.n + PB_COLS - 1) // PB_COLS, 1)
+        return (self.n + PB_COLS - 1) // PB_COLS + (self.n_lds + PB_SLICE - 1) // PB_SLICE
+
+    @property
+    def n_lds(self) -> int:
+        return int(self.lds_ids.numel())
 
     def struct(self) -> Pb:
         return Pb(self.n, self.nnz, self.n_rb, self.n_cb, _ptr(self.col), _ptr(self.ul), _ptr(self.cell_start),
-                  _ptr(self.cell_count))
+                  _ptr(self.cell_count), self.n_lds, _ptr(self.lds_ids) if self.n_lds else None)
 
 
-def pb_build(csr: DeviceCsr, stream=None, check: bool = True) -> DevicePb:
-    """Layout for gee_embed_pb from a unit-weight CSR (per-graph preprocessing)."""
+def pb_tier_slots(csr: DeviceCsr, min_per_row_block: int = 4, stream=None) -> int:
+    """Tier size for pb_build: leading slices of 2^17 hot slots whose entries average at
+    least ``min_per_row_block`` per 256-row block (gee_pb_tier_slots; synchronizes)."""
+    lib = load()
+    ws = torch.empty(256, dtype=torch.uint8, device=csr.row_ptr.device)
+    r = int(lib.gee_pb_tier_slots(ctypes.byref(csr.struct()), min_per_row_block, _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    if r < 0:
+        raise GeeError(r, "gee_pb_tier_slots")
+    return r
+
+
+def pb_build(csr: DeviceCsr, tier_slots: int | None = None, stream=None, check: bool = True) -> DevicePb:
+    """Layout for gee_embed_pb from a unit-weight CSR (per-graph preprocessing). The first
+    ``tier_slots`` hot slots are read from LDS; None takes pb_tier_slots(csr)."""
     lib = load()
     rs = csr.struct()
     dev = csr.row_ptr.device
-    cells = int(lib.gee_pb_cells(csr.n))
-    wsb = int(lib.gee_pb_build_workspace(ctypes.byref(rs)))
+    n_lds = pb_tier_slots(csr, stream=stream) if tier_slots is None else int(tier_slots)
+    cells = int(lib.gee_pb_cells(csr.n, n_lds))
+    wsb = int(lib.gee_pb_build_workspace(ctypes.byref(rs), n_lds))
     if wsb == 0 or cells == 0:
         raise GeeError(GEE_EINVAL, "gee_pb_build_workspace")
     col = torch.empty(max(csr.nnz, 1), dtype=torch.int32, device=dev)[: csr.nnz]
-    ul = torch.empty(max(csr.nnz, 1), dtype=torch.uint8, device=dev)[: csr.nnz]
+    ul = torch.empty((csr.nnz + 15) // 16 * 16 or 16, dtype=torch.uint8, device=dev)
     cell_start = torch.empty(cells, dtype=torch.int64, device=dev)
     cell_count = torch.empty(cells, dtype=torch.int32, device=dev)
+    lds_ids = torch.empty(n_lds, dtype=torch.int32, device=dev)
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     err = torch.zeros(1, dtype=torch.int32, device=dev)
-    _rc(lib.gee_pb_build(ctypes.byref(rs), _ptr(col), _ptr(ul), _ptr(cell_start), _ptr(cell_count), _ptr(ws), wsb,
-                         _ptr(err), _stream(stream)), "gee_pb_build")
+    _rc(lib.gee_pb_build(ctypes.byref(rs), n_lds, _ptr(col), _ptr(ul), _ptr(cell_start), _ptr(cell_count),
+                         _ptr(lds_ids) if n_lds else None, _ptr(ws), wsb, _ptr(err), _stream(stream)), "gee_pb_build")
     if check:
         _check_err(err, "gee_pb_build")
     del ws
-    return DevicePb(csr.n, col, ul, cell_start, cell_count)
+    return DevicePb(csr.n, col, ul, cell_start, cell_count, lds_ids)
 
 
 def embed_pb_workspace_bytes(pb: DevicePb, K: int) -> int:

@@ -433,29 +433,55 @@ int gee_embed_batch(const gee_csr *csr, const gee_batch *batch, void *ws, size_t
     return GEE_OK;
 }
 
-int64_t gee_pb_cells(int64_t n)
+int64_t gee_pb_cells(int64_t n, int64_t n_lds)
 {
-    if (n < 1 || n > kMaxN) return 0;
-    return pb_layout(n).cells;
+    if (n < 1 || n > kMaxN || n_lds < 0 || n_lds > kPbMaxSlices * kPbSlice) return 0;
+    return pb_layout(n, n_lds).cells;
 }
 
-size_t gee_pb_build_workspace(const gee_csr *csr)
+int64_t gee_pb_tier_slots(const gee_csr *csr, int64_t min_per_row_block, void *ws, size_t ws_bytes,
+                          hipStream_t stream)
 {
-    if (check_csr(csr) != GEE_OK || csr->val) return 0;
-    return pb_build_scratch(csr->n, csr->nnz);
+    int rc;
+    if ((rc = check_csr(csr)) != GEE_OK) return rc;
+    if (min_per_row_block < 0) return GEE_EINVAL;
+    const int64_t cap = csr->hot_ids ? (csr->n_hot < kPbMaxSlices * kPbSlice ? csr->n_hot : kPbMaxSlices * kPbSlice) : 0;
+    if (cap == 0) return 0;
+    if (!ws || !aligned(ws, 256) || ws_bytes < (size_t)kPbMaxSlices * 8) return GEE_EWORKSPACE;
+    int64_t *dev = static_cast<int64_t *>(ws);
+    int64_t host[kPbMaxSlices] = {};
+    const int64_t n_sl = (cap + kPbSlice - 1) >> kPbSliceBits;
+    if ((rc = hip_rc(launch_pb_slice_entries(cap, csr->hot_ids, csr->row_ptr, dev, stream)))) return rc;
+    if ((rc = hip_rc(hipMemcpyAsync(host, dev, (size_t)n_sl * 8, hipMemcpyDeviceToHost, stream)))) return rc;
+    if ((rc = hip_rc(hipStreamSynchronize(stream)))) return rc;
+    const int64_t need = min_per_row_block * ((csr->n + 255) / 256);
+    int64_t slices = 0;
+    while (slices < n_sl && host[slices] >= need) ++slices;
+    return slices == n_sl ? cap : slices * kPbSlice;
 }
 
-int gee_pb_build(const gee_csr *csr, int32_t *col, uint8_t *ul, int64_t *cell_start, uint32_t *cell_count, void *ws,
-                 size_t ws_bytes, int32_t *err, hipStream_t stream)
+size_t gee_pb_build_workspace(const gee_csr *csr, int64_t n_lds)
+{
+    if (check_csr(csr) != GEE_OK || csr->val || csr->nnz > kPbMaxNnz) return 0;
+    if (n_lds < 0 || n_lds > (csr->hot_ids ? csr->n_hot : 0) || n_lds > kPbMaxSlices * kPbSlice) return 0;
+    return pb_build_scratch(csr->n, csr->nnz, n_lds);
+}
+
+int gee_pb_build(const gee_csr *csr, int64_t n_lds, int32_t *col, uint8_t *ul, int64_t *cell_start,
+                 uint32_t *cell_count, int32_t *lds_ids, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream)
 {
     int rc;
     if ((rc = check_csr(csr)) != GEE_OK) return rc;
     if (csr->val) return GEE_EINVAL; // the layout serves unit-weight graphs
-    if ((csr->nnz > 0 && (!col || !ul)) || !cell_start || !cell_count || !aligned(col, 16)) return GEE_EINVAL;
-    const size_t need = pb_build_scratch(csr->n, csr->nnz);
+    if (csr->nnz > kPbMaxNnz) return GEE_EOVERFLOW;
+    if (n_lds < 0 || n_lds > (csr->hot_ids ? csr->n_hot : 0) || n_lds > kPbMaxSlices * kPbSlice) return GEE_EINVAL;
+    if ((csr->nnz > 0 && (!col || !ul)) || !cell_start || !cell_count || !aligned(col, 16) || !aligned(ul, 16) ||
+        (n_lds > 0 && !lds_ids))
+        return GEE_EINVAL;
+    const size_t need = pb_build_scratch(csr->n, csr->nnz, n_lds);
     if (!ws || !aligned(ws, 256) || ws_bytes < need) return GEE_EWORKSPACE;
-    return hip_rc(launch_pb_build(csr->n, csr->nnz, csr->row_ptr, csr->col, csr->hot_ids, csr->n_hot, col, ul,
-                                  cell_start, cell_count, ws, err, stream));
+    return hip_rc(launch_pb_build(csr->n, csr->nnz, csr->row_ptr, csr->col, csr->hot_ids, csr->n_hot, n_lds, col, ul,
+                                  cell_start, cell_count, lds_ids, ws, err, stream));
 }
 
 } // extern "C"
@@ -465,15 +491,18 @@ namespace {
 int check_pb(const gee_pb *pb)
 {
     if (!pb || pb->n < 1 || pb->n > kMaxN || pb->nnz < 0) return GEE_EINVAL;
-    const PbLayout L = pb_layout(pb->n);
+    if (pb->nnz > kPbMaxNnz) return GEE_EOVERFLOW;
+    if (pb->n_lds < 0 || pb->n_lds > kPbMaxSlices * kPbSlice || (pb->n_lds > 0 && !pb->lds_ids)) return GEE_EINVAL;
+    const PbLayout L = pb_layout(pb->n, pb->n_lds);
     if (pb->n_rb != L.n_rb || pb->n_cb != L.n_cb) return GEE_EINVAL;
-    if ((pb->nnz > 0 && (!pb->col || !pb->ul)) || !pb->cell_start || !pb->cell_count || !aligned(pb->col, 16))
+    if ((pb->nnz > 0 && (!pb->col || !pb->ul)) || !pb->cell_start || !pb->cell_count || !aligned(pb->col, 16) ||
+        !aligned(pb->ul, 16))
         return GEE_EINVAL;
     return GEE_OK;
 }
 
 struct PbPlan {
-    size_t o_counts = 0, o_inv = 0, o_lab = 0, o_yv = 0, total = 0;
+    size_t o_counts = 0, o_inv = 0, o_lab = 0, o_tab = 0, o_yv = 0, total = 0;
 };
 
 PbPlan pb_plan(const gee_pb *pb, int32_t K)
@@ -489,6 +518,7 @@ PbPlan pb_plan(const gee_pb *pb, int32_t K)
     P.o_counts = take(8 * (size_t)(K + 1));
     P.o_inv = take(8 * (size_t)(K + 1));
     P.o_lab = take((size_t)pb->n);
+    P.o_tab = take(align_up((size_t)pb->n_lds, 16));
     P.o_yv = take((size_t)pb->nnz + 16);
     P.total = align_up(off, 256);
     return P;
@@ -516,13 +546,16 @@ int gee_embed_pb(const gee_pb *pb, const int32_t *labels, int32_t K, float *Z, v
     uint64_t *counts = reinterpret_cast<uint64_t *>(w + p.o_counts);
     double *inv = reinterpret_cast<double *>(w + p.o_inv);
     uint8_t *lab = reinterpret_cast<uint8_t *>(w + p.o_lab);
+    uint8_t *tab = reinterpret_cast<uint8_t *>(w + p.o_tab);
     uint8_t *yv = reinterpret_cast<uint8_t *>(w + p.o_yv);
     if ((rc = hip_rc(launch_counts(labels, pb->n, K, counts, lab, Pack::U8, err, stream)))) return rc;
     if ((rc = hip_rc(launch_weights(counts, K, inv, stream)))) return rc;
     const bool timed = opts && opts->hot_begin && opts->hot_end;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_begin, stream)))) return rc;
-    if ((rc = hip_rc(launch_pb_gather(pb->nnz, pb->col, lab, yv, stream)))) return rc;
-    const PbLayout L = pb_layout(pb->n);
+    const PbLayout L = pb_layout(pb->n, pb->n_lds);
+    if ((rc = hip_rc(launch_pb_gather(pb->nnz, L, pb->n_lds, pb->cell_start, pb->col, pb->lds_ids, lab, tab, yv,
+                                      stream))))
+        return rc;
     if ((rc = hip_rc(launch_pb_rows(pb->n, K, L, pb->cell_start, pb->cell_count, pb->ul, yv, inv, Z, stream))))
         return rc;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;

@@ -115,21 +115,35 @@ hipError_t max_scan_i64(const int64_t *in, int64_t N, int64_t *out, int64_t *sca
 hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t value, hipStream_t s);
 
 // Propagation-blocked pull (unit-weight adjacency): entries of the CSR in column-block
-// order, 256-row blocks, 2^21-vertex column blocks.
+// order, 256-row blocks, 2^21-vertex column blocks, then up to 32 blocks ("tier slices")
+// of 2^17 hot slots each whose labels are read from LDS.
 constexpr int kPbRowBits = 8;
 constexpr int kPbColBits = 21;
-constexpr int kPbMaxK = 128; // bins of a row block: 256 x K uint32 in LDS
+constexpr int kPbMaxK = 128;                       // bins of a row block: 256 x K uint32 in LDS
+constexpr int kPbSliceBits = 17;                   // tier slice: 128 KB of 8-bit labels
+constexpr int64_t kPbSlice = (int64_t)1 << kPbSliceBits;
+constexpr int kPbMaxSlices = 32;                   // tier slots <= 2^22
+constexpr int64_t kPbMaxNnz = (int64_t)UINT32_MAX - 64; // cell lengths and word prefixes are 32-bit
 struct PbLayout {
     int64_t n_rb = 0;
-    int32_t n_cb = 0;
+    int32_t n_vcb = 0; // vertex column blocks
+    int32_t n_sl = 0;  // tier slices
+    int32_t n_cb = 0;  // n_vcb + n_sl
     int64_t cells = 0;
 };
-PbLayout pb_layout(int64_t n);
-size_t pb_build_scratch(int64_t n, int64_t nnz);
+PbLayout pb_layout(int64_t n, int64_t n_lds);
+size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds);
 hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const int32_t *hot_ids,
-                           int64_t n_hot, int32_t *colc, uint8_t *ul, int64_t *cell_start, uint32_t *cell_count,
-                           void *ws, int32_t *err, hipStream_t s);
-hipError_t launch_pb_gather(int64_t nnz, const int32_t *colc, const uint8_t *lab, uint8_t *yv, hipStream_t s);
+                           int64_t n_hot, int64_t n_lds, int32_t *colc, uint8_t *ul, int64_t *cell_start,
+                           uint32_t *cell_count, int32_t *lds_ids, void *ws, int32_t *err, hipStream_t s);
+// tab: per-call scratch of (n_lds rounded up to 16) bytes.
+hipError_t launch_pb_gather(int64_t nnz, const PbLayout &L, int64_t n_lds, const int64_t *cell_start,
+                            const int32_t *colc, const int32_t *lds_ids, const uint8_t *lab, uint8_t *tab,
+                            uint8_t *yv, hipStream_t s);
+// slice_entries [ceil(n_slots / 2^17)]: entries whose column is a hot slot of that slice.
+hipError_t launch_pb_slice_entries(int64_t n_slots, const int32_t *hot_ids, const int64_t *row_ptr,
+                                  int64_t *slice_entries, hipStream_t s);
+// ul and yv: 4-byte aligned, readable up to nnz rounded up to 4.
 hipError_t launch_pb_rows(int64_t n, int32_t K, const PbLayout &L, const int64_t *cell_start,
                           const uint32_t *cell_count, const uint8_t *ul, const uint8_t *yv, const double *inv, float *Z,
                           hipStream_t s);

@@ -8,16 +8,21 @@
 // streaming passes over a per-graph re-layout of the CSR entries:
 //
 //   layout (per graph): the entries sorted stably by column block (2^21 vertices),
-//     so within a block they stay in (row, column) order. A cell is the run of one
-//     column block's entries that belong to one block of 256 rows. Stored: the
-//     column of every entry, its row within the 256-row block (8 bits), and for each
-//     (row block, column block) the cell's start and length.
+//     so within a block they stay in (row, column) order. Entries whose column is one
+//     of the first n_lds hot slots of the CSR (its highest-degree vertices) go to
+//     extra column blocks after the vertex blocks, one per "tier slice" of 2^17 slots,
+//     and keep their slot within the slice instead of the vertex. A cell is the run of
+//     one column block's entries that belong to one block of 256 rows. Stored: the
+//     column (or slot) of every entry, its row within the 256-row block (8 bits), and
+//     for each (row block, column block) the cell's start and length.
 //   gather (per call): walk the entries in that order and write the 8-bit label of
-//     each entry's column; one column block's labels are 2 MB, so consecutive work
-//     reads them from L2.
-//   rows (per call): one workgroup per 256-row block reads the block's cells (one
-//     run per column block), counts (row, class) in LDS bins and writes its rows of Z
-//     once, count * 1/n_k.
+//     each entry's column. One vertex column block's labels are 2 MB, so consecutive
+//     work reads them from L2, one L2 request per entry. The tier's entries are read
+//     against one slice's labels (128 KB) held in LDS by the workgroup, so on a
+//     power-law graph most entries cost no L2 request at all.
+//   rows (per call): one workgroup per 256-row block reads the block's cells as one
+//     flattened run of 32-bit words (four entries a word, each lane its own words),
+//     counts (row, class) in LDS bins and writes its rows of Z once, count * 1/n_k.
 //
 // Counts are integers, so the result is independent of order and bit-identical to
 // the pull pass.
@@ -30,7 +35,13 @@ namespace gee {
 namespace {
 
 constexpr int kT = 256;
+constexpr int kRowsT = 512;    // rows kernel: 8 wavefronts per 256-row block
+constexpr int kRowsU = 4;      // words per lane in flight in the rows kernel
+constexpr int kLdsT = 1024;    // LDS-tier gather: 16 wavefronts share one label table
 constexpr int64_t kPbRows = (int64_t)1 << kPbRowBits;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 inline int grid_cap(int64_t items, int per_block)
 {
@@ -50,23 +61,31 @@ __global__ void __launch_bounds__(kT) k_pb_mark(int64_t n, const int64_t *__rest
     }
 }
 
-// keys[e] = (column << 32) | row, in place over the rows; hot-slot columns decoded.
+// keys[e] = (column << 32) | row, in place over the rows. Hot slot q below n_lds gets
+// the key column ((n_vcb + q / 2^17) << 21) | (q mod 2^17): column block n_vcb + slice;
+// other hot slots are decoded.
 __global__ void __launch_bounds__(kT)
 k_pb_key(int64_t nnz, int64_t n, const int32_t *__restrict__ col, const int32_t *__restrict__ hot_ids, int64_t n_hot,
-         uint64_t *keys, int32_t *err)
+         int64_t n_lds, int32_t n_vcb, uint64_t *keys, int32_t *err)
 {
     bool bad = false;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
-        int64_t c = col[e];
-        if (c < 0) {
-            const int64_t slot = (int64_t)((uint32_t)c & 0x7fffffffu);
-            c = slot < n_hot ? hot_ids[slot] : -1;
+        const int64_t c0 = col[e];
+        uint64_t kc;
+        if (c0 < 0) {
+            const int64_t slot = (int64_t)((uint32_t)c0 & 0x7fffffffu);
+            if (slot < n_lds) {
+                kc = ((uint64_t)(n_vcb + (slot >> kPbSliceBits)) << kPbColBits) | (uint64_t)(slot & (kPbSlice - 1));
+            } else {
+                const int64_t c = slot < n_hot ? hot_ids[slot] : -1;
+                if ((uint64_t)c >= (uint64_t)n) bad = true;
+                kc = (uint64_t)c < (uint64_t)n ? (uint64_t)c : 0;
+            }
+        } else {
+            if (c0 >= n) bad = true;
+            kc = c0 < n ? (uint64_t)c0 : 0;
         }
-        if ((uint64_t)c >= (uint64_t)n) {
-            bad = true;
-            c = 0;
-        }
-        keys[e] = ((uint64_t)c << 32) | (keys[e] & 0xffffffffull);
+        keys[e] = (kc << 32) | (keys[e] & 0xffffffffull);
     }
     if (bad) flag_error(err, GEE_EVERTEX);
 }
@@ -76,14 +95,16 @@ __device__ inline int64_t pb_cell(uint64_t key, int64_t n_rb)
     return (int64_t)(key >> (32 + kPbColBits)) * n_rb + (int64_t)((key & 0xffffffffull) >> kPbRowBits);
 }
 
-// colc / ul from the sorted keys; celllast[cell] = index + 1 of the cell's last entry.
+// colc / ul from the sorted keys (the slot within its slice for tier entries);
+// celllast[cell] = index + 1 of the cell's last entry.
 __global__ void __launch_bounds__(kT)
-k_pb_finalize(const uint64_t *__restrict__ keys, int64_t nnz, int64_t n_rb, int32_t *__restrict__ colc,
-              uint8_t *__restrict__ ul, int64_t *__restrict__ celllast)
+k_pb_finalize(const uint64_t *__restrict__ keys, int64_t nnz, int64_t n_rb, int32_t n_vcb,
+              int32_t *__restrict__ colc, uint8_t *__restrict__ ul, int64_t *__restrict__ celllast)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t k = keys[i];
-        colc[i] = (int32_t)(k >> 32);
+        const uint64_t c = k >> 32;
+        colc[i] = (int32_t)((c >> kPbColBits) >= (uint64_t)n_vcb ? (c & (kPbSlice - 1)) : c);
         ul[i] = (uint8_t)(k & (kPbRows - 1));
         const int64_t cell = pb_cell(k, n_rb);
         if (i + 1 == nnz || pb_cell(keys[i + 1], n_rb) != cell) celllast[cell] = i + 1;
@@ -106,12 +127,41 @@ k_pb_table(int64_t n_rb, int32_t n_cb, const int64_t *__restrict__ cellend, int6
     }
 }
 
-// yv[i] = lab[colc[i]], 16 entries per thread with 16-byte loads of columns and one
-// 16-byte store of labels.
+// slice_entries[j] = entries whose column is one of hot slots [j 2^17, (j + 1) 2^17) (the
+// row lengths of those vertices, the CSR being symmetric); one workgroup per slice.
 __global__ void __launch_bounds__(kT)
-k_pb_gather(int64_t nnz, const int32_t *__restrict__ colc, const uint8_t *__restrict__ lab, uint8_t *__restrict__ yv)
+k_pb_slice_entries(int64_t n_slots, const int32_t *__restrict__ hot_ids, const int64_t *__restrict__ row_ptr,
+                   int64_t *__restrict__ slice_entries)
 {
-    const int64_t nvec = nnz / 16;
+    __shared__ int64_t part[kT / kWave];
+    const int64_t j = blockIdx.x;
+    const int64_t a = j * kPbSlice, b = (j + 1) * kPbSlice < n_slots ? (j + 1) * kPbSlice : n_slots;
+    int64_t sum = 0;
+    for (int64_t q = a + threadIdx.x; q < b; q += kT) {
+        const int64_t v = hot_ids[q];
+        sum += row_ptr[v + 1] - row_ptr[v];
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) sum += __shfl_down(sum, o, kWave);
+    if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t tot = 0;
+        for (int w = 0; w < kT / kWave; ++w) tot += part[w];
+        slice_entries[j] = tot;
+    }
+}
+
+__device__ inline int64_t clamp_index(int64_t h, int64_t nnz) { return h < 0 ? 0 : (h > nnz ? nnz : h); }
+
+// yv[i] = lab[colc[i]] over the entries with vertex columns [0, h0), 16 entries per
+// thread with 16-byte loads of columns and one 16-byte store of labels. h0 is the
+// first tier entry (*tier_start), or nnz without a tier (tier_start null).
+__global__ void __launch_bounds__(kT)
+k_pb_gather(int64_t nnz, const int64_t *__restrict__ tier_start, const int32_t *__restrict__ colc,
+            const uint8_t *__restrict__ lab, uint8_t *__restrict__ yv)
+{
+    const int64_t h0 = tier_start ? clamp_index(*tier_start, nnz) : nnz;
+    const int64_t nvec = h0 / 16;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvec; v += (int64_t)gridDim.x * blockDim.x) {
         const int4 *cp = reinterpret_cast<const int4 *>(colc + v * 16);
         int4 c4[4];
@@ -124,90 +174,202 @@ k_pb_gather(int64_t nnz, const int32_t *__restrict__ colc, const uint8_t *__rest
                    ((uint32_t)lab[c4[q].w] << 24);
         *reinterpret_cast<uint4 *>(yv + v * 16) = make_uint4(w[0], w[1], w[2], w[3]);
     }
-    for (int64_t i = nvec * 16 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz;
+    for (int64_t i = nvec * 16 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < h0;
          i += (int64_t)gridDim.x * blockDim.x)
         yv[i] = lab[colc[i]];
 }
 
-constexpr int kPbCells = 4;    // cells a wavefront reads at once
-
-// One workgroup per 256-row block. Wavefront w takes the block's cells w, w + 4,
-// ..., four at a time: its lanes cover the cells' entries (row within the block and
-// label, both coalesced) so the loads of four cells are in flight together. One
-// count per entry into LDS bins [row][class], then the rows of Z are written once
-// (count * 1/n_k).
+// tab[q] = lab[lds_ids[q]] for the n_lds tier slots, zero-padded to a multiple of 16.
 __global__ void __launch_bounds__(kT)
-k_pb_rows(int64_t n, int32_t K, uint64_t magicK, int32_t n_cb, const int64_t *__restrict__ cell_start,
-          const uint32_t *__restrict__ cell_count, const uint8_t *__restrict__ ul, const uint8_t *__restrict__ yv,
+k_pb_tier_labels(int64_t n_lds, const int32_t *__restrict__ lds_ids, const uint8_t *__restrict__ lab,
+                 uint8_t *__restrict__ tab)
+{
+    const int64_t padded = (n_lds + 15) / 16 * 16;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < padded; i += (int64_t)gridDim.x * blockDim.x)
+        tab[i] = i < n_lds ? lab[lds_ids[i]] : 0;
+}
+
+// yv[i] = (labels of slice j)[colc[i]] over the tier entries [h0, nnz), where slice j's
+// entries start at sl_start[j] (cell (0, n_vcb + j)). The range is cut into one chunk
+// per workgroup (16-aligned); for every slice its chunk meets, the workgroup copies that
+// slice's labels (at most kPbSlice bytes) into an LDS table of kPbSlice bytes and reads
+// them there. Slots are masked to the table, so no LDS read leaves it.
+__global__ void __launch_bounds__(kLdsT)
+k_pb_gather_tier(int64_t nnz, int32_t n_sl, int64_t n_lds, const int64_t *__restrict__ sl_start,
+                 const int32_t *__restrict__ colc, const uint8_t *__restrict__ tab, uint8_t *__restrict__ yv)
+{
+    extern __shared__ __align__(16) uint8_t stab[];
+    __shared__ int64_t bnd[kPbMaxSlices + 1];
+    const int t = threadIdx.x;
+    if (t <= n_sl) bnd[t] = t < n_sl ? clamp_index(sl_start[t], nnz) : nnz;
+    __syncthreads();
+    const int64_t h0 = bnd[0];
+    const int64_t base = h0 & ~(int64_t)15;
+    const int64_t per = ((nnz - base + gridDim.x - 1) / gridDim.x + 15) & ~(int64_t)15;
+    int64_t lo = base + (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < nnz ? lo + per : nnz;
+    lo = lo > h0 ? lo : h0;
+    if (lo >= hi) return; // the whole workgroup
+    const uint32_t mask = (uint32_t)kPbSlice - 1;
+    for (int j = 0; j < n_sl; ++j) {
+        const int64_t a = lo > bnd[j] ? lo : bnd[j];
+        const int64_t b = hi < bnd[j + 1] ? hi : bnd[j + 1];
+        if (a >= b) continue; // the whole workgroup
+        __syncthreads(); // the previous slice's reads are done
+        const int64_t nj = n_lds - (int64_t)j * kPbSlice < kPbSlice ? n_lds - (int64_t)j * kPbSlice : kPbSlice;
+        const uint4 *src = reinterpret_cast<const uint4 *>(tab + (int64_t)j * kPbSlice);
+        for (int i = t; i < (int)((nj + 15) / 16); i += kLdsT) reinterpret_cast<uint4 *>(stab)[i] = src[i];
+        __syncthreads();
+        const int64_t v0 = (a + 15) / 16, v1 = b / 16;
+        for (int64_t v = v0 + t; v < v1; v += kLdsT) {
+            const int4 *cp = reinterpret_cast<const int4 *>(colc + v * 16);
+            int4 c4[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c4[q] = cp[q];
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                w[q] = (uint32_t)stab[(uint32_t)c4[q].x & mask] | ((uint32_t)stab[(uint32_t)c4[q].y & mask] << 8) |
+                       ((uint32_t)stab[(uint32_t)c4[q].z & mask] << 16) |
+                       ((uint32_t)stab[(uint32_t)c4[q].w & mask] << 24);
+            *reinterpret_cast<uint4 *>(yv + v * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        // entries outside the 16-aligned run: the head [a, 16 v0) and the tail [16 v1, b)
+        const int64_t head_end = v0 * 16 < b ? v0 * 16 : b;
+        for (int64_t i = a + t; i < head_end; i += kLdsT) yv[i] = stab[(uint32_t)colc[i] & mask];
+        const int64_t tail_begin = v1 * 16 > head_end ? v1 * 16 : head_end;
+        for (int64_t i = tail_begin + t; i < b; i += kLdsT) yv[i] = stab[(uint32_t)colc[i] & mask];
+    }
+}
+
+// One workgroup per 256-row block. The block's cells (one run per column block) are
+// read as one flattened sequence of 32-bit words of ul and yv: word f of the sequence
+// is found by a binary search over the cells' word prefix in LDS, and lane i of a
+// wavefront takes words i, i + 64, ... so loads stay coalesced and kRowsU of them per
+// array are in flight per lane. The bytes of a word that lie outside its cell (the
+// cells do not start on word boundaries) are masked. One count per entry into LDS
+// bins [row][class]; then the rows of Z are written once (count * 1/n_k), four
+// floats at a time when Z is 16-byte aligned (VEC).
+template <bool VEC>
+__global__ void __launch_bounds__(kRowsT)
+k_pb_rows(int64_t n, int32_t K, uint64_t magicK, int32_t n_cb, int32_t top, const int64_t *__restrict__ cell_start,
+          const uint32_t *__restrict__ cell_count, const uint32_t *__restrict__ ul4, const uint32_t *__restrict__ yv4,
           const double *__restrict__ inv, float *__restrict__ Z)
 {
-    // LDS: bins [kPbRows * K] uint32, inv [K] double, cell starts [n_cb] int64, counts [n_cb]
+    // LDS: bins [nb] uint32 (nb = 256 K rounded up to 4), invx [K + 3] double
+    // (invx[i] = 1/n_(i mod K) + 1), per cell: first word [n_cb] int64, word prefix
+    // [n_cb + 1], entry count [n_cb], byte offset of the start in its word [n_cb].
     extern __shared__ __align__(16) uint32_t bins[];
-    double *invs = reinterpret_cast<double *>(bins + align_up((size_t)kPbRows * K, 2));
-    int64_t *cst = reinterpret_cast<int64_t *>(invs + K);
-    uint32_t *ccn = reinterpret_cast<uint32_t *>(cst + n_cb);
+    const uint32_t nb = (uint32_t)align_up((size_t)kPbRows * K, 4);
+    double *invx = reinterpret_cast<double *>(bins + nb);
+    int64_t *cw0 = reinterpret_cast<int64_t *>(invx + K + 3);
+    uint32_t *pre = reinterpret_cast<uint32_t *>(cw0 + n_cb);
+    uint32_t *cm = pre + n_cb + 1;
+    uint32_t *coff = cm + n_cb;
     const int64_t rb = blockIdx.x;
     const int64_t r0 = rb * kPbRows;
     const int nr = (int)((n - r0) < kPbRows ? (n - r0) : kPbRows);
     const int t = threadIdx.x, lane = t % kWave;
     const int wave = __builtin_amdgcn_readfirstlane(t / kWave);
-    constexpr int kWaves = kT / kWave;
-    for (int i = t; i < kPbRows * K; i += kT) bins[i] = 0;
-    for (int k = t; k < K; k += kT) invs[k] = inv[k + 1];
-    for (int c = t; c < n_cb; c += kT) {
-        cst[c] = cell_start[rb * n_cb + c];
-        ccn[c] = cell_count[rb * n_cb + c];
+    for (uint32_t i = t; i < nb / 4; i += kRowsT) reinterpret_cast<u32x4 *>(bins)[i] = u32x4{0u, 0u, 0u, 0u};
+    for (int i = t; i < K + 3; i += kRowsT) invx[i] = inv[1 + i % K];
+    for (int c = t; c < n_cb; c += kRowsT) {
+        const int64_t a = cell_start[rb * n_cb + c];
+        cw0[c] = a >> 2;
+        cm[c] = cell_count[rb * n_cb + c];
+        coff[c] = (uint32_t)(a & 3);
     }
     __syncthreads();
-    for (int c0 = wave; c0 < n_cb; c0 += kWaves * kPbCells) {
-        int64_t a[kPbCells];
-        uint32_t m[kPbCells], mmax = 0;
+    if (wave == 0) { // exclusive prefix of the cells' word counts
+        uint32_t run = 0;
+        for (int c0 = 0; c0 < n_cb; c0 += kWave) {
+            const int c = c0 + lane;
+            const uint32_t d = (c < n_cb && cm[c] != 0u) ? (coff[c] + cm[c] + 3u) >> 2 : 0u;
+            uint32_t x = d;
 #pragma unroll
-        for (int j = 0; j < kPbCells; ++j) {
-            const int c = c0 + j * kWaves;
-            a[j] = c < n_cb ? cst[c] : 0;
-            m[j] = c < n_cb ? ccn[c] : 0u;
-            mmax = m[j] > mmax ? m[j] : mmax;
-        }
-        for (uint32_t q = lane; q < mmax; q += kWave) {
-            uint32_t u[kPbCells], y[kPbCells];
-#pragma unroll
-            for (int j = 0; j < kPbCells; ++j) {
-                const bool ok = q < m[j];
-                u[j] = ok ? ul[a[j] + q] : 0u;
-                y[j] = ok ? yv[a[j] + q] : 0u;
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o, kWave);
+                if (lane >= o) x += y;
             }
+            if (c < n_cb) pre[c] = run + x - d;
+            run += __shfl(x, kWave - 1, kWave);
+        }
+        if (lane == 0) pre[n_cb] = run;
+    }
+    __syncthreads();
+    const uint32_t T = pre[n_cb];
+    for (uint32_t f0 = (uint32_t)(wave * kWave + lane); f0 < T; f0 += kRowsU * kRowsT) {
+        uint32_t u[kRowsU], y[kRowsU], rel[kRowsU], m[kRowsU];
 #pragma unroll
-            for (int j = 0; j < kPbCells; ++j)
-                if (y[j] != 0) atomicAdd(&bins[u[j] * (uint32_t)K + (y[j] - 1)], 1u);
+        for (int j = 0; j < kRowsU; ++j) {
+            const uint32_t f = f0 + (uint32_t)j * kRowsT;
+            u[j] = 0u;
+            y[j] = 0u;
+            rel[j] = 0u;
+            m[j] = 0u;
+            if (f < T) {
+                int c = 0;
+                for (int st = top; st > 0; st >>= 1) {
+                    const int nc = c + st;
+                    if (nc < n_cb && pre[nc] <= f) c = nc;
+                }
+                const uint32_t k = f - pre[c];
+                const int64_t w = cw0[c] + k;
+                u[j] = ul4[w];
+                y[j] = yv4[w];
+                rel[j] = 4u * k - coff[c]; // entry index within the cell of the word's byte 0 (mod 2^32)
+                m[j] = cm[c];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kRowsU; ++j) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint32_t yb = (y[j] >> (8 * b)) & 0xffu;
+                const uint32_t ub = (u[j] >> (8 * b)) & 0xffu;
+                if (yb != 0u && rel[j] + (uint32_t)b < m[j]) atomicAdd(&bins[ub * (uint32_t)K + (yb - 1u)], 1u);
+            }
         }
     }
     __syncthreads();
     float *zb = Z + r0 * K;
     const uint32_t total = (uint32_t)nr * (uint32_t)K;
-    for (uint32_t f = t; f < total; f += kT) {
-        const uint32_t row = div_small(f, magicK);
-        const uint32_t k = f - row * (uint32_t)K;
-        __builtin_nontemporal_store((float)((double)bins[f] * invs[k]), zb + f);
+    uint32_t done = 0;
+    if (VEC) {
+        const uint32_t nv = total / 4;
+        for (uint32_t v = t; v < nv; v += kRowsT) {
+            const uint32_t f = 4u * v;
+            const uint32_t k = f - div_small(f, magicK) * (uint32_t)K;
+            const u32x4 c = reinterpret_cast<const u32x4 *>(bins)[v];
+            const f32x4 o = {(float)((double)c.x * invx[k]), (float)((double)c.y * invx[k + 1]),
+                             (float)((double)c.z * invx[k + 2]), (float)((double)c.w * invx[k + 3])};
+            __builtin_nontemporal_store(o, reinterpret_cast<f32x4 *>(zb) + v);
+        }
+        done = nv * 4;
+    }
+    for (uint32_t f = done + t; f < total; f += kRowsT) {
+        const uint32_t k = f - div_small(f, magicK) * (uint32_t)K;
+        __builtin_nontemporal_store((float)((double)bins[f] * invx[k]), zb + f);
     }
 }
 
 } // namespace
 
-PbLayout pb_layout(int64_t n)
+PbLayout pb_layout(int64_t n, int64_t n_lds)
 {
     PbLayout L;
     L.n_rb = (n + kPbRows - 1) / kPbRows;
-    L.n_cb = (int32_t)((n + ((int64_t)1 << kPbColBits) - 1) >> kPbColBits);
-    if (L.n_cb < 1) L.n_cb = 1;
+    L.n_vcb = (int32_t)((n + ((int64_t)1 << kPbColBits) - 1) >> kPbColBits);
+    L.n_sl = (int32_t)((n_lds + kPbSlice - 1) >> kPbSliceBits);
+    L.n_cb = L.n_vcb + L.n_sl;
     L.cells = L.n_rb * L.n_cb;
     return L;
 }
 
 // Build scratch: two key buffers [nnz], radix histograms, scan partials, two cell arrays.
-size_t pb_build_scratch(int64_t n, int64_t nnz)
+size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds)
 {
-    const PbLayout L = pb_layout(n);
+    const PbLayout L = pb_layout(n, n_lds);
     size_t hb, ob, pbytes;
     radix_scratch_bytes(nnz, nnz > L.cells ? nnz : L.cells, &hb, &ob, &pbytes);
     size_t off = 0;
@@ -226,10 +388,10 @@ size_t pb_build_scratch(int64_t n, int64_t nnz)
 }
 
 hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const int32_t *hot_ids,
-                           int64_t n_hot, int32_t *colc, uint8_t *ul, int64_t *cell_start, uint32_t *cell_count,
-                           void *ws, int32_t *err, hipStream_t s)
+                           int64_t n_hot, int64_t n_lds, int32_t *colc, uint8_t *ul, int64_t *cell_start,
+                           uint32_t *cell_count, int32_t *lds_ids, void *ws, int32_t *err, hipStream_t s)
 {
-    const PbLayout L = pb_layout(n);
+    const PbLayout L = pb_layout(n, n_lds);
     size_t hb, ob, pbytes;
     radix_scratch_bytes(nnz, nnz > L.cells ? nnz : L.cells, &hb, &ob, &pbytes);
     char *base = static_cast<char *>(ws);
@@ -249,6 +411,8 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
     int64_t *cellend = (int64_t *)take((size_t)L.cells * 8);
     hipError_t e;
     const dim3 b(kT);
+    if (n_lds > 0 && (e = hipMemcpyAsync(lds_ids, hot_ids, (size_t)n_lds * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return e;
     if (nnz > 0) {
         // row of every entry, then (column << 32) | row
         if ((e = launch_fill_i64(reinterpret_cast<int64_t *>(k1), nnz, 0, s)) != hipSuccess) return e;
@@ -257,7 +421,8 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
         if ((e = max_scan_i64(reinterpret_cast<const int64_t *>(k1), nnz, reinterpret_cast<int64_t *>(k0), part, s)) !=
             hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_pb_key, dim3(grid_cap(nnz, kT * 4)), b, 0, s, nnz, n, col, hot_ids, n_hot, k0, err);
+        hipLaunchKernelGGL(k_pb_key, dim3(grid_cap(nnz, kT * 4)), b, 0, s, nnz, n, col, hot_ids, n_hot, n_lds, L.n_vcb,
+                           k0, err);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // stable sort on the column-block bits (the entries are in row order already)
         uint64_t *sorted = k0;
@@ -268,7 +433,7 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
                 return e;
         }
         if ((e = launch_fill_i64(celllast, L.cells, 0, s)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_pb_finalize, dim3(grid_cap(nnz, kT * 4)), b, 0, s, sorted, nnz, L.n_rb, colc, ul,
+        hipLaunchKernelGGL(k_pb_finalize, dim3(grid_cap(nnz, kT * 4)), b, 0, s, sorted, nnz, L.n_rb, L.n_vcb, colc, ul,
                            celllast);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
@@ -280,21 +445,61 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
     return hipGetLastError();
 }
 
-hipError_t launch_pb_gather(int64_t nnz, const int32_t *colc, const uint8_t *lab, uint8_t *yv, hipStream_t s)
+hipError_t launch_pb_gather(int64_t nnz, const PbLayout &L, int64_t n_lds, const int64_t *cell_start,
+                            const int32_t *colc, const int32_t *lds_ids, const uint8_t *lab, uint8_t *tab,
+                            uint8_t *yv, hipStream_t s)
 {
     if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pb_gather, dim3(grid_cap(nnz, kT * 16)), dim3(kT), 0, s, nnz, colc, lab, yv);
+    const int64_t *sl_start = L.n_sl > 0 ? cell_start + L.n_vcb : nullptr; // cells (0, n_vcb + j)
+    hipLaunchKernelGGL(k_pb_gather, dim3(grid_cap(nnz, kT * 16)), dim3(kT), 0, s, nnz, sl_start, colc, lab, yv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || L.n_sl == 0) return e;
+    hipLaunchKernelGGL(k_pb_tier_labels, dim3(grid_cap(n_lds, kT * 4)), dim3(kT), 0, s, n_lds, lds_ids, lab, tab);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int dev = 0, cus = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    // one workgroup per CU (the table takes 128 KB of LDS), at least 64K entries each
+    int64_t grid = nnz / 65536;
+    if (grid > cus) grid = cus;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_pb_gather_tier, dim3((unsigned)grid), dim3(kLdsT), (size_t)kPbSlice, s, nnz, L.n_sl, n_lds,
+                       sl_start, colc, tab, yv);
     return hipGetLastError();
+}
+
+hipError_t launch_pb_slice_entries(int64_t n_slots, const int32_t *hot_ids, const int64_t *row_ptr,
+                                  int64_t *slice_entries, hipStream_t s)
+{
+    const int64_t n_sl = (n_slots + kPbSlice - 1) >> kPbSliceBits;
+    if (n_sl <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pb_slice_entries, dim3((unsigned)n_sl), dim3(kT), 0, s, n_slots, hot_ids, row_ptr,
+                       slice_entries);
+    return hipGetLastError();
+}
+
+size_t pb_rows_lds_bytes(int32_t K, int32_t n_cb)
+{
+    return align_up((size_t)kPbRows * K, 4) * 4 + (size_t)(K + 3) * 8 + (size_t)n_cb * 8 + (size_t)(n_cb + 1) * 4 +
+           (size_t)n_cb * 8;
 }
 
 hipError_t launch_pb_rows(int64_t n, int32_t K, const PbLayout &L, const int64_t *cell_start,
                           const uint32_t *cell_count, const uint8_t *ul, const uint8_t *yv, const double *inv, float *Z,
                           hipStream_t s)
 {
-    const size_t lds = align_up((size_t)kPbRows * K, 2) * 4 + (size_t)K * 8 + (size_t)L.n_cb * 12;
+    const size_t lds = pb_rows_lds_bytes(K, L.n_cb);
     const uint64_t magic = ((1ull << 32) + (uint64_t)K - 1) / (uint64_t)K;
-    hipLaunchKernelGGL(k_pb_rows, dim3((unsigned)L.n_rb), dim3(kT), lds, s, n, K, magic, L.n_cb, cell_start,
-                       cell_count, ul, yv, inv, Z);
+    int top = 1;
+    while (top * 2 <= L.n_cb - 1) top *= 2;
+    const uint32_t *ul4 = reinterpret_cast<const uint32_t *>(ul);
+    const uint32_t *yv4 = reinterpret_cast<const uint32_t *>(yv);
+    if ((reinterpret_cast<uintptr_t>(Z) & 15) == 0)
+        hipLaunchKernelGGL(k_pb_rows<true>, dim3((unsigned)L.n_rb), dim3(kRowsT), lds, s, n, K, magic, L.n_cb, top,
+                           cell_start, cell_count, ul4, yv4, inv, Z);
+    else
+        hipLaunchKernelGGL(k_pb_rows<false>, dim3((unsigned)L.n_rb), dim3(kRowsT), lds, s, n, K, magic, L.n_cb, top,
+                           cell_start, cell_count, ul4, yv4, inv, Z);
     return hipGetLastError();
 }
 

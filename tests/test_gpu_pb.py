@@ -25,27 +25,42 @@ def _same_bits(a, b):
 
 
 def _check_layout(csr, pb):
-    """Every (row, column) entry of the CSR appears once in the layout, cells ordered by column block."""
+    """Every (row, column) entry of the CSR appears once in the layout, cells ordered by
+    column block; the tier slices hold exactly the entries of the first n_lds hot slots."""
     rp = csr.row_ptr.cpu().numpy()
     cols = csr.plain_col().cpu().numpy()
+    raw = csr.col.cpu().numpy()
     rows = np.repeat(np.arange(csr.n, dtype=np.int64), np.diff(rp))
     start = pb.cell_start.cpu().numpy().reshape(pb.n_rb, pb.n_cb)
     count = pb.cell_count.cpu().numpy().reshape(pb.n_rb, pb.n_cb).astype(np.int64)
     assert count.sum() == csr.nnz
+    n_vcb = (csr.n + (1 << 21) - 1) // (1 << 21)
+    assert pb.n_cb == n_vcb + (pb.n_lds + (1 << 17) - 1) // (1 << 17)
+    if pb.n_lds:
+        assert torch.equal(pb.lds_ids.cpu(), csr.hot_ids[: pb.n_lds].cpu())
     # column-block-major order: cells (cb, rb) are consecutive
     order = np.argsort(start.T.reshape(-1), kind="stable")
     flat_start, flat_count = start.T.reshape(-1)[order], count.T.reshape(-1)[order]
     assert np.all(flat_start[1:] == (flat_start + flat_count)[:-1])
     pcol = pb.col.cpu().numpy().astype(np.int64)
-    pul = pb.ul.cpu().numpy().astype(np.int64)
+    pul = pb.ul.cpu().numpy()[: csr.nnz].astype(np.int64)
     rb_of = np.repeat(np.repeat(np.arange(pb.n_rb), pb.n_cb), count.reshape(-1))
+    cb_of = np.repeat(np.tile(np.arange(pb.n_cb), pb.n_rb), count.reshape(-1))
     idx = np.concatenate([np.arange(a, a + c) for a, c in zip(start.reshape(-1), count.reshape(-1)) if c]) \
         if csr.nnz else np.zeros(0, np.int64)
     prow = rb_of * 256 + pul[idx]
-    assert np.all(pcol[idx] >> 21 == np.repeat(np.tile(np.arange(pb.n_cb), pb.n_rb), count.reshape(-1)))
+    vcol = pcol[idx].copy()
+    tier = cb_of >= n_vcb
+    assert np.all(vcol[~tier] >> 21 == cb_of[~tier])
+    slots = vcol[tier] + ((cb_of[tier] - n_vcb) << 17)  # slot within the slice -> tier slot
+    assert np.all((vcol[tier] >= 0) & (vcol[tier] < (1 << 17)) & (slots < max(pb.n_lds, 1)))
+    if pb.n_lds:
+        vcol[tier] = pb.lds_ids.cpu().numpy()[slots]
+    in_tier = (raw < 0) & ((raw & 0x7FFFFFFF) < pb.n_lds)
+    assert int(tier.sum()) == int(in_tier.sum())
     a = np.lexsort((cols, rows))
-    b = np.lexsort((pcol[idx], prow))
-    assert np.array_equal(rows[a], prow[b]) and np.array_equal(cols[a], pcol[idx][b])
+    b = np.lexsort((vcol, prow))
+    assert np.array_equal(rows[a], prow[b]) and np.array_equal(cols[a], vcol[b])
 
 
 def test_small_graph_matches_pull_and_oracle():
@@ -61,10 +76,12 @@ def test_small_graph_matches_pull_and_oracle():
     assert_parity(Zb.cpu().numpy(), oracle.embed(g.n, g.src, g.dst, None, wl.labels, wl.K, False), what="sbm")
 
 
-@pytest.mark.parametrize("hot", [0, 5000])
+@pytest.mark.parametrize("hot,tier", [(0, 0), (5000, 5000), (200_000, 200_000), (200_000, 1 << 17), (300_000, 0)])
 @pytest.mark.parametrize("K", [1, 7, 50, 128])
-def test_several_column_blocks(hot, K):
-    """n = 2^21 + 1000 vertices: two column blocks and a partial last row block; R-MAT hubs."""
+def test_several_column_blocks(hot, tier, K):
+    """n = 2^21 + 1000 vertices: two column blocks and a partial last row block; R-MAT hubs.
+    Tiers of one slice, of two slices (the second partial), of exactly one full slice with
+    hot slots decoded beyond it, and hot slots without a tier."""
     n = (1 << 21) + 1000
     rng = np.random.default_rng(K + hot)
     g = gen.rmat(21, 6 << 21, seed=5)
@@ -72,19 +89,61 @@ def test_several_column_blocks(hot, K):
     dst = np.r_[g.dst, rng.integers(0, n, 200_000).astype(np.int32), rng.integers(0, n, 50_000).astype(np.int32)]
     coo = gee.to_device(n, src, dst, None, device=DEV)
     csr = gee.csr_build(coo, hot_budget=hot)
-    pb = gee.pb_build(csr)
-    assert pb.n_cb == 2
+    pb = gee.pb_build(csr, tier_slots=tier)
+    assert pb.n_lds == tier and pb.n_cb == 2 + (tier + (1 << 17) - 1) // (1 << 17)
+    if K == 50:
+        _check_layout(csr, pb)
     Y = torch.as_tensor(random_labels(rng, n, K, unknown=0.3)).to(DEV)
     _same_bits(gee.embed_pb(Y, K, pb), gee.embed(Y, K, csr=csr))
 
 
-def test_layout_of_two_column_blocks():
+@pytest.mark.parametrize("hot", [0, 1000, 150_000])
+def test_layout_of_two_column_blocks(hot):
     n = (1 << 21) + 300
     rng = np.random.default_rng(2)
     src = rng.integers(0, n, 400_000).astype(np.int32)
     dst = rng.integers(0, n, 400_000).astype(np.int32)
-    csr = gee.csr_build(gee.to_device(n, src, dst, None, device=DEV), hot_budget=1000)
-    _check_layout(csr, gee.pb_build(csr))
+    csr = gee.csr_build(gee.to_device(n, src, dst, None, device=DEV), hot_budget=hot)
+    _check_layout(csr, gee.pb_build(csr, tier_slots=hot))
+
+
+def test_tier_planner():
+    """Slices are kept while their entries average at least min_per_row_block per
+    256-row block: counted here from the CSR on the host."""
+    g = gen.rmat(20, 16 << 20, seed=9)
+    csr = gee.csr_build(gee.to_device(g.n, g.src, g.dst, None, device=DEV), hot_budget=600_000)
+    rp = csr.row_ptr.cpu().numpy()
+    hot = csr.hot_ids.cpu().numpy().astype(np.int64)
+    deg = rp[hot + 1] - rp[hot]
+    per_slice = [int(deg[j:j + (1 << 17)].sum()) for j in range(0, len(hot), 1 << 17)]
+    n_rb = (g.n + 255) // 256
+    for m in (0, 1, 4, 16, 64, 1 << 30):
+        k = 0
+        while k < len(per_slice) and per_slice[k] >= m * n_rb:
+            k += 1
+        want = len(hot) if k == len(per_slice) else k << 17
+        assert gee.pb_tier_slots(csr, m) == want
+    none = gee.csr_build(gee.to_device(g.n, g.src, g.dst, None, device=DEV), hot_budget=0)
+    assert gee.pb_tier_slots(none) == 0
+    pb = gee.pb_build(csr)  # the planner's tier
+    Y = torch.as_tensor(random_labels(np.random.default_rng(1), g.n, 20, unknown=0.1)).to(DEV)
+    _same_bits(gee.embed_pb(Y, 20, pb), gee.embed(Y, 20, csr=csr))
+
+
+def test_unaligned_z_and_ragged_entries():
+    """Z at an offset of one float (the rows kernel's scalar stores) and entry counts that
+    are not a multiple of 4 or 16 (the gathers' head and tail, the last word's mask)."""
+    rng = np.random.default_rng(11)
+    for s_extra in (1, 3, 13):
+        g = gen.rmat(14, 60_000 + s_extra, seed=s_extra)
+        csr = gee.csr_build(gee.to_device(g.n, g.src, g.dst, None, device=DEV), hot_budget=777)
+        pb = gee.pb_build(csr)
+        for K in (3, 50):
+            Y = torch.as_tensor(random_labels(rng, g.n, K, unknown=0.2)).to(DEV)
+            buf = torch.full((g.n * K + 1,), -1.0, dtype=torch.float32, device=DEV)
+            Zu = gee.embed_pb(Y, K, pb, Z=buf[1:].view(g.n, K))
+            _same_bits(Zu, gee.embed(Y, K, csr=csr))
+            assert buf[0].item() == -1.0
 
 
 def test_all_unknown_and_empty_graph():
