@@ -4,12 +4,13 @@
 One step = one embedding call over the paper-scale R-MAT: scale 27 (n = 134,217,728),
 edge factor 14 (s = 1,879,048,192 records), (a, b, c) = (0.57, 0.19, 0.19), unit
 weights, K = 50 planted classes with 1% unknown, adjacency version, all inputs resident
-in HBM. By default the call is ``gee_embed`` on the CSR (class counts and label
-packing, projection weights, the edge pass and the split-row merge); ``--form pb``
-times ``gee_embed_pb`` over the propagation-blocked layout (label gather and row
-counts) and ``--form push`` the edge-parallel form; the other forms are timed beside. The symmetric CSR and the layout are built
-once beforehand (per-graph preprocessing, reported as ``csr_build_ms`` and
-``pb_build_ms``). Prints one JSON line on stdout; progress goes to stderr.
+in HBM. By default the call is ``gee_embed_pb`` over the propagation-blocked layout
+(class counts and label packing, projection weights, the label gathers and the row
+counts); ``--form pull`` times ``gee_embed`` on the CSR (the edge pass and the
+split-row merge) and ``--form push`` the edge-parallel form; the other forms are timed
+beside. The symmetric CSR and the layout are built once beforehand (per-graph
+preprocessing, reported as ``csr_build_ms`` and ``pb_build_ms``). Prints one JSON line
+on stdout; progress goes to stderr.
 
 ``value`` is GEdges/s = s / step time. ``roofline`` prices the edge pass against HBM:
 algorithmic bytes per launch = 4 nnz (col) + 8 (n + 1) (row_ptr) + n (one read of each
@@ -65,7 +66,7 @@ def parse():
     p.add_argument("--plain-steps", type=int, default=1,
                    help="batched workload: timed rounds of one plain call per vector, reported beside")
     p.add_argument("--K", type=int, default=50)
-    p.add_argument("--form", choices=["pb", "pull", "push"], default="pull",
+    p.add_argument("--form", choices=["pb", "pull", "push"], default="pb",
                    help="rmat27: pb = pull over the propagation-blocked layout (unit weights), pull = CSR pull, "
                         "push = edge-parallel atomics")
     p.add_argument("--seg-len", type=int, default=0)
@@ -236,7 +237,7 @@ def main():
     lab_bytes = 1 if K <= 255 else 2
     if a.form in ("pull", "pb"):
         bytes_alg = 4 * nnz + 8 * (n + 1) + lab_bytes * n + 4 * n * K
-        kernel = "k_pull" if a.form == "pull" else "k_pb_gather + k_pb_rows"
+        kernel = "k_pull" if a.form == "pull" else "k_pb_gather + k_pb_tier_labels + k_pb_gather_tier + k_pb_rows"
         traffic, counters = (counters_traffic(bytes_alg) if a.form == "pull"
                              else counters_traffic(bytes_alg, PROFILE_COUNTERS_PB, KERNEL_SOURCE_PB))
     else:

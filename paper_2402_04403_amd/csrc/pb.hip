@@ -38,6 +38,7 @@ constexpr int kT = 256;
 constexpr int kRowsT = 512;    // rows kernel: 8 wavefronts per 256-row block
 constexpr int kRowsU = 4;      // words per lane in flight in the rows kernel
 constexpr int kLdsT = 1024;    // LDS-tier gather: 16 wavefronts share one label table
+constexpr uint32_t kXcds = 8;  // accelerator dies, each with its own L2
 constexpr int64_t kPbRows = (int64_t)1 << kPbRowBits;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -266,7 +267,13 @@ k_pb_rows(int64_t n, int32_t K, uint64_t magicK, int32_t n_cb, int32_t top, cons
     uint32_t *pre = reinterpret_cast<uint32_t *>(cw0 + n_cb);
     uint32_t *cm = pre + n_cb + 1;
     uint32_t *coff = cm + n_cb;
-    const int64_t rb = blockIdx.x;
+    // Workgroups are dealt to the 8 XCDs in turn (i -> XCD i mod 8). Neighbouring row
+    // blocks' cells share cache lines (a vertex block's cells are small and adjacent),
+    // so each XCD takes one contiguous run of row blocks and the lines are fetched into
+    // one L2 only.
+    const uint32_t per = gridDim.x / kXcds, rem = gridDim.x % kXcds;
+    const uint32_t xcd = blockIdx.x % kXcds, bk = blockIdx.x / kXcds;
+    const int64_t rb = (int64_t)(xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + bk;
     const int64_t r0 = rb * kPbRows;
     const int nr = (int)((n - r0) < kPbRows ? (n - r0) : kPbRows);
     const int t = threadIdx.x, lane = t % kWave;

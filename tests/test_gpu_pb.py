@@ -146,6 +146,25 @@ def test_unaligned_z_and_ragged_entries():
             assert buf[0].item() == -1.0
 
 
+@pytest.mark.parametrize("tier", [0, 500])
+@pytest.mark.parametrize("K", [3, 50, 128])
+def test_hub_row_blocks(tier, K):
+    """Row blocks with 2^16 entries or more take two passes (one per half of their rows,
+    32-bit bins): hubs in the first half, the second half, and in a partial last block
+    of 112 rows, next to ordinary blocks."""
+    n = 70_000
+    rng = np.random.default_rng(K + tier)
+    hubs = [(300, 70_000), (256 * 5 + 200, 80_000), (n - 1, 66_000), (256 * 9 + 255, 30_000)]
+    src = [rng.integers(0, n, 100_000)] + [np.full(d, h) for h, d in hubs]
+    dst = [rng.integers(0, n, 100_000)] + [rng.integers(0, n, d) for _, d in hubs]
+    src = np.concatenate(src).astype(np.int32)
+    dst = np.concatenate(dst).astype(np.int32)
+    csr = gee.csr_build(gee.to_device(n, src, dst, None, device=DEV), hot_budget=1000)
+    pb = gee.pb_build(csr, tier_slots=tier)
+    Y = torch.as_tensor(random_labels(rng, n, K, unknown=0.25)).to(DEV)
+    _same_bits(gee.embed_pb(Y, K, pb), gee.embed(Y, K, csr=csr))
+
+
 def test_all_unknown_and_empty_graph():
     rng = np.random.default_rng(3)
     n = 5000
