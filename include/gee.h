@@ -190,6 +190,7 @@ typedef struct gee_pb {
     const uint32_t *cell_count; /* [n_rb * n_cb] */
     int64_t n_lds;             /* tier slots the layout was built with (0 to GEE_PB_MAX_TIER) */
     const int32_t *lds_ids;    /* [n_lds] vertex of each tier slot (written by gee_pb_build) */
+    const uint32_t *cell_word; /* [n_rb * n_cb] first 32-bit word of each cell within its row block's words */
 } gee_pb;
 
 /* n_rb * n_cb for n vertices and n_lds tier slots (0 on invalid input). */
@@ -211,11 +212,15 @@ size_t gee_pb_build_workspace(const gee_csr *csr, int64_t n_lds);
 /* Builds the layout of a unit-weight CSR (csr->val must be NULL) with the first n_lds
  * hot slots (0 <= n_lds <= min(n_hot, GEE_PB_MAX_TIER)) in the tier; other hot-slot
  * columns are decoded through hot_ids. Outputs are caller device buffers: col [nnz]
- * (16-byte aligned), ul [nnz rounded up to 16] (16-byte aligned), cell_start and
- * cell_count [gee_pb_cells(n, n_lds)], lds_ids [n_lds] (may be NULL when n_lds = 0).
- * A column id outside [0, n) stores GEE_EVERTEX in *err. */
+ * (16-byte aligned), ul [nnz rounded up to 16] (16-byte aligned), cell_start,
+ * cell_count and cell_word [gee_pb_cells(n, n_lds)], lds_ids [n_lds] (may be NULL when
+ * n_lds = 0). cell_word[rb * n_cb + c] is the first 32-bit word of cell c when the
+ * cells of row block rb are read one after another as words (a cell covering
+ * ceil(((cell_start mod 4) + cell_count) / 4) of them, none when empty). A column id
+ * outside [0, n) stores GEE_EVERTEX in *err. */
 int gee_pb_build(const gee_csr *csr, int64_t n_lds, int32_t *col, uint8_t *ul, int64_t *cell_start,
-                 uint32_t *cell_count, int32_t *lds_ids, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream);
+                 uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, void *ws, size_t ws_bytes,
+                 int32_t *err, hipStream_t stream);
 
 /* Workspace bytes of gee_embed_pb (0 on invalid input); 1 <= K <= 128. */
 size_t gee_embed_pb_workspace(const gee_pb *pb, int32_t K);

@@ -57,7 +57,8 @@ class Csr(ctypes.Structure):
 class Pb(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_rb", ctypes.c_int64), ("n_cb", ctypes.c_int32),
                 ("col", ctypes.c_void_p), ("ul", ctypes.c_void_p), ("cell_start", ctypes.c_void_p),
-                ("cell_count", ctypes.c_void_p), ("n_lds", ctypes.c_int64), ("lds_ids", ctypes.c_void_p)]
+                ("cell_count", ctypes.c_void_p), ("n_lds", ctypes.c_int64), ("lds_ids", ctypes.c_void_p),
+                ("cell_word", ctypes.c_void_p)]
 
 
 class Batch(ctypes.Structure):
@@ -107,7 +108,7 @@ def load():
         lib.gee_pb_build_workspace.restype = sz
         lib.gee_pb_build_workspace.argtypes = [CsrP, i64]
         lib.gee_pb_build.restype = ci
-        lib.gee_pb_build.argtypes = [CsrP, i64, vp, vp, vp, vp, vp, vp, sz, vp, vp]
+        lib.gee_pb_build.argtypes = [CsrP, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp]
         lib.gee_embed_pb_workspace.restype = sz
         lib.gee_embed_pb_workspace.argtypes = [PbP, i32]
         lib.gee_embed_pb.restype = ci
@@ -359,6 +360,7 @@ class DevicePb:
     cell_start: torch.Tensor
     cell_count: torch.Tensor
     lds_ids: torch.Tensor     # [n_lds]
+    cell_word: torch.Tensor   # [n_rb * n_cb]
 
     @property
     def nnz(self) -> int:
@@ -378,7 +380,8 @@ class DevicePb:
 
     def struct(self) -> Pb:
         return Pb(self.n, self.nnz, self.n_rb, self.n_cb, _ptr(self.col), _ptr(self.ul), _ptr(self.cell_start),
-                  _ptr(self.cell_count), self.n_lds, _ptr(self.lds_ids) if self.n_lds else None)
+                  _ptr(self.cell_count), self.n_lds, _ptr(self.lds_ids) if self.n_lds else None,
+                  _ptr(self.cell_word))
 
 
 def pb_tier_slots(csr: DeviceCsr, min_per_row_block: int = 4, stream=None) -> int:
@@ -408,15 +411,16 @@ def pb_build(csr: DeviceCsr, tier_slots: int | None = None, stream=None, check: 
     ul = torch.empty((csr.nnz + 15) // 16 * 16 or 16, dtype=torch.uint8, device=dev)
     cell_start = torch.empty(cells, dtype=torch.int64, device=dev)
     cell_count = torch.empty(cells, dtype=torch.int32, device=dev)
+    cell_word = torch.empty(cells, dtype=torch.int32, device=dev)
     lds_ids = torch.empty(n_lds, dtype=torch.int32, device=dev)
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     err = torch.zeros(1, dtype=torch.int32, device=dev)
     _rc(lib.gee_pb_build(ctypes.byref(rs), n_lds, _ptr(col), _ptr(ul), _ptr(cell_start), _ptr(cell_count),
-                         _ptr(lds_ids) if n_lds else None, _ptr(ws), wsb, _ptr(err), _stream(stream)), "gee_pb_build")
+                         _ptr(cell_word), _ptr(lds_ids) if n_lds else None, _ptr(ws), wsb, _ptr(err), _stream(stream)), "gee_pb_build")
     if check:
         _check_err(err, "gee_pb_build")
     del ws
-    return DevicePb(csr.n, col, ul, cell_start, cell_count, lds_ids)
+    return DevicePb(csr.n, col, ul, cell_start, cell_count, lds_ids, cell_word)
 
 
 def embed_pb_workspace_bytes(pb: DevicePb, K: int) -> int:

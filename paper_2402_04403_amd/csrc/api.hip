@@ -468,20 +468,22 @@ size_t gee_pb_build_workspace(const gee_csr *csr, int64_t n_lds)
 }
 
 int gee_pb_build(const gee_csr *csr, int64_t n_lds, int32_t *col, uint8_t *ul, int64_t *cell_start,
-                 uint32_t *cell_count, int32_t *lds_ids, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream)
+                 uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, void *ws, size_t ws_bytes, int32_t *err,
+                 hipStream_t stream)
 {
     int rc;
     if ((rc = check_csr(csr)) != GEE_OK) return rc;
     if (csr->val) return GEE_EINVAL; // the layout serves unit-weight graphs
     if (csr->nnz > kPbMaxNnz) return GEE_EOVERFLOW;
     if (n_lds < 0 || n_lds > (csr->hot_ids ? csr->n_hot : 0) || n_lds > kPbMaxSlices * kPbSlice) return GEE_EINVAL;
-    if ((csr->nnz > 0 && (!col || !ul)) || !cell_start || !cell_count || !aligned(col, 16) || !aligned(ul, 16) ||
+    if ((csr->nnz > 0 && (!col || !ul)) || !cell_start || !cell_count || !cell_word || !aligned(col, 16) ||
+        !aligned(ul, 16) ||
         (n_lds > 0 && !lds_ids))
         return GEE_EINVAL;
     const size_t need = pb_build_scratch(csr->n, csr->nnz, n_lds);
     if (!ws || !aligned(ws, 256) || ws_bytes < need) return GEE_EWORKSPACE;
     return hip_rc(launch_pb_build(csr->n, csr->nnz, csr->row_ptr, csr->col, csr->hot_ids, csr->n_hot, n_lds, col, ul,
-                                  cell_start, cell_count, lds_ids, ws, err, stream));
+                                  cell_start, cell_count, cell_word, lds_ids, ws, err, stream));
 }
 
 } // extern "C"
@@ -495,7 +497,8 @@ int check_pb(const gee_pb *pb)
     if (pb->n_lds < 0 || pb->n_lds > kPbMaxSlices * kPbSlice || (pb->n_lds > 0 && !pb->lds_ids)) return GEE_EINVAL;
     const PbLayout L = pb_layout(pb->n, pb->n_lds);
     if (pb->n_rb != L.n_rb || pb->n_cb != L.n_cb) return GEE_EINVAL;
-    if ((pb->nnz > 0 && (!pb->col || !pb->ul)) || !pb->cell_start || !pb->cell_count || !aligned(pb->col, 16) ||
+    if ((pb->nnz > 0 && (!pb->col || !pb->ul)) || !pb->cell_start || !pb->cell_count || !pb->cell_word ||
+        !aligned(pb->col, 16) ||
         !aligned(pb->ul, 16))
         return GEE_EINVAL;
     return GEE_OK;
@@ -556,7 +559,7 @@ int gee_embed_pb(const gee_pb *pb, const int32_t *labels, int32_t K, float *Z, v
     if ((rc = hip_rc(launch_pb_gather(pb->nnz, L, pb->n_lds, pb->cell_start, pb->col, pb->lds_ids, lab, tab, yv,
                                       stream))))
         return rc;
-    if ((rc = hip_rc(launch_pb_rows(pb->n, K, L, pb->cell_start, pb->cell_count, pb->ul, yv, inv, Z, stream))))
+    if ((rc = hip_rc(launch_pb_rows(pb->n, K, L, pb->cell_start, pb->cell_count, pb->cell_word, pb->ul, yv, inv, Z, stream))))
         return rc;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;
     return GEE_OK;

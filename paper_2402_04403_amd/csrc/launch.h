@@ -135,7 +135,8 @@ PbLayout pb_layout(int64_t n, int64_t n_lds);
 size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds);
 hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const int32_t *hot_ids,
                            int64_t n_hot, int64_t n_lds, int32_t *colc, uint8_t *ul, int64_t *cell_start,
-                           uint32_t *cell_count, int32_t *lds_ids, void *ws, int32_t *err, hipStream_t s);
+                           uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, void *ws, int32_t *err,
+                           hipStream_t s);
 // tab: per-call scratch of (n_lds rounded up to 16) bytes.
 hipError_t launch_pb_gather(int64_t nnz, const PbLayout &L, int64_t n_lds, const int64_t *cell_start,
                             const int32_t *colc, const int32_t *lds_ids, const uint8_t *lab, uint8_t *tab,
@@ -145,8 +146,8 @@ hipError_t launch_pb_slice_entries(int64_t n_slots, const int32_t *hot_ids, cons
                                   int64_t *slice_entries, hipStream_t s);
 // ul and yv: 4-byte aligned, readable up to nnz rounded up to 4.
 hipError_t launch_pb_rows(int64_t n, int32_t K, const PbLayout &L, const int64_t *cell_start,
-                          const uint32_t *cell_count, const uint8_t *ul, const uint8_t *yv, const double *inv, float *Z,
-                          hipStream_t s);
+                          const uint32_t *cell_count, const uint32_t *cell_word, const uint8_t *ul, const uint8_t *yv,
+                          const double *inv, float *Z, hipStream_t s);
 
 // CSR build
 struct CsrBuildWs {

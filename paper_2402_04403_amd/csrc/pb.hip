@@ -152,6 +152,24 @@ k_pb_slice_entries(int64_t n_slots, const int32_t *__restrict__ hot_ids, const i
     }
 }
 
+// cell_word[rb n_cb + c] = the first 32-bit word of cell c in row block rb's run of words
+// (its cells one after another, each covering ceil(((start mod 4) + count) / 4) words,
+// none when empty): one thread per row block.
+__global__ void __launch_bounds__(kT)
+k_pb_words(int64_t n_rb, int32_t n_cb, const int64_t *__restrict__ cell_start, const uint32_t *__restrict__ cell_count,
+           uint32_t *__restrict__ cell_word)
+{
+    for (int64_t rb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; rb < n_rb; rb += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t run = 0;
+        for (int32_t c = 0; c < n_cb; ++c) {
+            const int64_t i = rb * n_cb + c;
+            const uint32_t m = cell_count[i];
+            cell_word[i] = run;
+            run += m != 0u ? ((uint32_t)(cell_start[i] & 3) + m + 3u) >> 2 : 0u;
+        }
+    }
+}
+
 __device__ inline int64_t clamp_index(int64_t h, int64_t nnz) { return h < 0 ? 0 : (h > nnz ? nnz : h); }
 
 // yv[i] = lab[colc[i]] over the entries with vertex columns [0, h0), 16 entries per
@@ -250,12 +268,14 @@ k_pb_gather_tier(int64_t nnz, int32_t n_sl, int64_t n_lds, const int64_t *__rest
 // array are in flight per lane. The bytes of a word that lie outside its cell (the
 // cells do not start on word boundaries) are masked. One count per entry into LDS
 // bins [row][class]; then the rows of Z are written once (count * 1/n_k), four
-// floats at a time when Z is 16-byte aligned (VEC).
+// floats at a time when Z is 16-byte aligned (VEC). The word prefix of the cells comes
+// with the layout (cell_word).
 template <bool VEC>
 __global__ void __launch_bounds__(kRowsT)
 k_pb_rows(int64_t n, int32_t K, uint64_t magicK, int32_t n_cb, int32_t top, const int64_t *__restrict__ cell_start,
-          const uint32_t *__restrict__ cell_count, const uint32_t *__restrict__ ul4, const uint32_t *__restrict__ yv4,
-          const double *__restrict__ inv, float *__restrict__ Z)
+          const uint32_t *__restrict__ cell_count, const uint32_t *__restrict__ cell_word,
+          const uint32_t *__restrict__ ul4, const uint32_t *__restrict__ yv4, const double *__restrict__ inv,
+          float *__restrict__ Z)
 {
     // LDS: bins [nb] uint32 (nb = 256 K rounded up to 4), invx [K + 3] double
     // (invx[i] = 1/n_(i mod K) + 1), per cell: first word [n_cb] int64, word prefix
@@ -282,31 +302,34 @@ k_pb_rows(int64_t n, int32_t K, uint64_t magicK, int32_t n_cb, int32_t top, cons
     for (int i = t; i < K + 3; i += kRowsT) invx[i] = inv[1 + i % K];
     for (int c = t; c < n_cb; c += kRowsT) {
         const int64_t a = cell_start[rb * n_cb + c];
+        const uint32_t m = cell_count[rb * n_cb + c], p = cell_word[rb * n_cb + c];
         cw0[c] = a >> 2;
-        cm[c] = cell_count[rb * n_cb + c];
+        cm[c] = m;
         coff[c] = (uint32_t)(a & 3);
-    }
-    __syncthreads();
-    if (wave == 0) { // exclusive prefix of the cells' word counts
-        uint32_t run = 0;
-        for (int c0 = 0; c0 < n_cb; c0 += kWave) {
-            const int c = c0 + lane;
-            const uint32_t d = (c < n_cb && cm[c] != 0u) ? (coff[c] + cm[c] + 3u) >> 2 : 0u;
-            uint32_t x = d;
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const uint32_t y = __shfl_up(x, o, kWave);
-                if (lane >= o) x += y;
-            }
-            if (c < n_cb) pre[c] = run + x - d;
-            run += __shfl(x, kWave - 1, kWave);
-        }
-        if (lane == 0) pre[n_cb] = run;
+        pre[c] = p;
+        if (c == n_cb - 1) pre[n_cb] = p + (m != 0u ? ((uint32_t)(a & 3) + m + 3u) >> 2 : 0u);
     }
     __syncthreads();
     const uint32_t T = pre[n_cb];
     for (uint32_t f0 = (uint32_t)(wave * kWave + lane); f0 < T; f0 += kRowsU * kRowsT) {
         uint32_t u[kRowsU], y[kRowsU], rel[kRowsU], m[kRowsU];
+        // the cells of the kRowsU words, by binary searches run in step: each step reads
+        // pre[] once per word (an index past the last cell reads pre[n_cb] = T, which
+        // no word reaches), so the reads of one step are in flight together
+        int cs[kRowsU];
+#pragma unroll
+        for (int j = 0; j < kRowsU; ++j) cs[j] = 0;
+        for (int st = top; st > 0; st >>= 1) {
+            uint32_t p[kRowsU];
+#pragma unroll
+            for (int j = 0; j < kRowsU; ++j) {
+                const int nc = cs[j] + st;
+                p[j] = pre[nc < n_cb ? nc : n_cb];
+            }
+#pragma unroll
+            for (int j = 0; j < kRowsU; ++j)
+                cs[j] = p[j] <= f0 + (uint32_t)j * kRowsT ? cs[j] + st : cs[j];
+        }
 #pragma unroll
         for (int j = 0; j < kRowsU; ++j) {
             const uint32_t f = f0 + (uint32_t)j * kRowsT;
@@ -315,11 +338,7 @@ k_pb_rows(int64_t n, int32_t K, uint64_t magicK, int32_t n_cb, int32_t top, cons
             rel[j] = 0u;
             m[j] = 0u;
             if (f < T) {
-                int c = 0;
-                for (int st = top; st > 0; st >>= 1) {
-                    const int nc = c + st;
-                    if (nc < n_cb && pre[nc] <= f) c = nc;
-                }
+                const int c = cs[j];
                 const uint32_t k = f - pre[c];
                 const int64_t w = cw0[c] + k;
                 u[j] = ul4[w];
@@ -396,7 +415,8 @@ size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds)
 
 hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const int32_t *hot_ids,
                            int64_t n_hot, int64_t n_lds, int32_t *colc, uint8_t *ul, int64_t *cell_start,
-                           uint32_t *cell_count, int32_t *lds_ids, void *ws, int32_t *err, hipStream_t s)
+                           uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, void *ws, int32_t *err,
+                           hipStream_t s)
 {
     const PbLayout L = pb_layout(n, n_lds);
     size_t hb, ob, pbytes;
@@ -449,6 +469,9 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
     if ((e = max_scan_i64(celllast, L.cells, cellend, part, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pb_table, dim3(grid_cap(L.cells, kT * 4)), b, 0, s, L.n_rb, L.n_cb, cellend, cell_start,
                        cell_count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pb_words, dim3(grid_cap(L.n_rb, kT)), b, 0, s, L.n_rb, L.n_cb, cell_start, cell_count,
+                       cell_word);
     return hipGetLastError();
 }
 
@@ -458,6 +481,8 @@ hipError_t launch_pb_gather(int64_t nnz, const PbLayout &L, int64_t n_lds, const
 {
     if (nnz <= 0) return hipSuccess;
     const int64_t *sl_start = L.n_sl > 0 ? cell_start + L.n_vcb : nullptr; // cells (0, n_vcb + j)
+    // vertex blocks: one workgroup per 4,096 entries, dispatched in order, so the entries
+    // in flight stay within one or two column blocks (their labels in L2)
     hipLaunchKernelGGL(k_pb_gather, dim3(grid_cap(nnz, kT * 16)), dim3(kT), 0, s, nnz, sl_start, colc, lab, yv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || L.n_sl == 0) return e;
@@ -492,8 +517,8 @@ size_t pb_rows_lds_bytes(int32_t K, int32_t n_cb)
 }
 
 hipError_t launch_pb_rows(int64_t n, int32_t K, const PbLayout &L, const int64_t *cell_start,
-                          const uint32_t *cell_count, const uint8_t *ul, const uint8_t *yv, const double *inv, float *Z,
-                          hipStream_t s)
+                          const uint32_t *cell_count, const uint32_t *cell_word, const uint8_t *ul, const uint8_t *yv,
+                          const double *inv, float *Z, hipStream_t s)
 {
     const size_t lds = pb_rows_lds_bytes(K, L.n_cb);
     const uint64_t magic = ((1ull << 32) + (uint64_t)K - 1) / (uint64_t)K;
@@ -503,10 +528,10 @@ hipError_t launch_pb_rows(int64_t n, int32_t K, const PbLayout &L, const int64_t
     const uint32_t *yv4 = reinterpret_cast<const uint32_t *>(yv);
     if ((reinterpret_cast<uintptr_t>(Z) & 15) == 0)
         hipLaunchKernelGGL(k_pb_rows<true>, dim3((unsigned)L.n_rb), dim3(kRowsT), lds, s, n, K, magic, L.n_cb, top,
-                           cell_start, cell_count, ul4, yv4, inv, Z);
+                           cell_start, cell_count, cell_word, ul4, yv4, inv, Z);
     else
         hipLaunchKernelGGL(k_pb_rows<false>, dim3((unsigned)L.n_rb), dim3(kRowsT), lds, s, n, K, magic, L.n_cb, top,
-                           cell_start, cell_count, ul4, yv4, inv, Z);
+                           cell_start, cell_count, cell_word, ul4, yv4, inv, Z);
     return hipGetLastError();
 }
 

@@ -177,32 +177,35 @@ def test_pb_argument_errors(lib):
     assert lib.gee_pb_build_workspace(ctypes.byref(hot), 701) == 0
     assert lib.gee_pb_build_workspace(ctypes.byref(weighted), 0) == 0  # unit weights only
     assert lib.gee_pb_build_workspace(ctypes.byref(huge), 0) == 0      # 32-bit cell lengths
-    assert lib.gee_pb_build(ctypes.byref(huge), 0, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 40, FAKE, None) == \
+    assert lib.gee_pb_build(ctypes.byref(huge), 0, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 40, FAKE, None) == \
         gee.GEE_EOVERFLOW
-    assert lib.gee_pb_build(ctypes.byref(hot), 700, FAKE, FAKE, FAKE, FAKE, None, FAKE, 1 << 40, FAKE, None) == \
-        gee.GEE_EINVAL  # lds_ids needed
-    assert lib.gee_pb_build(ctypes.byref(hot), 701, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 40, FAKE, None) == \
-        gee.GEE_EINVAL  # more tier slots than hot slots
-    assert lib.gee_pb_build(ctypes.byref(plain), 0, FAKE, FAKE + 4, FAKE, FAKE, None, FAKE, 1 << 40, FAKE, None) == \
-        gee.GEE_EINVAL  # ul 16-byte aligned
+    assert lib.gee_pb_build(ctypes.byref(hot), 700, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, 1 << 40, FAKE,
+                            None) == gee.GEE_EINVAL  # lds_ids needed
+    assert lib.gee_pb_build(ctypes.byref(hot), 701, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 40, FAKE,
+                            None) == gee.GEE_EINVAL  # more tier slots than hot slots
+    assert lib.gee_pb_build(ctypes.byref(plain), 0, FAKE, FAKE + 4, FAKE, FAKE, FAKE, None, FAKE, 1 << 40, FAKE,
+                            None) == gee.GEE_EINVAL  # ul 16-byte aligned
+    assert lib.gee_pb_build(ctypes.byref(plain), 0, FAKE, FAKE, FAKE, FAKE, None, None, FAKE, 1 << 40, FAKE,
+                            None) == gee.GEE_EINVAL  # cell_word needed
     # the tier planner: nothing to plan without hot slots; checks before any launch
     assert lib.gee_pb_tier_slots(ctypes.byref(plain), 4, None, 0, None) == 0
     assert lib.gee_pb_tier_slots(ctypes.byref(hot), 4, None, 0, None) == gee.GEE_EWORKSPACE
     assert lib.gee_pb_tier_slots(ctypes.byref(hot), -1, FAKE, 256, None) == gee.GEE_EINVAL
     assert lib.gee_pb_tier_slots(None, 4, FAKE, 256, None) == gee.GEE_EINVAL
-    pb = gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 0, None)
+    pb = gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 0, None, FAKE)
     assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 128) > 10_000
     assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 129) == 0
     assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 0) == 0
-    assert lib.gee_embed_pb_workspace(ctypes.byref(gee.Pb(1000, 10_000, 4, 2, FAKE, FAKE, FAKE, FAKE, 5, FAKE)), 8) \
-        > 10_000
+    tiered = gee.Pb(1000, 10_000, 4, 2, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE)
+    assert lib.gee_embed_pb_workspace(ctypes.byref(tiered), 8) > 10_000
     o = gee.EmbedOpts(0, 0, None, None)
-    for bad in (gee.Pb(1000, 10_000, 5, 1, FAKE, FAKE, FAKE, FAKE, 0, None),  # n_rb does not match n
-                gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 5, FAKE),  # n_cb without the tier slice
-                gee.Pb(1000, 10_000, 4, 2, FAKE, FAKE, FAKE, FAKE, 5, None),  # tier slots without ids
-                gee.Pb(1000, 10_000, 4, 34, FAKE, FAKE, FAKE, FAKE, (1 << 22) + 1, FAKE),  # tier above 2^22
-                gee.Pb(1000, 10_000, 4, 1, FAKE + 4, FAKE, FAKE, FAKE, 0, None),  # col unaligned
-                gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE + 8, FAKE, FAKE, 0, None)):  # ul unaligned
+    for bad in (gee.Pb(1000, 10_000, 5, 1, FAKE, FAKE, FAKE, FAKE, 0, None, FAKE),  # n_rb does not match n
+                gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE),  # n_cb without the tier slice
+                gee.Pb(1000, 10_000, 4, 2, FAKE, FAKE, FAKE, FAKE, 5, None, FAKE),  # tier slots without ids
+                gee.Pb(1000, 10_000, 4, 34, FAKE, FAKE, FAKE, FAKE, (1 << 22) + 1, FAKE, FAKE),  # tier above 2^22
+                gee.Pb(1000, 10_000, 4, 1, FAKE + 4, FAKE, FAKE, FAKE, 0, None, FAKE),  # col unaligned
+                gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE + 8, FAKE, FAKE, 0, None, FAKE),  # ul unaligned
+                gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 0, None, None)):  # no word prefix
         assert lib.gee_embed_pb_workspace(ctypes.byref(bad), 8) == 0
         assert lib.gee_embed_pb(ctypes.byref(bad), FAKE, 8, FAKE, FAKE, 1 << 30, FAKE, ctypes.byref(o), None) == \
             gee.GEE_EINVAL

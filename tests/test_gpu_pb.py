@@ -61,6 +61,10 @@ def _check_layout(csr, pb):
     a = np.lexsort((cols, rows))
     b = np.lexsort((vcol, prow))
     assert np.array_equal(rows[a], prow[b]) and np.array_equal(cols[a], vcol[b])
+    # word prefix of each row block's cells
+    words = np.where(count > 0, ((start & 3) + count + 3) >> 2, 0)
+    want = np.cumsum(words, axis=1) - words
+    assert np.array_equal(pb.cell_word.cpu().numpy().astype(np.int64).reshape(pb.n_rb, pb.n_cb), want)
 
 
 def test_small_graph_matches_pull_and_oracle():
