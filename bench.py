@@ -603,7 +603,7 @@ def main_sweep(a):
                    "sweep": rows, "fit": fit},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "kernel": "k_pb_gather + k_pb_rows" if use_pb else "k_pull",
+                     "kernel": "k_pb_gather + k_pb_tier_labels + k_pb_gather_tier + k_pb_rows" if use_pb else "k_pull",
                      "bytes_alg_per_launch": big["bytes_alg_pull"], "kernel_ms": kms},
         "cpu_baseline": cpu,
     }
