@@ -293,6 +293,58 @@ size_t gee_csr_workspace(int64_t n, int64_t s, int weighted, int64_t hot_budget)
 int gee_csr_build(const gee_coo *g, int64_t hot_budget, int64_t *row_ptr, int32_t *col, float *val,
                   int32_t *hot_ids, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream);
 
+/* Labels from an embedding (Section II: labels may be known ground truth or the
+ * output of a clustering; Section I: embeddings serve classification and clustering).
+ * labels[u] = 1 + the first k with Z[u][k] equal to the largest entry of row u when
+ * that entry is above zero, else 0 (no labelled neighbour): each vertex takes the
+ * class to which it has the most weight per class member. Z is [n * ldz] (K <= ldz
+ * columns used), labels [n] int32. When prev is given, *changed (a device word, may
+ * be NULL) receives the number of vertices whose label differs from prev[u]; labels
+ * and prev must not overlap. Launches kernels only, so it can be recorded. */
+int gee_argmax(const float *Z, int64_t n, int32_t K, int64_t ldz, const int32_t *prev, int32_t *labels,
+               uint64_t *changed, hipStream_t stream);
+
+/* Segment length for gee_embed_batch on this graph and batch (the autotuner of the
+ * batched form): for each of the n_cand candidate lengths in seg_lens (host array,
+ * each a multiple of 64, at most 2^22, or 0 for the library's choice) it makes one
+ * untimed call, then reps timed calls bracketed by HIP events on stream, and returns
+ * the fastest candidate in *best and its mean time per call in *best_ms (host
+ * pointers). ws must hold gee_embed_batch_workspace() for every candidate. The
+ * batch's Z receives the result of the last candidate's calls (for unit-weight
+ * adjacency vectors the same bits with any segment length; other sums may differ in
+ * rounding order). SYNCHRONIZES the stream; returns a status code. */
+int gee_embed_batch_tune(const gee_csr *csr, const gee_batch *batch, const int32_t *seg_lens, int n_cand, int reps,
+                         void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream, int32_t *best, float *best_ms);
+
+/* ------------------------------------------------------------------------------
+ * Recording repeated calls as a HIP graph. A sequence of calls that runs again and
+ * again on the same buffers (the passes of a clustering loop over one graph, a
+ * serving step of fixed shape) can be recorded once and replayed with one launch,
+ * which removes the host cost of its many kernel launches. Between gee_capture_begin
+ * and gee_capture_end on a stream (not the null stream) the gee_* calls made on that
+ * stream by this host thread are recorded, not run; their arguments, pointers
+ * included, are fixed at that point, and each replay reads whatever the buffers hold
+ * then (new labels, say). The embedding and CSR entry points record cleanly (they
+ * launch kernels only, with no memset or host synchronization); gee_pb_tier_slots
+ * synchronizes and must not be recorded. The data-error word is not reset by a
+ * replay: clear it between replays if it is read.
+ * ------------------------------------------------------------------------------ */
+typedef struct gee_graph gee_graph; /* opaque; host memory */
+
+/* Starts recording on stream (GEE_EINVAL for the null stream). */
+int gee_capture_begin(hipStream_t stream);
+
+/* Ends recording on stream and instantiates what was recorded; *graph receives the
+ * handle, or NULL on failure (a failed or unrecordable call inside; the recording is
+ * then discarded). */
+int gee_capture_end(hipStream_t stream, gee_graph **graph);
+
+/* Enqueues one replay of graph on stream. */
+int gee_graph_launch(const gee_graph *graph, hipStream_t stream);
+
+/* Frees graph (NULL is ignored); no replay of it may still be pending. */
+void gee_graph_destroy(gee_graph *graph);
+
 /* Measurement probe: copy `bytes` bytes from src to dst with a plain streaming
  * kernel (16-byte loads and stores). Used to calibrate memory-traffic counters
  * and to measure the attainable copy bandwidth. Both pointers 16-byte aligned. */

@@ -6,6 +6,9 @@ anything here, and the two share no code.
 
 * ``counts / weights / degrees / embed / embed_rows`` wrap ``gee_oracle.c``: plain C,
   FP64, single thread, Algorithm 1 of the paper (Section II) taken step by step.
+* ``argmax_labels`` / ``refine``: labels from an embedding (the class of a row's largest
+  entry) and the loop that re-embeds with them until they stop changing; NumPy over
+  ``embed``.
 * ``csr`` builds the symmetric CSR of S = A + A^T with NumPy: row u lists, for every
   record (u, v, w), the entry (v, w) and, for every record (v, u, w), the entry (v, w);
   a self-loop therefore appears twice in its row. Rows are sorted by (column, bit
@@ -135,6 +138,35 @@ def embed_rows(n: int, src, dst, w, Y, K: int, laplacian: bool, rows) -> np.ndar
                                      _p(Y, I32P), K, 1 if laplacian else 0, rows.shape[0],
                                      _p(rows, I64P), _p(Z, F64P)))
     return Z
+
+
+def argmax_labels(Z, prev=None):
+    """Labels from an embedding: 1 + the first k of row u's largest entry when it is above
+    zero, else 0 (each vertex takes the class to which it has the most weight per class
+    member; Section II allows labels derived from a clustering). The decision is taken on
+    FP32 values, the precision of the library's Z, so that both sides compare the same
+    numbers; numpy's argmax returns the first maximum. With prev, also the number of
+    labels that differ from it."""
+    Zf = np.asarray(Z, dtype=np.float64).astype(np.float32)
+    lab = (np.argmax(Zf, axis=1) + 1).astype(np.int32)
+    lab[Zf.max(axis=1) <= 0] = 0
+    if prev is None:
+        return lab
+    return lab, int(np.count_nonzero(lab != np.asarray(prev)))
+
+
+def refine(n: int, src, dst, Y, K: int, max_iter: int = 50):
+    """Repeat (embed with the current labels, argmax_labels) until no label changes or
+    max_iter rounds; returns (labels, rounds, changes per round). Unit weights,
+    adjacency version."""
+    Y = np.asarray(Y, dtype=np.int32).copy()
+    history = []
+    for _ in range(max_iter):
+        Y, ch = argmax_labels(embed(n, src, dst, None, Y, K), Y)
+        history.append(ch)
+        if ch == 0:
+            break
+    return Y, len(history), history
 
 
 def csr(n: int, src, dst, w=None):

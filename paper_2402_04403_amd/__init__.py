@@ -124,6 +124,19 @@ def load():
         lib.gee_embed_batch_workspace.argtypes = [CsrP, BatchP, OptP]
         lib.gee_embed_batch.restype = ci
         lib.gee_embed_batch.argtypes = [CsrP, BatchP, vp, sz, vp, OptP, vp]
+        lib.gee_embed_batch_tune.restype = ci
+        lib.gee_embed_batch_tune.argtypes = [CsrP, BatchP, ctypes.POINTER(ctypes.c_int32), ci, ci, vp, sz, vp, vp,
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
+        lib.gee_argmax.restype = ci
+        lib.gee_argmax.argtypes = [vp, i64, i32, i64, vp, vp, vp, vp]
+        lib.gee_capture_begin.restype = ci
+        lib.gee_capture_begin.argtypes = [vp]
+        lib.gee_capture_end.restype = ci
+        lib.gee_capture_end.argtypes = [vp, ctypes.POINTER(vp)]
+        lib.gee_graph_launch.restype = ci
+        lib.gee_graph_launch.argtypes = [vp, vp]
+        lib.gee_graph_destroy.restype = None
+        lib.gee_graph_destroy.argtypes = [vp]
         lib.gee_copy.restype = ci
         lib.gee_copy.argtypes = [vp, vp, sz, vp]
         _lib = lib
@@ -574,6 +587,155 @@ def embed_batch(labels: torch.Tensor, Ks, laplacian, csr: DeviceCsr, Z: torch.Te
     if check:
         _check_err(err, "gee_embed_batch")
     return Z, list(zoff)
+
+
+def embed_batch_tune(labels: torch.Tensor, Ks, laplacian, csr: DeviceCsr, seg_lens=(2048, 4096, 8192, 16384, 32768),
+                     reps: int = 3, Z: torch.Tensor | None = None, zoff=None, stream=None):
+    """Segment length for embed_batch on this graph and batch (``gee_embed_batch_tune``):
+    times each candidate and returns (best seg_len, mean ms per call). Synchronizes."""
+    lib = load()
+    B = len(Ks)
+    dev = csr.row_ptr.device
+    _need(labels, torch.int32, B * csr.n, "labels", dev)
+    if zoff is None:
+        zoff, acc = [], 0
+        for k in Ks:
+            zoff.append(acc)
+            acc += int(k)
+    if Z is None:
+        Z = torch.empty((csr.n, int(max(z + k for z, k in zip(zoff, Ks)))), dtype=torch.float32, device=dev)
+    st, keep = _batch_struct(labels, Ks, laplacian, zoff, Z.shape[1], Z)
+    rs = csr.struct()
+    wsb = max(int(lib.gee_embed_batch_workspace(ctypes.byref(rs), ctypes.byref(st), ctypes.byref(_opts(L, 0))))
+              for L in seg_lens)
+    if wsb == 0:
+        raise GeeError(GEE_EINVAL, "gee_embed_batch_workspace")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    err = torch.zeros(1, dtype=torch.int32, device=dev)
+    cands = (ctypes.c_int32 * len(seg_lens))(*[int(x) for x in seg_lens])
+    best, ms = ctypes.c_int32(0), ctypes.c_float(0.0)
+    _rc(lib.gee_embed_batch_tune(ctypes.byref(rs), ctypes.byref(st), cands, len(seg_lens), int(reps), _ptr(ws), wsb,
+                                 _ptr(err), _stream(stream), ctypes.byref(best), ctypes.byref(ms)),
+        "gee_embed_batch_tune")
+    del keep
+    _check_err(err, "gee_embed_batch_tune")
+    return int(best.value), float(ms.value)
+
+
+class Graph:
+    """Library calls recorded once (``gee_capture_begin`` / ``gee_capture_end``) and replayed
+    with one launch each time; every replay reads what the recorded buffers hold then."""
+
+    def __init__(self, handle: int, stream):
+        self._h = handle
+        self.stream = stream
+
+    def replay(self, stream=None):
+        if not self._h:
+            raise RuntimeError("graph destroyed")
+        _rc(load().gee_graph_launch(self._h, _stream(stream if stream is not None else self.stream)),
+            "gee_graph_launch")
+
+    def close(self):
+        if self._h:
+            load().gee_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def capture(fn, stream) -> Graph:
+    """Record the library calls ``fn()`` makes on ``stream`` (a non-default torch stream) as
+    a graph. ``fn`` must pass every buffer (Z, ws, err) and ``check=False``: nothing may be
+    allocated or synchronized while recording."""
+    lib = load()
+    s = _stream(stream)
+    _rc(lib.gee_capture_begin(s), "gee_capture_begin")
+    h = ctypes.c_void_p()
+    try:
+        with torch.cuda.stream(stream):
+            fn()
+    except BaseException:
+        lib.gee_capture_end(s, ctypes.byref(h))
+        if h.value:
+            lib.gee_graph_destroy(h)
+        raise
+    _rc(lib.gee_capture_end(s, ctypes.byref(h)), "gee_capture_end")
+    return Graph(h.value, stream)
+
+
+def argmax(Z: torch.Tensor, K: int | None = None, prev: torch.Tensor | None = None, out: torch.Tensor | None = None,
+           changed: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Labels from an embedding (``gee_argmax``): 1 + the first column of each row's largest
+    positive entry, 0 for a row without one. With ``prev``, ``changed`` (int64 [1]) gets the
+    number of labels that differ from it."""
+    lib = load()
+    if Z.dim() != 2 or Z.dtype != torch.float32 or not Z.is_contiguous():
+        raise ValueError("Z: expected a contiguous float32 [n, ldz] tensor")
+    n, ldz = Z.shape
+    K = ldz if K is None else int(K)
+    dev = Z.device
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=dev)
+    _need(out, torch.int32, n, "out", dev)
+    if prev is not None:
+        _need(prev, torch.int32, n, "prev", dev)
+    _rc(lib.gee_argmax(_ptr(Z), n, K, ldz, _ptr(prev), _ptr(out), _ptr(changed), _stream(stream)), "gee_argmax")
+    return out
+
+
+def refine(labels: torch.Tensor, K: int, csr: DeviceCsr | None = None, pb: DevicePb | None = None,
+           max_iter: int = 50, record: bool = True):
+    """Refine a labelling by GEE: embed with the current labels, give every vertex the class
+    of its largest entry of Z (``argmax``), repeat until no label changes or ``max_iter``
+    rounds. Runs over the CSR (pull form) or the propagation-blocked layout. With
+    ``record`` the two alternating rounds (labels A -> B and B -> A) are recorded once as
+    graphs and replayed. Returns (labels, rounds run, changes per round)."""
+    if (csr is None) == (pb is None):
+        raise ValueError("refine: give csr or pb")
+    n = (csr or pb).n
+    dev = labels.device
+    _need(labels, torch.int32, n, "labels", dev)
+    bufs = [labels.clone(), torch.empty_like(labels)]
+    Z = torch.empty((n, K), dtype=torch.float32, device=dev)
+    wsb = embed_workspace_bytes(K, csr=csr) if csr is not None else embed_pb_workspace_bytes(pb, K)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    err = torch.zeros(1, dtype=torch.int32, device=dev)
+    changed = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+
+    def round_(src, dst):
+        if csr is not None:
+            embed(src, K, csr=csr, Z=Z, ws=ws, err=err, stream=stream, check=False)
+        else:
+            embed_pb(src, K, pb, Z=Z, ws=ws, err=err, stream=stream, check=False)
+        argmax(Z, K, prev=src, out=dst, changed=changed, stream=stream)
+
+    torch.cuda.synchronize(dev)
+    graphs = None
+    if record:
+        graphs = [capture(lambda: round_(bufs[0], bufs[1]), stream), capture(lambda: round_(bufs[1], bufs[0]), stream)]
+    history = []
+    cur = 0
+    for _ in range(max_iter):
+        if graphs is not None:
+            graphs[cur].replay(stream)
+        else:
+            round_(bufs[cur], bufs[1 - cur])
+        stream.synchronize()
+        cur = 1 - cur
+        history.append(int(changed.item()))
+        if history[-1] == 0:
+            break
+    _check_err(err, "refine")
+    if graphs is not None:
+        for g in graphs:
+            g.close()
+    return bufs[cur], len(history), history
 
 
 def embed_batch_workspace_bytes(n: int, Ks, laplacian, csr: DeviceCsr, seg_len: int = 0, zoff=None, ldz=None) -> int:

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgee.so")
-SOURCES = ["embed.hip", "csr_build.hip", "batch.hip", "pb.hip", "api.hip"]
+SOURCES = ["embed.hip", "csr_build.hip", "batch.hip", "pb.hip", "label.hip", "api.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

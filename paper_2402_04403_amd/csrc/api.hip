@@ -5,6 +5,7 @@
 #include <limits.h>
 
 #include <algorithm>
+#include <new>
 #include <numeric>
 #include <vector>
 
@@ -585,6 +586,107 @@ int gee_csr_build(const gee_coo *g, int64_t hot_budget, int64_t *row_ptr, int32_
     csr_build_layout(g->n, g->s, g->w != nullptr, n_hot, static_cast<char *>(ws), &w);
     return hip_rc(
         launch_csr_build(g->n, g->s, g->src, g->dst, g->w, n_hot, row_ptr, col, val, hot_ids, w, err, stream));
+}
+
+int gee_argmax(const float *Z, int64_t n, int32_t K, int64_t ldz, const int32_t *prev, int32_t *labels,
+               uint64_t *changed, hipStream_t stream)
+{
+    if (!Z || !labels || n < 1 || n > kMaxN || K < 1 || K > kMaxK || ldz < K) return GEE_EINVAL;
+    if (prev == labels) return GEE_EINVAL;
+    if ((uint64_t)n > (uint64_t)INT64_MAX / (uint64_t)ldz) return GEE_EOVERFLOW;
+    return hip_rc(launch_argmax(n, K, ldz, Z, prev, labels, prev ? changed : nullptr, stream));
+}
+
+int gee_embed_batch_tune(const gee_csr *csr, const gee_batch *batch, const int32_t *seg_lens, int n_cand, int reps,
+                         void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream, int32_t *best, float *best_ms)
+{
+    if (!seg_lens || n_cand < 1 || reps < 1 || !best || !best_ms) return GEE_EINVAL;
+    for (int i = 0; i < n_cand; ++i)
+        if (seg_lens[i] < 0 || seg_lens[i] % 64 != 0 || seg_lens[i] > (1 << 22)) return GEE_EINVAL;
+    int rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((rc = hip_rc(hipEventCreate(&e0)))) return rc;
+    if ((rc = hip_rc(hipEventCreate(&e1)))) {
+        (void)hipEventDestroy(e0);
+        return rc;
+    }
+    float best_t = 0.f;
+    int32_t best_l = -1;
+    for (int i = 0; i < n_cand && rc == GEE_OK; ++i) {
+        gee_embed_opts o = {};
+        o.seg_len = seg_lens[i];
+        if ((rc = gee_embed_batch(csr, batch, ws, ws_bytes, err, &o, stream))) break;
+        if ((rc = hip_rc(hipEventRecord(e0, stream)))) break;
+        for (int r = 0; r < reps && rc == GEE_OK; ++r) rc = gee_embed_batch(csr, batch, ws, ws_bytes, err, &o, stream);
+        if (rc || (rc = hip_rc(hipEventRecord(e1, stream))) || (rc = hip_rc(hipEventSynchronize(e1)))) break;
+        float ms = 0.f;
+        if ((rc = hip_rc(hipEventElapsedTime(&ms, e0, e1)))) break;
+        ms /= (float)reps;
+        if (best_l < 0 || ms < best_t) {
+            best_t = ms;
+            best_l = seg_lens[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *best = best_l;
+    *best_ms = best_t;
+    return GEE_OK;
+}
+
+} // extern "C"
+
+struct gee_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" {
+
+int gee_capture_begin(hipStream_t stream)
+{
+    if (!stream) return GEE_EINVAL;
+    return hip_rc(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+}
+
+int gee_capture_end(hipStream_t stream, gee_graph **graph)
+{
+    if (!stream || !graph) return GEE_EINVAL;
+    *graph = nullptr;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(stream, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_rc(e);
+    }
+    hipGraphExec_t x = nullptr;
+    if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_rc(e);
+    }
+    gee_graph *r = new (std::nothrow) gee_graph{g, x};
+    if (!r) {
+        (void)hipGraphExecDestroy(x);
+        (void)hipGraphDestroy(g);
+        return GEE_EHIP;
+    }
+    *graph = r;
+    return GEE_OK;
+}
+
+int gee_graph_launch(const gee_graph *graph, hipStream_t stream)
+{
+    if (!graph) return GEE_EINVAL;
+    return hip_rc(hipGraphLaunch(graph->exec, stream));
+}
+
+void gee_graph_destroy(gee_graph *graph)
+{
+    if (!graph) return;
+    (void)hipGraphExecDestroy(graph->exec);
+    (void)hipGraphDestroy(graph->graph);
+    delete graph;
 }
 
 int gee_copy(void *dst, const void *src, size_t bytes, hipStream_t stream)

@@ -149,6 +149,12 @@ hipError_t launch_pb_rows(int64_t n, int32_t K, const PbLayout &L, const int64_t
                           const uint32_t *cell_count, const uint32_t *cell_word, const uint8_t *ul, const uint8_t *yv,
                           const double *inv, float *Z, hipStream_t s);
 
+// Labels from an embedding: out[u] = 1 + argmax_k Z[u][k] (first maximum; 0 for a row
+// with no positive entry); changed (nullable) is set to the number of rows where out
+// differs from prev (prev nullable).
+hipError_t launch_argmax(int64_t n, int32_t K, int64_t ldz, const float *Z, const int32_t *prev, int32_t *out,
+                         uint64_t *changed, hipStream_t s);
+
 // CSR build
 struct CsrBuildWs {
     uint64_t *keys[2];

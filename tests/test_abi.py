@@ -209,3 +209,23 @@ def test_pb_argument_errors(lib):
         assert lib.gee_embed_pb_workspace(ctypes.byref(bad), 8) == 0
         assert lib.gee_embed_pb(ctypes.byref(bad), FAKE, 8, FAKE, FAKE, 1 << 30, FAKE, ctypes.byref(o), None) == \
             gee.GEE_EINVAL
+
+
+def test_capture_and_tune_argument_errors(lib):
+    """Recording needs a real stream and a handle; the tuner checks its candidates first."""
+    h = ctypes.c_void_p()
+    assert lib.gee_capture_begin(None) == gee.GEE_EINVAL
+    assert lib.gee_capture_end(None, ctypes.byref(h)) == gee.GEE_EINVAL
+    assert lib.gee_capture_end(FAKE, None) == gee.GEE_EINVAL
+    assert lib.gee_graph_launch(None, None) == gee.GEE_EINVAL
+    lib.gee_graph_destroy(None)  # ignored
+    best, ms = ctypes.c_int32(), ctypes.c_float()
+    c = (ctypes.c_int32 * 2)(4096, 8192)
+    bad = (ctypes.c_int32 * 2)(4096, 100)  # not a multiple of 64
+    csr = gee.Csr(1000, 10_000, FAKE, FAKE, None, 0, None)
+    st = gee.Batch(1, FAKE, None, None, None, 8, FAKE)
+    for args in ((c, 0, 3), (c, 2, 0), (bad, 2, 3)):
+        assert lib.gee_embed_batch_tune(ctypes.byref(csr), ctypes.byref(st), args[0], args[1], args[2], FAKE, 1 << 30,
+                                        FAKE, None, ctypes.byref(best), ctypes.byref(ms)) == gee.GEE_EINVAL
+    assert lib.gee_embed_batch_tune(ctypes.byref(csr), ctypes.byref(st), c, 2, 3, FAKE, 1 << 30, FAKE, None, None,
+                                    ctypes.byref(ms)) == gee.GEE_EINVAL
