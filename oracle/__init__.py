@@ -156,15 +156,16 @@ def argmax_labels(Z, prev=None):
 
 
 def refine(n: int, src, dst, Y, K: int, max_iter: int = 50):
-    """Repeat (embed with the current labels, argmax_labels) until no label changes or
-    max_iter rounds; returns (labels, rounds, changes per round). Unit weights,
-    adjacency version."""
+    """Repeat (embed with the current labels, argmax_labels) until no label changes, until a
+    round changes no fewer labels than the round two before it (synchronous updates that
+    have settled into a cycle), or max_iter rounds; returns (labels, rounds, changes per
+    round). Unit weights, adjacency version."""
     Y = np.asarray(Y, dtype=np.int32).copy()
     history = []
     for _ in range(max_iter):
         Y, ch = argmax_labels(embed(n, src, dst, None, Y, K), Y)
         history.append(ch)
-        if ch == 0:
+        if ch == 0 or (len(history) >= 3 and history[-1] >= history[-3]):
             break
     return Y, len(history), history
 

@@ -20,6 +20,7 @@ Functions mirror the C entry points:
 from __future__ import annotations
 
 import ctypes
+import time
 import os
 from dataclasses import dataclass
 
@@ -689,12 +690,14 @@ def argmax(Z: torch.Tensor, K: int | None = None, prev: torch.Tensor | None = No
 
 
 def refine(labels: torch.Tensor, K: int, csr: DeviceCsr | None = None, pb: DevicePb | None = None,
-           max_iter: int = 50, record: bool = True):
+           max_iter: int = 50, record: bool = True, stats: dict | None = None):
     """Refine a labelling by GEE: embed with the current labels, give every vertex the class
-    of its largest entry of Z (``argmax``), repeat until no label changes or ``max_iter``
-    rounds. Runs over the CSR (pull form) or the propagation-blocked layout. With
-    ``record`` the two alternating rounds (labels A -> B and B -> A) are recorded once as
-    graphs and replayed. Returns (labels, rounds run, changes per round)."""
+    of its largest entry of Z (``argmax``), repeat until no label changes, until a round
+    changes no fewer labels than the round two before it (the synchronous updates have
+    settled into a cycle), or ``max_iter`` rounds. Runs over the CSR (pull form) or the
+    propagation-blocked layout. With ``record`` the two alternating rounds (labels A -> B
+    and B -> A) are recorded once as graphs and replayed. Returns (labels, rounds run,
+    changes per round); ``stats`` (if given) receives the recording and loop times in ms."""
     if (csr is None) == (pb is None):
         raise ValueError("refine: give csr or pb")
     n = (csr or pb).n
@@ -716,9 +719,11 @@ def refine(labels: torch.Tensor, K: int, csr: DeviceCsr | None = None, pb: Devic
         argmax(Z, K, prev=src, out=dst, changed=changed, stream=stream)
 
     torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
     graphs = None
     if record:
         graphs = [capture(lambda: round_(bufs[0], bufs[1]), stream), capture(lambda: round_(bufs[1], bufs[0]), stream)]
+    t1 = time.perf_counter()
     history = []
     cur = 0
     for _ in range(max_iter):
@@ -729,8 +734,12 @@ def refine(labels: torch.Tensor, K: int, csr: DeviceCsr | None = None, pb: Devic
         stream.synchronize()
         cur = 1 - cur
         history.append(int(changed.item()))
-        if history[-1] == 0:
+        if history[-1] == 0 or (len(history) >= 3 and history[-1] >= history[-3]):
             break
+    t2 = time.perf_counter()
+    if stats is not None:
+        stats["record_ms"] = (t1 - t0) * 1e3
+        stats["loop_ms"] = (t2 - t1) * 1e3
     _check_err(err, "refine")
     if graphs is not None:
         for g in graphs:

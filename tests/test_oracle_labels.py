@@ -45,3 +45,12 @@ def test_refine_two_cliques():
     # the truth is a fixed point
     Y, rounds, hist = oracle.refine(n, src, dst, truth, 2)
     assert Y.tolist() == truth.tolist() and hist == [0]
+
+
+def test_refine_stops_on_a_cycle():
+    """A path of two vertices with swapped labels swaps back and forth forever under
+    synchronous updates: the loop stops once a round changes as many labels as the round
+    two before it."""
+    Y, rounds, hist = oracle.refine(2, np.array([0], np.int32), np.array([1], np.int32),
+                                    np.array([1, 2], np.int32), 2)
+    assert hist == [2, 2, 2] and rounds == 3 and Y.tolist() == [2, 1]  # three swaps
