@@ -70,6 +70,8 @@ def parse():
                    help="rmat27: pb = pull over the propagation-blocked layout (unit weights), pull = CSR pull, "
                         "push = edge-parallel atomics")
     p.add_argument("--seg-len", type=int, default=0)
+    p.add_argument("--no-tune", dest="tune", action="store_false",
+                   help="batched workload: keep the default segment length instead of the autotuner's choice")
     p.add_argument("--rows-per-window", type=int, default=0)
     p.add_argument("--hot-budget", type=int, default=-1, help="hot-vertex slots of the CSR (-1: library default)")
     p.add_argument("--push-steps", type=int, default=3, help="timed steps of each other form, reported beside")
@@ -314,7 +316,9 @@ def main_batched(a):
     s * B / step time. The roofline prices the group loop
     (label packing, edge pass and split-row merge of every group, between the two HIP
     events the call records) against one read of the labels, the CSR and one write of
-    Z. Beside it: one plain ``gee_embed`` call per vector (same CSR, same seg_len)."""
+    Z. Beside it: one plain ``gee_embed`` call per vector (same CSR, same seg_len). Unless
+    --seg-len or --no-tune is given, the segment length is the one gee_embed_batch_tune picks
+    for this graph and batch (among 8,192, 16,384 and 32,768)."""
     import numpy as np
     import torch
 
@@ -359,6 +363,17 @@ def main_batched(a):
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     err = torch.zeros(1, dtype=torch.int32, device=dev)
     log(f"Z {n * KS * 4 / 1e9:.1f} GB, workspace {wsb / 1e9:.2f} GB")
+
+    tuned = None
+    if not a.seg_len and a.tune:
+        # the autotuner of the batched form picks the segment length for this graph and batch
+        cands = (8192, 16384, 32768)
+        best, best_ms = gee.embed_batch_tune(labels, Ks, laps, csr, seg_lens=cands, reps=1, Z=Z, zoff=zoff)
+        tuned = {"candidates": list(cands), "best": best, "best_ms": round(best_ms, 3)}
+        a.seg_len = best
+        wsb = gee.embed_batch_workspace_bytes(n, Ks, laps, csr, seg_len=a.seg_len, zoff=zoff, ldz=KS)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        log(f"tuner: seg_len {best} ({best_ms:.3f} ms per call) among {cands}")
 
     def step(events=None):
         gee.embed_batch(labels, Ks, laps, csr, Z=Z, zoff=zoff, ws=ws, err=err, seg_len=a.seg_len,
@@ -450,7 +465,7 @@ def main_batched(a):
             "workload": f"rmat-s{a.scale}-ef{a.edge_factor}-B{B}-batched",
             "n": n, "s": s, "nnz": nnz, "B": B, "sum_K": KS, "Ks": Ks,
             "versions": "even b adjacency, odd b Laplacian", "layout": "blocks side by side in vector order",
-            "seg_len": a.seg_len or 16384, "hot_slots": csr.n_hot, "csr_build_ms": round(csr_ms, 2),
+            "seg_len": a.seg_len or 16384, "tuner": tuned, "hot_slots": csr.n_hot, "csr_build_ms": round(csr_ms, 2),
             "Z_GB": round(n * KS * 4 / 1e9, 2), "copy_probe_GBps": round(copy_gbps, 1),
             "plain_ms_per_batch": None if plain_ms is None else round(plain_ms, 3),
             "plain_value": None if plain_ms is None else round(s * B / (plain_ms * 1e-3) / 1e9, 3),
