@@ -360,7 +360,7 @@ def csr_build(coo: DeviceCoo, hot_budget: int = 0, stream=None, check: bool = Tr
 PB_ROWS = 256
 PB_COLS = 1 << 21
 PB_SLICE = 1 << 17
-PB_MAX_TIER = 1 << 22
+PB_MAX_TIER = 1 << 23
 
 
 @dataclass
@@ -402,7 +402,7 @@ def pb_tier_slots(csr: DeviceCsr, min_per_row_block: int = 4, stream=None) -> in
     """Tier size for pb_build: leading slices of 2^17 hot slots whose entries average at
     least ``min_per_row_block`` per 256-row block (gee_pb_tier_slots; synchronizes)."""
     lib = load()
-    ws = torch.empty(256, dtype=torch.uint8, device=csr.row_ptr.device)
+    ws = torch.empty(512, dtype=torch.uint8, device=csr.row_ptr.device)
     r = int(lib.gee_pb_tier_slots(ctypes.byref(csr.struct()), min_per_row_block, _ptr(ws), ws.numel(),
                                   _stream(stream)))
     if r < 0:

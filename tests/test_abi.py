@@ -163,8 +163,8 @@ def test_pb_argument_errors(lib):
     assert lib.gee_pb_cells(256, 1) == 2  # one vertex column block + one tier slice
     assert lib.gee_pb_cells(256, 1 << 17) == 2
     assert lib.gee_pb_cells(256, (1 << 17) + 1) == 3
-    assert lib.gee_pb_cells(256, 1 << 22) == 33
-    assert lib.gee_pb_cells(256, (1 << 22) + 1) == 0
+    assert lib.gee_pb_cells(256, 1 << 23) == 65
+    assert lib.gee_pb_cells(256, (1 << 23) + 1) == 0
     assert lib.gee_pb_cells(256, -1) == 0
     assert lib.gee_pb_cells((1 << 21) + 1, 0) == 2 * ((((1 << 21) + 1) + 255) // 256)
     plain = gee.Csr(1000, 10_000, FAKE, FAKE, None, 0, None)
@@ -190,7 +190,8 @@ def test_pb_argument_errors(lib):
     # the tier planner: nothing to plan without hot slots; checks before any launch
     assert lib.gee_pb_tier_slots(ctypes.byref(plain), 4, None, 0, None) == 0
     assert lib.gee_pb_tier_slots(ctypes.byref(hot), 4, None, 0, None) == gee.GEE_EWORKSPACE
-    assert lib.gee_pb_tier_slots(ctypes.byref(hot), -1, FAKE, 256, None) == gee.GEE_EINVAL
+    assert lib.gee_pb_tier_slots(ctypes.byref(hot), -1, FAKE, 512, None) == gee.GEE_EINVAL
+    assert lib.gee_pb_tier_slots(ctypes.byref(hot), 4, FAKE, 256, None) == gee.GEE_EWORKSPACE
     assert lib.gee_pb_tier_slots(None, 4, FAKE, 256, None) == gee.GEE_EINVAL
     pb = gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 0, None, FAKE)
     assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 128) > 10_000
@@ -202,7 +203,7 @@ def test_pb_argument_errors(lib):
     for bad in (gee.Pb(1000, 10_000, 5, 1, FAKE, FAKE, FAKE, FAKE, 0, None, FAKE),  # n_rb does not match n
                 gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE),  # n_cb without the tier slice
                 gee.Pb(1000, 10_000, 4, 2, FAKE, FAKE, FAKE, FAKE, 5, None, FAKE),  # tier slots without ids
-                gee.Pb(1000, 10_000, 4, 34, FAKE, FAKE, FAKE, FAKE, (1 << 22) + 1, FAKE, FAKE),  # tier above 2^22
+                gee.Pb(1000, 10_000, 4, 66, FAKE, FAKE, FAKE, FAKE, (1 << 23) + 1, FAKE, FAKE),  # tier above 2^23
                 gee.Pb(1000, 10_000, 4, 1, FAKE + 4, FAKE, FAKE, FAKE, 0, None, FAKE),  # col unaligned
                 gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE + 8, FAKE, FAKE, 0, None, FAKE),  # ul unaligned
                 gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 0, None, None)):  # no word prefix
