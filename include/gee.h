@@ -173,7 +173,10 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
  *
  * Cell (rb, cb) of the layout is the run of column block cb's entries whose rows
  * lie in [256 rb, 256 rb + 256); cell_start[rb * n_cb + cb] is its first index in
- * col/ul and cell_count[...] its length. n_rb = ceil(n / 256),
+ * the layout and cell_count[...] its length. The tier's entries start at H0, the
+ * first multiple of 16 at or after the end of the vertex blocks (the gap before it
+ * belongs to no cell); tier entry i keeps its slot in bytes 4 H0 + 3 (i - H0) ..
+ * + 2 of col, little-endian. n_rb = ceil(n / 256),
  * n_cb = ceil(n / 2^21) + ceil(n_lds / 2^17). The layout holds at most 2^32 - 65
  * entries (GEE_EOVERFLOW beyond).
  * ------------------------------------------------------------------------------ */
@@ -184,8 +187,9 @@ typedef struct gee_pb {
     int64_t n, nnz;            /* vertices, entries (as in the CSR) */
     int64_t n_rb;              /* row blocks */
     int32_t n_cb;              /* column blocks: vertex blocks, then tier slices */
-    const int32_t *col;        /* [nnz] column (slot within the slice for tier entries), layout order; 16-byte aligned */
-    const uint8_t *ul;         /* [nnz rounded up to 16] row within its 256-row block; 16-byte aligned */
+    const int32_t *col;        /* [nnz + 16] layout order, 16-byte aligned: the column of each vertex-block entry;
+                                  each tier entry's slot within its slice in 3 bytes from byte 4 H0 on */
+    const uint8_t *ul;         /* [nnz + 32 rounded up to 16] row within its 256-row block; 16-byte aligned */
     const int64_t *cell_start; /* [n_rb * n_cb] */
     const uint32_t *cell_count; /* [n_rb * n_cb] */
     int64_t n_lds;             /* tier slots the layout was built with (0 to GEE_PB_MAX_TIER) */
@@ -211,8 +215,8 @@ size_t gee_pb_build_workspace(const gee_csr *csr, int64_t n_lds);
 
 /* Builds the layout of a unit-weight CSR (csr->val must be NULL) with the first n_lds
  * hot slots (0 <= n_lds <= min(n_hot, GEE_PB_MAX_TIER)) in the tier; other hot-slot
- * columns are decoded through hot_ids. Outputs are caller device buffers: col [nnz]
- * (16-byte aligned), ul [nnz rounded up to 16] (16-byte aligned), cell_start,
+ * columns are decoded through hot_ids. Outputs are caller device buffers: col
+ * [nnz + 16] (16-byte aligned), ul [nnz + 32 rounded up to 16] (16-byte aligned), cell_start,
  * cell_count and cell_word [gee_pb_cells(n, n_lds)], lds_ids [n_lds] (may be NULL when
  * n_lds = 0). cell_word[rb * n_cb + c] is the first 32-bit word of cell c when the
  * cells of row block rb are read one after another as words (a cell covering

@@ -369,16 +369,13 @@ class DevicePb:
     block, then by tier slice of 2^17 hot slots; cells of 256-row blocks)."""
 
     n: int
-    col: torch.Tensor
-    ul: torch.Tensor          # [nnz rounded up to 16]
+    col: torch.Tensor         # [nnz + 16] int32; tier slots packed in 3 bytes from byte 4 H0
+    ul: torch.Tensor          # [nnz + 32 rounded up to 16]
     cell_start: torch.Tensor
     cell_count: torch.Tensor
     lds_ids: torch.Tensor     # [n_lds]
     cell_word: torch.Tensor   # [n_rb * n_cb]
-
-    @property
-    def nnz(self) -> int:
-        return int(self.col.numel())
+    nnz: int = 0
 
     @property
     def n_rb(self) -> int:
@@ -421,8 +418,8 @@ def pb_build(csr: DeviceCsr, tier_slots: int | None = None, stream=None, check: 
     wsb = int(lib.gee_pb_build_workspace(ctypes.byref(rs), n_lds))
     if wsb == 0 or cells == 0:
         raise GeeError(GEE_EINVAL, "gee_pb_build_workspace")
-    col = torch.empty(max(csr.nnz, 1), dtype=torch.int32, device=dev)[: csr.nnz]
-    ul = torch.empty((csr.nnz + 15) // 16 * 16 or 16, dtype=torch.uint8, device=dev)
+    col = torch.empty(csr.nnz + 16, dtype=torch.int32, device=dev)
+    ul = torch.empty((csr.nnz + 32 + 15) // 16 * 16, dtype=torch.uint8, device=dev)
     cell_start = torch.empty(cells, dtype=torch.int64, device=dev)
     cell_count = torch.empty(cells, dtype=torch.int32, device=dev)
     cell_word = torch.empty(cells, dtype=torch.int32, device=dev)
@@ -434,7 +431,7 @@ def pb_build(csr: DeviceCsr, tier_slots: int | None = None, stream=None, check: 
     if check:
         _check_err(err, "gee_pb_build")
     del ws
-    return DevicePb(csr.n, col, ul, cell_start, cell_count, lds_ids, cell_word)
+    return DevicePb(csr.n, col, ul, cell_start, cell_count, lds_ids, cell_word, csr.nnz)
 
 
 def embed_pb_workspace_bytes(pb: DevicePb, K: int) -> int:

@@ -523,7 +523,7 @@ PbPlan pb_plan(const gee_pb *pb, int32_t K)
     P.o_inv = take(8 * (size_t)(K + 1));
     P.o_lab = take((size_t)pb->n);
     P.o_tab = take(align_up((size_t)pb->n_lds, 16));
-    P.o_yv = take((size_t)pb->nnz + 16);
+    P.o_yv = take((size_t)pb->nnz + 48); // the gap before the tier and word reads past the end
     P.total = align_up(off, 256);
     return P;
 }
@@ -557,8 +557,8 @@ int gee_embed_pb(const gee_pb *pb, const int32_t *labels, int32_t K, float *Z, v
     const bool timed = opts && opts->hot_begin && opts->hot_end;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_begin, stream)))) return rc;
     const PbLayout L = pb_layout(pb->n, pb->n_lds);
-    if ((rc = hip_rc(launch_pb_gather(pb->nnz, L, pb->n_lds, pb->cell_start, pb->col, pb->lds_ids, lab, tab, yv,
-                                      stream))))
+    if ((rc = hip_rc(launch_pb_gather(pb->nnz, L, pb->n_lds, pb->cell_start, pb->cell_count, pb->col, pb->lds_ids,
+                                      lab, tab, yv, stream))))
         return rc;
     if ((rc = hip_rc(launch_pb_rows(pb->n, K, L, pb->cell_start, pb->cell_count, pb->cell_word, pb->ul, yv, inv, Z, stream))))
         return rc;

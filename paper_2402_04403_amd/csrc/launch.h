@@ -139,12 +139,12 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
                            hipStream_t s);
 // tab: per-call scratch of (n_lds rounded up to 16) bytes.
 hipError_t launch_pb_gather(int64_t nnz, const PbLayout &L, int64_t n_lds, const int64_t *cell_start,
-                            const int32_t *colc, const int32_t *lds_ids, const uint8_t *lab, uint8_t *tab,
-                            uint8_t *yv, hipStream_t s);
+                            const uint32_t *cell_count, const int32_t *colc, const int32_t *lds_ids,
+                            const uint8_t *lab, uint8_t *tab, uint8_t *yv, hipStream_t s);
 // slice_entries [ceil(n_slots / 2^17)]: entries whose column is a hot slot of that slice.
 hipError_t launch_pb_slice_entries(int64_t n_slots, const int32_t *hot_ids, const int64_t *row_ptr,
                                   int64_t *slice_entries, hipStream_t s);
-// ul and yv: 4-byte aligned, readable up to nnz rounded up to 4.
+// ul and yv: 4-byte aligned, readable up to nnz + 32 (the gap before the tier included).
 hipError_t launch_pb_rows(int64_t n, int32_t K, const PbLayout &L, const int64_t *cell_start,
                           const uint32_t *cell_count, const uint32_t *cell_word, const uint8_t *ul, const uint8_t *yv,
                           const double *inv, float *Z, hipStream_t s);

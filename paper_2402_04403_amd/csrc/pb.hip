@@ -13,8 +13,11 @@
 //     extra column blocks after the vertex blocks, one per "tier slice" of 2^17 slots,
 //     and keep their slot within the slice instead of the vertex. A cell is the run of
 //     one column block's entries that belong to one block of 256 rows. Stored: the
-//     column (or slot) of every entry, its row within the 256-row block (8 bits), and
-//     for each (row block, column block) the cell's start and length.
+//     column of every vertex-block entry (32 bits), the slot of every tier entry (17
+//     bits in 3 bytes), its row within the 256-row block (8 bits), and for each (row
+//     block, column block) the cell's start and length. The tier entries start at H0,
+//     the first multiple of 16 at or after the last vertex-block entry; the gap of
+//     fewer than 16 entries before it belongs to no cell (its columns are 0).
 //   gather (per call): walk the entries in that order and write the 8-bit label of
 //     each entry's column. One vertex column block's labels are 2 MB, so consecutive
 //     work reads them from L2, one L2 request per entry. The tier's entries are read
@@ -96,35 +99,72 @@ __device__ inline int64_t pb_cell(uint64_t key, int64_t n_rb)
     return (int64_t)(key >> (32 + kPbColBits)) * n_rb + (int64_t)((key & 0xffffffffull) >> kPbRowBits);
 }
 
-// colc / ul from the sorted keys (the slot within its slice for tier entries);
-// celllast[cell] = index + 1 of the cell's last entry.
+// tier[0] = h0, the number of vertex-block entries (the first sorted key whose column
+// block is a tier slice, by binary search); tier[1] = H0, h0 rounded up to 16.
+__global__ void k_pb_tier_start(const uint64_t *__restrict__ keys, int64_t nnz, int32_t n_vcb, int64_t *tier)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t lo = 0, hi = nnz;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if ((keys[mid] >> (32 + kPbColBits)) >= (uint64_t)n_vcb) hi = mid;
+        else lo = mid + 1;
+    }
+    tier[0] = lo;
+    tier[1] = (lo + 15) & ~(int64_t)15;
+}
+
+// Layout arrays from the sorted keys. Sorted index i goes to o = i before h0 and to
+// i + (H0 - h0) from h0 on. A vertex-block entry stores its column in colc[o]; a tier
+// entry stores its slot within the slice in 3 bytes at colb[4 H0 + 3 (o - H0)]. ul[o]
+// is the row within its block; celllast[cell] = o + 1 for a cell's last entry. The gap
+// [h0, H0) gets column 0 and row 0. tier = {h0, H0} (null: no tier, h0 = H0 = nnz).
 __global__ void __launch_bounds__(kT)
 k_pb_finalize(const uint64_t *__restrict__ keys, int64_t nnz, int64_t n_rb, int32_t n_vcb,
-              int32_t *__restrict__ colc, uint8_t *__restrict__ ul, int64_t *__restrict__ celllast)
+              const int64_t *__restrict__ tier, int32_t *__restrict__ colc, uint8_t *__restrict__ colb,
+              uint8_t *__restrict__ ul, int64_t *__restrict__ celllast)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t h0 = tier ? tier[0] : nnz, H0 = tier ? tier[1] : nnz;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gs = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gt; i < nnz; i += gs) {
         const uint64_t k = keys[i];
         const uint64_t c = k >> 32;
-        colc[i] = (int32_t)((c >> kPbColBits) >= (uint64_t)n_vcb ? (c & (kPbSlice - 1)) : c);
-        ul[i] = (uint8_t)(k & (kPbRows - 1));
+        const int64_t o = i < h0 ? i : i + (H0 - h0);
+        if (i < h0) {
+            colc[o] = (int32_t)c;
+        } else {
+            const uint32_t slot = (uint32_t)(c & (kPbSlice - 1));
+            uint8_t *q = colb + 4 * H0 + 3 * (o - H0);
+            q[0] = (uint8_t)slot;
+            q[1] = (uint8_t)(slot >> 8);
+            q[2] = (uint8_t)(slot >> 16);
+        }
+        ul[o] = (uint8_t)(k & (kPbRows - 1));
         const int64_t cell = pb_cell(k, n_rb);
-        if (i + 1 == nnz || pb_cell(keys[i + 1], n_rb) != cell) celllast[cell] = i + 1;
+        if (i + 1 == nnz || pb_cell(keys[i + 1], n_rb) != cell) celllast[cell] = o + 1;
+    }
+    for (int64_t i = h0 + gt; i < H0; i += gs) {
+        colc[i] = 0;
+        ul[i] = 0;
     }
 }
 
 // Row-block-major table: cell (rb, cb) starts where cell (cb, rb) - 1 of the sorted
-// (column-block-major) order ends.
+// (column-block-major) order ends, a tier cell no earlier than H0 (past the gap).
 __global__ void __launch_bounds__(kT)
-k_pb_table(int64_t n_rb, int32_t n_cb, const int64_t *__restrict__ cellend, int64_t *__restrict__ cell_start,
-           uint32_t *__restrict__ cell_count)
+k_pb_table(int64_t n_rb, int32_t n_cb, int32_t n_vcb, const int64_t *__restrict__ tier,
+           const int64_t *__restrict__ cellend, int64_t *__restrict__ cell_start, uint32_t *__restrict__ cell_count)
 {
+    const int64_t H0 = tier ? tier[1] : 0;
     const int64_t cells = n_rb * n_cb;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t rb = i / n_cb, cb = i - rb * n_cb;
         const int64_t c = cb * n_rb + rb;
-        const int64_t a = c == 0 ? 0 : cellend[c - 1];
+        int64_t a = c == 0 ? 0 : cellend[c - 1];
+        if (cb >= n_vcb && a < H0) a = H0;
+        const int64_t e = cellend[c];
         cell_start[i] = a;
-        cell_count[i] = (uint32_t)(cellend[c] - a);
+        cell_count[i] = (uint32_t)(e > a ? e - a : 0);
     }
 }
 
@@ -208,26 +248,37 @@ k_pb_tier_labels(int64_t n_lds, const int32_t *__restrict__ lds_ids, const uint8
         tab[i] = i < n_lds ? lab[lds_ids[i]] : 0;
 }
 
-// yv[i] = (labels of slice j)[colc[i]] over the tier entries [h0, nnz), where slice j's
-// entries start at sl_start[j] (cell (0, n_vcb + j)). The range is cut into one chunk
-// per workgroup (16-aligned); for every slice its chunk meets, the workgroup copies that
+// The slot of tier entry i: 3 bytes at colb[4 H0 + 3 (i - H0)].
+__device__ inline uint32_t tier_slot(const uint8_t *colb, int64_t H0, int64_t i)
+{
+    const uint8_t *q = colb + 4 * H0 + 3 * (i - H0);
+    return (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16);
+}
+
+// yv[i] = (labels of slice j)[slot of i] over the tier entries [H0, E), where slice j's
+// entries start at sl_start[j] (cell (0, n_vcb + j); sl_start[0] = H0, a multiple of 16)
+// and E = cell_start + cell_count of the last cell. The range is cut into one chunk per
+// workgroup (16-aligned); for every slice its chunk meets, the workgroup copies that
 // slice's labels (at most kPbSlice bytes) into an LDS table of kPbSlice bytes and reads
-// them there. Slots are masked to the table, so no LDS read leaves it.
+// them there. Sixteen entries' slots are three 16-byte loads. Slots are masked to the
+// table, so no LDS read leaves it.
 __global__ void __launch_bounds__(kLdsT)
 k_pb_gather_tier(int64_t nnz, int32_t n_sl, int64_t n_lds, const int64_t *__restrict__ sl_start,
-                 const int32_t *__restrict__ colc, const uint8_t *__restrict__ tab, uint8_t *__restrict__ yv)
+                 const int64_t *__restrict__ last_start, const uint32_t *__restrict__ last_count,
+                 const uint8_t *__restrict__ colb, const uint8_t *__restrict__ tab, uint8_t *__restrict__ yv)
 {
     extern __shared__ __align__(16) uint8_t stab[];
     __shared__ int64_t bnd[kPbMaxSlices + 1];
     const int t = threadIdx.x;
-    if (t <= n_sl) bnd[t] = t < n_sl ? clamp_index(sl_start[t], nnz) : nnz;
+    const int64_t lim = nnz + 16; // entries of the layout, gap included, are at most nnz + 15
+    const int64_t E = clamp_index(*last_start + (int64_t)*last_count, lim);
+    if (t <= n_sl) bnd[t] = t < n_sl ? clamp_index(sl_start[t], E) : E;
     __syncthreads();
-    const int64_t h0 = bnd[0];
-    const int64_t base = h0 & ~(int64_t)15;
-    const int64_t per = ((nnz - base + gridDim.x - 1) / gridDim.x + 15) & ~(int64_t)15;
-    int64_t lo = base + (int64_t)blockIdx.x * per;
-    const int64_t hi = lo + per < nnz ? lo + per : nnz;
-    lo = lo > h0 ? lo : h0;
+    const int64_t H0 = bnd[0] & ~(int64_t)15; // a multiple of 16 by construction
+    const int64_t per = ((E - H0 + gridDim.x - 1) / gridDim.x + 15) & ~(int64_t)15;
+    int64_t lo = H0 + (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < E ? lo + per : E;
+    lo = lo > bnd[0] ? lo : bnd[0];
     if (lo >= hi) return; // the whole workgroup
     const uint32_t mask = (uint32_t)kPbSlice - 1;
     for (int j = 0; j < n_sl; ++j) {
@@ -241,23 +292,24 @@ k_pb_gather_tier(int64_t nnz, int32_t n_sl, int64_t n_lds, const int64_t *__rest
         __syncthreads();
         const int64_t v0 = (a + 15) / 16, v1 = b / 16;
         for (int64_t v = v0 + t; v < v1; v += kLdsT) {
-            const int4 *cp = reinterpret_cast<const int4 *>(colc + v * 16);
-            int4 c4[4];
+            // entries 16 v .. 16 v + 15: 48 bytes at 4 H0 + 3 (16 v - H0), 16-byte aligned
+            const uint4 *cp = reinterpret_cast<const uint4 *>(colb + 4 * H0 + 48 * (v - H0 / 16));
+            const uint4 q0 = cp[0], q1 = cp[1], q2 = cp[2];
+            const uint32_t x[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) c4[q] = cp[q];
-            uint32_t w[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                w[q] = (uint32_t)stab[(uint32_t)c4[q].x & mask] | ((uint32_t)stab[(uint32_t)c4[q].y & mask] << 8) |
-                       ((uint32_t)stab[(uint32_t)c4[q].z & mask] << 16) |
-                       ((uint32_t)stab[(uint32_t)c4[q].w & mask] << 24);
+            for (int e = 0; e < 16; ++e) {
+                const int bit = 24 * e, wd = bit / 32, sh = bit % 32;
+                const uint32_t slot = sh <= 8 ? (x[wd] >> sh) : ((x[wd] >> sh) | (x[wd + 1] << (32 - sh)));
+                w[e / 4] |= (uint32_t)stab[slot & mask] << (8 * (e % 4));
+            }
             *reinterpret_cast<uint4 *>(yv + v * 16) = make_uint4(w[0], w[1], w[2], w[3]);
         }
         // entries outside the 16-aligned run: the head [a, 16 v0) and the tail [16 v1, b)
         const int64_t head_end = v0 * 16 < b ? v0 * 16 : b;
-        for (int64_t i = a + t; i < head_end; i += kLdsT) yv[i] = stab[(uint32_t)colc[i] & mask];
+        for (int64_t i = a + t; i < head_end; i += kLdsT) yv[i] = stab[tier_slot(colb, H0, i) & mask];
         const int64_t tail_begin = v1 * 16 > head_end ? v1 * 16 : head_end;
-        for (int64_t i = tail_begin + t; i < b; i += kLdsT) yv[i] = stab[(uint32_t)colc[i] & mask];
+        for (int64_t i = tail_begin + t; i < b; i += kLdsT) yv[i] = stab[tier_slot(colb, H0, i) & mask];
     }
 }
 
@@ -410,6 +462,7 @@ size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds)
     take(pbytes);
     take((size_t)L.cells * 8);
     take((size_t)L.cells * 8);
+    take(16);
     return align_up(off, 256);
 }
 
@@ -436,6 +489,7 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
     int64_t *part = (int64_t *)take(pbytes);
     int64_t *celllast = (int64_t *)take((size_t)L.cells * 8);
     int64_t *cellend = (int64_t *)take((size_t)L.cells * 8);
+    int64_t *tier = L.n_sl > 0 ? (int64_t *)take(16) : nullptr; // {h0, H0}
     hipError_t e;
     const dim3 b(kT);
     if (n_lds > 0 && (e = hipMemcpyAsync(lds_ids, hot_ids, (size_t)n_lds * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess)
@@ -460,15 +514,20 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
                 return e;
         }
         if ((e = launch_fill_i64(celllast, L.cells, 0, s)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_pb_finalize, dim3(grid_cap(nnz, kT * 4)), b, 0, s, sorted, nnz, L.n_rb, L.n_vcb, colc, ul,
-                           celllast);
+        if (tier) {
+            hipLaunchKernelGGL(k_pb_tier_start, dim3(1), dim3(kWave), 0, s, sorted, nnz, L.n_vcb, tier);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_pb_finalize, dim3(grid_cap(nnz, kT * 4)), b, 0, s, sorted, nnz, L.n_rb, L.n_vcb, tier,
+                           colc, reinterpret_cast<uint8_t *>(colc), ul, celllast);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
         if ((e = launch_fill_i64(celllast, L.cells, 0, s)) != hipSuccess) return e;
+        if (tier && (e = launch_fill_i64(tier, 2, 0, s)) != hipSuccess) return e;
     }
     if ((e = max_scan_i64(celllast, L.cells, cellend, part, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pb_table, dim3(grid_cap(L.cells, kT * 4)), b, 0, s, L.n_rb, L.n_cb, cellend, cell_start,
-                       cell_count);
+    hipLaunchKernelGGL(k_pb_table, dim3(grid_cap(L.cells, kT * 4)), b, 0, s, L.n_rb, L.n_cb, L.n_vcb, tier, cellend,
+                       cell_start, cell_count);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pb_words, dim3(grid_cap(L.n_rb, kT)), b, 0, s, L.n_rb, L.n_cb, cell_start, cell_count,
                        cell_word);
@@ -476,8 +535,8 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
 }
 
 hipError_t launch_pb_gather(int64_t nnz, const PbLayout &L, int64_t n_lds, const int64_t *cell_start,
-                            const int32_t *colc, const int32_t *lds_ids, const uint8_t *lab, uint8_t *tab,
-                            uint8_t *yv, hipStream_t s)
+                            const uint32_t *cell_count, const int32_t *colc, const int32_t *lds_ids,
+                            const uint8_t *lab, uint8_t *tab, uint8_t *yv, hipStream_t s)
 {
     if (nnz <= 0) return hipSuccess;
     const int64_t *sl_start = L.n_sl > 0 ? cell_start + L.n_vcb : nullptr; // cells (0, n_vcb + j)
@@ -495,8 +554,10 @@ hipError_t launch_pb_gather(int64_t nnz, const PbLayout &L, int64_t n_lds, const
     int64_t grid = nnz / 65536;
     if (grid > cus) grid = cus;
     if (grid < 1) grid = 1;
+    const int64_t last = L.cells - 1; // the last cell of the column-block-major order
     hipLaunchKernelGGL(k_pb_gather_tier, dim3((unsigned)grid), dim3(kLdsT), (size_t)kPbSlice, s, nnz, L.n_sl, n_lds,
-                       sl_start, colc, tab, yv);
+                       sl_start, cell_start + last, cell_count + last, reinterpret_cast<const uint8_t *>(colc), tab,
+                       yv);
     return hipGetLastError();
 }
 

@@ -38,12 +38,18 @@ def _check_layout(csr, pb):
     assert pb.n_cb == n_vcb + (pb.n_lds + (1 << 17) - 1) // (1 << 17)
     if pb.n_lds:
         assert torch.equal(pb.lds_ids.cpu(), csr.hot_ids[: pb.n_lds].cpu())
-    # column-block-major order: cells (cb, rb) are consecutive
+    # column-block-major order: cells (cb, rb) are consecutive, except the gap of fewer
+    # than 16 entries before the first tier cell, which starts on a multiple of 16
     order = np.argsort(start.T.reshape(-1), kind="stable")
     flat_start, flat_count = start.T.reshape(-1)[order], count.T.reshape(-1)[order]
-    assert np.all(flat_start[1:] == (flat_start + flat_count)[:-1])
+    flat_cb = np.repeat(np.arange(pb.n_cb), pb.n_rb)[order]
+    gaps = flat_start[1:] - (flat_start + flat_count)[:-1]
+    boundary = (flat_cb[1:] >= n_vcb) & (flat_cb[:-1] < n_vcb)
+    assert np.all(gaps[~boundary] == 0)
+    assert np.all((gaps[boundary] >= 0) & (gaps[boundary] < 16) & (flat_start[1:][boundary] % 16 == 0))
+    colbytes = pb.col.cpu().numpy().view(np.uint8)
     pcol = pb.col.cpu().numpy().astype(np.int64)
-    pul = pb.ul.cpu().numpy()[: csr.nnz].astype(np.int64)
+    pul = pb.ul.cpu().numpy().astype(np.int64)
     rb_of = np.repeat(np.repeat(np.arange(pb.n_rb), pb.n_cb), count.reshape(-1))
     cb_of = np.repeat(np.tile(np.arange(pb.n_cb), pb.n_rb), count.reshape(-1))
     idx = np.concatenate([np.arange(a, a + c) for a, c in zip(start.reshape(-1), count.reshape(-1)) if c]) \
@@ -52,6 +58,13 @@ def _check_layout(csr, pb):
     vcol = pcol[idx].copy()
     tier = cb_of >= n_vcb
     assert np.all(vcol[~tier] >> 21 == cb_of[~tier])
+    if tier.any():  # tier slots: 3 bytes each from byte 4 H0, H0 the first tier index (a multiple of 16)
+        ti = idx[tier]
+        H0 = int(ti.min())
+        assert H0 % 16 == 0 and int(idx[~tier].max(initial=-1)) < H0
+        off = 4 * H0 + 3 * (ti - H0)
+        vcol[tier] = (colbytes[off].astype(np.int64) | (colbytes[off + 1].astype(np.int64) << 8)
+                      | (colbytes[off + 2].astype(np.int64) << 16))
     slots = vcol[tier] + ((cb_of[tier] - n_vcb) << 17)  # slot within the slice -> tier slot
     assert np.all((vcol[tier] >= 0) & (vcol[tier] < (1 << 17)) & (slots < max(pb.n_lds, 1)))
     if pb.n_lds:
