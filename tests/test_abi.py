@@ -230,3 +230,14 @@ def test_capture_and_tune_argument_errors(lib):
                                         FAKE, None, ctypes.byref(best), ctypes.byref(ms)) == gee.GEE_EINVAL
     assert lib.gee_embed_batch_tune(ctypes.byref(csr), ctypes.byref(st), c, 2, 3, FAKE, 1 << 30, FAKE, None, None,
                                     ctypes.byref(ms)) == gee.GEE_EINVAL
+
+
+def test_argmax_argument_errors(lib):
+    """Checks done before anything launches: buffers, sizes, K within ldz, distinct labels and prev."""
+    E = gee.GEE_EINVAL
+    assert lib.gee_argmax(None, 10, 5, 5, None, FAKE, None, None) == E
+    assert lib.gee_argmax(FAKE, 10, 5, 5, None, None, None, None) == E
+    assert lib.gee_argmax(FAKE, 0, 5, 5, None, FAKE, None, None) == E
+    assert lib.gee_argmax(FAKE, 10, 0, 5, None, FAKE, None, None) == E
+    assert lib.gee_argmax(FAKE, 10, 6, 5, None, FAKE, None, None) == E  # K above ldz
+    assert lib.gee_argmax(FAKE, 10, 5, 5, FAKE, FAKE, None, None) == E  # labels overwrite prev
