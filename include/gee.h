@@ -274,7 +274,10 @@ size_t gee_embed_batch_workspace(const gee_csr *csr, const gee_batch *batch, con
  * taken in CSR order, so results are bit-reproducible. Vector b's block holds the
  * values gee_embed returns for it (identical bits for unit-weight adjacency
  * vectors; other sums may differ in rounding order). Laplacian vectors share one
- * degree pass. Per-segment work follows opts->seg_len as in gee_embed;
+ * degree pass. Per-segment work follows opts->seg_len as in gee_embed, except that
+ * 0 picks the power of two at or above (n + nnz) / 4096 within [512, 16384] (its
+ * lanes are vectors, so a wavefront walks a segment's entries one at a time and a
+ * small graph needs short segments; the choice depends only on the graph);
  * opts->hot_begin / hot_end bracket the group passes (label packing, edge pass and
  * split-row merge of every group). Data errors as for gee_embed; columns of Z
  * outside the blocks are not touched. GEE_EINVAL also when ldz > 2^31 - 1. */

@@ -21,6 +21,18 @@ constexpr int64_t kMaxRecords = (int64_t)1 << 40;
 constexpr int32_t kMaxK = 65535;
 constexpr int32_t kMaxKPull = 4096;
 constexpr int32_t kDefaultSegLen = 16384;
+
+// Default segment length of the batched pass. Its lanes are vectors, so a wavefront
+// walks its segment's entries one at a time: a small graph needs short segments to
+// give the GPU enough wavefronts. The power of two at or above (n + nnz) / 4096, in
+// [512, kDefaultSegLen]; it depends only on the graph.
+int32_t batch_default_seg_len(int64_t n, int64_t nnz)
+{
+    const int64_t want = (n + nnz) / 4096;
+    int64_t L = 512;
+    while (L < want && L < kDefaultSegLen) L *= 2;
+    return (int32_t)L;
+}
 constexpr int32_t kMaxSegLen = 65535; // 16-bit per-segment class counters
 constexpr size_t kWaveLdsBudget = 16384;
 
@@ -194,7 +206,7 @@ int make_batch_plan(const gee_csr *csr, const gee_batch *bt, const gee_embed_opt
         P.Gs_max = std::max(P.Gs_max, d.Gs);
         P.KT_max = std::max(P.KT_max, d.KT);
     }
-    P.L = (o && o->seg_len) ? o->seg_len : kDefaultSegLen;
+    P.L = (o && o->seg_len) ? o->seg_len : batch_default_seg_len(P.n, P.nnz);
     P.nseg = (P.n + P.nnz + P.L - 1) / P.L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
