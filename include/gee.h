@@ -99,7 +99,9 @@ typedef struct gee_csr {
 /* Optional knobs of gee_embed (host struct; pass NULL for the defaults). */
 typedef struct gee_embed_opts {
     /* CSR-pull form: work items (rows + entries) per wavefront segment; 0 picks
-     * the default (16384). Must be 0 or in [64, 65535]. */
+     * the default: the power of two at or above (n + nnz) / 8192 within
+     * [1024, 16384], so that small graphs still give the GPU enough wavefronts
+     * (it depends only on the graph). Must be 0 or in [64, 65535]. */
     int32_t seg_len;
     /* CSR-pull form: rows per LDS window; 0 picks the largest that fits the
      * per-wavefront LDS budget (at most 64). Must be 0 or in [1, 64]. */

@@ -22,6 +22,17 @@ constexpr int32_t kMaxK = 65535;
 constexpr int32_t kMaxKPull = 4096;
 constexpr int32_t kDefaultSegLen = 16384;
 
+// Default segment length of the pull pass: one wavefront per segment, so a small graph
+// needs shorter segments to give the GPU enough wavefronts. The power of two at or
+// above (n + nnz) / 8192, in [1024, kDefaultSegLen]; it depends only on the graph.
+int32_t pull_default_seg_len(int64_t n, int64_t nnz)
+{
+    const int64_t want = (n + nnz) / 8192;
+    int64_t L = 1024;
+    while (L < want && L < kDefaultSegLen) L *= 2;
+    return (int32_t)L;
+}
+
 // Default segment length of the batched pass. Its lanes are vectors, so a wavefront
 // walks its segment's entries one at a time: a small graph needs short segments to
 // give the GPU enough wavefronts. The power of two at or above (n + nnz) / 4096, in
@@ -100,7 +111,7 @@ int make_plan(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian, co
         if (o->rows_per_window < 0 || o->rows_per_window > 64) return GEE_EINVAL;
     }
     if (P.pull) {
-        P.L = (o && o->seg_len) ? o->seg_len : kDefaultSegLen;
+        P.L = (o && o->seg_len) ? o->seg_len : pull_default_seg_len(P.n, P.nnz);
         P.nseg = (P.n + P.nnz + P.L - 1) / P.L;
         if (o && o->rows_per_window) {
             P.rw = o->rows_per_window;
