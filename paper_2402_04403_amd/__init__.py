@@ -267,6 +267,12 @@ class DeviceCsr:
         return 0 if self.hot_ids is None else int(self.hot_ids.numel())
 
     def struct(self) -> Csr:
+        # the checked struct is kept while the fields name the same buffers (serving loops
+        # call this once per launch)
+        key = (self.n, _ptr(self.row_ptr), _ptr(self.col), self.nnz, _ptr(self.val), _ptr(self.hot_ids), self.n_hot)
+        got = self.__dict__.get("_struct")
+        if got is not None and got[0] == key:
+            return got[1]
         dev = self.row_ptr.device
         _need(self.row_ptr, torch.int64, self.n + 1, "row_ptr", dev)
         _need(self.col, torch.int32, None, "col", dev)
@@ -274,8 +280,10 @@ class DeviceCsr:
             _need(self.val, torch.float32, self.nnz, "val", dev)
         if self.hot_ids is not None:
             _need(self.hot_ids, torch.int32, None, "hot_ids", dev)
-        return Csr(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val), self.n_hot,
-                   _ptr(self.hot_ids))
+        st = Csr(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val), self.n_hot,
+                 _ptr(self.hot_ids))
+        self.__dict__["_struct"] = (key, st)
+        return st
 
     def plain_col(self) -> torch.Tensor:
         """Columns as vertex ids (hot slots resolved)."""

@@ -400,12 +400,11 @@ int gee_embed_batch(const gee_csr *csr, const gee_batch *batch, void *ws, size_t
     int64_t *seg_e = reinterpret_cast<int64_t *>(w + p.o_sege);
     float *rsd = p.any_lap ? reinterpret_cast<float *>(w + p.o_rsd) : nullptr;
 
-    // class counts and weights of every vector
-    for (int b = 0; b < batch->B; ++b) {
-        const int32_t *lb = batch->labels + (int64_t)b * p.n;
-        if ((rc = hip_rc(launch_counts(lb, p.n, batch->K[b], cnt + p.cnt_off[b], nullptr, Pack::U8, err, stream))))
-            return rc;
-        if ((rc = hip_rc(launch_weights(cnt + p.cnt_off[b], batch->K[b], inv + p.cnt_off[b], stream)))) return rc;
+    // class counts and weights of every vector, one launch of each per group
+    if ((rc = hip_rc(launch_fill_u64(cnt, p.cnt_total, 0, stream)))) return rc;
+    for (const GroupDesc &d : p.groups) {
+        if ((rc = hip_rc(launch_counts_group(batch->labels, p.n, d, cnt, err, stream)))) return rc;
+        if ((rc = hip_rc(launch_weights_group(cnt, d, inv, stream)))) return rc;
     }
     // one degree pass shared by the Laplacian vectors
     if (p.any_lap) {

@@ -98,6 +98,11 @@ int batch_waves_per_block(int KT); // wavefronts whose bins fit one block's LDS 
 size_t batch_lds_bytes(int KT, int nw);
 hipError_t launch_pack_group(const int32_t *labels, int64_t n, const GroupDesc &d, uint16_t *labmat, int32_t *err,
                              hipStream_t s);
+// Class counts (added to counts, which start at zero) and weights of every vector of a
+// group; each vector's tables at its inv_off.
+hipError_t launch_counts_group(const int32_t *labels, int64_t n, const GroupDesc &d, uint64_t *counts, int32_t *err,
+                               hipStream_t s);
+hipError_t launch_weights_group(const uint64_t *counts, const GroupDesc &d, double *inv, hipStream_t s);
 hipError_t launch_pack_group_hot(const int32_t *hot_ids, int64_t n_hot, int64_t n, int Gs, const uint16_t *labmat,
                                  uint16_t *labhot, const float *rsd, float *rsdhot, int32_t *err, hipStream_t s);
 hipError_t launch_group_cols(const double *inv_all, const GroupDesc &d, double *cscale, uint32_t *vmeta,

@@ -71,7 +71,7 @@ class _Launch:
     reqs: list
     graph: _Graph
     bytes: int
-    err: torch.Tensor
+    slot: int  # this launch's word of the error mirrors
     keep: list = field(default_factory=list)
     Z: torch.Tensor | None = None
     zoff: list | None = None
@@ -80,6 +80,8 @@ class _Launch:
 class Server:
     """Continuous-batching GEE server over a pool of graphs (``graphs[gid] = (n, src, dst)``
     host arrays). ``hbm_budget`` bounds resident graphs plus in-flight outputs and scratch."""
+
+    MAX_INFLIGHT = 1024  # launches in flight at once
 
     def __init__(self, graphs: dict, hbm_budget: int, streams: int = 4, mode: str = "batched",
                  seg_len: int = 0, hot_budget: int = DEFAULT_HOT_BUDGET, keep_results: bool = False,
@@ -100,6 +102,11 @@ class Server:
         self.inflight: list[_Launch] = []
         self.used = 0  # bytes: resident graphs + in-flight launches
         self.evictions = 0
+        # one error word per in-flight launch, copied back to pinned host memory behind the
+        # launch on its stream: a finished launch's word is read without a device sync
+        self._err_dev = torch.zeros(self.MAX_INFLIGHT, dtype=torch.int32, device=self.dev)
+        self._err_host = torch.zeros(self.MAX_INFLIGHT, dtype=torch.int32, pin_memory=True)
+        self._free_slots = list(range(self.MAX_INFLIGHT - 1, -1, -1))
         self.ref = HipEvent()
         self.ref.record(torch.cuda.current_stream(self.dev))
         self.ref.synchronize()
@@ -168,8 +175,11 @@ class Server:
         limit = 1 if self.mode == "plain" else len(self.pending)
         if self.mode == "plain" and self.inflight:
             return out
+        gids = set()  # one launch per graph, each holding an error slot
         while self.pending and len(out) < limit:
             r = self.pending[0]
+            if r.gid not in gids and len(gids) >= len(self._free_slots):
+                break
             g = self._resident(r.gid)
             if g is None:
                 break
@@ -181,10 +191,11 @@ class Server:
             self.pending.popleft()
             self.used += need
             g.busy += 1
+            gids.add(r.gid)
             out.append((r, g, need))
         return out
 
-    def _launch(self, group: list):
+    def _launch(self, group: list, slot: int):
         g = group[0][1]
         reqs = [r for r, _, _ in group]
         nbytes = sum(b for _, _, b in group)
@@ -194,7 +205,8 @@ class Server:
         laps = [l for r in reqs for l in r.laplacian]
         n = g.csr.n
         with torch.cuda.stream(stream):
-            err = torch.zeros(1, dtype=torch.int32, device=self.dev)
+            err = self._err_dev[slot:slot + 1]
+            err.zero_()
             labels = torch.cat([r.labels.to(self.dev, non_blocking=True) for r in reqs]) if len(reqs) > 1 else \
                 reqs[0].labels.to(self.dev, non_blocking=True)
             Z = torch.empty((n, int(sum(Ks))), dtype=torch.float32, device=self.dev)
@@ -212,9 +224,10 @@ class Server:
                           stream=stream, check=False)
                     if self.keep:  # results side by side, as the batched launch returns them
                         Z[:, zoff[b]:zoff[b] + k].copy_(Zb)
+            self._err_host[slot:slot + 1].copy_(err, non_blocking=True)
             ev = HipEvent()
             ev.record(stream)
-        self.inflight.append(_Launch(ev, reqs, g, nbytes, err, keep=[labels, Z] + [r.labels for r in reqs],
+        self.inflight.append(_Launch(ev, reqs, g, nbytes, slot, keep=[labels, Z] + [r.labels for r in reqs],
                                      Z=Z if self.keep else None, zoff=zoff))
 
     def poll(self) -> list:
@@ -226,7 +239,8 @@ class Server:
                 still.append(L)
                 continue
             t = self._host_time(L.event)
-            e = int(L.err.item())
+            e = int(self._err_host[L.slot])
+            self._free_slots.append(L.slot)
             col = 0
             for r in L.reqs:
                 kz = int(sum(r.Ks))
@@ -242,7 +256,7 @@ class Server:
         for item in admitted:
             by_graph.setdefault(item[0].gid, []).append(item)
         for group in by_graph.values():
-            self._launch(group)
+            self._launch(group, self._free_slots.pop())
         return finished
 
     def drain(self) -> list:
