@@ -91,12 +91,22 @@ k_counts_group(const int32_t *__restrict__ labels, int64_t n, GroupDesc d, uint6
     const int32_t *__restrict__ lab = labels + (int64_t)d.vec[i] * n;
     for (int b = threadIdx.x; b <= K; b += blockDim.x) hist[b] = 0;
     __syncthreads();
+    // four labels per lane are loaded before any is added
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     bool bad = false;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t y = lab[v];
-        const bool ok = (uint32_t)y <= (uint32_t)K;
-        bad |= !ok;
-        if (ok) atomicAdd(&hist[y], 1u);
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v0 < n; v0 += 4 * stride) {
+        int32_t y[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t v = v0 + q * stride;
+            y[q] = v < n ? lab[v] : -1; // -1: past the end (not counted, not an error)
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool ok = (uint32_t)y[q] <= (uint32_t)K;
+            bad |= !ok && v0 + q * stride < n;
+            if (ok) atomicAdd(&hist[y[q]], 1u);
+        }
     }
     if (bad) flag_error(err, GEE_ELABEL);
     __syncthreads();
@@ -734,7 +744,9 @@ hipError_t launch_counts_group(const int32_t *labels, int64_t n, const GroupDesc
                                hipStream_t s)
 {
     if (d.G < 1 || d.G > kGroupMax) return hipErrorInvalidValue;
-    const dim3 g(grid_for(n, kBlock * 16, 4096), d.G), b(kBlock);
+    // about 4,096 workgroups over the group: every workgroup ends with K + 1 global adds
+    // into its vector's counts, and many workgroups per vector would queue on those words
+    const dim3 g(grid_for(n, kBlock * 16, 4096 / d.G), d.G), b(kBlock);
     hipLaunchKernelGGL(k_counts_group, g, b, 0, s, labels, n, d, counts, err);
     return hipGetLastError();
 }
