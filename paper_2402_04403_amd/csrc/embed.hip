@@ -52,15 +52,27 @@ k_counts(const int32_t *__restrict__ labels, int64_t n, int32_t K, uint64_t *__r
         for (int b = threadIdx.x; b <= K; b += blockDim.x) hist[b] = 0;
     __syncthreads();
     bool bad = false;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t y = labels[v];
-        const bool ok = (uint32_t)y <= (uint32_t)K;
-        bad |= !ok;
-        if (ok) {
-            if (lds) atomicAdd(&hist[y], 1u);
-            else atomicAdd((unsigned long long *)&counts[y], 1ull);
+    // four labels per lane are loaded before any is added
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v0 < n; v0 += 4 * stride) {
+        int32_t y[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t v = v0 + q * stride;
+            y[q] = v < n ? labels[v] : -1; // -1: past the end
         }
-        if (packed) packed[v] = (P)(ok ? y : 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t v = v0 + q * stride;
+            if (v >= n) break;
+            const bool ok = (uint32_t)y[q] <= (uint32_t)K;
+            bad |= !ok;
+            if (ok) {
+                if (lds) atomicAdd(&hist[y[q]], 1u);
+                else atomicAdd((unsigned long long *)&counts[y[q]], 1ull);
+            }
+            if (packed) packed[v] = (P)(ok ? y[q] : 0);
+        }
     }
     if (bad) flag_error(err, GEE_ELABEL);
     __syncthreads();
@@ -731,7 +743,8 @@ hipError_t launch_counts(const int32_t *labels, int64_t n, int32_t K, uint64_t *
 {
     hipError_t e = launch_fill_u64(counts, (int64_t)K + 1, 0, s);
     if (e != hipSuccess) return e;
-    const dim3 g(grid_for(n, kBlock * 16, 4096)), b(kBlock);
+    // 1,024 workgroups at most: each ends with K + 1 global adds into the same counts
+    const dim3 g(grid_for(n, kBlock * 16, 1024)), b(kBlock);
     if (pack == Pack::U16)
         hipLaunchKernelGGL(k_counts<uint16_t>, g, b, 0, s, labels, n, K, counts, as<uint16_t>(packed), err);
     else
