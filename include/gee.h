@@ -99,7 +99,7 @@ typedef struct gee_csr {
 /* Optional knobs of gee_embed (host struct; pass NULL for the defaults). */
 typedef struct gee_embed_opts {
     /* CSR-pull form: work items (rows + entries) per wavefront segment; 0 picks
-     * the default: the power of two at or above (n + nnz) / 8192 within
+     * the default: the power of two at or above (n + nnz) / 131072 within
      * [1024, 16384], so that small graphs still give the GPU enough wavefronts
      * (it depends only on the graph). Must be 0 or in [64, 65535]. */
     int32_t seg_len;
@@ -277,9 +277,9 @@ size_t gee_embed_batch_workspace(const gee_csr *csr, const gee_batch *batch, con
  * values gee_embed returns for it (identical bits for unit-weight adjacency
  * vectors; other sums may differ in rounding order). Laplacian vectors share one
  * degree pass. Per-segment work follows opts->seg_len as in gee_embed, except that
- * 0 picks the power of two at or above (n + nnz) / 4096 within [512, 16384] (its
- * lanes are vectors, so a wavefront walks a segment's entries one at a time and a
- * small graph needs short segments; the choice depends only on the graph);
+ * 0 picks the power of two at or above (n + nnz) / 32768 within [512, 16384] (its
+ * lanes are vectors, so a wavefront walks a segment's entries one at a time and
+ * short segments keep the GPU busy; the choice depends only on the graph);
  * opts->hot_begin / hot_end bracket the group passes (label packing, edge pass and
  * split-row merge of every group). Data errors as for gee_embed; columns of Z
  * outside the blocks are not touched. GEE_EINVAL also when ldz > 2^31 - 1. */

@@ -24,22 +24,23 @@ constexpr int32_t kDefaultSegLen = 16384;
 
 // Default segment length of the pull pass: one wavefront per segment, so a small graph
 // needs shorter segments to give the GPU enough wavefronts. The power of two at or
-// above (n + nnz) / 8192, in [1024, kDefaultSegLen]; it depends only on the graph.
+// above (n + nnz) / 131072, in [1024, kDefaultSegLen]; it depends only on the graph.
 int32_t pull_default_seg_len(int64_t n, int64_t nnz)
 {
-    const int64_t want = (n + nnz) / 8192;
+    const int64_t want = (n + nnz) / 131072;
     int64_t L = 1024;
     while (L < want && L < kDefaultSegLen) L *= 2;
     return (int32_t)L;
 }
 
 // Default segment length of the batched pass. Its lanes are vectors, so a wavefront
-// walks its segment's entries one at a time: a small graph needs short segments to
-// give the GPU enough wavefronts. The power of two at or above (n + nnz) / 4096, in
+// walks its segment's entries one at a time: short segments give the GPU enough
+// wavefronts (about 16K-32K of them up to graphs of 2^29 work items), at the price of
+// more split rows. The power of two at or above (n + nnz) / 32768, in
 // [512, kDefaultSegLen]; it depends only on the graph.
 int32_t batch_default_seg_len(int64_t n, int64_t nnz)
 {
-    const int64_t want = (n + nnz) / 4096;
+    const int64_t want = (n + nnz) / 32768;
     int64_t L = 512;
     while (L < want && L < kDefaultSegLen) L *= 2;
     return (int32_t)L;
