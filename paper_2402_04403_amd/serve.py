@@ -7,12 +7,20 @@ evicted when memory is needed), admits arrived jobs in arrival order while their
 output and scratch fit an HBM budget, and at every poll launches all admitted jobs:
 the jobs on one graph are fused into one ``gee_embed_batch`` call (continuous
 batching: a job that arrives while others run joins the next launch), and calls on
-different graphs go to different HIP streams so their work overlaps on the device.
+different graphs go to different HIP streams so their work overlaps on the device; each
+launch takes the stream with the least estimated work in flight.
 
 A job's result does not depend on which other jobs share its launch: the batched
 pass gives every vector its own bins, filled in CSR order, and the segmentation
-depends only on the graph and the segment length. ``plain`` mode is the comparison:
-one job at a time, one ``gee_embed`` call per vector, in arrival order.
+depends only on the graph and the segment length. Optionally a job of few vectors on
+a large graph (at most ``route_vectors`` vectors, default 0: none; at least
+``route_items`` rows + entries) runs as one ``gee_embed`` call per vector instead,
+inside the same launch: the batched pass gives its lanes to vectors, so a call with few
+vectors leaves most lanes idle, while the plain pull gives them to entries. The choice
+depends only on the job and its graph. It shortens such jobs but costs throughput when
+jobs on one graph could have shared a batched call.
+``plain`` mode is the comparison: one job at a time, one ``gee_embed`` call per vector,
+in arrival order.
 
 Latency of a job = device completion of its launch minus its arrival, both on the
 host clock (the completion is read from HIP events against a reference event).
@@ -72,6 +80,8 @@ class _Launch:
     graph: _Graph
     bytes: int
     slot: int  # this launch's word of the error mirrors
+    stream: int = 0
+    work: float = 0.0  # estimated device bytes (Z written, entries read per vector)
     keep: list = field(default_factory=list)
     Z: torch.Tensor | None = None
     zoff: list | None = None
@@ -85,13 +95,15 @@ class Server:
 
     def __init__(self, graphs: dict, hbm_budget: int, streams: int = 4, mode: str = "batched",
                  seg_len: int = 0, hot_budget: int = DEFAULT_HOT_BUDGET, keep_results: bool = False,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", route_vectors: int = 0, route_items: int = 1 << 22):
         if mode not in ("batched", "plain"):
             raise ValueError("mode: batched or plain")
         self.pool = graphs
         self.budget = int(hbm_budget)
         self.mode = mode
         self.seg_len = seg_len
+        self.route_vectors = route_vectors
+        self.route_items = route_items
         self.hot_budget = hot_budget
         self.keep = keep_results
         self.dev = torch.device(device)
@@ -102,11 +114,18 @@ class Server:
         self.inflight: list[_Launch] = []
         self.used = 0  # bytes: resident graphs + in-flight launches
         self.evictions = 0
+        self._ws_plain = {}  # (gid, K, laplacian) -> gee_embed workspace bytes
         # one error word per in-flight launch, copied back to pinned host memory behind the
         # launch on its stream: a finished launch's word is read without a device sync
         self._err_dev = torch.zeros(self.MAX_INFLIGHT, dtype=torch.int32, device=self.dev)
         self._err_host = torch.zeros(self.MAX_INFLIGHT, dtype=torch.int32, pin_memory=True)
         self._free_slots = list(range(self.MAX_INFLIGHT - 1, -1, -1))
+        # one small launch on every stream, so that the first jobs do not wait while the
+        # runtime sets up the streams' queues
+        for st in self.streams:
+            with torch.cuda.stream(st):
+                self._err_dev.zero_()
+        torch.cuda.synchronize(self.dev)
         self.ref = HipEvent()
         self.ref.record(torch.cuda.current_stream(self.dev))
         self.ref.synchronize()
@@ -117,13 +136,25 @@ class Server:
         hot = min(self.hot_budget, n)
         return 8 * (n + 1) + 4 * 2 * s + 4 * hot
 
+    def _routes_plain(self, g: _Graph, Ks) -> bool:
+        """The job runs as one gee_embed call per vector (plain mode, or few vectors on a
+        large graph)."""
+        return self.mode == "plain" or (len(Ks) <= self.route_vectors and g.csr.n + g.csr.nnz >= self.route_items)
+
     def _launch_bytes(self, g: _Graph, Ks, laps) -> int:
         n = g.csr.n
-        if self.mode == "batched":
+        if not self._routes_plain(g, Ks):
             ws = embed_batch_workspace_bytes(n, Ks, laps, g.csr, seg_len=self.seg_len)
             return ws + 4 * n * int(sum(Ks)) + 4 * n * len(Ks) * 2
-        ws = max(embed_workspace_bytes(k, csr=g.csr, laplacian=l, seg_len=self.seg_len) for k, l in zip(Ks, laps))
-        return ws + 4 * n * int(sum(Ks)) + 4 * n * len(Ks)
+        ws = max(self._plain_ws(g, k, l) for k, l in zip(Ks, laps))
+        return ws + 4 * n * int(sum(Ks)) + 4 * n * len(Ks) + 4 * n * max(Ks)
+
+    def _plain_ws(self, g: _Graph, k: int, lap: bool) -> int:
+        key = (g.gid, int(k), bool(lap))
+        b = self._ws_plain.get(key)
+        if b is None:
+            b = self._ws_plain[key] = embed_workspace_bytes(k, csr=g.csr, laplacian=lap, seg_len=self.seg_len)
+        return b
 
     def _evict_for(self, need: int, keep_gid: int) -> bool:
         while self.used + need > self.budget:
@@ -133,6 +164,7 @@ class Server:
             victim = min(idle, key=lambda g: g.last_use)
             self.used -= victim.bytes
             del self.resident[victim.gid]
+            self._ws_plain = {k: b for k, b in self._ws_plain.items() if k[0] != victim.gid}
             self.evictions += 1
         return True
 
@@ -158,6 +190,24 @@ class Server:
             if self._resident(gid) is None:
                 break
         return len(self.resident)
+
+    SMALL_RESERVE = 512  # 1 MiB blocks kept for small buffers (torch serves those from a separate pool)
+
+    def reserve(self) -> int:
+        """Allocate and free one block of the budget not held by resident graphs, so that
+        torch's caching allocator keeps it as one segment and later launches are carved
+        from it instead of calling the device allocator while jobs wait; likewise
+        SMALL_RESERVE blocks of 1 MiB for the pool torch keeps for buffers of at most
+        1 MiB. Returns the bytes set aside."""
+        free = self.budget - self.used
+        if free <= 0:
+            return 0
+        small = min(self.SMALL_RESERVE, free // (4 << 20))
+        blocks = [torch.empty(1 << 20, dtype=torch.uint8, device=self.dev) for _ in range(small)]
+        big = free - small * (2 << 20)  # a 1 MiB block takes half of a 2 MiB segment
+        block = torch.empty(big, dtype=torch.uint8, device=self.dev) if big > 0 else None
+        del blocks, block
+        return free
 
     # ------------------------------------------------------------ serving ----
     def submit(self, req: Request):
@@ -199,35 +249,76 @@ class Server:
         g = group[0][1]
         reqs = [r for r, _, _ in group]
         nbytes = sum(b for _, _, b in group)
-        stream = self.streams[self._next_stream]
-        self._next_stream = (self._next_stream + 1) % len(self.streams)
         Ks = [k for r in reqs for k in r.Ks]
+        # the stream with the least estimated work in flight, so that a short launch does
+        # not queue behind a long one while another stream is idle
+        work = 4.0 * g.csr.n * sum(Ks) + 4.0 * (g.csr.n + g.csr.nnz) * len(Ks)
+        load = [0.0] * len(self.streams)
+        for L in self.inflight:
+            load[L.stream] += L.work
+        si = min(range(len(self.streams)), key=lambda i: (load[i], (i - self._next_stream) % len(self.streams)))
+        self._next_stream = (si + 1) % len(self.streams)
+        stream = self.streams[si]
         laps = [l for r in reqs for l in r.laplacian]
+        zoff, acc = [], 0
+        for k in Ks:
+            zoff.append(acc)
+            acc += k
+        # vector index of each job's first vector in the launch
+        first, b0 = [], 0
+        for r in reqs:
+            first.append(b0)
+            b0 += len(r.Ks)
         n = g.csr.n
+        fused = [i for i, r in enumerate(reqs) if not self._routes_plain(g, r.Ks)]
+        fset = set(fused)
+        vs = [first[i] + b for i in fused for b in range(len(reqs[i].Ks))]  # fused vectors
+        pv = [first[i] + b for i, r in enumerate(reqs) if i not in fset for b in range(len(r.Ks))]
+        # Device buffers come from the pool of torch's current stream, which reserve()
+        # fills, and are marked as used by the launch's stream: torch keeps free blocks per
+        # stream, so buffers allocated on the launch's stream would bypass the reservation
+        # and reach the device allocator while jobs wait. Label rows: the fused jobs'
+        # vectors first (one contiguous block for the batched call), then the others.
+        labels = torch.empty((len(Ks), n), dtype=torch.int32, device=self.dev)
+        Z = torch.empty((n, int(sum(Ks))), dtype=torch.float32, device=self.dev)
+        bufs = [labels, Z]
+        if vs:
+            fK, fl, fz = [Ks[v] for v in vs], [laps[v] for v in vs], [zoff[v] for v in vs]
+            ws_b = torch.empty(embed_batch_workspace_bytes(n, fK, fl, g.csr, seg_len=self.seg_len, zoff=fz,
+                                                           ldz=Z.shape[1]), dtype=torch.uint8, device=self.dev)
+            bufs.append(ws_b)
+        if pv:
+            ws_p = torch.empty(max(self._plain_ws(g, Ks[v], laps[v]) for v in pv), dtype=torch.uint8, device=self.dev)
+            zb = torch.empty(n * max(Ks[v] for v in pv), dtype=torch.float32, device=self.dev)
+            bufs += [ws_p, zb]
+        for t in bufs:
+            t.record_stream(stream)
         with torch.cuda.stream(stream):
             err = self._err_dev[slot:slot + 1]
             err.zero_()
-            labels = torch.cat([r.labels.to(self.dev, non_blocking=True) for r in reqs]) if len(reqs) > 1 else \
-                reqs[0].labels.to(self.dev, non_blocking=True)
-            Z = torch.empty((n, int(sum(Ks))), dtype=torch.float32, device=self.dev)
-            zoff, acc = [], 0
-            for k in Ks:
-                zoff.append(acc)
-                acc += k
-            if self.mode == "batched":
-                embed_batch(labels.view(-1), Ks, laps, g.csr, Z=Z, zoff=zoff, err=err, seg_len=self.seg_len,
-                            stream=stream, check=False)
-            else:
-                for b, (k, lap) in enumerate(zip(Ks, laps)):
-                    Zb = torch.empty((n, k), dtype=torch.float32, device=self.dev)
-                    embed(labels[b], k, csr=g.csr, laplacian=lap, Z=Zb, err=err, seg_len=self.seg_len,
-                          stream=stream, check=False)
-                    if self.keep:  # results side by side, as the batched launch returns them
-                        Z[:, zoff[b]:zoff[b] + k].copy_(Zb)
+            row, rows = [0, len(vs)], []
+            for i, r in enumerate(reqs):
+                side = 0 if i in fset else 1
+                rows.append(row[side])
+                labels[row[side]:row[side] + len(r.Ks)].copy_(r.labels, non_blocking=True)
+                row[side] += len(r.Ks)
+            if vs:  # one batched call over the fused jobs' vectors, their blocks of Z in place
+                embed_batch(labels[:len(vs)].reshape(-1), fK, fl, g.csr, Z=Z, zoff=fz, ws=ws_b, err=err,
+                            seg_len=self.seg_len, stream=stream, check=False)
+            for i, r in enumerate(reqs):
+                if i in fset:
+                    continue
+                for b, (k, lap) in enumerate(zip(r.Ks, r.laplacian)):
+                    v = first[i] + b
+                    Zb = zb[:n * k].view(n, k)
+                    embed(labels[rows[i] + b], k, csr=g.csr, laplacian=lap, Z=Zb, ws=ws_p, err=err,
+                          seg_len=self.seg_len, stream=stream, check=False)
+                    if self.keep:  # results side by side, as a batched launch returns them
+                        Z[:, zoff[v]:zoff[v] + k].copy_(Zb)
             self._err_host[slot:slot + 1].copy_(err, non_blocking=True)
             ev = HipEvent()
             ev.record(stream)
-        self.inflight.append(_Launch(ev, reqs, g, nbytes, slot, keep=[labels, Z] + [r.labels for r in reqs],
+        self.inflight.append(_Launch(ev, reqs, g, nbytes, slot, si, work, keep=bufs + [r.labels for r in reqs],
                                      Z=Z if self.keep else None, zoff=zoff))
 
     def poll(self) -> list:

@@ -96,3 +96,44 @@ def test_small_budget_evicts_and_refuses():
     tiny.submit(_reqs(graphs, jobs[:1])[0])
     with pytest.raises(ValueError):
         tiny.drain()
+
+
+def test_routed_jobs_alone_equal_in_the_mix():
+    """Jobs of at most three vectors run as one plain call per vector (route_items=0 routes
+    them on every graph); beside fused jobs in one launch, each job's Z is the same as when
+    it runs alone, and it matches the oracle."""
+    pool, graphs, jobs = _pool()
+    jobs = jobs[:16]
+    assert any(len(j.Ks) <= 3 for j in jobs) and any(len(j.Ks) > 3 for j in jobs)
+
+    def server(streams):
+        return Server(graphs, 8 << 30, streams=streams, keep_results=True, route_vectors=3, route_items=0)
+
+    mix = _run(server(3), _reqs(graphs, jobs))
+    assert len(mix) == len(jobs) and all(d.error == 0 for d in mix.values())
+    for j in jobs:
+        alone = _run(server(1), _reqs(graphs, [j]))
+        assert torch.equal(alone[j.jid].Z.view(torch.int32), mix[j.jid].Z.view(torch.int32)), j.jid
+    for j in jobs[:8]:
+        n, src, dst = graphs[j.gid]
+        Y = j.labels(n)
+        col = 0
+        for k, y in zip(j.Ks, Y):
+            assert_parity(mix[j.jid].Z.cpu().numpy()[:, col:col + k], oracle.embed(n, src, dst, None, y, k, j.laplacian),
+                          what=f"job {j.jid} ({len(j.Ks)} vectors) vs oracle")
+            col += k
+
+
+def test_reserve_then_serve():
+    """reserve() sets aside what the resident graphs leave of the budget in torch's cache;
+    jobs served afterwards give the same Z as without it."""
+    pool, graphs, jobs = _pool()
+    jobs = jobs[:6]
+    srv = Server(graphs, 2 << 30, keep_results=True)
+    assert srv.warm([j.gid for j in jobs]) >= 1
+    got = srv.reserve()
+    assert got == srv.budget - srv.used > 0
+    a = _run(srv, _reqs(graphs, jobs))
+    b = _run(Server(graphs, 2 << 30, keep_results=True), _reqs(graphs, jobs))
+    for j in jobs:
+        assert torch.equal(a[j.jid].Z.view(torch.int32), b[j.jid].Z.view(torch.int32)), j.jid
