@@ -144,8 +144,9 @@ class Server:
     def _launch_bytes(self, g: _Graph, Ks, laps) -> int:
         n = g.csr.n
         if not self._routes_plain(g, Ks):
+            # the job's share of a fused launch is at most what it would need alone
             ws = embed_batch_workspace_bytes(n, Ks, laps, g.csr, seg_len=self.seg_len)
-            return ws + 4 * n * int(sum(Ks)) + 4 * n * len(Ks) * 2
+            return ws + 4 * n * int(sum(Ks)) + 4 * n * len(Ks)
         ws = max(self._plain_ws(g, k, l) for k, l in zip(Ks, laps))
         return ws + 4 * n * int(sum(Ks)) + 4 * n * len(Ks) + 4 * n * max(Ks)
 
@@ -204,7 +205,7 @@ class Server:
             return 0
         small = min(self.SMALL_RESERVE, free // (4 << 20))
         blocks = [torch.empty(1 << 20, dtype=torch.uint8, device=self.dev) for _ in range(small)]
-        big = free - small * (2 << 20)  # a 1 MiB block takes half of a 2 MiB segment
+        big = free - small * (1 << 20)  # two 1 MiB blocks share a 2 MiB segment
         block = torch.empty(big, dtype=torch.uint8, device=self.dev) if big > 0 else None
         del blocks, block
         return free
