@@ -416,8 +416,8 @@ int gee_embed_batch(const gee_csr *csr, const gee_batch *batch, void *ws, size_t
     if ((rc = hip_rc(launch_seg_bounds(p.n, p.nnz, csr->row_ptr, p.L, p.nseg, seg_i, seg_e, stream)))) return rc;
     const bool timed = opts && opts->hot_begin && opts->hot_end;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_begin, stream)))) return rc;
-    uint16_t *labmat = reinterpret_cast<uint16_t *>(w + p.o_lab);
-    uint16_t *labhot = reinterpret_cast<uint16_t *>(w + p.o_labhot);
+    void *labmat = w + p.o_lab;    // sized for 16-bit labels; 8-bit groups use half
+    void *labhot = w + p.o_labhot;
     float *rsdhot = p.any_lap ? reinterpret_cast<float *>(w + p.o_rsdhot) : nullptr;
     double *cscale = reinterpret_cast<double *>(w + p.o_cscale);
     uint32_t *vmeta = reinterpret_cast<uint32_t *>(w + p.o_vmeta);
@@ -431,6 +431,9 @@ int gee_embed_batch(const gee_csr *csr, const gee_batch *batch, void *ws, size_t
         g.n_hot = p.n_hot;
         g.labmat = labmat;
         g.labhot = labhot;
+        int32_t kmax = 0;
+        for (int i = 0; i < d.G; ++i) kmax = d.K[i] > kmax ? d.K[i] : kmax;
+        g.u8 = kmax <= 255; // 8-bit label rows: half the bytes per gathered row
         g.Gs = d.Gs;
         g.KT = d.KT;
         g.lap = p.lap[gi];
@@ -446,9 +449,9 @@ int gee_embed_batch(const gee_csr *csr, const gee_batch *batch, void *ws, size_t
         g.zcol = d.zoff[0];
         g.part = reinterpret_cast<double *>(w + p.o_part);
         g.err = err;
-        if ((rc = hip_rc(launch_pack_group(batch->labels, p.n, d, labmat, err, stream)))) return rc;
-        if ((rc = hip_rc(launch_pack_group_hot(csr->hot_ids, p.n_hot, p.n, d.Gs, labmat, labhot, g.rsd, g.lap ? rsdhot : nullptr, err,
-                                               stream))))
+        if ((rc = hip_rc(launch_pack_group(batch->labels, p.n, d, labmat, g.u8, err, stream)))) return rc;
+        if ((rc = hip_rc(launch_pack_group_hot(csr->hot_ids, p.n_hot, p.n, d.Gs * (g.u8 ? 1 : 2), labmat, labhot,
+                                               g.rsd, g.lap ? rsdhot : nullptr, err, stream))))
             return rc;
         if ((rc = hip_rc(launch_group_cols(inv, d, cscale, vmeta, stream)))) return rc;
         if ((rc = hip_rc(launch_pull_group(g, stream)))) return rc;

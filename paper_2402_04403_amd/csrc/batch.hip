@@ -4,8 +4,8 @@
 // Algorithm 1 (Section II of the paper) is a single pass over the edges for one
 // label vector. For B vectors on the same graph the pass is shared. The vectors of
 // a group (up to 64, any mix of adjacency and Laplacian) are stored transposed: one
-// row of 16-bit labels per vertex, so one 128-byte line holds a vertex's labels in
-// all 64 vectors. Hot vertices (the CSR's hot slots) get a compact copy of their
+// row of labels per vertex (8-bit when every vector of the group has K <= 255, else
+// 16-bit), so one 64- or 128-byte piece holds a vertex's labels in all 64 vectors. Hot vertices (the CSR's hot slots) get a compact copy of their
 // rows, addressed by slot, so an entry whose column is a slot needs no id lookup.
 //
 // One wavefront owns a segment of the merge-path split (rows + entries). Lane b is
@@ -30,6 +30,7 @@ constexpr int kCW = 32;       // entries per chunk (a chunk never spans two rows
 constexpr int kMaxWavesPerBlock = 8;
 constexpr uint32_t kNoVec = 0xffffffffu;
 typedef __attribute__((address_space(1))) const uint16_t global_u16;
+typedef __attribute__((address_space(1))) const uint8_t global_u8;
 
 inline int grid_cap(int64_t items, int per_block)
 {
@@ -41,10 +42,12 @@ inline int grid_cap(int64_t items, int per_block)
 
 // labmat[v * Gs + b] = label of vertex v in vector b of the group (0 for a label
 // outside [0, K_b] and for the padding columns b >= G); row n is all zeros and is
-// where invalid column ids point. A 64 x 64 tile goes through LDS so both the read
-// (along v) and the write (along b) are coalesced.
+// where invalid column ids point. Labels are 8-bit (L = uint8_t) when every vector
+// of the group has K <= 255, else 16-bit. A 64 x 64 tile goes through LDS so both the
+// read (along v) and the write (along b) are coalesced.
+template <typename L>
 __global__ void __launch_bounds__(kBT)
-k_pack_group(const int32_t *__restrict__ labels, int64_t n, GroupDesc d, uint16_t *__restrict__ labmat, int32_t *err)
+k_pack_group(const int32_t *__restrict__ labels, int64_t n, GroupDesc d, L *__restrict__ labmat, int32_t *err)
 {
     __shared__ uint16_t tile[64][65];
     const int64_t v0 = (int64_t)blockIdx.x * 64;
@@ -64,20 +67,22 @@ k_pack_group(const int32_t *__restrict__ labels, int64_t n, GroupDesc d, uint16_
     __syncthreads();
     for (int r = ty; r < 64; r += kBT / 64) {
         const int64_t v = v0 + r;
-        if (v < n && tx < d.Gs) labmat[v * d.Gs + tx] = tile[r][tx];
+        if (v < n && tx < d.Gs) labmat[v * d.Gs + tx] = (L)tile[r][tx];
     }
-    if (blockIdx.x == 0 && threadIdx.x < d.Gs) labmat[n * d.Gs + threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < d.Gs) labmat[n * d.Gs + threadIdx.x] = (L)0;
     if (bad) flag_error(err, GEE_ELABEL);
 }
 
-// Hot rows in slot order: labhot[s] = labmat[hot_ids[s]] (8 labels per thread), and
-// for a group with Laplacian vectors rsdhot[s] = d^-1/2 of that vertex.
+// Hot rows in slot order: labhot[s] = labmat[hot_ids[s]] (rows of rb bytes, copied in
+// pieces of sizeof(P) bytes), and for a group with Laplacian vectors rsdhot[s] =
+// d^-1/2 of that vertex.
+template <typename P>
 __global__ void __launch_bounds__(kBT)
-k_pack_group_hot(const int32_t *__restrict__ hot_ids, int64_t n_hot, int64_t n, int Gs,
-                 const uint16_t *__restrict__ labmat, uint16_t *__restrict__ labhot, const float *__restrict__ rsd,
+k_pack_group_hot(const int32_t *__restrict__ hot_ids, int64_t n_hot, int64_t n, int rb,
+                 const uint8_t *__restrict__ labmat, uint8_t *__restrict__ labhot, const float *__restrict__ rsd,
                  float *__restrict__ rsdhot, int32_t *err)
 {
-    const int pieces = Gs / 8;
+    const int pieces = rb / (int)sizeof(P);
     const int64_t total = n_hot * pieces;
     bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
@@ -88,8 +93,8 @@ k_pack_group_hot(const int32_t *__restrict__ hot_ids, int64_t n_hot, int64_t n, 
             bad = true;
             v = n; // the zero row
         }
-        const uint4 q = *reinterpret_cast<const uint4 *>(labmat + v * Gs + p * 8);
-        *reinterpret_cast<uint4 *>(labhot + s * Gs + p * 8) = q;
+        const P q = *reinterpret_cast<const P *>(labmat + v * rb + p * (int)sizeof(P));
+        *reinterpret_cast<P *>(labhot + s * rb + p * (int)sizeof(P)) = q;
         if (rsdhot && p == 0) rsdhot[s] = v < n ? rsd[v] : 0.0f;
     }
     if (bad) flag_error(err, GEE_EVERTEX);
@@ -168,12 +173,12 @@ struct Chunk {
 // ids of chunk k+2 are in flight while chunk k is added and its row written. The
 // row writes read nothing from global memory (column scales sit in LDS, shared by
 // the block's wavefronts; row ends and d^-1/2 in a 64-row register window), so they
-// never wait on those loads.
-template <bool W, bool LAP>
+// never wait on those loads. L is the label type of the group's rows (8- or 16-bit).
+template <bool W, bool LAP, typename L>
 __global__ void __launch_bounds__(kWave * kMaxWavesPerBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_batch_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-             const float *__restrict__ val, int64_t n_hot, const uint16_t *__restrict__ labmat,
-             const uint16_t *__restrict__ labhot, int Gs, const float *__restrict__ rsd,
+             const float *__restrict__ val, int64_t n_hot, const L *__restrict__ labmat,
+             const L *__restrict__ labhot, int Gs, const float *__restrict__ rsd,
              const float *__restrict__ rsdhot, const uint32_t *__restrict__ vmeta, const double *__restrict__ cscale,
              int KT, const int32_t *__restrict__ seg_i, const int64_t *__restrict__ seg_e, int64_t nseg,
              float *__restrict__ Z, int64_t ldz, int64_t zcol, double *__restrict__ part, int32_t *err)
@@ -260,7 +265,7 @@ k_batch_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__re
         // row address per entry (lane j), then per entry one scalar address and one
         // coalesced load; in groups of 8 under a wave-uniform guard (all of them are
         // complete by the time the next step's wait for its column ids returns)
-        const uint16_t *rowp = hot && ok ? labhot + slot * Gs : labmat + (int64_t)c * Gs;
+        const L *rowp = hot && ok ? labhot + slot * Gs : labmat + (int64_t)c * Gs;
         const uint32_t ralo = (uint32_t)(uintptr_t)rowp, rahi = (uint32_t)((uintptr_t)rowp >> 32);
 #pragma unroll
         for (int q0 = 0; q0 < kCW; q0 += 8) {
@@ -269,7 +274,8 @@ k_batch_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__re
                 for (int q = q0; q < q0 + 8; ++q) {
                     const uint64_t sa = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(rahi, q) << 32) |
                                         (uint64_t)(uint32_t)__builtin_amdgcn_readlane(ralo, q);
-                    lab[q] = reinterpret_cast<const global_u16 *>(sa)[lsrc]; // global, not flat
+                    using GL = typename std::conditional<sizeof(L) == 1, global_u8, global_u16>::type;
+                    lab[q] = reinterpret_cast<const GL *>(sa)[lsrc]; // global, not flat
                 }
             } else {
 #pragma unroll
@@ -449,19 +455,30 @@ size_t batch_lds_bytes(int KT, int nw)
     return sizeof(double) * (KTp + (KTp + kWave) * (size_t)nw);
 }
 
-hipError_t launch_pack_group(const int32_t *labels, int64_t n, const GroupDesc &d, uint16_t *labmat, int32_t *err,
-                             hipStream_t s)
+hipError_t launch_pack_group(const int32_t *labels, int64_t n, const GroupDesc &d, void *labmat, bool u8,
+                             int32_t *err, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pack_group, dim3((unsigned)((n + 63) / 64)), dim3(kBT), 0, s, labels, n, d, labmat, err);
+    const dim3 g((unsigned)((n + 63) / 64)), b(kBT);
+    if (u8)
+        hipLaunchKernelGGL(k_pack_group<uint8_t>, g, b, 0, s, labels, n, d, static_cast<uint8_t *>(labmat), err);
+    else
+        hipLaunchKernelGGL(k_pack_group<uint16_t>, g, b, 0, s, labels, n, d, static_cast<uint16_t *>(labmat), err);
     return hipGetLastError();
 }
 
-hipError_t launch_pack_group_hot(const int32_t *hot_ids, int64_t n_hot, int64_t n, int Gs, const uint16_t *labmat,
-                                 uint16_t *labhot, const float *rsd, float *rsdhot, int32_t *err, hipStream_t s)
+hipError_t launch_pack_group_hot(const int32_t *hot_ids, int64_t n_hot, int64_t n, int row_bytes, const void *labmat,
+                                 void *labhot, const float *rsd, float *rsdhot, int32_t *err, hipStream_t s)
 {
     if (n_hot == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_group_hot, dim3(grid_cap(n_hot * (Gs / 8), kBT * 4)), dim3(kBT), 0, s, hot_ids, n_hot,
-                       n, Gs, labmat, labhot, rsd, rsdhot, err);
+    if (row_bytes <= 0 || row_bytes % 8 != 0) return hipErrorInvalidValue;
+    const uint8_t *src = static_cast<const uint8_t *>(labmat);
+    uint8_t *dst = static_cast<uint8_t *>(labhot);
+    if (row_bytes % 16 == 0)
+        hipLaunchKernelGGL(k_pack_group_hot<uint4>, dim3(grid_cap(n_hot * (row_bytes / 16), kBT * 4)), dim3(kBT), 0,
+                           s, hot_ids, n_hot, n, row_bytes, src, dst, rsd, rsdhot, err);
+    else
+        hipLaunchKernelGGL(k_pack_group_hot<uint2>, dim3(grid_cap(n_hot * (row_bytes / 8), kBT * 4)), dim3(kBT), 0,
+                           s, hot_ids, n_hot, n, row_bytes, src, dst, rsd, rsdhot, err);
     return hipGetLastError();
 }
 
@@ -484,17 +501,24 @@ hipError_t launch_pull_group(const GroupArgs &g, hipStream_t s)
     if (nw < 1) return hipErrorInvalidValue;
     const size_t lds = batch_lds_bytes(g.KT, nw);
     const unsigned blocks = (unsigned)((g.nseg + nw - 1) / nw);
-#define GEE_GROUP(W, LAP)                                                                                            \
-    hipLaunchKernelGGL((k_batch_pull<W, LAP>), dim3(blocks), dim3(kWave * nw), lds, s, g.n, g.row_ptr, g.col,        \
-                       g.val, g.n_hot, g.labmat, g.labhot, g.Gs, g.rsd, g.rsdhot, g.vmeta, g.cscale, g.KT, g.seg_i,  \
-                       g.seg_e, g.nseg, g.Z, g.ldz, g.zcol, g.part, g.err)
+#define GEE_GROUP(W, LAP, L)                                                                                         \
+    hipLaunchKernelGGL((k_batch_pull<W, LAP, L>), dim3(blocks), dim3(kWave * nw), lds, s, g.n, g.row_ptr, g.col,     \
+                       g.val, g.n_hot, static_cast<const L *>(g.labmat), static_cast<const L *>(g.labhot), g.Gs,     \
+                       g.rsd, g.rsdhot, g.vmeta, g.cscale, g.KT, g.seg_i, g.seg_e, g.nseg, g.Z, g.ldz, g.zcol,       \
+                       g.part, g.err)
+#define GEE_GROUP_L(W, LAP)                                                                                          \
+    do {                                                                                                             \
+        if (g.u8) GEE_GROUP(W, LAP, uint8_t);                                                                        \
+        else GEE_GROUP(W, LAP, uint16_t);                                                                            \
+    } while (0)
     if (g.lap) {
-        if (g.val) GEE_GROUP(true, true);
-        else GEE_GROUP(false, true);
+        if (g.val) GEE_GROUP_L(true, true);
+        else GEE_GROUP_L(false, true);
     } else {
-        if (g.val) GEE_GROUP(true, false);
-        else GEE_GROUP(false, false);
+        if (g.val) GEE_GROUP_L(true, false);
+        else GEE_GROUP_L(false, false);
     }
+#undef GEE_GROUP_L
 #undef GEE_GROUP
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -78,8 +78,9 @@ struct GroupArgs {
     const int32_t *col = nullptr;
     const float *val = nullptr;
     int64_t n_hot = 0;
-    const uint16_t *labmat = nullptr; // [(n + 1) * Gs]
-    const uint16_t *labhot = nullptr; // [n_hot * Gs]
+    const void *labmat = nullptr; // [(n + 1) * Gs] labels, 8-bit (u8) or 16-bit
+    const void *labhot = nullptr; // [n_hot * Gs]
+    bool u8 = false;              // every vector of the group has K <= 255
     int Gs = 0, KT = 0;
     const float *rsd = nullptr;       // [n], Laplacian groups
     const float *rsdhot = nullptr;    // [n_hot], Laplacian groups
@@ -96,15 +97,15 @@ struct GroupArgs {
 };
 int batch_waves_per_block(int KT); // wavefronts whose bins fit one block's LDS beside the scale table
 size_t batch_lds_bytes(int KT, int nw);
-hipError_t launch_pack_group(const int32_t *labels, int64_t n, const GroupDesc &d, uint16_t *labmat, int32_t *err,
+hipError_t launch_pack_group(const int32_t *labels, int64_t n, const GroupDesc &d, void *labmat, bool u8, int32_t *err,
                              hipStream_t s);
 // Class counts (added to counts, which start at zero) and weights of every vector of a
 // group; each vector's tables at its inv_off.
 hipError_t launch_counts_group(const int32_t *labels, int64_t n, const GroupDesc &d, uint64_t *counts, int32_t *err,
                                hipStream_t s);
 hipError_t launch_weights_group(const uint64_t *counts, const GroupDesc &d, double *inv, hipStream_t s);
-hipError_t launch_pack_group_hot(const int32_t *hot_ids, int64_t n_hot, int64_t n, int Gs, const uint16_t *labmat,
-                                 uint16_t *labhot, const float *rsd, float *rsdhot, int32_t *err, hipStream_t s);
+hipError_t launch_pack_group_hot(const int32_t *hot_ids, int64_t n_hot, int64_t n, int row_bytes, const void *labmat,
+                                 void *labhot, const float *rsd, float *rsdhot, int32_t *err, hipStream_t s);
 hipError_t launch_group_cols(const double *inv_all, const GroupDesc &d, double *cscale, uint32_t *vmeta,
                              hipStream_t s);
 hipError_t launch_rsd(const double *deg, int64_t n, float *rsd, hipStream_t s);

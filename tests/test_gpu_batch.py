@@ -138,3 +138,25 @@ def test_group_at_the_class_limit():
                 Zs = gee.embed(torch.as_tensor(Y[b]).to(DEV), K, csr=csr, seg_len=512).cpu().numpy()
                 assert np.array_equal(blk.view(np.uint32), Zs.view(np.uint32)), b
             assert_parity(blk, oracle.embed(n, src, dst, w, Y[b], K, lap), what=f"K={K} lap={lap}")
+
+
+@pytest.mark.parametrize("Ks", [[255, 255, 3, 40], [255, 256, 3]])
+def test_label_width_boundary(Ks):
+    """Groups whose classes all fit 8 bits (K <= 255) gather 8-bit label rows, others
+    16-bit: labels up to 255 (and 256) survive either width. Adjacency blocks equal the
+    single-vector calls bit for bit; every block matches the oracle."""
+    n, src, dst, w = _graph(False, seed=57, scale=12, ef=8, hub=500)
+    rng = np.random.default_rng(9)
+    Y = _labels(rng, n, Ks)
+    for b, K in enumerate(Ks):
+        Y[b, rng.choice(n, 64, replace=False)] = K  # the largest class is well populated
+    laps = [False, True] + [False] * (len(Ks) - 2)
+    csr = gee.csr_build(gee.to_device(n, src, dst, w, device=DEV))
+    Z, zoff = gee.embed_batch(torch.as_tensor(Y).to(DEV), Ks, laps, csr)
+    Zh = Z.cpu().numpy()
+    for b, K in enumerate(Ks):
+        blk = Zh[:, zoff[b]:zoff[b] + K]
+        if not laps[b]:
+            Zs = gee.embed(torch.as_tensor(Y[b]).to(DEV), K, csr=csr).cpu().numpy()
+            assert np.array_equal(blk.view(np.uint32), Zs.view(np.uint32)), f"vector {b} K={K}"
+        assert_parity(blk, oracle.embed(n, src, dst, w, Y[b], K, laps[b]), what=f"vector {b} K={K} lap={laps[b]}")
