@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--serve-jobs", type=int, default=2000)
     p.add_argument("--serve-budget-gb", type=float, default=200.0)
     p.add_argument("--serve-streams", type=int, default=4)
+    p.add_argument("--serve-pack-items", type=int, default=1 << 20,
+                   help="serve: graphs of at most this many rows + entries are packed (0: no packing run)")
     p.add_argument("--sweep", default="20,22,24,26,28,30", help="er-sweep: log2 of the record counts")
     p.add_argument("--sweep-records-per-vertex", type=int, default=16)
     p.add_argument("--sweep-weighted", action="store_true",
@@ -755,13 +757,13 @@ def main_serve(a):
     def reqs():
         return [Request(j.jid, j.gid, j.Ks, [j.laplacian] * len(j.Ks), labels[i], 0.0) for i, j in enumerate(jobs)]
 
-    def run(mode, arrivals):
+    def run(mode, arrivals, pack_items=0):
         # every run builds the pool's CSRs anew: release the blocks the previous run left in
         # torch's cache, so that no allocation inside the timed loop has to fall back to
         # freeing and retrying
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
-        srv = Server(graphs, budget, streams=a.serve_streams, mode=mode)
+        srv = Server(graphs, budget, streams=a.serve_streams, mode=mode, pack_items=pack_items)
         srv.warm(range(len(pool)))  # every graph of the pool fits the budget: build all CSRs first
         srv.reserve()
         torch.cuda.synchronize()
@@ -780,7 +782,8 @@ def main_serve(a):
         errs = sum(1 for d in done if d.error)
         if errs:
             raise SystemExit(f"{errs} jobs reported errors")
-        return {"mode": mode, "jobs": len(done), "seconds": round(span, 4),
+        return {"mode": mode + (f"+packs<={pack_items}" if pack_items else ""), "jobs": len(done),
+                "launch_units": len(set(srv.unit[j.gid][0] for j in jobs)), "seconds": round(span, 4),
                 "jobs_per_s": round(len(done) / span, 2),
                 "G_label_edges_per_s": round(work / span / 1e9, 3),
                 "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
@@ -791,14 +794,22 @@ def main_serve(a):
     log(f"plain, all ready: {plain_sat}")
     batched_sat = run("batched", zero)
     log(f"batched, all ready: {batched_sat}")
+    pk = a.serve_pack_items
+    packed_sat = run("batched", zero, pk) if pk else None
+    if pk:
+        log(f"batched with packs, all ready: {packed_sat}")
     cap = plain_sat["jobs_per_s"]
     loads = {}
     for f in (0.5, 0.9):
         arr = gen.poisson_arrivals(f * cap, len(jobs))
         loads[f"{f}x"] = {"rate_jobs_per_s": round(f * cap, 2), "plain": run("plain", arr),
                           "batched": run("batched", arr)}
-        log(f"load {f}x: plain p50/p99 {loads[f'{f}x']['plain']['p50_ms']}/{loads[f'{f}x']['plain']['p99_ms']} ms, "
-            f"batched {loads[f'{f}x']['batched']['p50_ms']}/{loads[f'{f}x']['batched']['p99_ms']} ms")
+        if pk:
+            loads[f"{f}x"]["packed"] = run("batched", arr, pk)
+        L = loads[f"{f}x"]
+        log(f"load {f}x: plain p50/p99 {L['plain']['p50_ms']}/{L['plain']['p99_ms']} ms, "
+            f"batched {L['batched']['p50_ms']}/{L['batched']['p99_ms']} ms"
+            + (f", packed {L['packed']['p50_ms']}/{L['packed']['p99_ms']} ms" if pk else ""))
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -836,7 +847,7 @@ def main_serve(a):
         "config": {"workload": f"serve-mix-100-graphs-{len(jobs)}-jobs", "graphs": len(pool),
                    "records_total": int(sum(p.s for p in pool)), "vectors": int(sum(len(j.Ks) for j in jobs)),
                    "label_edges": int(work), "budget_GB": a.serve_budget_gb, "streams": a.serve_streams,
-                   "saturation": {"plain": plain_sat, "batched": batched_sat,
+                   "saturation": {"plain": plain_sat, "batched": batched_sat, "packed": packed_sat,
                                   "speedup": round(plain_sat["seconds"] / batched_sat["seconds"], 3)},
                    "poisson": loads},
         "roofline": {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": None,

@@ -19,6 +19,13 @@ inside the same launch: the batched pass gives its lanes to vectors, so a call w
 vectors leaves most lanes idle, while the plain pull gives them to entries. The choice
 depends only on the job and its graph. It shortens such jobs but costs throughput when
 jobs on one graph could have shared a batched call.
+Small graphs can be packed (``pack_items`` > 0): the graphs whose rows + entries are at
+most ``pack_items`` are grouped, in id order, into disjoint-union CSRs of at most
+``pack_limit`` rows + entries, and the jobs on all members of a pack run in one launch
+over their union (each job's label rows hold zeros, unknown, outside its graph, and its
+result is its graph's rows of Z). A member is always served through its pack, alone or
+in a mix, so packing keeps every job's result independent of the mix; each vector then
+writes the union's rows of Z, which costs little for small graphs.
 ``plain`` mode is the comparison: one job at a time, one ``gee_embed`` call per vector,
 in arrival order.
 
@@ -31,6 +38,7 @@ import collections
 import time
 from dataclasses import dataclass, field
 
+import numpy as np
 import torch
 
 from . import (DEFAULT_HOT_BUDGET, DeviceCsr, HipEvent, csr_build, embed, embed_batch,
@@ -92,10 +100,12 @@ class Server:
     host arrays). ``hbm_budget`` bounds resident graphs plus in-flight outputs and scratch."""
 
     MAX_INFLIGHT = 1024  # launches in flight at once
+    MAX_LAUNCH_VECTORS = 4096  # label vectors in one launch (one gee_embed_batch call)
 
     def __init__(self, graphs: dict, hbm_budget: int, streams: int = 4, mode: str = "batched",
                  seg_len: int = 0, hot_budget: int = DEFAULT_HOT_BUDGET, keep_results: bool = False,
-                 device: str = "cuda:0", route_vectors: int = 0, route_items: int = 1 << 22):
+                 device: str = "cuda:0", route_vectors: int = 0, route_items: int = 1 << 22,
+                 pack_items: int = 0, pack_limit: int = 1 << 22):
         if mode not in ("batched", "plain"):
             raise ValueError("mode: batched or plain")
         self.pool = graphs
@@ -114,6 +124,28 @@ class Server:
         self.inflight: list[_Launch] = []
         self.used = 0  # bytes: resident graphs + in-flight launches
         self.evictions = 0
+        # Small graphs (rows + entries <= pack_items) are served in packs: the members of
+        # a pack, in id order, form one disjoint-union CSR of at most pack_limit rows +
+        # entries, and all jobs on any member run in one launch over it. A member is
+        # always served through its pack, so its jobs' results do not depend on the mix.
+        # unit[gid] = (key of the resident CSR, first row of the graph in it); packs have
+        # negative keys.
+        self.unit: dict[int, tuple[int, int]] = {}
+        self.members: dict[int, list[int]] = {}
+        fill = 0
+        for gid in sorted(graphs):
+            n, src, _ = graphs[gid]
+            items = n + 2 * len(src)
+            if pack_items <= 0 or items > pack_items:
+                self.unit[gid] = (gid, 0)
+                continue
+            if not self.members or fill + items > pack_limit:
+                self.members[-1 - len(self.members)] = []
+                fill = 0
+            key = -len(self.members)
+            self.unit[gid] = (key, sum(graphs[m][0] for m in self.members[key]))
+            self.members[key].append(gid)
+            fill += items
         self._ws_plain = {}  # (gid, K, laplacian) -> gee_embed workspace bytes
         # one error word per in-flight launch, copied back to pinned host memory behind the
         # launch on its stream: a finished launch's word is read without a device sync
@@ -173,7 +205,14 @@ class Server:
         g = self.resident.get(gid)
         if g is not None:
             return g
-        n, src, dst = self.pool[gid]
+        if gid < 0:  # a pack: members side by side, each shifted to its first row
+            parts = [self.pool[m] for m in self.members[gid]]
+            offs = np.cumsum([0] + [p[0] for p in parts])
+            n = int(offs[-1])
+            src = np.concatenate([np.asarray(p[1], np.int64) + o for p, o in zip(parts, offs)]).astype(np.int32)
+            dst = np.concatenate([np.asarray(p[2], np.int64) + o for p, o in zip(parts, offs)]).astype(np.int32)
+        else:
+            n, src, dst = self.pool[gid]
         need = self._graph_bytes(n, len(src))
         if not self._evict_for(need, gid):
             return None
@@ -188,7 +227,7 @@ class Server:
     def warm(self, gids) -> int:
         """Make graphs resident ahead of their first job (while the budget allows); returns how many are."""
         for gid in gids:
-            if self._resident(gid) is None:
+            if self._resident(self.unit[gid][0]) is None:
                 break
         return len(self.resident)
 
@@ -212,6 +251,8 @@ class Server:
 
     # ------------------------------------------------------------ serving ----
     def submit(self, req: Request):
+        if len(req.Ks) > self.MAX_LAUNCH_VECTORS:
+            raise ValueError(f"job {req.jid} has {len(req.Ks)} vectors; a launch holds {self.MAX_LAUNCH_VECTORS}")
         self.pending.append(req)
 
     def idle(self) -> bool:
@@ -226,23 +267,26 @@ class Server:
         limit = 1 if self.mode == "plain" else len(self.pending)
         if self.mode == "plain" and self.inflight:
             return out
-        gids = set()  # one launch per graph, each holding an error slot
+        gids = {}  # unit -> vectors admitted: one launch per unit, each holding an error slot
         while self.pending and len(out) < limit:
             r = self.pending[0]
-            if r.gid not in gids and len(gids) >= len(self._free_slots):
+            u = self.unit[r.gid][0]
+            if u not in gids and len(gids) >= len(self._free_slots):
                 break
-            g = self._resident(r.gid)
+            if gids.get(u, 0) + len(r.Ks) > self.MAX_LAUNCH_VECTORS:
+                break  # the launch is full; the job waits for the next poll
+            g = self._resident(u)
             if g is None:
                 break
             need = self._launch_bytes(g, r.Ks, r.laplacian)
             if need > self.budget - g.bytes:
                 raise ValueError(f"job {r.jid} needs {need} bytes beside its graph; the budget is {self.budget}")
-            if self.used + need > self.budget and not self._evict_for(need, r.gid):
+            if self.used + need > self.budget and not self._evict_for(need, u):
                 break
             self.pending.popleft()
             self.used += need
             g.busy += 1
-            gids.add(r.gid)
+            gids[u] = gids.get(u, 0) + len(r.Ks)
             out.append((r, g, need))
         return out
 
@@ -283,6 +327,12 @@ class Server:
         labels = torch.empty((len(Ks), n), dtype=torch.int32, device=self.dev)
         Z = torch.empty((n, int(sum(Ks))), dtype=torch.float32, device=self.dev)
         bufs = [labels, Z]
+        pack = g.gid < 0  # labels go to the member's rows of the union, zeros elsewhere
+        if pack:
+            r0s = [self.unit[r.gid][1] for r in reqs]
+            ns = [self.pool[r.gid][0] for r in reqs]
+            stage = torch.empty(sum(len(r.Ks) * m for r, m in zip(reqs, ns)), dtype=torch.int32, device=self.dev)
+            bufs.append(stage)
         if vs:
             fK, fl, fz = [Ks[v] for v in vs], [laps[v] for v in vs], [zoff[v] for v in vs]
             ws_b = torch.empty(embed_batch_workspace_bytes(n, fK, fl, g.csr, seg_len=self.seg_len, zoff=fz,
@@ -297,12 +347,21 @@ class Server:
         with torch.cuda.stream(stream):
             err = self._err_dev[slot:slot + 1]
             err.zero_()
-            row, rows = [0, len(vs)], []
+            row, rows, at = [0, len(vs)], [], 0
+            if pack:
+                labels.zero_()
             for i, r in enumerate(reqs):
                 side = 0 if i in fset else 1
                 rows.append(row[side])
-                labels[row[side]:row[side] + len(r.Ks)].copy_(r.labels, non_blocking=True)
-                row[side] += len(r.Ks)
+                B = len(r.Ks)
+                if pack:
+                    st = stage[at:at + B * ns[i]].view(B, ns[i])
+                    at += B * ns[i]
+                    st.copy_(r.labels, non_blocking=True)
+                    labels[row[side]:row[side] + B, r0s[i]:r0s[i] + ns[i]].copy_(st)
+                else:
+                    labels[row[side]:row[side] + B].copy_(r.labels, non_blocking=True)
+                row[side] += B
             if vs:  # one batched call over the fused jobs' vectors, their blocks of Z in place
                 embed_batch(labels[:len(vs)].reshape(-1), fK, fl, g.csr, Z=Z, zoff=fz, ws=ws_b, err=err,
                             seg_len=self.seg_len, stream=stream, check=False)
@@ -336,9 +395,11 @@ class Server:
             col = 0
             for r in L.reqs:
                 kz = int(sum(r.Ks))
-                Zr = L.Z[:, col:col + kz] if L.Z is not None else None
+                n, src, _ = self.pool[r.gid]
+                r0 = self.unit[r.gid][1]
+                Zr = L.Z[r0:r0 + n, col:col + kz] if L.Z is not None else None
                 col += kz
-                finished.append(Done(r.jid, r.gid, r.arrival, t, L.graph.s, len(r.Ks), e, Zr))
+                finished.append(Done(r.jid, r.gid, r.arrival, t, len(src), len(r.Ks), e, Zr))
             self.used -= L.bytes
             L.graph.busy -= len(L.reqs)
             L.graph.last_use = t
@@ -346,7 +407,7 @@ class Server:
         admitted = self._admit()
         by_graph = collections.OrderedDict()
         for item in admitted:
-            by_graph.setdefault(item[0].gid, []).append(item)
+            by_graph.setdefault(item[1].gid, []).append(item)
         for group in by_graph.values():
             self._launch(group, self._free_slots.pop())
         return finished

@@ -137,3 +137,34 @@ def test_reserve_then_serve():
     b = _run(Server(graphs, 2 << 30, keep_results=True), _reqs(graphs, jobs))
     for j in jobs:
         assert torch.equal(a[j.jid].Z.view(torch.int32), b[j.jid].Z.view(torch.int32)), j.jid
+
+
+def test_packed_small_graphs():
+    """With packing, the pool's three small graphs form one union CSR and their jobs share
+    launches: a job's Z is the same alone and in the mix, adjacency jobs equal the unpacked
+    server's bits (integer sums), and every checked job matches the oracle."""
+    pool, graphs, jobs = _pool()
+    jobs = jobs[:18]
+
+    def server(streams, pack=True):
+        return Server(graphs, 8 << 30, streams=streams, keep_results=True, pack_items=(1 << 20) if pack else 0)
+
+    probe = server(1)
+    assert len(probe.members) == 1 and sorted(probe.members[-1]) == sorted(graphs)
+    assert len({j.gid for j in jobs}) > 1
+    mix = _run(server(3), _reqs(graphs, jobs))
+    assert len(mix) == len(jobs) and all(d.error == 0 for d in mix.values())
+    flat = _run(server(3, pack=False), _reqs(graphs, jobs))
+    for j in jobs:
+        n = graphs[j.gid][0]
+        assert mix[j.jid].Z.shape == (n, sum(j.Ks))
+        if not j.laplacian:
+            assert torch.equal(mix[j.jid].Z.view(torch.int32), flat[j.jid].Z.view(torch.int32)), j.jid
+    for j in jobs[::3]:
+        alone = _run(server(1), _reqs(graphs, [j]))
+        assert torch.equal(alone[j.jid].Z.view(torch.int32), mix[j.jid].Z.view(torch.int32)), j.jid
+    for j in jobs[:6]:
+        n, src, dst = graphs[j.gid]
+        Y = j.labels(n)
+        assert_parity(mix[j.jid].Z.cpu().numpy()[:, :j.Ks[0]], oracle.embed(n, src, dst, None, Y[0], j.Ks[0], j.laplacian),
+                      what=f"packed job {j.jid} vs oracle")
