@@ -155,10 +155,10 @@ struct BatchPlan {
     bool any_lap = false, weighted = false;
     std::vector<GroupDesc> groups;
     std::vector<bool> lap;        // the group holds Laplacian vectors
-    std::vector<int64_t> cnt_off; // per vector: offset of its counts / inv tables
+    std::vector<int64_t> cnt_off; // per vector: offset of its K + 1 class counts
     int64_t cnt_total = 0;
     int Gs_max = 0, KT_max = 0;
-    size_t o_cnt = 0, o_inv = 0, o_lab = 0, o_labhot = 0, o_rsdhot = 0, o_cscale = 0, o_vmeta = 0,
+    size_t o_cnt = 0, o_lab = 0, o_labhot = 0, o_rsdhot = 0, o_cscale = 0, o_vmeta = 0,
            o_segi = 0, o_sege = 0, o_part = 0, o_deg = 0, o_rsd = 0, total = 0;
 };
 
@@ -228,7 +228,6 @@ int make_batch_plan(const gee_csr *csr, const gee_batch *bt, const gee_embed_opt
         return at;
     };
     P.o_cnt = take(8 * (size_t)P.cnt_total);
-    P.o_inv = take(8 * (size_t)P.cnt_total);
     P.o_lab = take(2 * (size_t)(P.n + 1) * (size_t)P.Gs_max);
     P.o_labhot = take(2 * (size_t)P.n_hot * (size_t)P.Gs_max);
     P.o_cscale = take(8 * (size_t)P.KT_max);
@@ -396,17 +395,15 @@ int gee_embed_batch(const gee_csr *csr, const gee_batch *batch, void *ws, size_t
     if (!ws || !aligned(ws, 256) || ws_bytes < p.total) return GEE_EWORKSPACE;
     char *w = static_cast<char *>(ws);
     uint64_t *cnt = reinterpret_cast<uint64_t *>(w + p.o_cnt);
-    double *inv = reinterpret_cast<double *>(w + p.o_inv);
     int32_t *seg_i = reinterpret_cast<int32_t *>(w + p.o_segi);
     int64_t *seg_e = reinterpret_cast<int64_t *>(w + p.o_sege);
     float *rsd = p.any_lap ? reinterpret_cast<float *>(w + p.o_rsd) : nullptr;
 
-    // class counts and weights of every vector, one launch of each per group
+    // class counts of every vector, one launch per group (the weights 1 / n_k are taken
+    // from them where each group's column scales are built)
     if ((rc = hip_rc(launch_fill_u64(cnt, p.cnt_total, 0, stream)))) return rc;
-    for (const GroupDesc &d : p.groups) {
+    for (const GroupDesc &d : p.groups)
         if ((rc = hip_rc(launch_counts_group(batch->labels, p.n, d, cnt, err, stream)))) return rc;
-        if ((rc = hip_rc(launch_weights_group(cnt, d, inv, stream)))) return rc;
-    }
     // one degree pass shared by the Laplacian vectors
     if (p.any_lap) {
         double *deg = reinterpret_cast<double *>(w + p.o_deg);
@@ -453,7 +450,7 @@ int gee_embed_batch(const gee_csr *csr, const gee_batch *batch, void *ws, size_t
         if ((rc = hip_rc(launch_pack_group_hot(csr->hot_ids, p.n_hot, p.n, d.Gs * (g.u8 ? 1 : 2), labmat, labhot,
                                                g.rsd, g.lap ? rsdhot : nullptr, err, stream))))
             return rc;
-        if ((rc = hip_rc(launch_group_cols(inv, d, cscale, vmeta, stream)))) return rc;
+        if ((rc = hip_rc(launch_group_cols(cnt, d, cscale, vmeta, stream)))) return rc;
         if ((rc = hip_rc(launch_pull_group(g, stream)))) return rc;
     }
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;

@@ -100,10 +100,11 @@ k_pack_group_hot(const int32_t *__restrict__ hot_ids, int64_t n_hot, int64_t n, 
     if (bad) flag_error(err, GEE_EVERTEX);
 }
 
-// Per column f of the group: cscale[f] = 1 / n_{b,k+1}, negated (sign bit set, also
-// for a zero) when vector b is a Laplacian one. Per lane: vmeta[b] = coff_b |
-// (Laplacian << 31), kNoVec for the lanes b >= G.
-__global__ void k_group_cols(const double *__restrict__ inv_all, GroupDesc d, double *__restrict__ cscale,
+// Per column f of the group: cscale[f] = 1 / n_{b,k+1} (IEEE division of the class
+// count, 0 for an empty class), negated (sign bit set, also for a zero) when vector b is
+// a Laplacian one. Per lane: vmeta[b] = coff_b | (Laplacian << 31), kNoVec for the
+// lanes b >= G. counts_all holds each vector's K_b + 1 counts at its inv_off.
+__global__ void k_group_cols(const uint64_t *__restrict__ counts_all, GroupDesc d, double *__restrict__ cscale,
                              uint32_t *__restrict__ vmeta)
 {
     const int b = blockIdx.x;
@@ -113,7 +114,8 @@ __global__ void k_group_cols(const double *__restrict__ inv_all, GroupDesc d, do
     }
     const bool lap = d.lap[b] != 0;
     for (int k = threadIdx.x; k < d.K[b]; k += blockDim.x) {
-        const double inv = inv_all[d.inv_off[b] + k + 1];
+        const uint64_t c = counts_all[d.inv_off[b] + k + 1];
+        const double inv = c == 0 ? 0.0 : 1.0 / (double)c;
         cscale[d.coff[b] + k] = lap ? -inv : inv;
     }
     if (threadIdx.x == 0) vmeta[b] = (uint32_t)d.coff[b] | (lap ? 0x80000000u : 0u);
@@ -482,10 +484,10 @@ hipError_t launch_pack_group_hot(const int32_t *hot_ids, int64_t n_hot, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_group_cols(const double *inv_all, const GroupDesc &d, double *cscale, uint32_t *vmeta,
+hipError_t launch_group_cols(const uint64_t *counts_all, const GroupDesc &d, double *cscale, uint32_t *vmeta,
                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_group_cols, dim3(d.G + 1), dim3(256), 0, s, inv_all, d, cscale, vmeta);
+    hipLaunchKernelGGL(k_group_cols, dim3(d.G + 1), dim3(256), 0, s, counts_all, d, cscale, vmeta);
     return hipGetLastError();
 }
 

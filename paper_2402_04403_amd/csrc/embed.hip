@@ -90,9 +90,9 @@ __global__ void k_weights(const uint64_t *__restrict__ counts, int32_t K, double
     inv[k] = (k == 0 || c == 0) ? 0.0 : 1.0 / (double)c;
 }
 
-// The same two steps for every vector of a batch group, one launch each: blockIdx.y
-// picks the vector (labels at labels + vec * n, tables at inv_off), so a batch of many
-// small vectors does not pay two launches per vector. Counts start at zero.
+// Class counts of every vector of a batch group in one launch: blockIdx.y picks the
+// vector (labels at labels + vec * n, counts at inv_off), so a batch of many small
+// vectors does not pay a launch per vector. Counts start at zero.
 __global__ void __launch_bounds__(kBlock)
 k_counts_group(const int32_t *__restrict__ labels, int64_t n, GroupDesc d, uint64_t *__restrict__ counts,
                int32_t *err)
@@ -125,15 +125,6 @@ k_counts_group(const int32_t *__restrict__ labels, int64_t n, GroupDesc d, uint6
     uint64_t *__restrict__ cnt = counts + d.inv_off[i];
     for (int b = threadIdx.x; b <= K; b += blockDim.x)
         if (hist[b]) atomicAdd((unsigned long long *)&cnt[b], (unsigned long long)hist[b]);
-}
-
-__global__ void k_weights_group(const uint64_t *__restrict__ counts, GroupDesc d, double *__restrict__ inv)
-{
-    const int i = blockIdx.y;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > d.K[i]) return;
-    const uint64_t c = counts[d.inv_off[i] + k];
-    inv[d.inv_off[i] + k] = (k == 0 || c == 0) ? 0.0 : 1.0 / (double)c;
 }
 
 // ----------------------------------------------------------------- degrees --
@@ -761,16 +752,6 @@ hipError_t launch_counts_group(const int32_t *labels, int64_t n, const GroupDesc
     // into its vector's counts, and many workgroups per vector would queue on those words
     const dim3 g(grid_for(n, kBlock * 16, 4096 / d.G), d.G), b(kBlock);
     hipLaunchKernelGGL(k_counts_group, g, b, 0, s, labels, n, d, counts, err);
-    return hipGetLastError();
-}
-
-hipError_t launch_weights_group(const uint64_t *counts, const GroupDesc &d, double *inv, hipStream_t s)
-{
-    if (d.G < 1 || d.G > kGroupMax) return hipErrorInvalidValue;
-    int32_t kmax = 0;
-    for (int i = 0; i < d.G; ++i) kmax = d.K[i] > kmax ? d.K[i] : kmax;
-    const dim3 g(grid_for((int64_t)kmax + 1, kBlock, 1 << 20), d.G), b(kBlock);
-    hipLaunchKernelGGL(k_weights_group, g, b, 0, s, counts, d, inv);
     return hipGetLastError();
 }
 

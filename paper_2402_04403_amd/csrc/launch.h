@@ -69,7 +69,7 @@ struct GroupDesc {
     int32_t K[kGroupMax];       // classes of each vector
     int32_t coff[kGroupMax];    // first group column of each vector
     int64_t zoff[kGroupMax];    // first Z column of each vector
-    int64_t inv_off[kGroupMax]; // offset of each vector's inv table in the batch's inv array
+    int64_t inv_off[kGroupMax]; // offset of each vector's class counts in the batch's counts array
     uint8_t lap[kGroupMax];     // 1: Laplacian version
 };
 struct GroupArgs {
@@ -99,14 +99,13 @@ int batch_waves_per_block(int KT); // wavefronts whose bins fit one block's LDS 
 size_t batch_lds_bytes(int KT, int nw);
 hipError_t launch_pack_group(const int32_t *labels, int64_t n, const GroupDesc &d, void *labmat, bool u8, int32_t *err,
                              hipStream_t s);
-// Class counts (added to counts, which start at zero) and weights of every vector of a
-// group; each vector's tables at its inv_off.
+// Class counts of every vector of a group (added to counts, which start at zero); each
+// vector's K + 1 counts at its inv_off.
 hipError_t launch_counts_group(const int32_t *labels, int64_t n, const GroupDesc &d, uint64_t *counts, int32_t *err,
                                hipStream_t s);
-hipError_t launch_weights_group(const uint64_t *counts, const GroupDesc &d, double *inv, hipStream_t s);
 hipError_t launch_pack_group_hot(const int32_t *hot_ids, int64_t n_hot, int64_t n, int row_bytes, const void *labmat,
                                  void *labhot, const float *rsd, float *rsdhot, int32_t *err, hipStream_t s);
-hipError_t launch_group_cols(const double *inv_all, const GroupDesc &d, double *cscale, uint32_t *vmeta,
+hipError_t launch_group_cols(const uint64_t *counts_all, const GroupDesc &d, double *cscale, uint32_t *vmeta,
                              hipStream_t s);
 hipError_t launch_rsd(const double *deg, int64_t n, float *rsd, hipStream_t s);
 hipError_t launch_pull_group(const GroupArgs &g, hipStream_t s);
