@@ -125,8 +125,8 @@ def copy_probe(gee, torch, dev):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (the path shards by rows, "
-              "see DESIGN.md, but no multi-GPU run is part of this build)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (the embedding would shard "
+              "by row ranges across GPUs, but only the one-GPU path is implemented)", file=sys.stderr)
         sys.exit(2)
     if a.workload == "batched":
         return main_batched(a)

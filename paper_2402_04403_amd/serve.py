@@ -95,6 +95,31 @@ class _Launch:
     zoff: list | None = None
 
 
+def plan_packs(graphs: dict, pack_items: int, pack_limit: int):
+    """Packs of small graphs. Graphs whose rows + entries (n + 2s) are at most pack_items
+    go, in id order, into packs of at most pack_limit rows + entries; the others stand
+    alone. Returns (unit, members): unit[gid] = (key of the CSR that serves the graph,
+    first row of the graph in it), with key = gid for a graph on its own and a negative
+    key for a pack; members[key] = the pack's graph ids in order."""
+    unit: dict[int, tuple[int, int]] = {}
+    members: dict[int, list[int]] = {}
+    fill = 0
+    for gid in sorted(graphs):
+        n, src = graphs[gid][0], graphs[gid][1]
+        items = n + 2 * len(src)
+        if pack_items <= 0 or items > pack_items:
+            unit[gid] = (gid, 0)
+            continue
+        if not members or fill + items > pack_limit:
+            members[-1 - len(members)] = []
+            fill = 0
+        key = -len(members)
+        unit[gid] = (key, sum(graphs[m][0] for m in members[key]))
+        members[key].append(gid)
+        fill += items
+    return unit, members
+
+
 class Server:
     """Continuous-batching GEE server over a pool of graphs (``graphs[gid] = (n, src, dst)``
     host arrays). ``hbm_budget`` bounds resident graphs plus in-flight outputs and scratch."""
@@ -130,22 +155,7 @@ class Server:
         # always served through its pack, so its jobs' results do not depend on the mix.
         # unit[gid] = (key of the resident CSR, first row of the graph in it); packs have
         # negative keys.
-        self.unit: dict[int, tuple[int, int]] = {}
-        self.members: dict[int, list[int]] = {}
-        fill = 0
-        for gid in sorted(graphs):
-            n, src, _ = graphs[gid]
-            items = n + 2 * len(src)
-            if pack_items <= 0 or items > pack_items:
-                self.unit[gid] = (gid, 0)
-                continue
-            if not self.members or fill + items > pack_limit:
-                self.members[-1 - len(self.members)] = []
-                fill = 0
-            key = -len(self.members)
-            self.unit[gid] = (key, sum(graphs[m][0] for m in self.members[key]))
-            self.members[key].append(gid)
-            fill += items
+        self.unit, self.members = plan_packs(graphs, pack_items, pack_limit)
         self._ws_plain = {}  # (gid, K, laplacian) -> gee_embed workspace bytes
         # one error word per in-flight launch, copied back to pinned host memory behind the
         # launch on its stream: a finished launch's word is read without a device sync
