@@ -367,19 +367,24 @@ def main_batched(a):
     log(f"Z {n * KS * 4 / 1e9:.1f} GB, workspace {wsb / 1e9:.2f} GB")
 
     tuned = None
+    group = 0  # vectors per group; 0 is the library's 64
     if not a.seg_len and a.tune:
-        # the autotuner of the batched form picks the segment length for this graph and batch
-        cands = (8192, 16384, 32768)
-        best, best_ms = gee.embed_batch_tune(labels, Ks, laps, csr, seg_lens=cands, reps=1, Z=Z, zoff=zoff)
-        tuned = {"candidates": list(cands), "best": best, "best_ms": round(best_ms, 3)}
+        # the autotuner of the batched form picks the segment length and the label tile
+        # (vectors per group) for this graph and batch
+        cands, gcands = (8192, 16384, 32768), (64, 32)
+        best, group, best_ms = gee.embed_batch_tune(labels, Ks, laps, csr, seg_lens=cands, group_vectors=gcands, reps=1,
+                                                    Z=Z, zoff=zoff)
+        tuned = {"candidates": list(cands), "group_candidates": list(gcands), "best": best, "best_group": group,
+                 "best_ms": round(best_ms, 3)}
         a.seg_len = best
-        wsb = gee.embed_batch_workspace_bytes(n, Ks, laps, csr, seg_len=a.seg_len, zoff=zoff, ldz=KS)
+        del ws
+        wsb = gee.embed_batch_workspace_bytes(n, Ks, laps, csr, seg_len=a.seg_len, zoff=zoff, ldz=KS, group_vectors=group)
         ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
-        log(f"tuner: seg_len {best} ({best_ms:.3f} ms per call) among {cands}")
+        log(f"tuner: seg_len {best}, {group} vectors per group ({best_ms:.3f} ms per call) among {cands} x {gcands}")
 
     def step(events=None):
         gee.embed_batch(labels, Ks, laps, csr, Z=Z, zoff=zoff, ws=ws, err=err, seg_len=a.seg_len,
-                        events=events, check=False)
+                        events=events, check=False, group_vectors=group)
 
     for _ in range(a.warmup):
         step()
@@ -467,7 +472,7 @@ def main_batched(a):
             "workload": f"rmat-s{a.scale}-ef{a.edge_factor}-B{B}-batched",
             "n": n, "s": s, "nnz": nnz, "B": B, "sum_K": KS, "Ks": Ks,
             "versions": "even b adjacency, odd b Laplacian", "layout": "blocks side by side in vector order",
-            "seg_len": a.seg_len or 16384, "tuner": tuned, "hot_slots": csr.n_hot, "csr_build_ms": round(csr_ms, 2),
+            "seg_len": a.seg_len or 16384, "group_vectors": group or 64, "tuner": tuned, "hot_slots": csr.n_hot, "csr_build_ms": round(csr_ms, 2),
             "Z_GB": round(n * KS * 4 / 1e9, 2), "copy_probe_GBps": round(copy_gbps, 1),
             "plain_ms_per_batch": None if plain_ms is None else round(plain_ms, 3),
             "plain_value": None if plain_ms is None else round(s * B / (plain_ms * 1e-3) / 1e9, 3),

@@ -111,6 +111,11 @@ typedef struct gee_embed_opts {
      * alone. */
     hipEvent_t hot_begin;
     hipEvent_t hot_end;
+    /* Batched form: at most this many vectors per group (the label tile: fewer vectors
+     * per group mean fewer FP64 bins per wavefront and more wavefronts per CU, but one
+     * more pass over the CSR per group); 0 picks 64. Must be 0 or in [1, 64]. A
+     * vector's result does not depend on its group. */
+    int32_t group_vectors;
 } gee_embed_opts;
 
 /* Class counts, Algorithm 1's count(Y = k): counts[k] = #{v : labels[v] = k} for
@@ -313,17 +318,20 @@ int gee_csr_build(const gee_coo *g, int64_t hot_budget, int64_t *row_ptr, int32_
 int gee_argmax(const float *Z, int64_t n, int32_t K, int64_t ldz, const int32_t *prev, int32_t *labels,
                uint64_t *changed, hipStream_t stream);
 
-/* Segment length for gee_embed_batch on this graph and batch (the autotuner of the
- * batched form): for each of the n_cand candidate lengths in seg_lens (host array,
- * each a multiple of 64, at most 2^22, or 0 for the library's choice) it makes one
+/* Segment length and label tile for gee_embed_batch on this graph and batch (the
+ * autotuner of the batched form): for each pair of a candidate length in seg_lens
+ * (host array of n_seg, each a multiple of 64, at most 2^22, or 0 for the library's
+ * choice) and a candidate group size in group_vectors (host array of n_group, each 0
+ * or in [1, 64]; NULL with n_group = 0 tries only the default 64) it makes one
  * untimed call, then reps timed calls bracketed by HIP events on stream, and returns
- * the fastest candidate in *best and its mean time per call in *best_ms (host
- * pointers). ws must hold gee_embed_batch_workspace() for every candidate. The
- * batch's Z receives the result of the last candidate's calls (for unit-weight
- * adjacency vectors the same bits with any segment length; other sums may differ in
- * rounding order). SYNCHRONIZES the stream; returns a status code. */
-int gee_embed_batch_tune(const gee_csr *csr, const gee_batch *batch, const int32_t *seg_lens, int n_cand, int reps,
-                         void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream, int32_t *best, float *best_ms);
+ * the fastest pair in *best_seg and *best_group and its mean time per call in
+ * *best_ms (host pointers). ws must hold gee_embed_batch_workspace() for every pair.
+ * The batch's Z receives the result of the last pair's calls (for unit-weight
+ * adjacency vectors the same bits with any pair; other sums may differ in rounding
+ * order with the segment length). SYNCHRONIZES the stream; returns a status code. */
+int gee_embed_batch_tune(const gee_csr *csr, const gee_batch *batch, const int32_t *seg_lens, int n_seg,
+                         const int32_t *group_vectors, int n_group, int reps, void *ws, size_t ws_bytes, int32_t *err,
+                         hipStream_t stream, int32_t *best_seg, int32_t *best_group, float *best_ms);
 
 /* ------------------------------------------------------------------------------
  * Recording repeated calls as a HIP graph. A sequence of calls that runs again and

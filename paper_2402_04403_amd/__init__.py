@@ -70,7 +70,7 @@ class Batch(ctypes.Structure):
 
 class EmbedOpts(ctypes.Structure):
     _fields_ = [("seg_len", ctypes.c_int32), ("rows_per_window", ctypes.c_int32),
-                ("hot_begin", ctypes.c_void_p), ("hot_end", ctypes.c_void_p)]
+                ("hot_begin", ctypes.c_void_p), ("hot_end", ctypes.c_void_p), ("group_vectors", ctypes.c_int32)]
 
 
 _lib = None
@@ -126,8 +126,10 @@ def load():
         lib.gee_embed_batch.restype = ci
         lib.gee_embed_batch.argtypes = [CsrP, BatchP, vp, sz, vp, OptP, vp]
         lib.gee_embed_batch_tune.restype = ci
-        lib.gee_embed_batch_tune.argtypes = [CsrP, BatchP, ctypes.POINTER(ctypes.c_int32), ci, ci, vp, sz, vp, vp,
-                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
+        lib.gee_embed_batch_tune.argtypes = [CsrP, BatchP, ctypes.POINTER(ctypes.c_int32), ci,
+                                             ctypes.POINTER(ctypes.c_int32), ci, ci, vp, sz, vp, vp,
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_float)]
         lib.gee_argmax.restype = ci
         lib.gee_argmax.argtypes = [vp, i64, i32, i64, vp, vp, vp, vp]
         lib.gee_capture_begin.restype = ci
@@ -471,8 +473,8 @@ def embed_pb(labels: torch.Tensor, K: int, pb: DevicePb, Z: torch.Tensor | None 
     return Z
 
 
-def _opts(seg_len=0, rows_per_window=0, events=None):
-    o = EmbedOpts(seg_len, rows_per_window, None, None)
+def _opts(seg_len=0, rows_per_window=0, events=None, group_vectors=0):
+    o = EmbedOpts(seg_len, rows_per_window, None, None, group_vectors)
     if events is not None:
         o.hot_begin, o.hot_end = events[0].handle, events[1].handle
     return o
@@ -558,8 +560,9 @@ def _batch_struct(labels, Ks, laps, zoff, ldz, Z):
 
 def embed_batch(labels: torch.Tensor, Ks, laplacian, csr: DeviceCsr, Z: torch.Tensor | None = None, zoff=None,
                 ws: torch.Tensor | None = None, err: torch.Tensor | None = None, seg_len: int = 0, events=None,
-                stream=None, check: bool = True):
-    """Embed B label vectors (``labels`` [B, n] int32) over one graph in one pass per group.
+                stream=None, check: bool = True, group_vectors: int = 0):
+    """Embed B label vectors (``labels`` [B, n] int32) over one graph in one pass per group
+    (at most ``group_vectors`` vectors per group; 0 is the library's 64).
 
     ``Ks[b]`` and ``laplacian[b]`` give each vector's classes and version. By default the blocks
     are packed side by side: Z is [n, sum(Ks)] and vector b owns columns zoff[b] .. zoff[b]+Ks[b].
@@ -579,7 +582,7 @@ def embed_batch(labels: torch.Tensor, Ks, laplacian, csr: DeviceCsr, Z: torch.Te
         raise ValueError("Z: expected a contiguous float32 [n, ldz] tensor")
     st, keep = _batch_struct(labels, Ks, laplacian, zoff, Z.shape[1], Z)
     rs = csr.struct()
-    o = _opts(seg_len, 0, events)
+    o = _opts(seg_len, 0, events, group_vectors)
     wsb = int(lib.gee_embed_batch_workspace(ctypes.byref(rs), ctypes.byref(st), ctypes.byref(o)))
     if wsb == 0:
         raise GeeError(GEE_EINVAL, "gee_embed_batch_workspace")
@@ -596,9 +599,10 @@ def embed_batch(labels: torch.Tensor, Ks, laplacian, csr: DeviceCsr, Z: torch.Te
 
 
 def embed_batch_tune(labels: torch.Tensor, Ks, laplacian, csr: DeviceCsr, seg_lens=(2048, 4096, 8192, 16384, 32768),
-                     reps: int = 3, Z: torch.Tensor | None = None, zoff=None, stream=None):
-    """Segment length for embed_batch on this graph and batch (``gee_embed_batch_tune``):
-    times each candidate and returns (best seg_len, mean ms per call). Synchronizes."""
+                     group_vectors=(0,), reps: int = 3, Z: torch.Tensor | None = None, zoff=None, stream=None):
+    """Segment length and group size for embed_batch on this graph and batch
+    (``gee_embed_batch_tune``): times every pair of candidates and returns (best seg_len,
+    best group_vectors, mean ms per call). group_vectors 0 is the library's 64. Synchronizes."""
     lib = load()
     B = len(Ks)
     dev = csr.row_ptr.device
@@ -612,20 +616,23 @@ def embed_batch_tune(labels: torch.Tensor, Ks, laplacian, csr: DeviceCsr, seg_le
         Z = torch.empty((csr.n, int(max(z + k for z, k in zip(zoff, Ks)))), dtype=torch.float32, device=dev)
     st, keep = _batch_struct(labels, Ks, laplacian, zoff, Z.shape[1], Z)
     rs = csr.struct()
-    wsb = max(int(lib.gee_embed_batch_workspace(ctypes.byref(rs), ctypes.byref(st), ctypes.byref(_opts(L, 0))))
-              for L in seg_lens)
+    sizes = [int(lib.gee_embed_batch_workspace(ctypes.byref(rs), ctypes.byref(st), ctypes.byref(_opts(L, 0, None, G))))
+             for L in seg_lens for G in group_vectors]
+    wsb = max(sizes) if min(sizes) > 0 else 0
     if wsb == 0:
         raise GeeError(GEE_EINVAL, "gee_embed_batch_workspace")
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     err = torch.zeros(1, dtype=torch.int32, device=dev)
     cands = (ctypes.c_int32 * len(seg_lens))(*[int(x) for x in seg_lens])
-    best, ms = ctypes.c_int32(0), ctypes.c_float(0.0)
-    _rc(lib.gee_embed_batch_tune(ctypes.byref(rs), ctypes.byref(st), cands, len(seg_lens), int(reps), _ptr(ws), wsb,
-                                 _ptr(err), _stream(stream), ctypes.byref(best), ctypes.byref(ms)),
+    gcands = (ctypes.c_int32 * len(group_vectors))(*[int(x) for x in group_vectors])
+    best, bestg, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0.0)
+    _rc(lib.gee_embed_batch_tune(ctypes.byref(rs), ctypes.byref(st), cands, len(seg_lens), gcands, len(group_vectors),
+                                 int(reps), _ptr(ws), wsb, _ptr(err), _stream(stream), ctypes.byref(best),
+                                 ctypes.byref(bestg), ctypes.byref(ms)),
         "gee_embed_batch_tune")
     del keep
     _check_err(err, "gee_embed_batch_tune")
-    return int(best.value), float(ms.value)
+    return int(best.value), int(bestg.value), float(ms.value)
 
 
 class Graph:
@@ -752,7 +759,8 @@ def refine(labels: torch.Tensor, K: int, csr: DeviceCsr | None = None, pb: Devic
     return bufs[cur], len(history), history
 
 
-def embed_batch_workspace_bytes(n: int, Ks, laplacian, csr: DeviceCsr, seg_len: int = 0, zoff=None, ldz=None) -> int:
+def embed_batch_workspace_bytes(n: int, Ks, laplacian, csr: DeviceCsr, seg_len: int = 0, zoff=None, ldz=None,
+                                group_vectors: int = 0) -> int:
     lib = load()
     if zoff is None:
         zoff, acc = [], 0
@@ -761,7 +769,7 @@ def embed_batch_workspace_bytes(n: int, Ks, laplacian, csr: DeviceCsr, seg_len: 
             acc += int(k)
     ldz = ldz or int(max(z + k for z, k in zip(zoff, Ks)))
     st, keep = _batch_struct(None, Ks, laplacian, zoff, ldz, None)
-    o = _opts(seg_len, 0, None)
+    o = _opts(seg_len, 0, None, group_vectors)
     return int(lib.gee_embed_batch_workspace(ctypes.byref(csr.struct()), ctypes.byref(st), ctypes.byref(o)))
 
 

@@ -169,6 +169,8 @@ int make_batch_plan(const gee_csr *csr, const gee_batch *bt, const gee_embed_opt
     if (!bt || bt->B < 1 || bt->B > kMaxBatch || !bt->K || !bt->laplacian || !bt->zoff || bt->ldz < 1)
         return GEE_EINVAL;
     if (o && o->seg_len != 0 && (o->seg_len < 64 || o->seg_len > kMaxSegLen)) return GEE_EINVAL;
+    if (o && (o->group_vectors < 0 || o->group_vectors > kGroupMax)) return GEE_EINVAL;
+    const int gmax = (o && o->group_vectors) ? o->group_vectors : kGroupMax;
     if (bt->ldz > INT32_MAX) return GEE_EINVAL; // Z column ids are 32-bit in the edge pass
     BatchPlan P;
     P.n = csr->n;
@@ -198,7 +200,7 @@ int make_batch_plan(const gee_csr *csr, const gee_batch *bt, const gee_embed_opt
     for (int i = 0; i < B;) {
         GroupDesc d{};
         bool lap = false;
-        while (i < B && d.G < kGroupMax) {
+        while (i < B && d.G < gmax) {
             const int b = ord[i];
             if (d.G > 0 && (d.KT + bt->K[b] > kBatchMaxKT || bt->zoff[b] != d.zoff[0] + d.KT)) break;
             d.vec[d.G] = b;
@@ -620,12 +622,19 @@ int gee_argmax(const float *Z, int64_t n, int32_t K, int64_t ldz, const int32_t 
     return hip_rc(launch_argmax(n, K, ldz, Z, prev, labels, prev ? changed : nullptr, stream));
 }
 
-int gee_embed_batch_tune(const gee_csr *csr, const gee_batch *batch, const int32_t *seg_lens, int n_cand, int reps,
-                         void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream, int32_t *best, float *best_ms)
+int gee_embed_batch_tune(const gee_csr *csr, const gee_batch *batch, const int32_t *seg_lens, int n_seg,
+                         const int32_t *group_vectors, int n_group, int reps, void *ws, size_t ws_bytes, int32_t *err,
+                         hipStream_t stream, int32_t *best_seg, int32_t *best_group, float *best_ms)
 {
-    if (!seg_lens || n_cand < 1 || reps < 1 || !best || !best_ms) return GEE_EINVAL;
-    for (int i = 0; i < n_cand; ++i)
+    if (!seg_lens || n_seg < 1 || reps < 1 || !best_seg || !best_group || !best_ms) return GEE_EINVAL;
+    if (n_group < 0 || (n_group > 0 && !group_vectors)) return GEE_EINVAL;
+    for (int i = 0; i < n_seg; ++i)
         if (seg_lens[i] < 0 || seg_lens[i] % 64 != 0 || seg_lens[i] > (1 << 22)) return GEE_EINVAL;
+    for (int i = 0; i < n_group; ++i)
+        if (group_vectors[i] < 0 || group_vectors[i] > kGroupMax) return GEE_EINVAL;
+    const int32_t default_group = 0;
+    const int32_t *groups = n_group > 0 ? group_vectors : &default_group;
+    const int ng = n_group > 0 ? n_group : 1;
     int rc;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if ((rc = hip_rc(hipEventCreate(&e0)))) return rc;
@@ -634,26 +643,32 @@ int gee_embed_batch_tune(const gee_csr *csr, const gee_batch *batch, const int32
         return rc;
     }
     float best_t = 0.f;
-    int32_t best_l = -1;
-    for (int i = 0; i < n_cand && rc == GEE_OK; ++i) {
-        gee_embed_opts o = {};
-        o.seg_len = seg_lens[i];
-        if ((rc = gee_embed_batch(csr, batch, ws, ws_bytes, err, &o, stream))) break;
-        if ((rc = hip_rc(hipEventRecord(e0, stream)))) break;
-        for (int r = 0; r < reps && rc == GEE_OK; ++r) rc = gee_embed_batch(csr, batch, ws, ws_bytes, err, &o, stream);
-        if (rc || (rc = hip_rc(hipEventRecord(e1, stream))) || (rc = hip_rc(hipEventSynchronize(e1)))) break;
-        float ms = 0.f;
-        if ((rc = hip_rc(hipEventElapsedTime(&ms, e0, e1)))) break;
-        ms /= (float)reps;
-        if (best_l < 0 || ms < best_t) {
-            best_t = ms;
-            best_l = seg_lens[i];
+    int32_t best_l = -1, best_g = -1;
+    for (int gi = 0; gi < ng && rc == GEE_OK; ++gi) {
+        for (int i = 0; i < n_seg && rc == GEE_OK; ++i) {
+            gee_embed_opts o = {};
+            o.seg_len = seg_lens[i];
+            o.group_vectors = groups[gi];
+            if ((rc = gee_embed_batch(csr, batch, ws, ws_bytes, err, &o, stream))) break;
+            if ((rc = hip_rc(hipEventRecord(e0, stream)))) break;
+            for (int r = 0; r < reps && rc == GEE_OK; ++r)
+                rc = gee_embed_batch(csr, batch, ws, ws_bytes, err, &o, stream);
+            if (rc || (rc = hip_rc(hipEventRecord(e1, stream))) || (rc = hip_rc(hipEventSynchronize(e1)))) break;
+            float ms = 0.f;
+            if ((rc = hip_rc(hipEventElapsedTime(&ms, e0, e1)))) break;
+            ms /= (float)reps;
+            if (best_l < 0 || ms < best_t) {
+                best_t = ms;
+                best_l = seg_lens[i];
+                best_g = groups[gi];
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    *best = best_l;
+    *best_seg = best_l;
+    *best_group = best_g;
     *best_ms = best_t;
     return GEE_OK;
 }

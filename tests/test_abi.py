@@ -127,7 +127,7 @@ def test_python_binding_refuses_host_tensors(lib):
 
 def test_batch_argument_errors(lib):
     csr = gee.Csr(1000, 10_000, FAKE, FAKE, None, 0, None)
-    o = gee.EmbedOpts(0, 0, None, None)
+    o = gee.EmbedOpts(0, 0, None, None, 0)
 
     def ws(Ks, laps, zoff, ldz):
         st, keep = gee._batch_struct(None, Ks, laps, zoff, ldz, None)
@@ -144,6 +144,12 @@ def test_batch_argument_errors(lib):
     big = ws([50] * 64, [0] * 64, [50 * i for i in range(64)], 3200)
     lap = ws([50] * 64, [1] * 64, [50 * i for i in range(64)], 3200)
     assert big > 0 and lap > big  # degrees and d^-1/2 for the Laplacian vectors
+    for g, ok in ((0, True), (1, True), (64, True), (-1, False), (65, False)):
+        o.group_vectors = g
+        assert (ws([5, 7, 3], [0, 1, 0], [0, 5, 12], 15) > 0) == ok, g
+    o.group_vectors = 16  # four groups of 16: smaller label matrices than one group of 64
+    assert 0 < ws([50] * 64, [0] * 64, [50 * i for i in range(64)], 3200) < big
+    o.group_vectors = 0
     st, keep = gee._batch_struct(None, [5], [0], [0], 5, None)
     assert lib.gee_embed_batch(ctypes.byref(csr), ctypes.byref(st), FAKE, 1 << 30, FAKE, None, None) == gee.GEE_EINVAL
 
@@ -220,16 +226,20 @@ def test_capture_and_tune_argument_errors(lib):
     assert lib.gee_capture_end(FAKE, None) == gee.GEE_EINVAL
     assert lib.gee_graph_launch(None, None) == gee.GEE_EINVAL
     lib.gee_graph_destroy(None)  # ignored
-    best, ms = ctypes.c_int32(), ctypes.c_float()
+    best, group, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
     c = (ctypes.c_int32 * 2)(4096, 8192)
     bad = (ctypes.c_int32 * 2)(4096, 100)  # not a multiple of 64
+    g = (ctypes.c_int32 * 2)(64, 32)
+    gbad = (ctypes.c_int32 * 2)(64, 65)  # more than 64 vectors per group
     csr = gee.Csr(1000, 10_000, FAKE, FAKE, None, 0, None)
     st = gee.Batch(1, FAKE, None, None, None, 8, FAKE)
-    for args in ((c, 0, 3), (c, 2, 0), (bad, 2, 3)):
-        assert lib.gee_embed_batch_tune(ctypes.byref(csr), ctypes.byref(st), args[0], args[1], args[2], FAKE, 1 << 30,
-                                        FAKE, None, ctypes.byref(best), ctypes.byref(ms)) == gee.GEE_EINVAL
-    assert lib.gee_embed_batch_tune(ctypes.byref(csr), ctypes.byref(st), c, 2, 3, FAKE, 1 << 30, FAKE, None, None,
-                                    ctypes.byref(ms)) == gee.GEE_EINVAL
+    for args in ((c, 0, g, 2, 3), (c, 2, g, 2, 0), (bad, 2, g, 2, 3), (c, 2, gbad, 2, 3), (c, 2, None, 2, 3),
+                 (c, 2, g, -1, 3)):
+        assert lib.gee_embed_batch_tune(ctypes.byref(csr), ctypes.byref(st), args[0], args[1], args[2], args[3],
+                                        args[4], FAKE, 1 << 30, FAKE, None, ctypes.byref(best), ctypes.byref(group),
+                                        ctypes.byref(ms)) == gee.GEE_EINVAL
+    assert lib.gee_embed_batch_tune(ctypes.byref(csr), ctypes.byref(st), c, 2, g, 2, 3, FAKE, 1 << 30, FAKE, None, None,
+                                    ctypes.byref(group), ctypes.byref(ms)) == gee.GEE_EINVAL
 
 
 def test_argmax_argument_errors(lib):

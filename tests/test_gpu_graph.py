@@ -73,10 +73,10 @@ def test_batch_tuner_returns_a_candidate():
     Ks, laps = [wl.K, 3, wl.K], [False, False, True]
     host = [wl.labels, random_labels(rng, g.n, 3, unknown=0.1), wl.labels]
     lab = torch.as_tensor(np.concatenate(host).astype(np.int32)).to(DEV)
-    cands = (1024, 0, 4096)
-    best, ms = gee.embed_batch_tune(lab, Ks, laps, csr, seg_lens=cands, reps=2)
-    assert best in cands and ms > 0
-    Z, zoff = gee.embed_batch(lab, Ks, laps, csr, seg_len=best)
+    cands, gcands = (1024, 0, 4096), (0, 2, 1)
+    best, group, ms = gee.embed_batch_tune(lab, Ks, laps, csr, seg_lens=cands, group_vectors=gcands, reps=2)
+    assert best in cands and group in gcands and ms > 0
+    Z, zoff = gee.embed_batch(lab, Ks, laps, csr, seg_len=best, group_vectors=group)
     for b in range(len(Ks)):
         Zo = oracle.embed(g.n, g.src, g.dst, None, host[b], Ks[b], laps[b])
         assert_parity(Z[:, zoff[b]:zoff[b] + Ks[b]].cpu().numpy(), Zo, what=f"vector {b}")
