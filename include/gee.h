@@ -274,10 +274,11 @@ size_t gee_embed_batch_workspace(const gee_csr *csr, const gee_batch *batch, con
 
 /* Batched Algorithm 1: every vector of the batch embedded over one graph with one
  * pass of the CSR per group of vectors. Vectors taken in column order whose blocks
- * are contiguous form groups of up to 64 with at most 4096 classes in total, any
- * mix of adjacency and Laplacian vectors; the group's labels are stored transposed, one row of 16-bit
- * labels per vertex, so one gather of a neighbour's row serves the whole group, and
- * each row of Z gets the group's columns written once. Every bin is an FP64 sum
+ * are contiguous form groups of up to opts->group_vectors (default 64) with at most
+ * 4096 classes in total, any mix of adjacency and Laplacian vectors; the group's
+ * labels are stored transposed, one row per vertex (8-bit labels when every vector of
+ * the group has K <= 255, else 16-bit), so one gather of a neighbour's row serves the
+ * whole group, and each row of Z gets the group's columns written once. Every bin is an FP64 sum
  * taken in CSR order, so results are bit-reproducible. Vector b's block holds the
  * values gee_embed returns for it (identical bits for unit-weight adjacency
  * vectors; other sums may differ in rounding order). Laplacian vectors share one
