@@ -160,3 +160,19 @@ def test_label_width_boundary(Ks):
             Zs = gee.embed(torch.as_tensor(Y[b]).to(DEV), K, csr=csr).cpu().numpy()
             assert np.array_equal(blk.view(np.uint32), Zs.view(np.uint32)), f"vector {b} K={K}"
         assert_parity(blk, oracle.embed(n, src, dst, w, Y[b], K, laps[b]), what=f"vector {b} K={K} lap={laps[b]}")
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_group_size_does_not_change_bits(weighted):
+    """Vectors per group (the label tile) only changes how the vectors share passes: every
+    vector's block has the same bits with groups of 1, 3 and 64, Laplacian ones included."""
+    n, src, dst, w = _graph(weighted, seed=58, scale=12, ef=8, hub=800)
+    rng = np.random.default_rng(10)
+    Ks = [int(k) for k in rng.integers(2, 70, 11)]
+    laps = [b % 3 == 1 for b in range(len(Ks))]
+    Y = torch.as_tensor(_labels(rng, n, Ks)).to(DEV)
+    csr = gee.csr_build(gee.to_device(n, src, dst, w, device=DEV))
+    ref, zoff = gee.embed_batch(Y, Ks, laps, csr, seg_len=512)
+    for gv in (1, 3):
+        Z, _ = gee.embed_batch(Y, Ks, laps, csr, seg_len=512, group_vectors=gv)
+        assert torch.equal(Z.view(torch.int32), ref.view(torch.int32)), gv
