@@ -566,6 +566,7 @@ def embed_batch(labels: torch.Tensor, Ks, laplacian, csr: DeviceCsr, Z: torch.Te
 
     ``Ks[b]`` and ``laplacian[b]`` give each vector's classes and version. By default the blocks
     are packed side by side: Z is [n, sum(Ks)] and vector b owns columns zoff[b] .. zoff[b]+Ks[b].
+    A given ``ws`` must hold ``embed_batch_workspace_bytes`` (else GeeError GEE_EWORKSPACE).
     Returns (Z, zoff)."""
     lib = load()
     B = len(Ks)
@@ -583,10 +584,10 @@ def embed_batch(labels: torch.Tensor, Ks, laplacian, csr: DeviceCsr, Z: torch.Te
     st, keep = _batch_struct(labels, Ks, laplacian, zoff, Z.shape[1], Z)
     rs = csr.struct()
     o = _opts(seg_len, 0, events, group_vectors)
-    wsb = int(lib.gee_embed_batch_workspace(ctypes.byref(rs), ctypes.byref(st), ctypes.byref(o)))
-    if wsb == 0:
-        raise GeeError(GEE_EINVAL, "gee_embed_batch_workspace")
-    if ws is None or ws.numel() < wsb:
+    if ws is None:  # a given workspace is checked by the library (GEE_EWORKSPACE when short)
+        wsb = int(lib.gee_embed_batch_workspace(ctypes.byref(rs), ctypes.byref(st), ctypes.byref(o)))
+        if wsb == 0:
+            raise GeeError(GEE_EINVAL, "gee_embed_batch_workspace")
         ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     if err is None:
         err = torch.zeros(1, dtype=torch.int32, device=dev)

@@ -95,6 +95,30 @@ class _Launch:
     zoff: list | None = None
 
 
+def batch_workspace_bound(n: int, nnz: int, n_hot: int, Ks, laps, seg_len: int = 0) -> int:
+    """An upper bound, in closed form, on gee_embed_batch's workspace for one graph and
+    batch (admission needs a bound per job, and the library's exact query costs a few
+    ctypes objects per call). It takes the widest label row (min(64, B rounded up to 8)
+    vectors) and the most classes of a group (min(sum K, 4096)) for every group-sized
+    table, and the library's default segment length (the power of two at or above
+    (n + nnz) / 32768 within [512, 16384]) when seg_len is 0."""
+    if seg_len:
+        L = seg_len
+    else:
+        want, L = (n + nnz) // 32768, 512
+        while L < want and L < 16384:
+            L *= 2
+    nseg = (n + nnz + L - 1) // L
+    B, S = len(Ks), int(sum(Ks))
+    gs = min(64, (B + 7) // 8 * 8)
+    kt = min(S, 4096)
+    parts = [8 * (S + B), 2 * (n + 1) * gs, 2 * n_hot * gs, 8 * kt, 4 * 64, 4 * (nseg + 1), 8 * (nseg + 1),
+             16 * nseg * kt]
+    if any(laps):
+        parts += [8 * n, 4 * n, 4 * n_hot]
+    return sum(p + 256 for p in parts) + 256  # each table starts 256-byte aligned
+
+
 def plan_packs(graphs: dict, pack_items: int, pack_limit: int):
     """Packs of small graphs. Graphs whose rows + entries (n + 2s) are at most pack_items
     go, in id order, into packs of at most pack_limit rows + entries; the others stand
@@ -187,7 +211,7 @@ class Server:
         n = g.csr.n
         if not self._routes_plain(g, Ks):
             # the job's share of a fused launch is at most what it would need alone
-            ws = embed_batch_workspace_bytes(n, Ks, laps, g.csr, seg_len=self.seg_len)
+            ws = batch_workspace_bound(n, g.csr.nnz, g.csr.n_hot, Ks, laps, self.seg_len)
             return ws + 4 * n * int(sum(Ks)) + 4 * n * len(Ks)
         ws = max(self._plain_ws(g, k, l) for k, l in zip(Ks, laps))
         return ws + 4 * n * int(sum(Ks)) + 4 * n * len(Ks) + 4 * n * max(Ks)

@@ -46,3 +46,38 @@ def test_plan_packs_off():
     graphs = _pool([(10, 10), (100, 100)])
     unit, members = plan_packs(graphs, pack_items=0, pack_limit=1 << 22)
     assert members == {} and unit == {0: (0, 0), 1: (1, 0)}
+
+
+def test_batch_workspace_bound_covers_the_library():
+    """The serving loop admits jobs on a closed-form bound of the batched workspace: it is
+    never below the library's exact size, over random graphs and batches (one group and
+    many, both versions, default and given segment lengths)."""
+    import ctypes
+
+    import paper_2402_04403_amd as gee
+    from paper_2402_04403_amd.serve import batch_workspace_bound
+
+    lib = gee.load()
+    fake = ctypes.c_void_p(256)
+    rng = np.random.default_rng(12)
+    worst = 0.0
+    for trial in range(300):
+        n = int(rng.integers(1, 1 << 26))
+        nnz = int(rng.integers(0, 1 << 30))
+        n_hot = int(rng.integers(0, min(n, 1 << 22) + 1))
+        B = int(rng.integers(1, 9)) if trial % 3 else int(rng.integers(1, 200))
+        Ks = [int(k) for k in rng.integers(1, 300 if trial % 2 else 4097, B)]
+        laps = [bool(x) for x in rng.integers(0, 2, B)]
+        seg = 0 if trial % 4 else int(rng.integers(1, 1024)) * 64
+        csr = gee.Csr(n, nnz, fake, fake, None, n_hot, fake if n_hot else None)
+        zoff = list(np.cumsum([0] + Ks[:-1]))
+        st, keep = gee._batch_struct(None, Ks, laps, zoff, int(sum(Ks)), None)
+        o = gee.EmbedOpts(seg, 0, None, None, 0)
+        exact = int(lib.gee_embed_batch_workspace(ctypes.byref(csr), ctypes.byref(st), ctypes.byref(o)))
+        if exact == 0:
+            continue  # a shape the library refuses (too many segments, say)
+        bound = batch_workspace_bound(n, nnz, n_hot, Ks, laps, seg)
+        assert bound >= exact, (trial, n, nnz, n_hot, B, seg)
+        if B <= 8 and max(Ks) < 300:
+            worst = max(worst, bound / exact)
+    assert worst < 3.0  # and not wildly above it for the serving loop's one-group jobs
