@@ -42,7 +42,7 @@ import numpy as np
 import torch
 
 from . import (DEFAULT_HOT_BUDGET, DeviceCsr, HipEvent, csr_build, embed, embed_batch,
-               embed_batch_workspace_bytes, embed_workspace_bytes, to_device)
+               embed_workspace_bytes, to_device)
 
 
 @dataclass
@@ -369,8 +369,8 @@ class Server:
             bufs.append(stage)
         if vs:
             fK, fl, fz = [Ks[v] for v in vs], [laps[v] for v in vs], [zoff[v] for v in vs]
-            ws_b = torch.empty(embed_batch_workspace_bytes(n, fK, fl, g.csr, seg_len=self.seg_len, zoff=fz,
-                                                           ldz=Z.shape[1]), dtype=torch.uint8, device=self.dev)
+            ws_b = torch.empty(batch_workspace_bound(n, g.csr.nnz, g.csr.n_hot, fK, fl, self.seg_len),
+                               dtype=torch.uint8, device=self.dev)
             bufs.append(ws_b)
         if pv:
             ws_p = torch.empty(max(self._plain_ws(g, Ks[v], laps[v]) for v in pv), dtype=torch.uint8, device=self.dev)
