@@ -443,7 +443,17 @@ class Server:
         for item in admitted:
             by_graph.setdefault(item[1].gid, []).append(item)
         for group in by_graph.values():
-            self._launch(group, self._free_slots.pop())
+            slot = self._free_slots.pop()
+            try:
+                self._launch(group, slot)
+            except Exception:
+                # a refused call (the library checks its arguments before queuing work):
+                # give back the jobs' memory and graph; the error slot stays out of use,
+                # since work queued before the refusal may still write it (buffers that
+                # work uses are held by torch's allocator until the stream passes them)
+                self.used -= sum(b for _, _, b in group)
+                group[0][1].busy -= len(group)
+                raise
         return finished
 
     def drain(self) -> list:

@@ -168,3 +168,20 @@ def test_packed_small_graphs():
         Y = j.labels(n)
         assert_parity(mix[j.jid].Z.cpu().numpy()[:, :j.Ks[0]], oracle.embed(n, src, dst, None, Y[0], j.Ks[0], j.laplacian),
                       what=f"packed job {j.jid} vs oracle")
+
+
+def test_refused_launch_returns_its_memory():
+    """A job the library refuses (a class count beyond the batched limit) raises from the
+    poll that launches it, and the server gives back the memory and graph it had taken."""
+    pool, graphs, jobs = _pool()
+    srv = Server(graphs, 8 << 30)
+    srv.warm([0])
+    used = srv.used
+    n = graphs[0][0]
+    srv.submit(Request(999, 0, [5000], [False], torch.ones((1, n), dtype=torch.int32).pin_memory(), time.perf_counter()))
+    with pytest.raises(gee.GeeError):
+        srv.poll()
+    assert srv.used == used and srv.resident[0].busy == 0
+    good = _reqs(graphs, [j for j in jobs if j.gid == 0][:2])
+    done = _run(srv, good)
+    assert len(done) == len(good) and all(d.error == 0 for d in done.values())
