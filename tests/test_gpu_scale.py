@@ -1,8 +1,9 @@
 """Parity at the workload sizes: the Erdős–Rényi weighted graph (n = 2^22, s = 2^26,
-K = 50) in full against the oracle, and the paper-scale R-MAT (scale 27, edge factor
+K = 50) in full against the oracle, the paper-scale R-MAT (scale 27, edge factor
 14, 1,879,048,192 records) on sampled rows, in the launch configuration the
 benchmark times (default segment length and window), with the propagation-blocked
-pass compared in full against the pull pass."""
+pass compared in full against the pull pass, and the batched workload (R-MAT scale 24,
+64 vectors) on sampled rows of four vectors."""
 import time
 
 import numpy as np
@@ -92,3 +93,42 @@ def test_rmat_paper_scale_sampled_rows():
     # unit weights: both forms hold exact integer sums, so they agree bit for bit
     assert np.array_equal(pull_rows.view(np.uint32), push_rows.view(np.uint32))
     assert not pull_rows[np.isin(rows, iso)].any()
+
+
+@pytest.mark.timeout(900)
+def test_batched_full_size_sampled_rows():
+    """The batched benchmark's workload (R-MAT scale 24, edge factor 16, 64 vectors, K
+    log-uniform on [2, 256], even vectors adjacency and odd Laplacian) in the launch
+    configuration it times (default segment length, 64 vectors per group): sampled rows
+    of two adjacency and two Laplacian vectors against the oracle, and adjacency vector 0
+    bit for bit against a single pull call."""
+    t0 = time.time()
+    wl = gen.rmat_batched()
+    g = wl.graph
+    announce(f"  generated s={g.s} B={len(wl.Ks)} {time.time() - t0:.1f}s")
+    coo = gee.to_device(g.n, g.src, g.dst, device=DEV)
+    labels = torch.as_tensor(wl.labels).to(DEV)
+    csr = gee.csr_build(coo, hot_budget=gee.DEFAULT_HOT_BUDGET)
+    del coo
+    torch.cuda.empty_cache()
+    Z, zoff = gee.embed_batch(labels.view(-1), wl.Ks, wl.laps, csr)
+    torch.cuda.synchronize()
+    announce(f"  batched pass done {time.time() - t0:.1f}s")
+    rng = np.random.default_rng(24)
+    deg = csr.row_ptr[1:] - csr.row_ptr[:-1]
+    top = torch.topk(deg, 32).indices.cpu().numpy()
+    iso = torch.nonzero(deg == 0)[:32, 0].cpu().numpy()
+    rows = np.unique(np.r_[rng.choice(g.n, 2000, replace=False), top, iso]).astype(np.int64)
+    idx = torch.as_tensor(rows, device=DEV)
+    picked = {b: Z[idx, zoff[b]:zoff[b] + wl.Ks[b]].cpu().numpy() for b in (0, 1, 32, 33)}
+    del Z
+    torch.cuda.empty_cache()
+    Zs = gee.embed(labels[0], wl.Ks[0], csr=csr)
+    assert np.array_equal(Zs[idx].cpu().numpy().view(np.uint32), picked[0].view(np.uint32))
+    del Zs
+    for b, blk in picked.items():
+        assert wl.laps[b] == (b % 2 == 1)
+        Zo = oracle.embed_rows(g.n, g.src, g.dst, None, wl.labels[b], wl.Ks[b], wl.laps[b], rows)
+        assert_parity(blk, Zo, what=f"vector {b} (K={wl.Ks[b]}, laplacian={wl.laps[b]}), sampled rows")
+        assert not blk[np.isin(rows, iso)].any()
+    announce(f"  oracle rows checked {time.time() - t0:.1f}s")
