@@ -132,3 +132,41 @@ def test_batched_full_size_sampled_rows():
         assert_parity(blk, Zo, what=f"vector {b} (K={wl.Ks[b]}, laplacian={wl.laps[b]}), sampled rows")
         assert not blk[np.isin(rows, iso)].any()
     announce(f"  oracle rows checked {time.time() - t0:.1f}s")
+
+
+@pytest.mark.timeout(900)
+def test_serving_pool_sampled_jobs():
+    """The serving benchmark's pool (100 graphs, log-normal sizes up to 5*10^7 records) and
+    the first 60 jobs of its mix, through the batched serving loop: one job per distinct
+    graph among them, checked against the oracle on sampled rows of its first vector."""
+    from paper_2402_04403_amd.serve import Request, Server
+
+    t0 = time.time()
+    pool = gen.serve_pool()
+    jobs = gen.serve_jobs(pool)[:60]
+    gids = sorted({j.gid for j in jobs})
+    graphs = {}
+    for gid in gids:
+        g = pool[gid].make()
+        graphs[gid] = (pool[gid].n, g.src, g.dst)
+    announce(f"  {len(gids)} graphs generated {time.time() - t0:.1f}s")
+    srv = Server(graphs, int(200e9), keep_results=True)
+    for j in jobs:
+        srv.submit(Request(j.jid, j.gid, j.Ks, [j.laplacian] * len(j.Ks),
+                           torch.from_numpy(j.labels(graphs[j.gid][0])).pin_memory(), time.perf_counter()))
+    done = {d.jid: d for d in srv.drain()}
+    assert len(done) == len(jobs) and all(d.error == 0 for d in done.values())
+    announce(f"  served {time.time() - t0:.1f}s")
+    rng = np.random.default_rng(5)
+    seen = set()
+    for j in jobs:
+        if j.gid in seen:
+            continue
+        seen.add(j.gid)
+        n, src, dst = graphs[j.gid]
+        Y = j.labels(n)
+        rows = np.unique(rng.choice(n, min(n, 500), replace=False)).astype(np.int64)
+        Zo = oracle.embed_rows(n, src, dst, None, Y[0], j.Ks[0], j.laplacian, rows)
+        got = done[j.jid].Z[torch.as_tensor(rows, device=DEV), :j.Ks[0]].cpu().numpy()
+        assert_parity(got, Zo, what=f"job {j.jid} on graph {j.gid} (n={n}, s={len(src)})")
+    announce(f"  {len(seen)} jobs checked {time.time() - t0:.1f}s")
