@@ -2,8 +2,9 @@
 K = 50) in full against the oracle, the paper-scale R-MAT (scale 27, edge factor
 14, 1,879,048,192 records) on sampled rows, in the launch configuration the
 benchmark times (default segment length and window), with the propagation-blocked
-pass compared in full against the pull pass, and the batched workload (R-MAT scale 24,
-64 vectors) on sampled rows of four vectors."""
+pass compared in full against the pull pass, the batched workload (R-MAT scale 24,
+64 vectors) on sampled rows of four vectors, and the serving pool's first 60 jobs through
+the serving loop."""
 import time
 
 import numpy as np
