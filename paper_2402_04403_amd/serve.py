@@ -18,7 +18,10 @@ a large graph (at most ``route_vectors`` vectors, default 0: none; at least
 inside the same launch: the batched pass gives its lanes to vectors, so a call with few
 vectors leaves most lanes idle, while the plain pull gives them to entries. The choice
 depends only on the job and its graph. It shortens such jobs but costs throughput when
-jobs on one graph could have shared a batched call.
+jobs on one graph could have shared a batched call. Unit-weight adjacency vectors get the
+same bits from either pass, so on a graph of at least ``route_items`` they follow the
+load instead: a launch with no batched Laplacian work and at most ``route_adjacency``
+adjacency vectors (default 0: off) runs them as plain calls.
 Small graphs can be packed (``pack_items`` > 0): the graphs whose rows + entries are at
 most ``pack_items`` are grouped, in id order, into disjoint-union CSRs of at most
 ``pack_limit`` rows + entries, and the jobs on all members of a pack run in one launch
@@ -154,7 +157,7 @@ class Server:
     def __init__(self, graphs: dict, hbm_budget: int, streams: int = 4, mode: str = "batched",
                  seg_len: int = 0, hot_budget: int = DEFAULT_HOT_BUDGET, keep_results: bool = False,
                  device: str = "cuda:0", route_vectors: int = 0, route_items: int = 1 << 22,
-                 pack_items: int = 0, pack_limit: int = 1 << 22):
+                 pack_items: int = 0, pack_limit: int = 1 << 22, route_adjacency: int = 0):
         if mode not in ("batched", "plain"):
             raise ValueError("mode: batched or plain")
         self.pool = graphs
@@ -163,6 +166,7 @@ class Server:
         self.seg_len = seg_len
         self.route_vectors = route_vectors
         self.route_items = route_items
+        self.route_adjacency = route_adjacency
         self.hot_budget = hot_budget
         self.keep = keep_results
         self.dev = torch.device(device)
@@ -209,12 +213,19 @@ class Server:
 
     def _launch_bytes(self, g: _Graph, Ks, laps) -> int:
         n = g.csr.n
-        if not self._routes_plain(g, Ks):
-            # the job's share of a fused launch is at most what it would need alone
-            ws = batch_workspace_bound(n, g.csr.nnz, g.csr.n_hot, Ks, laps, self.seg_len)
-            return ws + 4 * n * int(sum(Ks)) + 4 * n * len(Ks)
-        ws = max(self._plain_ws(g, k, l) for k, l in zip(Ks, laps))
-        return ws + 4 * n * int(sum(Ks)) + 4 * n * len(Ks) + 4 * n * max(Ks)
+
+        def plain():
+            ws = max(self._plain_ws(g, k, l) for k, l in zip(Ks, laps))
+            return ws + 4 * n * int(sum(Ks)) + 4 * n * len(Ks) + 4 * n * max(Ks)
+
+        if self._routes_plain(g, Ks):
+            return plain()
+        # the job's share of a fused launch is at most what it would need alone
+        ws = batch_workspace_bound(n, g.csr.nnz, g.csr.n_hot, Ks, laps, self.seg_len)
+        fused = ws + 4 * n * int(sum(Ks)) + 4 * n * len(Ks)
+        if self.route_adjacency > 0 and n + g.csr.nnz >= self.route_items and not any(laps):
+            return max(fused, plain())  # the launch may run it either way
+        return fused
 
     def _plain_ws(self, g: _Graph, k: int, lap: bool) -> int:
         key = (g.gid, int(k), bool(lap))
@@ -349,7 +360,17 @@ class Server:
             first.append(b0)
             b0 += len(r.Ks)
         n = g.csr.n
-        fused = [i for i, r in enumerate(reqs) if not self._routes_plain(g, r.Ks)]
+        plain = [self._routes_plain(g, r.Ks) for r in reqs]
+        if self.route_adjacency > 0 and g.csr.n + g.csr.nnz >= self.route_items:
+            # adjacency vectors take the same bits in either pass, so they may follow the
+            # load: when nothing else in this launch needs the batched pass and they are
+            # few, one plain call each is shorter than the batched walk
+            lap_batched = any(not plain[i] and any(r.laplacian) for i, r in enumerate(reqs))
+            adj = [i for i, r in enumerate(reqs) if not plain[i] and not any(r.laplacian)]
+            if not lap_batched and 0 < sum(len(reqs[i].Ks) for i in adj) <= self.route_adjacency:
+                for i in adj:
+                    plain[i] = True
+        fused = [i for i, r in enumerate(reqs) if not plain[i]]
         fset = set(fused)
         vs = [first[i] + b for i in fused for b in range(len(reqs[i].Ks))]  # fused vectors
         pv = [first[i] + b for i, r in enumerate(reqs) if i not in fset for b in range(len(r.Ks))]

@@ -185,3 +185,24 @@ def test_refused_launch_returns_its_memory():
     good = _reqs(graphs, [j for j in jobs if j.gid == 0][:2])
     done = _run(srv, good)
     assert len(done) == len(good) and all(d.error == 0 for d in done.values())
+
+
+def test_adjacency_routing_follows_the_load():
+    """On a graph counted as large (route_items=0), adjacency jobs alone in their launch run
+    as plain calls and fused ones as a batched call; adjacency vectors have the same bits
+    either way, so every job's Z is the same alone and in the mix."""
+    pool, graphs, jobs = _pool()
+    jobs = [j for j in jobs if not j.laplacian][:10]
+    assert len({j.gid for j in jobs}) > 1
+
+    def server(streams):
+        return Server(graphs, 8 << 30, streams=streams, keep_results=True, route_items=0, route_adjacency=6)
+
+    mix = _run(server(3), _reqs(graphs, jobs))
+    for j in jobs:
+        alone = _run(server(1), _reqs(graphs, [j]))
+        assert torch.equal(alone[j.jid].Z.view(torch.int32), mix[j.jid].Z.view(torch.int32)), j.jid
+    n, src, dst = graphs[jobs[0].gid]
+    Y = jobs[0].labels(n)
+    assert_parity(mix[jobs[0].jid].Z.cpu().numpy()[:, :jobs[0].Ks[0]],
+                  oracle.embed(n, src, dst, None, Y[0], jobs[0].Ks[0], False), what="routed adjacency job vs oracle")
