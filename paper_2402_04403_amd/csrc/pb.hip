@@ -212,28 +212,31 @@ k_pb_words(int64_t n_rb, int32_t n_cb, const int64_t *__restrict__ cell_start, c
 
 __device__ inline int64_t clamp_index(int64_t h, int64_t nnz) { return h < 0 ? 0 : (h > nnz ? nnz : h); }
 
-// yv[i] = lab[colc[i]] over the entries with vertex columns [0, h0), 16 entries per
-// thread with 16-byte loads of columns and one 16-byte store of labels. h0 is the
+// yv[i] = lab[colc[i]] over the entries with vertex columns [0, h0), 32 entries per
+// thread: eight 16-byte loads of columns, their 32 label reads in flight together, and
+// two 16-byte stores of labels (32 entries measured faster than 16 or 64). h0 is the
 // first tier entry (*tier_start), or nnz without a tier (tier_start null).
 __global__ void __launch_bounds__(kT)
 k_pb_gather(int64_t nnz, const int64_t *__restrict__ tier_start, const int32_t *__restrict__ colc,
             const uint8_t *__restrict__ lab, uint8_t *__restrict__ yv)
 {
     const int64_t h0 = tier_start ? clamp_index(*tier_start, nnz) : nnz;
-    const int64_t nvec = h0 / 16;
+    const int64_t nvec = h0 / 32;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvec; v += (int64_t)gridDim.x * blockDim.x) {
-        const int4 *cp = reinterpret_cast<const int4 *>(colc + v * 16);
-        int4 c4[4];
+        const int4 *cp = reinterpret_cast<const int4 *>(colc + v * 32);
+        int4 c4[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) c4[q] = cp[q];
-        uint32_t w[4];
+        for (int q = 0; q < 8; ++q) c4[q] = cp[q];
+        uint32_t w[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 8; ++q)
             w[q] = (uint32_t)lab[c4[q].x] | ((uint32_t)lab[c4[q].y] << 8) | ((uint32_t)lab[c4[q].z] << 16) |
                    ((uint32_t)lab[c4[q].w] << 24);
-        *reinterpret_cast<uint4 *>(yv + v * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+        uint4 *out = reinterpret_cast<uint4 *>(yv + v * 32);
+        out[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        out[1] = make_uint4(w[4], w[5], w[6], w[7]);
     }
-    for (int64_t i = nvec * 16 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < h0;
+    for (int64_t i = nvec * 32 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < h0;
          i += (int64_t)gridDim.x * blockDim.x)
         yv[i] = lab[colc[i]];
 }
@@ -540,9 +543,9 @@ hipError_t launch_pb_gather(int64_t nnz, const PbLayout &L, int64_t n_lds, const
 {
     if (nnz <= 0) return hipSuccess;
     const int64_t *sl_start = L.n_sl > 0 ? cell_start + L.n_vcb : nullptr; // cells (0, n_vcb + j)
-    // vertex blocks: one workgroup per 4,096 entries, dispatched in order, so the entries
+    // vertex blocks: one workgroup per 8,192 entries, dispatched in order, so the entries
     // in flight stay within one or two column blocks (their labels in L2)
-    hipLaunchKernelGGL(k_pb_gather, dim3(grid_cap(nnz, kT * 16)), dim3(kT), 0, s, nnz, sl_start, colc, lab, yv);
+    hipLaunchKernelGGL(k_pb_gather, dim3(grid_cap(nnz, kT * 32)), dim3(kT), 0, s, nnz, sl_start, colc, lab, yv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || L.n_sl == 0) return e;
     hipLaunchKernelGGL(k_pb_tier_labels, dim3(grid_cap(n_lds, kT * 4)), dim3(kT), 0, s, n_lds, lds_ids, lab, tab);
