@@ -463,17 +463,25 @@ class Server:
         by_graph = collections.OrderedDict()
         for item in admitted:
             by_graph.setdefault(item[1].gid, []).append(item)
-        for group in by_graph.values():
+        groups = list(by_graph.values())
+        for gi, group in enumerate(groups):
             slot = self._free_slots.pop()
             try:
                 self._launch(group, slot)
-            except Exception:
+            except Exception as exc:
                 # a refused call (the library checks its arguments before queuing work):
-                # give back the jobs' memory and graph; the error slot stays out of use,
-                # since work queued before the refusal may still write it (buffers that
-                # work uses are held by torch's allocator until the stream passes them)
-                self.used -= sum(b for _, _, b in group)
-                group[0][1].busy -= len(group)
+                # give back the memory and graph of its jobs and of the groups not yet
+                # launched, whose jobs wait again at the head of the queue in arrival
+                # order; the refused launch's jobs are dropped and named on the exception.
+                # Its error slot stays out of use, since work queued before the refusal
+                # may still write it (buffers that work uses are held by torch's allocator
+                # until the stream passes them).
+                for grp in groups[gi:]:
+                    self.used -= sum(b for _, _, b in grp)
+                    grp[0][1].busy -= len(grp)
+                later = {id(item) for grp in groups[gi + 1:] for item in grp}
+                self.pending.extendleft(reversed([item[0] for item in admitted if id(item) in later]))
+                exc.refused_jobs = [r.jid for r, _, _ in group]
                 raise
         return finished
 

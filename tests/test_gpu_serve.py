@@ -175,13 +175,21 @@ def test_refused_launch_returns_its_memory():
     poll that launches it, and the server gives back the memory and graph it had taken."""
     pool, graphs, jobs = _pool()
     srv = Server(graphs, 8 << 30)
-    srv.warm([0])
+    srv.warm([0, 2])
     used = srv.used
     n = graphs[0][0]
     srv.submit(Request(999, 0, [5000], [False], torch.ones((1, n), dtype=torch.int32).pin_memory(), time.perf_counter()))
-    with pytest.raises(gee.GeeError):
+    # a job on another graph, admitted in the same poll and launched after the refused one,
+    # waits again in the queue and completes on the next polls
+    other = _reqs(graphs, [j for j in jobs if j.gid == 2][:1])[0]
+    srv.submit(other)
+    with pytest.raises(gee.GeeError) as info:
         srv.poll()
-    assert srv.used == used and srv.resident[0].busy == 0
+    assert info.value.refused_jobs == [999]
+    assert srv.used == used and srv.resident[0].busy == 0 and srv.resident[2].busy == 0
+    assert [r.jid for r in srv.pending] == [other.jid]
+    done = {d.jid: d for d in srv.drain()}
+    assert list(done) == [other.jid] and done[other.jid].error == 0
     good = _reqs(graphs, [j for j in jobs if j.gid == 0][:2])
     done = _run(srv, good)
     assert len(done) == len(good) and all(d.error == 0 for d in done.values())
