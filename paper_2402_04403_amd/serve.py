@@ -325,7 +325,16 @@ class Server:
                 break
             need = self._launch_bytes(g, r.Ks, r.laplacian)
             if need > self.budget - g.bytes:
-                raise ValueError(f"job {r.jid} needs {need} bytes beside its graph; the budget is {self.budget}")
+                # the job can never run: drop it, and put the jobs admitted before it in
+                # this poll back at the head of the queue, in arrival order
+                self.pending.popleft()
+                for q, gq, b in reversed(out):
+                    self.used -= b
+                    gq.busy -= 1
+                    self.pending.appendleft(q)
+                exc = ValueError(f"job {r.jid} needs {need} bytes beside its graph; the budget is {self.budget}")
+                exc.refused_jobs = [r.jid]
+                raise exc
             if self.used + need > self.budget and not self._evict_for(need, u):
                 break
             self.pending.popleft()

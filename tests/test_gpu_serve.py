@@ -92,10 +92,20 @@ def test_small_budget_evicts_and_refuses():
     ref = _run(Server(graphs, 8 << 30, keep_results=True, hot_budget=0), _reqs(graphs, jobs))
     for j in jobs:
         assert torch.equal(got[j.jid].Z.view(torch.int32), ref[j.jid].Z.view(torch.int32))
+    # a job that can never fit is dropped with an error; a job admitted before it in the
+    # same poll waits again and runs
+    small = gen.Job(100, 0, [2], [0.5], False, 999)
+    assert probe._launch_bytes(g, [2], [False]) <= L // 2
     tiny = Server(graphs, G + L // 2, hot_budget=0)
+    tiny.submit(_reqs(graphs, [small])[0])
     tiny.submit(_reqs(graphs, jobs[:1])[0])
-    with pytest.raises(ValueError):
-        tiny.drain()
+    with pytest.raises(ValueError) as info:
+        tiny.poll()
+    assert info.value.refused_jobs == [jobs[0].jid]
+    assert [r.jid for r in tiny.pending] == [small.jid] and tiny.resident[0].busy == 0
+    assert tiny.used == sum(x.bytes for x in tiny.resident.values())
+    done = {d.jid: d for d in tiny.drain()}
+    assert list(done) == [small.jid] and done[small.jid].error == 0
 
 
 def test_routed_jobs_alone_equal_in_the_mix():
