@@ -94,13 +94,16 @@ def source_hash(path):
 
 def counters_traffic(launch_bytes_alg, path=PROFILE_COUNTERS, source=KERNEL_SOURCE):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it still
-    describes the current kernel source; else None."""
+    describes the current kernel source and was taken on this workload (the same
+    algorithmic bytes per launch, which follow n, nnz, K and the batch); else None."""
     try:
         with open(path) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None, None
     if c.get("kernel_source_sha256") != source_hash(source):
+        return None, c
+    if int(c.get("bytes_alg_per_launch", -1)) != int(launch_bytes_alg):
         return None, c
     return float(c["hbm_bytes_per_launch"]), c
 
@@ -246,6 +249,8 @@ def main():
         kernel = "k_pull" if a.form == "pull" else "k_pb_gather + k_pb_tier_labels + k_pb_gather_tier + k_pb_rows"
         traffic, counters = (counters_traffic(bytes_alg) if a.form == "pull"
                              else counters_traffic(bytes_alg, PROFILE_COUNTERS_PB, KERNEL_SOURCE_PB))
+        if a.hot_budget != -1 or a.seg_len or a.rows_per_window:
+            traffic = None  # the counters were taken with the library's defaults
     else:
         bytes_alg = 8 * s + lab_bytes * n + 2 * 8 * s  # records once, labels once, two 8-byte atomic RMW
         kernel = "k_push"

@@ -163,8 +163,29 @@ def test_unaligned_z_and_ragged_entries():
             assert buf[0].item() == -1.0
 
 
+@pytest.mark.parametrize("K", [65, 66, 100, 127, 128])
+def test_large_K(K):
+    """Above 64 classes a row block's bins take more than 64 KB of LDS: class counts that
+    are not a multiple of 4, with Z aligned (four-float stores when K is a multiple of 4)
+    and at an offset of one float (scalar stores), nothing written outside Z."""
+    rng = np.random.default_rng(K)
+    g = gen.rmat(16, 400_000, seed=K)
+    csr = gee.csr_build(gee.to_device(g.n, g.src, g.dst, None, device=DEV), hot_budget=5000)
+    pb = gee.pb_build(csr)
+    labels = random_labels(rng, g.n, K, unknown=0.2)
+    Y = torch.as_tensor(labels).to(DEV)
+    ref = gee.embed(Y, K, csr=csr)
+    Zb = gee.embed_pb(Y, K, pb)
+    _same_bits(Zb, ref)
+    buf = torch.full((g.n * K + 2,), -1.0, dtype=torch.float32, device=DEV)
+    _same_bits(gee.embed_pb(Y, K, pb, Z=buf[1:-1].view(g.n, K)), ref)
+    assert buf[0].item() == -1.0 and buf[-1].item() == -1.0
+    if K == 100:
+        assert_parity(Zb.cpu().numpy(), oracle.embed(g.n, g.src, g.dst, None, labels, K, False), what="K100")
+
+
 @pytest.mark.parametrize("tier", [0, 500])
-@pytest.mark.parametrize("K", [3, 50, 128])
+@pytest.mark.parametrize("K", [3, 50, 100, 128])
 def test_hub_row_blocks(tier, K):
     """Row blocks with 2^16 entries or more take two passes (one per half of their rows,
     32-bit bins): hubs in the first half, the second half, and in a partial last block

@@ -1,5 +1,7 @@
-"""Host-side logic that needs no GPU: the benchmark's refusal of several GPUs and the
-serving loop's packing plan."""
+"""Host-side logic that needs no GPU: the benchmark's refusal of several GPUs, its use of
+the committed counter summaries, and the serving loop's packing plan."""
+import importlib.util
+import json
 import os
 import subprocess
 import sys
@@ -16,6 +18,29 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_counter_traffic_only_for_its_kernel_and_workload(tmp_path):
+    """The counter summary's HBM bytes are reported only while the kernel source hashes the
+    same and the run has the algorithmic bytes per launch the counters were taken at."""
+    bench = _bench()
+    src = tmp_path / "k.hip"
+    src.write_text("kernel v1")
+    summary = tmp_path / "c.json"
+    summary.write_text(json.dumps({"kernel_source_sha256": bench.source_hash(str(src)),
+                                   "bytes_alg_per_launch": 1000, "hbm_bytes_per_launch": 1234.5}))
+    assert bench.counters_traffic(1000, str(summary), str(src))[0] == 1234.5
+    assert bench.counters_traffic(2000, str(summary), str(src))[0] is None  # another workload
+    src.write_text("kernel v2")
+    assert bench.counters_traffic(1000, str(summary), str(src))[0] is None  # the kernel changed
+    assert bench.counters_traffic(1000, str(tmp_path / "missing.json"), str(src)) == (None, None)
 
 
 def _pool(sizes):
