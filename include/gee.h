@@ -24,7 +24,8 @@
  *  - Unless marked "host", every pointer is device memory on the current HIP
  *    device, owned by the caller. The library allocates no device memory: the
  *    calls that need scratch take a caller-provided workspace of the size the
- *    matching *_workspace() query returns, aligned to 256 bytes.
+ *    matching *_workspace() query returns, aligned to 256 bytes (gee_embed_noalloc
+ *    instead uses a static array the library holds on each device).
  *  - Every call is stream-ordered on `stream` and returns before the GPU work
  *    finishes. Inputs must stay valid, and outputs untouched, until then.
  *  - Calls are stateless and reentrant; calls on different streams with
@@ -160,6 +161,24 @@ size_t gee_embed_workspace(const gee_coo *g, const gee_csr *csr, int32_t K, int 
 int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32_t K, int laplacian,
               float *Z, void *ws, size_t ws_bytes, int32_t *err, const gee_embed_opts *opts,
               hipStream_t stream);
+
+/* Bytes of the scratch that gee_embed_noalloc uses: one static device array of this
+ * size on every GPU the library runs on, held until the process ends. */
+#define GEE_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (work recorded into a HIP graph,
+ * tight serving loops, harnesses that forbid hipMalloc): gee_embed with the library's
+ * own static scratch in place of the workspace argument. Same arguments (minus ws and
+ * ws_bytes), forms, results and errors as gee_embed; the kernels are the same. Calls
+ * no hipMalloc, hipFree or other allocating routine. GEE_EWORKSPACE, with nothing
+ * launched, when gee_embed_workspace() for these arguments exceeds
+ * GEE_NOALLOC_SCRATCH_BYTES. The first call on a device looks up that device's scratch
+ * address (GEE_EHIP if that fails). Every call on one GPU shares that GPU's scratch,
+ * which keeps the last call's contents (the call clears what it needs zeroed itself):
+ * calls that overlap in time on one GPU, on any streams, race and give wrong results;
+ * order them on one stream or synchronise between them. */
+int gee_embed_noalloc(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32_t K, int laplacian,
+                      float *Z, int32_t *err, const gee_embed_opts *opts, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------
  * Propagation-blocked layout of a unit-weight CSR, and the pull pass over it.

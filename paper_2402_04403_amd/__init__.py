@@ -13,6 +13,8 @@ Functions mirror the C entry points:
 * :func:`csr_build` — ``gee_csr_build``: canonical symmetric CSR of A + A^T.
 * :func:`embed`    — ``gee_embed``: Z by the edge-parallel push form (COO) or the
   deterministic CSR-pull form (CSR), adjacency or Laplacian version.
+* :func:`embed_noalloc` — ``gee_embed_noalloc``: the same with the library's static
+  scratch instead of a workspace, for callers that cannot allocate.
 * :func:`embed_batch` — ``gee_embed_batch``: many label vectors over one graph, one CSR
   pass per group of up to 64 vectors.
 * :func:`copy`     — ``gee_copy``: the streaming copy probe used for measurement.
@@ -101,6 +103,8 @@ def load():
         lib.gee_embed_workspace.argtypes = [CooP, CsrP, i32, ci, OptP]
         lib.gee_embed.restype = ci
         lib.gee_embed.argtypes = [CooP, CsrP, vp, i32, ci, vp, vp, sz, vp, OptP, vp]
+        lib.gee_embed_noalloc.restype = ci
+        lib.gee_embed_noalloc.argtypes = [CooP, CsrP, vp, i32, ci, vp, vp, OptP, vp]
         PbP = ctypes.POINTER(Pb)
         lib.gee_pb_cells.restype = i64
         lib.gee_pb_cells.argtypes = [i64, i64]
@@ -517,6 +521,34 @@ def embed(labels: torch.Tensor, K: int, coo: DeviceCoo | None = None, csr: Devic
                       ctypes.byref(o), _stream(stream)), "gee_embed")
     if check:
         _check_err(err, "gee_embed")
+    return Z
+
+
+# Bytes of the library's static scratch used by gee_embed_noalloc (GEE_NOALLOC_SCRATCH_BYTES).
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def embed_noalloc(labels: torch.Tensor, K: int, Z: torch.Tensor, err: torch.Tensor, coo: DeviceCoo | None = None,
+                  csr: DeviceCsr | None = None, laplacian: bool = False, seg_len: int = 0, rows_per_window: int = 0,
+                  stream=None, check: bool = True) -> torch.Tensor:
+    """``gee_embed_noalloc``: the embedding with the library's static scratch in place of a
+    workspace, for callers that cannot allocate. The caller passes Z and the error word;
+    the library allocates nothing. Calls that overlap on one GPU race on the scratch."""
+    lib = load()
+    g = csr if csr is not None else coo
+    if g is None:
+        raise ValueError("embed_noalloc: give coo (push form) or csr (pull form)")
+    dev = (csr.row_ptr if csr is not None else coo.src).device
+    _need(labels, torch.int32, g.n, "labels", dev)
+    _need(Z, torch.float32, g.n * K, "Z", dev)
+    _need(err, torch.int32, 1, "err", dev)
+    cs = ctypes.byref(coo.struct()) if (coo is not None and csr is None) else None
+    rs = ctypes.byref(csr.struct()) if csr is not None else None
+    o = _opts(seg_len, rows_per_window)
+    _rc(lib.gee_embed_noalloc(cs, rs, _ptr(labels), K, 1 if laplacian else 0, _ptr(Z), _ptr(err), ctypes.byref(o),
+                              _stream(stream)), "gee_embed_noalloc")
+    if check:
+        _check_err(err, "gee_embed_noalloc")
     return Z
 
 

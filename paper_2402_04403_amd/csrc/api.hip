@@ -5,6 +5,7 @@
 #include <limits.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -371,6 +372,52 @@ int gee_embed(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32
               void *ws, size_t ws_bytes, int32_t *err, const gee_embed_opts *opts, hipStream_t stream)
 {
     return embed_impl(g, csr, labels, K, laplacian, Z, ws, ws_bytes, err, opts, stream, true);
+}
+
+} // extern "C"
+
+namespace {
+
+// Scratch of gee_embed_noalloc: one static array per GPU, which the code object brings
+// with it when the library is loaded on that device. Host code never passes the
+// array's name to a kernel (on the host it names a host-side stand-in): the device
+// address is looked up once per device with hipGetSymbolAddress and kept.
+__device__ __align__(256) unsigned char scratch[GEE_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_dev[kMaxDevices];
+
+// Device address of the current device's scratch (looked up on the first call there).
+int current_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GEE_EHIP;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GEE_EHIP;
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return GEE_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int gee_embed_noalloc(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int32_t K, int laplacian,
+                      float *Z, int32_t *err, const gee_embed_opts *opts, hipStream_t stream)
+{
+    Plan p;
+    int rc = make_plan(g, csr, K, laplacian, opts, &p);
+    if (rc != GEE_OK) return rc;
+    if (p.total > (size_t)GEE_NOALLOC_SCRATCH_BYTES) return GEE_EWORKSPACE;
+    void *ws = nullptr;
+    if ((rc = current_scratch(&ws)) != GEE_OK) return rc;
+    return embed_impl(g, csr, labels, K, laplacian, Z, ws, (size_t)GEE_NOALLOC_SCRATCH_BYTES, err, opts, stream,
+                      true);
 }
 
 int gee_embed_push_nonatomic(const gee_coo *g, const int32_t *labels, int32_t K, int laplacian, float *Z, void *ws,

@@ -154,6 +154,24 @@ def test_batch_argument_errors(lib):
     assert lib.gee_embed_batch(ctypes.byref(csr), ctypes.byref(st), FAKE, 1 << 30, FAKE, None, None) == gee.GEE_EINVAL
 
 
+def test_noalloc_argument_errors(lib):
+    """The static-scratch entry point checks its arguments as gee_embed does and refuses a
+    call whose workspace exceeds the scratch before touching the GPU."""
+    m = re.search(r"#define GEE_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == gee.NOALLOC_SCRATCH_BYTES
+    o = gee.EmbedOpts(0, 0, None, None)
+    assert lib.gee_embed_noalloc(None, None, FAKE, 5, 0, FAKE, FAKE, ctypes.byref(o), None) == gee.GEE_EINVAL
+    assert lib.gee_embed_noalloc(None, None, FAKE, 0, 0, FAKE, FAKE, ctypes.byref(o), None) == gee.GEE_EINVAL
+    big_n = gee.NOALLOC_SCRATCH_BYTES // 8 + 1  # Laplacian records alone: 8 bytes a vertex
+    big = gee.Coo(big_n, 0, None, None, None)
+    assert lib.gee_embed_workspace(ctypes.byref(big), None, 5, 1, ctypes.byref(o)) > gee.NOALLOC_SCRATCH_BYTES
+    assert lib.gee_embed_noalloc(ctypes.byref(big), None, FAKE, 5, 1, FAKE, FAKE, ctypes.byref(o), None) == \
+        gee.GEE_EWORKSPACE
+    rp = gee.Csr(big_n, 0, FAKE, None, None, 0, None)
+    assert lib.gee_embed_noalloc(None, ctypes.byref(rp), FAKE, 5, 1, FAKE, FAKE, ctypes.byref(o), None) == \
+        gee.GEE_EWORKSPACE
+
+
 def test_push_nonatomic_argument_errors(lib):
     """The atomics-off diagnostic needs the edge list (its push form has no CSR input)."""
     o = gee.EmbedOpts(0, 0, None, None)
