@@ -12,11 +12,16 @@ beside. The symmetric CSR and the layout are built once beforehand (per-graph
 preprocessing, reported as ``csr_build_ms`` and ``pb_build_ms``). Prints one JSON line
 on stdout; progress goes to stderr.
 
-``value`` is GEdges/s = s / step time. ``roofline`` prices the edge pass against HBM:
-algorithmic bytes per launch = 4 nnz (col) + 8 (n + 1) (row_ptr) + n (one read of each
-packed label) + 4 n K (Z written once), divided by the pass's mean duration measured
-with HIP events recorded around its kernels on the stream they run on. ``cpu_baseline``
-times the FP64 oracle, single thread, on a prefix of the same record list.
+``value`` is GEdges/s = s / step time. ``roofline`` prices the whole call against HBM:
+algorithmic bytes per call = 4 nnz (col) + 8 (n + 1) (row_ptr) + n (one read of each
+packed label) + 4 n K (Z written once) + 4 n (the class-count pass's read of the labels),
+divided by the call's mean duration measured with HIP events on the stream it runs on;
+``roofline.edge_pass`` gives the same for the edge pass alone (events around its
+kernels). ``cpu_baseline`` times the FP64 oracle, single thread, on a prefix of the same
+record list; ``cpu_parallel`` an edge-parallel FP64 pass with lock-free atomic adds on
+all the host's threads over every record. ``er_weighted`` times the weighted
+Erdos-Renyi workload (n = 2^22, s = 2^26, K = 50): CSR pull and push, adjacency and
+Laplacian, each with its roofline and the CPU baselines.
 """
 from __future__ import annotations
 
@@ -46,7 +51,8 @@ def log(msg):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--workload", choices=["rmat27", "batched", "er-sweep", "serve", "refine"], default="rmat27",
+    p.add_argument("--workload", choices=["rmat27", "batched", "er-sweep", "serve", "refine", "er-weighted"],
+                   default="rmat27",
                    help="rmat27: one label vector on the paper-scale R-MAT (the headline line); "
                         "batched: 64 label vectors on an R-MAT of scale 24, edge factor 16; "
                         "er-sweep: Erdos-Renyi graphs of growing size (the paper's Fig. 4 family); "
@@ -77,8 +83,13 @@ def parse():
     p.add_argument("--rows-per-window", type=int, default=0)
     p.add_argument("--hot-budget", type=int, default=-1, help="hot-vertex slots of the CSR (-1: library default)")
     p.add_argument("--push-steps", type=int, default=3, help="timed steps of each other form, reported beside")
-    p.add_argument("--cpu-records", type=int, default=400_000_000)
+    p.add_argument("--cpu-records", type=int, default=400_000_000,
+                   help="records of the one-thread oracle's timed prefix (the all-threads run takes every record)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--er-rw-sweep", type=lambda x: [int(v) for v in x.split(",") if v], default=[],
+                   help="weighted Erdos-Renyi leg: also time the pull form at these rows per window")
+    p.add_argument("--no-er-weighted", dest="er_weighted", action="store_false",
+                   help="rmat27: skip the weighted Erdos-Renyi leg (n = 2^22, s = 2^26, adjacency and Laplacian)")
     a = p.parse_args()
     if a.scale is None:
         a.scale = 27 if a.workload == "rmat27" else 24
@@ -139,6 +150,20 @@ def main():
         return main_serve(a)
     if a.workload == "refine":
         return main_refine(a)
+    if a.workload == "er-weighted":
+        import torch
+
+        import paper_2402_04403_amd as gee
+
+        gee.load()
+        leg = er_weighted_leg(a, gee, torch, torch.device("cuda:0"))
+        pull = leg["pull_adjacency"]
+        print(json.dumps({"metric": "GEdges/s", "value": pull["GEdges_per_s"], "unit": "GEdges/s", "n_gpus": 1,
+                          "steps": a.steps, "warmup": a.warmup, "ms_per_step": pull["ms_per_call"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                          "data": "synthetic", "config": {"workload": leg["workload"], "form": "csr-pull"},
+                          "roofline": pull["roofline"], "er_weighted": leg}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -153,8 +178,7 @@ def main():
     g = wl.graph
     n, s, K = g.n, g.s, wl.K
     log(f"generated {wl.name}: n={n} s={s} in {time.time() - t0:.1f}s")
-    cpu_src = g.src[: a.cpu_records].copy()
-    cpu_dst = g.dst[: a.cpu_records].copy()
+    host_src, host_dst = g.src, g.dst  # kept for the CPU baselines
     coo = gee.to_device(n, g.src, g.dst, None, device=dev)
     labels = torch.as_tensor(wl.labels).to(dev)
     Y_host = wl.labels
@@ -171,7 +195,7 @@ def main():
     e1.synchronize()
     csr_ms = e0.elapsed_ms(e1)
     torch.cuda.empty_cache()
-    nnz = csr.nnz
+    nnz, n_hot = csr.nnz, csr.n_hot
     log(f"csr built nnz={nnz} in {csr_ms:.1f} ms")
 
     copy_gbps = copy_probe(gee, torch, dev)
@@ -255,27 +279,30 @@ def main():
         bytes_alg = 8 * s + lab_bytes * n + 2 * 8 * s  # records once, labels once, two 8-byte atomic RMW
         kernel = "k_push"
         traffic, counters = None, None
-    achieved = bytes_alg / (hot_avg * 1e-3) / 1e9
-    step_bytes = bytes_alg + 4 * n + lab_bytes * n  # + the label read and pack of the counts kernel
+    # The whole call (class counts and label packing, weights, the edge pass) is what the
+    # headline times, so the roofline prices the call: the edge pass's algorithmic bytes
+    # plus the counts kernel's read of the labels; the edge pass alone is reported beside.
+    edge_achieved = bytes_alg / (hot_avg * 1e-3) / 1e9
+    step_bytes = bytes_alg + 4 * n  # + the counts kernel's read of the int32 labels
+    achieved = step_bytes / (step_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": kernel,
-                "bytes_alg_per_launch": int(bytes_alg), "kernel_ms": round(hot_avg, 4)}
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": f"whole call: k_counts + k_weights + {kernel}",
+                "bytes_alg_per_launch": int(step_bytes), "kernel_ms": round(step_ms, 4),
+                "edge_pass": {"kernel": kernel, "bytes_alg_per_launch": int(bytes_alg), "kernel_ms": round(hot_avg, 4),
+                              "achieved": round(edge_achieved, 1), "frac": round(edge_achieved / HBM_PEAK_GBPS, 4)}}
 
-    cpu = None
+    cpu, cpu_par = None, None
     if not a.no_cpu_baseline and a.cpu_records > 0:
-        import oracle
+        cpu, cpu_par = cpu_baselines(n, host_src, host_dst, None, Y_host, K, False, a.cpu_records,
+                                     f"the same R-MAT list, all n={n:,} vertices and labels, K={K}, adjacency")
+    del host_src, host_dst
 
-        ns = int(cpu_src.shape[0])
-        log(f"cpu baseline: oracle on the first {ns} records ...")
-        c_t0 = time.perf_counter()
-        oracle.embed(n, cpu_src, cpu_dst, None, Y_host, K, False)
-        c_t = time.perf_counter() - c_t0
-        cpu = {"value": round(ns / c_t / 1e9, 6), "unit": "GEdges/s", "cores": 1, "kind": "oracle",
-               "seconds": round(c_t, 2),
-               "sample": f"first {ns:,} of {s:,} records of the same R-MAT list, all n={n:,} vertices and labels, "
-                         f"K={K}, adjacency; FP64 Algorithm 1, one thread, Z (n x K FP64) allocated zeroed "
-                         f"and first touched inside the timed call"}
-        log(f"cpu baseline {cpu['value']} GEdges/s in {c_t:.1f}s")
+    er_leg = None
+    if a.er_weighted:
+        del Z, ws, pb, csr, coo
+        torch.cuda.empty_cache()
+        er_leg = er_weighted_leg(a, gee, torch, dev)
 
     out = {
         "metric": "GEdges/s",
@@ -295,21 +322,156 @@ def main():
             "n": n, "s": s, "nnz": nnz, "K": K,
             "form": {"pb": "propagation-blocked pull", "pull": "csr-pull", "push": "edge-push"}[a.form],
             "seg_len": a.seg_len or 16384, "rows_per_window": a.rows_per_window or "auto",
-            "hot_slots": csr.n_hot,
+            "hot_slots": n_hot,
             "csr_build_ms": round(csr_ms, 2),
             "pb_build_ms": None if pb_ms is None else round(pb_ms, 2),
-            "step_hbm_frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "copy_probe_GBps": round(copy_gbps, 1),
             **{f"{k}_ms_per_step": round(v, 3) for k, v in beside.items()},
             "paper_context": "6.42 s for Friendster (1.8B edges) on a 24-core Xeon Platinum 8259CL, Table I",
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_parallel": cpu_par,
+        "er_weighted": er_leg,
     }
     if counters is not None:
         out["config"]["counters_file"] = os.path.relpath(PROFILE_COUNTERS if a.form == "pull" else PROFILE_COUNTERS_PB,
                                                          ROOT)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baselines(n, src, dst, w, Y, K, lap, prefix, what):
+    """The FP64 oracle on one thread over a prefix of the records (Z allocated inside the
+    timed call, as the oracle does), and the edge-parallel FP64 atomic pass on all the
+    host threads over every record (Z zeroed, its pages brought in, before the timed call)."""
+    import cpu_baseline
+    import oracle
+
+    s = int(src.shape[0])
+    ns = min(int(prefix), s)
+    log(f"cpu baseline: oracle on the first {ns} records ...")
+    c_t0 = time.perf_counter()
+    oracle.embed(n, src[:ns], dst[:ns], None if w is None else w[:ns], Y, K, lap)
+    c_t = time.perf_counter() - c_t0
+    whole = "all" if ns == s else f"the first {ns:,} of"
+    cpu = {"value": round(ns / c_t / 1e9, 6), "unit": "GEdges/s", "cores": 1, "kind": "oracle",
+           "seconds": round(c_t, 2),
+           "sample": f"{whole} {s:,} records of {what}; FP64 Algorithm 1, one thread, Z (n x K FP64) "
+                     f"allocated zeroed and first touched inside the timed call"
+                     + ("" if ns == s else "; a prefix, so the rate is an estimate of a full pass (its Z "
+                                           "allocation is paid over fewer records: a lower bound on the rate)")}
+    log(f"cpu baseline {cpu['value']} GEdges/s in {c_t:.1f}s")
+    threads = cpu_baseline.host_threads()
+    Zc = cpu_baseline.zeros(n, K, threads)
+    log(f"cpu parallel: {threads} threads over all {s} records ...")
+    c_t0 = time.perf_counter()
+    cpu_baseline.embed_atomic(n, src, dst, w, Y, K, laplacian=lap, threads=threads, Z=Zc)
+    c_t = time.perf_counter() - c_t0
+    del Zc
+    par = {"value": round(s / c_t / 1e9, 6), "unit": "GEdges/s", "cores": threads,
+           "kind": "edge-parallel FP64 lock-free atomic adds (the paper's Section III design), not the oracle",
+           "cpu_model": cpu_baseline.cpu_model(), "seconds": round(c_t, 2),
+           "sample": f"all {s:,} records of {what}; Z (n x K FP64) zeroed by the threads before the timed call"}
+    log(f"cpu parallel {par['value']} GEdges/s in {c_t:.1f}s on {threads} threads")
+    return cpu, par
+
+
+def er_weighted_leg(a, gee, torch, dev):
+    """The weighted Erdos-Renyi workload (n = 2^22, s = 2^26 records, weights on the 2^-24
+    grid in (0, 1], K = 50 uniform classes, 5% unknown): the CSR pull and the push form,
+    adjacency and Laplacian versions, each call timed with HIP events; the roofline of each
+    pull call prices it in algorithmic bytes (below), and the CPU baselines run on the same
+    records."""
+    import numpy as np
+
+    import gen
+
+    t0 = time.time()
+    wl = gen.er_weighted()
+    g = wl.graph
+    n, s, K = g.n, g.s, wl.K
+    coo = gee.to_device(n, g.src, g.dst, g.w, device=dev)
+    labels = torch.as_tensor(wl.labels).to(dev)
+    csr = gee.csr_build(coo, check=False)
+    torch.cuda.synchronize()
+    nnz = csr.nnz
+    log(f"er-weighted: n={n} s={s} nnz={nnz} ready in {time.time() - t0:.1f}s")
+    Z = torch.empty((n, K), dtype=torch.float32, device=dev)
+    err = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = {"workload": f"er-n2^22-s2^26-K{K}-weighted", "n": n, "s": s, "nnz": nnz, "K": K}
+    for lap in (False, True):
+        ver = "laplacian" if lap else "adjacency"
+        for form in ("pull", "push"):
+            ws = torch.empty(max(gee.embed_workspace_bytes(K, coo=coo if form == "push" else None,
+                                                           csr=csr if form == "pull" else None, laplacian=lap,
+                                                           rows_per_window=rw)
+                                 for rw in [a.rows_per_window] + a.er_rw_sweep),
+                             dtype=torch.uint8, device=dev)
+
+            def call(events=None, rw=a.rows_per_window):
+                gee.embed(labels, K, coo=coo, csr=csr if form == "pull" else None, laplacian=lap, Z=Z, ws=ws,
+                          err=err, rows_per_window=rw if form == "pull" else 0, events=events, check=False)
+
+            for _ in range(a.warmup):
+                call()
+            torch.cuda.synchronize()
+            hot = [(gee.HipEvent(), gee.HipEvent()) for _ in range(a.steps)]
+            c0, c1 = gee.HipEvent(), gee.HipEvent()
+            c0.record()
+            for i in range(a.steps):
+                call(events=hot[i])
+            c1.record()
+            torch.cuda.synchronize()
+            if int(err.item()) != 0:
+                raise SystemExit(f"er-weighted {form} {ver}: error {int(err.item())}")
+            ms = c0.elapsed_ms(c1) / a.steps
+            edge_ms = float(np.mean([b.elapsed_ms(e) for b, e in hot]))
+            if form == "pull":
+                # records' columns and weights once, row pointers, one read of each label
+                # (Laplacian: an 8-byte record of class and d^-1/2), Z written once, and the
+                # counts kernel's read of the int32 labels; the Laplacian adds the degree pass
+                # (weights and row pointers again, degrees written) and its label records
+                b_alg = 8 * nnz + 8 * (n + 1) + n + 4 * n * K + 4 * n
+                if lap:
+                    b_alg += 4 * nnz + 8 * (n + 1) + 8 * n + 8 * n
+            else:
+                # records once (8 + 4 bytes), two 4-byte atomic read-modify-writes into Z per
+                # record, Z zeroed and scaled, labels read; the Laplacian adds the degree pass
+                b_alg = 12 * s + 16 * s + 4 * n * K + 8 * n * K + 4 * n + n
+                if lap:
+                    b_alg += 12 * s + 8 * n + 16 * n
+            ach = b_alg / (ms * 1e-3) / 1e9
+            out[f"{form}_{ver}"] = {"ms_per_call": round(ms, 4), "edge_pass_ms": round(edge_ms, 4),
+                                   "GEdges_per_s": round(s / (ms * 1e-3) / 1e9, 3),
+                                   "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
+                                                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
+                                                "bytes_alg_per_launch": int(b_alg)}}
+            log(f"er-weighted {form} {ver}: {ms:.4f} ms per call ({edge_ms:.4f} edge pass), "
+                f"{ach / HBM_PEAK_GBPS:.3f} of peak")
+            if form == "pull" and a.er_rw_sweep:
+                sweep = {}
+                for rw in a.er_rw_sweep:
+                    call(rw=rw)
+                    s0, s1 = gee.HipEvent(), gee.HipEvent()
+                    s0.record()
+                    for _ in range(a.steps):
+                        call(rw=rw)
+                    s1.record()
+                    s1.synchronize()
+                    sweep[rw] = round(s0.elapsed_ms(s1) / a.steps, 4)
+                out[f"{form}_{ver}"]["rows_per_window_sweep_ms"] = sweep
+                log(f"er-weighted {form} {ver}: rows per window {sweep}")
+            del ws
+    del Z, csr, coo
+    torch.cuda.empty_cache()
+    if not a.no_cpu_baseline:
+        for lap in (False, True):
+            ver = "laplacian" if lap else "adjacency"
+            cpu, par = cpu_baselines(n, g.src, g.dst, g.w, wl.labels, K, lap, s,
+                                     f"the weighted Erdos-Renyi list, K={K}, {ver}")
+            out[f"cpu_baseline_{ver}"] = cpu
+            out[f"cpu_parallel_{ver}"] = par
+    return out
 
 
 def main_batched(a):
@@ -735,9 +897,10 @@ def main_serve(a):
     (1) plain mode (one job at a time, one gee_embed per vector) with every job ready at
     t = 0, which gives its capacity in jobs/s; (2) batched mode (continuous batching over
     4 streams) likewise; (3) Poisson arrivals at 0.5x and 0.9x the plain capacity through
-    both modes. Latency = arrival to device completion of the job's launch; labels are
-    uploaded from pinned host memory inside it. ``value`` is the batched mode's p99
-    latency at 0.9x load."""
+    both modes; (4) Poisson arrivals at 0.5x and 0.9x the batched loop's own saturated
+    rate through the batched loop. Latency = arrival to device completion of the job's
+    launch; labels are uploaded from pinned host memory inside it. ``value`` is the
+    batched mode's p99 latency at 0.9x the plain capacity."""
     import numpy as np
     import torch
 
@@ -824,6 +987,15 @@ def main_serve(a):
         log(f"load {f}x: plain p50/p99 {L['plain']['p50_ms']}/{L['plain']['p99_ms']} ms, "
             f"batched {L['batched']['p50_ms']}/{L['batched']['p99_ms']} ms"
             + (f", packed {L['packed']['p50_ms']}/{L['packed']['p99_ms']} ms" if pk else ""))
+    # the batched loop under its own load: Poisson arrivals at fractions of its saturated rate
+    bcap = batched_sat["jobs_per_s"]
+    own = {}
+    for f in (0.5, 0.9):
+        arr = gen.poisson_arrivals(f * bcap, len(jobs))
+        own[f"{f}x"] = {"rate_jobs_per_s": round(f * bcap, 2), "batched": run("batched", arr)}
+        B_ = own[f"{f}x"]["batched"]
+        log(f"batched at {f}x its own capacity ({f * bcap:.0f} jobs/s): p50/p99 {B_['p50_ms']}/{B_['p99_ms']} ms, "
+            f"{B_['G_label_edges_per_s']} G label-edges/s")
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -863,7 +1035,7 @@ def main_serve(a):
                    "label_edges": int(work), "budget_GB": a.serve_budget_gb, "streams": a.serve_streams,
                    "saturation": {"plain": plain_sat, "batched": batched_sat, "packed": packed_sat,
                                   "speedup": round(plain_sat["seconds"] / batched_sat["seconds"], 3)},
-                   "poisson": loads},
+                   "poisson": loads, "poisson_batched_capacity": own},
         "roofline": {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": None,
                      "traffic": None, "kernel": "served mix: latency-bound by launches on small graphs; the "
                      "throughput kernels are priced on their own workloads"},

@@ -34,6 +34,11 @@ in arrival order.
 
 Latency of a job = device completion of its launch minus its arrival, both on the
 host clock (the completion is read from HIP events against a reference event).
+
+A job that cannot be served comes back from ``poll`` as a ``Done`` with a nonzero
+``error`` and no result, and the loop keeps serving: ``ERR_BUDGET`` when its launch can
+never fit the HBM budget beside its graph, or the library's status code when the library
+refuses the launch it is in (it checks arguments before queuing work).
 """
 from __future__ import annotations
 
@@ -44,8 +49,12 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from . import (DEFAULT_HOT_BUDGET, DeviceCsr, HipEvent, csr_build, embed, embed_batch,
+from . import (DEFAULT_HOT_BUDGET, DeviceCsr, GeeError, HipEvent, csr_build, embed, embed_batch,
                embed_workspace_bytes, to_device)
+
+# Done.error of a job whose launch can never fit the HBM budget beside its graph (the
+# library's own status codes are 0 and negative numbers above -100).
+ERR_BUDGET = -100
 
 
 @dataclass
@@ -190,6 +199,13 @@ class Server:
         self._err_dev = torch.zeros(self.MAX_INFLIGHT, dtype=torch.int32, device=self.dev)
         self._err_host = torch.zeros(self.MAX_INFLIGHT, dtype=torch.int32, pin_memory=True)
         self._free_slots = list(range(self.MAX_INFLIGHT - 1, -1, -1))
+        # slots of refused launches, each freed once an event recorded behind the work
+        # queued before the refusal has completed
+        self._slot_wait: list[tuple[HipEvent, int]] = []
+        # jobs finished or refused but not yet returned (a poll that raised keeps them)
+        self._ready: list[Done] = []
+        self._admitted_last = 0
+        self._last_stream = 0
         # one small launch on every stream, so that the first jobs do not wait while the
         # runtime sets up the streams' queues
         for st in self.streams:
@@ -246,6 +262,11 @@ class Server:
             self.evictions += 1
         return True
 
+    def _unit_bytes(self, gid: int) -> int:
+        """Resident bytes of the CSR that serves unit gid (a graph, or a pack of graphs)."""
+        parts = [self.pool[m] for m in self.members[gid]] if gid < 0 else [self.pool[gid]]
+        return self._graph_bytes(sum(p[0] for p in parts), sum(len(p[1]) for p in parts))
+
     def _resident(self, gid: int) -> _Graph | None:
         g = self.resident.get(gid)
         if g is not None:
@@ -301,7 +322,7 @@ class Server:
         self.pending.append(req)
 
     def idle(self) -> bool:
-        return not self.pending and not self.inflight
+        return not self.pending and not self.inflight and not self._ready
 
     def _host_time(self, ev: HipEvent) -> float:
         return self.ref_host + self.ref.elapsed_ms(ev) * 1e-3
@@ -322,19 +343,17 @@ class Server:
                 break  # the launch is full; the job waits for the next poll
             g = self._resident(u)
             if g is None:
+                if self._unit_bytes(u) > self.budget:  # the graph alone can never fit
+                    self.pending.popleft()
+                    self._ready.append(self._refused(r, ERR_BUDGET))
+                    continue
                 break
             need = self._launch_bytes(g, r.Ks, r.laplacian)
             if need > self.budget - g.bytes:
-                # the job can never run: drop it, and put the jobs admitted before it in
-                # this poll back at the head of the queue, in arrival order
+                # the job can never run: it is finished with an error and the loop goes on
                 self.pending.popleft()
-                for q, gq, b in reversed(out):
-                    self.used -= b
-                    gq.busy -= 1
-                    self.pending.appendleft(q)
-                exc = ValueError(f"job {r.jid} needs {need} bytes beside its graph; the budget is {self.budget}")
-                exc.refused_jobs = [r.jid]
-                raise exc
+                self._ready.append(self._refused(r, ERR_BUDGET))
+                continue
             if self.used + need > self.budget and not self._evict_for(need, u):
                 break
             self.pending.popleft()
@@ -343,6 +362,21 @@ class Server:
             gids[u] = gids.get(u, 0) + len(r.Ks)
             out.append((r, g, need))
         return out
+
+    def _hold_slot(self, slot: int):
+        """Keep a refused launch's error slot out of use until the work queued before the
+        refusal on its stream has completed (if even the event cannot be recorded, the slot
+        stays out of use)."""
+        try:
+            ev = HipEvent()
+            ev.record(self.streams[self._last_stream])
+        except Exception:
+            return
+        self._slot_wait.append((ev, slot))
+
+    def _refused(self, r: Request, code: int) -> Done:
+        n, src, _ = self.pool[r.gid]
+        return Done(r.jid, r.gid, r.arrival, time.perf_counter(), len(src), len(r.Ks), int(code), None)
 
     def _launch(self, group: list, slot: int):
         g = group[0][1]
@@ -357,6 +391,7 @@ class Server:
             load[L.stream] += L.work
         si = min(range(len(self.streams)), key=lambda i: (load[i], (i - self._next_stream) % len(self.streams)))
         self._next_stream = (si + 1) % len(self.streams)
+        self._last_stream = si
         stream = self.streams[si]
         laps = [l for r in reqs for l in r.laplacian]
         zoff, acc = [], 0
@@ -446,8 +481,26 @@ class Server:
                                      Z=Z if self.keep else None, zoff=zoff))
 
     def poll(self) -> list:
-        """Retire finished launches, admit and launch pending jobs; returns the jobs finished."""
-        finished = []
+        """Retire finished launches, admit and launch pending jobs; returns the jobs finished
+        (those refused included, with their error code)."""
+        finished, self._ready = self._ready, []
+        try:
+            self._poll(finished)
+        except BaseException:
+            self._ready = finished + self._ready  # returned by the next poll
+            raise
+        finished += self._ready
+        self._ready = []
+        return finished
+
+    def _poll(self, finished: list):
+        waiting = []
+        for ev, slot in self._slot_wait:
+            if ev.done():
+                self._free_slots.append(slot)
+            else:
+                waiting.append((ev, slot))
+        self._slot_wait = waiting
         still = []
         for L in self.inflight:
             if not L.event.done():
@@ -469,6 +522,7 @@ class Server:
             L.graph.last_use = t
         self.inflight = still
         admitted = self._admit()
+        self._admitted_last = len(admitted)
         by_graph = collections.OrderedDict()
         for item in admitted:
             by_graph.setdefault(item[1].gid, []).append(item)
@@ -477,25 +531,40 @@ class Server:
             slot = self._free_slots.pop()
             try:
                 self._launch(group, slot)
-            except Exception as exc:
-                # a refused call (the library checks its arguments before queuing work):
-                # give back the memory and graph of its jobs and of the groups not yet
-                # launched, whose jobs wait again at the head of the queue in arrival
-                # order; the refused launch's jobs are dropped and named on the exception.
-                # Its error slot stays out of use, since work queued before the refusal
-                # may still write it (buffers that work uses are held by torch's allocator
-                # until the stream passes them).
+            except GeeError as exc:
+                # the library refused a call of this launch (it checks its arguments before
+                # queuing work): its jobs finish with the library's code, their memory and
+                # graph claim are given back, and the other launches go ahead. The error
+                # slot returns to use once the work queued on the stream before the refusal
+                # (which may write it) has completed; buffers that work uses are held by
+                # torch's allocator until the stream passes them.
+                self.used -= sum(b for _, _, b in group)
+                group[0][1].busy -= len(group)
+                self._hold_slot(slot)
+                self._ready += [self._refused(r, exc.code) for r, _, _ in group]
+            except BaseException as exc:
+                # anything else ends the poll: the memory and graph claims of this launch and
+                # of those not yet made are given back, their jobs wait again at the head of
+                # the queue in arrival order, and the exception names this launch's jobs
                 for grp in groups[gi:]:
                     self.used -= sum(b for _, _, b in grp)
                     grp[0][1].busy -= len(grp)
-                later = {id(item) for grp in groups[gi + 1:] for item in grp}
-                self.pending.extendleft(reversed([item[0] for item in admitted if id(item) in later]))
+                self.pending.extendleft(reversed([item[0] for grp in groups[gi:] for item in grp]))
+                self._hold_slot(slot)
                 exc.refused_jobs = [r.jid for r, _, _ in group]
                 raise
-        return finished
 
     def drain(self) -> list:
+        """Poll until every submitted job has come back. Raises RuntimeError if jobs are
+        pending that no poll can ever admit (nothing in flight, no slot coming free, and
+        the last poll admitted and returned nothing)."""
         out = []
         while not self.idle():
-            out += self.poll()
+            got = self.poll()
+            out += got
+            if (not got and not self._admitted_last and self.pending and not self.inflight
+                    and not self._slot_wait):
+                raise RuntimeError(f"{len(self.pending)} pending jobs cannot be admitted "
+                                   f"({len(self._free_slots)} free launch slots, {self.used} of "
+                                   f"{self.budget} bytes in use)")
         return out

@@ -3,8 +3,9 @@ K = 50) in full against the oracle, the paper-scale R-MAT (scale 27, edge factor
 14, 1,879,048,192 records) on sampled rows, in the launch configuration the
 benchmark times (default segment length and window), with the propagation-blocked
 pass compared in full against the pull pass, the batched workload (R-MAT scale 24,
-64 vectors) on sampled rows of four vectors, and the serving pool's first 60 jobs through
-the serving loop."""
+64 vectors) on sampled rows of every vector, and the serving pool's first 60 jobs through
+the serving loop. At the paper scale every row and every column of the push and pull
+forms is also checked against sums taken on the host from the records."""
 import time
 
 import numpy as np
@@ -51,6 +52,59 @@ def test_er_weighted_full_parity():
         del Zo, Zp, Za
 
 
+def labelled_neighbour_sums(n, src, dst, Y, K, chunk=1 << 28):
+    """Host sums over the records, for unit weights (Algorithm 1 with every W factor taken
+    out): rows[u] = the labelled entries of row u of A + A^T (its records' other endpoints
+    with a class), cols[k - 1] = the sum of the degrees of the class-k vertices (every
+    entry (u, v) with Y(v) = k counted once); int64, exact."""
+    rows = np.zeros(n, np.int64)
+    deg = np.zeros(n, np.int64)
+    for a in range(0, len(src), chunk):
+        s_, d_ = src[a:a + chunk], dst[a:a + chunk]
+        rows += np.bincount(s_[Y[d_] > 0], minlength=n)
+        rows += np.bincount(d_[Y[s_] > 0], minlength=n)
+        deg += np.bincount(s_, minlength=n)
+        deg += np.bincount(d_, minlength=n)
+    cols = np.bincount(Y, weights=deg, minlength=K + 1)  # FP64 sums of integers below 2^53: exact
+    return rows, cols[1:].astype(np.int64)
+
+
+def check_all_rows(Z, counts, want_rows, want_cols, what, chunk=1 << 22):
+    """For unit weights Z[u, k-1] is count(u, k) / n_k rounded once to FP32, with count(u, k)
+    the number of row u's entries of class k (below 2^23 here), so Z * n_k rounds back to
+    that integer. Every row's recovered counts must add up to its labelled entries and
+    every column's to its class's degree sum, exactly. The FP64 sums of Z * n_k must
+    also meet the row bar (1e-5 relative) and, per column, the bound of one FP32
+    rounding per element (2^-23 relative covers the 2^-24 rounding of every term; the
+    roundings of equal counts do not cancel, so a column cannot be held much tighter)."""
+    n, K = Z.shape
+    nk = counts[1:].to(torch.float64)
+    wr = torch.as_tensor(want_rows, device=Z.device)
+    col_int = torch.zeros(K, dtype=torch.int64, device=Z.device)
+    col_fp = torch.zeros(K, dtype=torch.float64, device=Z.device)
+    worst = 0.0
+    for a in range(0, n, chunk):
+        x = Z[a:a + chunk].to(torch.float64) * nk
+        c = torch.round(x)
+        assert bool((c >= 0).all()), f"{what}: negative entry in rows {a}.."
+        row_int = c.to(torch.int64).sum(1)
+        bad = torch.nonzero(row_int != wr[a:a + chunk])
+        assert bad.numel() == 0, f"{what}: row {a + int(bad[0, 0])} counts {int(row_int[bad[0, 0]])} " \
+                                 f"labelled entries, the records give {int(wr[a + int(bad[0, 0])])}"
+        row_fp = x.sum(1)
+        ref = wr[a:a + chunk].to(torch.float64)
+        e = ((row_fp - ref).abs() / ref.clamp(min=1)).max().item()
+        worst = max(worst, e)
+        col_int += c.to(torch.int64).sum(0)
+        col_fp += x.sum(0)
+    assert worst <= 1e-5, f"{what}: row sum relative error {worst:.3e}"
+    wc = torch.as_tensor(want_cols, device=Z.device)
+    assert torch.equal(col_int, wc), f"{what}: column counts differ from the class degree sums"
+    ce = ((col_fp - wc.to(torch.float64)).abs() / wc.to(torch.float64).clamp(min=1)).max().item()
+    assert ce <= 2.0 ** -23, f"{what}: column sum relative error {ce:.3e}"
+    announce(f"  {what}: all {n} rows and {K} columns agree (row sums {worst:.1e}, columns {ce:.1e})")
+
+
 @pytest.mark.slow
 @pytest.mark.timeout(1200)
 def test_rmat_paper_scale_sampled_rows():
@@ -85,8 +139,18 @@ def test_rmat_paper_scale_sampled_rows():
     announce(f"  propagation-blocked pass equal in full {time.time() - t0:.1f}s")
     Za = gee.embed(labels, wl.K, coo=coo)
     push_rows = Za[idx].cpu().numpy()
-    del Za
     announce(f"  push done {time.time() - t0:.1f}s")
+    # every row and every column of both forms against sums taken on the host from the
+    # records (the propagation-blocked Z equals the pull form's bit for bit)
+    want_rows, want_cols = labelled_neighbour_sums(g.n, g.src, g.dst, wl.labels, wl.K)
+    announce(f"  host invariants {time.time() - t0:.1f}s")
+    cnt = torch.as_tensor(oracle.counts(wl.labels, wl.K), device=DEV)
+    for name, Zf in (("push", Za), ("pull", gee.embed(labels, wl.K, csr=csr))):
+        check_all_rows(Zf, cnt, want_rows, want_cols, name)
+        del Zf
+        torch.cuda.empty_cache()
+    del Za
+    announce(f"  all-row invariants {time.time() - t0:.1f}s")
     Zo = oracle.embed_rows(g.n, g.src, g.dst, None, wl.labels, wl.K, False, rows)
     announce(f"  oracle rows {time.time() - t0:.1f}s")
     assert_parity(pull_rows, Zo, what="pull, sampled rows")
@@ -101,8 +165,8 @@ def test_batched_full_size_sampled_rows():
     """The batched benchmark's workload (R-MAT scale 24, edge factor 16, 64 vectors, K
     log-uniform on [2, 256], even vectors adjacency and odd Laplacian) in the launch
     configuration it times (default segment length, 64 vectors per group): sampled rows
-    of two adjacency and two Laplacian vectors against the oracle, and adjacency vector 0
-    bit for bit against a single pull call."""
+    of every vector against the oracle, and adjacency vector 0 bit for bit against a
+    single pull call."""
     t0 = time.time()
     wl = gen.rmat_batched()
     g = wl.graph
@@ -121,7 +185,7 @@ def test_batched_full_size_sampled_rows():
     iso = torch.nonzero(deg == 0)[:32, 0].cpu().numpy()
     rows = np.unique(np.r_[rng.choice(g.n, 2000, replace=False), top, iso]).astype(np.int64)
     idx = torch.as_tensor(rows, device=DEV)
-    picked = {b: Z[idx, zoff[b]:zoff[b] + wl.Ks[b]].cpu().numpy() for b in (0, 1, 32, 33)}
+    picked = {b: Z[idx, zoff[b]:zoff[b] + wl.Ks[b]].cpu().numpy() for b in range(len(wl.Ks))}
     del Z
     torch.cuda.empty_cache()
     Zs = gee.embed(labels[0], wl.Ks[0], csr=csr)

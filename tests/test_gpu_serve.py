@@ -1,6 +1,7 @@
 """Serving loop: a job's Z is the same alone and in the mix (bit for bit), plain and batched
 modes agree, graphs are evicted and rebuilt under a small HBM budget, and a job that can
-never fit is refused."""
+never fit, or that the library refuses, comes back with an error while the loop keeps
+serving."""
 import time
 
 import numpy as np
@@ -11,7 +12,7 @@ import gen
 import oracle
 import paper_2402_04403_amd as gee
 from gpu_util import announce, assert_parity
-from paper_2402_04403_amd.serve import Request, Server
+from paper_2402_04403_amd.serve import ERR_BUDGET, Request, Server
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
@@ -92,20 +93,51 @@ def test_small_budget_evicts_and_refuses():
     ref = _run(Server(graphs, 8 << 30, keep_results=True, hot_budget=0), _reqs(graphs, jobs))
     for j in jobs:
         assert torch.equal(got[j.jid].Z.view(torch.int32), ref[j.jid].Z.view(torch.int32))
-    # a job that can never fit is dropped with an error; a job admitted before it in the
-    # same poll waits again and runs
+    # a job that can never fit comes back with an error and no result; the jobs around it
+    # run as usual
     small = gen.Job(100, 0, [2], [0.5], False, 999)
+    small2 = gen.Job(101, 0, [3], [0.2], True, 998)
     assert probe._launch_bytes(g, [2], [False]) <= L // 2
-    tiny = Server(graphs, G + L // 2, hot_budget=0)
-    tiny.submit(_reqs(graphs, [small])[0])
-    tiny.submit(_reqs(graphs, jobs[:1])[0])
-    with pytest.raises(ValueError) as info:
-        tiny.poll()
-    assert info.value.refused_jobs == [jobs[0].jid]
-    assert [r.jid for r in tiny.pending] == [small.jid] and tiny.resident[0].busy == 0
-    assert tiny.used == sum(x.bytes for x in tiny.resident.values())
+    tiny = Server(graphs, G + L // 2, hot_budget=0, keep_results=True)
+    for r in _reqs(graphs, [small, jobs[0], small2]):
+        tiny.submit(r)
     done = {d.jid: d for d in tiny.drain()}
-    assert list(done) == [small.jid] and done[small.jid].error == 0
+    assert sorted(done) == sorted([small.jid, jobs[0].jid, small2.jid])
+    assert done[jobs[0].jid].error == ERR_BUDGET and done[jobs[0].jid].Z is None
+    assert done[small.jid].error == 0 and done[small2.jid].error == 0
+    assert tiny.resident[0].busy == 0 and tiny.used == sum(x.bytes for x in tiny.resident.values())
+    ref = _run(Server(graphs, 8 << 30, keep_results=True, hot_budget=0), _reqs(graphs, [small, small2]))
+    for j in (small, small2):
+        assert torch.equal(done[j.jid].Z.view(torch.int32), ref[j.jid].Z.view(torch.int32))
+    # a graph that alone exceeds the budget: its job is refused the same way
+    nograph = Server(graphs, G // 2, hot_budget=0)
+    nograph.submit(_reqs(graphs, [small])[0])
+    done = nograph.drain()
+    assert [(d.jid, d.error) for d in done] == [(small.jid, ERR_BUDGET)]
+
+
+def test_refusal_beside_a_launch_in_flight():
+    """A job refused at admission while another launch is in flight: the poll that refuses it
+    also returns whatever it retired, and the in-flight job's result still comes back."""
+    pool, graphs, jobs = _pool()
+    big = [j for j in jobs if j.gid == 0][0]
+    srv = Server(graphs, 8 << 30, keep_results=True)
+    srv.warm([0])
+    g = srv.resident[0]
+    first = _reqs(graphs, [big])[0]
+    first.arrival = time.perf_counter()
+    srv.submit(first)
+    assert srv.poll() == [] and len(srv.inflight) == 1
+    hog = Request(500, 0, [4096] * 4, [False] * 4, torch.zeros((4, graphs[0][0]), dtype=torch.int32).pin_memory(),
+                  time.perf_counter())
+    srv.budget = g.bytes + srv._launch_bytes(g, big.Ks, [big.laplacian] * len(big.Ks))
+    assert srv._launch_bytes(g, hog.Ks, hog.laplacian) > srv.budget - g.bytes  # the hog never fits
+    srv.submit(hog)
+    done = {d.jid: d for d in srv.drain()}
+    assert sorted(done) == [big.jid, 500]
+    assert done[500].error == ERR_BUDGET and done[big.jid].error == 0
+    ref = _run(Server(graphs, 8 << 30, keep_results=True), _reqs(graphs, [big]))
+    assert torch.equal(done[big.jid].Z.view(torch.int32), ref[big.jid].Z.view(torch.int32))
 
 
 def test_routed_jobs_alone_equal_in_the_mix():
@@ -181,25 +213,26 @@ def test_packed_small_graphs():
 
 
 def test_refused_launch_returns_its_memory():
-    """A job the library refuses (a class count beyond the batched limit) raises from the
-    poll that launches it, and the server gives back the memory and graph it had taken."""
+    """A job the library refuses (a class count beyond the batched limit) comes back from the
+    poll that launches it with the library's code; the server gives back the memory and graph
+    it had taken, the job launched after it in the same poll runs, and the refused launch's
+    error slot returns to use once its stream has passed the refusal."""
     pool, graphs, jobs = _pool()
-    srv = Server(graphs, 8 << 30)
+    srv = Server(graphs, 8 << 30, keep_results=True)
     srv.warm([0, 2])
     used = srv.used
+    slots = len(srv._free_slots)
     n = graphs[0][0]
     srv.submit(Request(999, 0, [5000], [False], torch.ones((1, n), dtype=torch.int32).pin_memory(), time.perf_counter()))
-    # a job on another graph, admitted in the same poll and launched after the refused one,
-    # waits again in the queue and completes on the next polls
     other = _reqs(graphs, [j for j in jobs if j.gid == 2][:1])[0]
     srv.submit(other)
-    with pytest.raises(gee.GeeError) as info:
-        srv.poll()
-    assert info.value.refused_jobs == [999]
-    assert srv.used == used and srv.resident[0].busy == 0 and srv.resident[2].busy == 0
-    assert [r.jid for r in srv.pending] == [other.jid]
     done = {d.jid: d for d in srv.drain()}
-    assert list(done) == [other.jid] and done[other.jid].error == 0
+    assert sorted(done) == sorted([999, other.jid])
+    assert done[999].error == gee.GEE_EINVAL and done[999].Z is None and done[other.jid].error == 0
+    assert srv.used == used and srv.resident[0].busy == 0 and srv.resident[2].busy == 0
+    torch.cuda.synchronize()
+    srv.poll()
+    assert len(srv._free_slots) == slots and not srv._slot_wait
     good = _reqs(graphs, [j for j in jobs if j.gid == 0][:2])
     done = _run(srv, good)
     assert len(done) == len(good) and all(d.error == 0 for d in done.values())
