@@ -133,11 +133,13 @@ int gee_counts(const int32_t *labels, int64_t n, int32_t K, int64_t *counts, int
 int gee_weights(const int64_t *counts, int32_t K, double *inv, hipStream_t stream);
 
 /* Weighted degree d = (A + A^T) 1 (a self-loop adds 2 w), the preprocessing of
- * the Laplacian version. With csr != NULL the rows of the CSR are summed, each in
- * its stored order (deterministic); otherwise the records of g are accumulated
- * with FP64 atomics (exact for unit weights, and for weights on a 2^-k grid
- * whose sums stay below 2^(53-k)). deg: [n] double, overwritten. Exactly the
- * graph given is read: g may be NULL when csr is not, and vice versa. */
+ * the Laplacian version. With csr != NULL the rows of the CSR are summed in FP64,
+ * each in a fixed order (bit-reproducible): its stored order, except that a row of
+ * more than 4,096 entries is summed as 64 interleaved partial sums that are then
+ * added pairwise. Otherwise the records of g are accumulated with FP64 atomics.
+ * Both are exact for unit weights, and for weights on a 2^-k grid whose sums stay
+ * below 2^(53-k). deg: [n] double, overwritten. Exactly the graph given is read: g
+ * may be NULL when csr is not, and vice versa. */
 int gee_degrees(const gee_coo *g, const gee_csr *csr, double *deg, int32_t *err, hipStream_t stream);
 
 /* Workspace bytes gee_embed needs for this graph, K and variant (csr == NULL:
@@ -181,21 +183,28 @@ int gee_embed_noalloc(const gee_coo *g, const gee_csr *csr, const int32_t *label
                       float *Z, int32_t *err, const gee_embed_opts *opts, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------
- * Propagation-blocked layout of a unit-weight CSR, and the pull pass over it.
+ * Propagation-blocked layout of a CSR, and the pull pass over it (adjacency version).
  *
  * The pull pass of Algorithm 1 (Section II; Section III's per-vertex edge lists)
- * reads the label of every entry's column at a random address. For unit weights
- * the pass only needs, per entry, its row and the label of its column, so the
- * entries can be re-laid out once per graph: sorted stably by column block (2^21
- * vertices), each entry keeping its column and its row within a block of 256 rows.
+ * reads the label of every entry's column at a random address. The adjacency
+ * version only needs, per entry, its row, its weight and the label of its column,
+ * so the entries can be re-laid out once per graph: sorted stably by column block
+ * (2^21 vertices), each entry keeping its column, its row within a block of 256 rows
+ * and, for a weighted CSR, its weight.
  * Entries whose column is one of the CSR's first n_lds hot slots (its highest-degree
  * vertices, n_lds <= 2^23) go instead to "tier slices" of 2^17 slots each, one extra
  * column block per slice after the vertex blocks, and keep their slot within the
  * slice. Per call, one streaming pass writes every entry's label in that order (a
  * vertex block's labels stay in L2; a slice's labels, 128 KB, are read from LDS) and
  * a second pass counts, per 256-row block, the (row, class) pairs of the block's
- * cells in LDS and writes those rows of Z once. Counts are integers: Z is
- * bit-identical to gee_embed on the same CSR.
+ * cells in LDS and writes those rows of Z once. Unit-weight counts are integers: Z
+ * is bit-identical to gee_embed on the same CSR. With weights the second pass adds
+ * them into FP32 sums, which the layout allows only for row blocks whose rows have at
+ * most 128 entries and no negative weight (rb_flag 0): such a sum of m terms is within
+ * (m - 1) 2^-24 of its value, relative; the other blocks take FP64 sums. Results then
+ * agree with gee_embed within rounding, not bit for bit, and since a block's wavefronts
+ * add into shared bins in an order that varies, two calls agree within rounding too
+ * (the CSR pull form of gee_embed is the bit-reproducible one).
  *
  * Cell (rb, cb) of the layout is the run of column block cb's entries whose rows
  * lie in [256 rb, 256 rb + 256); cell_start[rb * n_cb + cb] is its first index in
@@ -221,6 +230,13 @@ typedef struct gee_pb {
     int64_t n_lds;             /* tier slots the layout was built with (0 to GEE_PB_MAX_TIER) */
     const int32_t *lds_ids;    /* [n_lds] vertex of each tier slot (written by gee_pb_build) */
     const uint32_t *cell_word; /* [n_rb * n_cb] first 32-bit word of each cell within its row block's words */
+    const float *val;          /* [nnz + 32 rounded up to 16] layout order, 16-byte aligned: the weight of each
+                                  entry; NULL for a unit-weight layout */
+    const uint8_t *rb_flag;    /* [n_rb] weighted layouts: 1 where a row of the block has more than 128 entries
+                                  or a negative weight (FP64 sums), else 0; NULL for a unit-weight layout */
+    const int64_t *meta;       /* [4] written by gee_pb_build: n, nnz, n_lds and 1 if weighted. A layout whose
+                                  meta disagrees with these fields (one built for another graph) makes
+                                  gee_embed_pb skip its passes and raise GEE_EVERTEX */
 } gee_pb;
 
 /* n_rb * n_cb for n vertices and n_lds tier slots (0 on invalid input). */
@@ -235,30 +251,32 @@ int64_t gee_pb_cells(int64_t n, int64_t n_lds);
 int64_t gee_pb_tier_slots(const gee_csr *csr, int64_t min_per_row_block, void *ws, size_t ws_bytes,
                           hipStream_t stream);
 
-/* Scratch bytes gee_pb_build needs (0 on invalid input, a weighted CSR, more than
- * 2^32 - 65 entries, or n_lds above min(n_hot, GEE_PB_MAX_TIER)). */
+/* Scratch bytes gee_pb_build needs (0 on invalid input, more than 2^32 - 65 entries,
+ * or n_lds above min(n_hot, GEE_PB_MAX_TIER)). */
 size_t gee_pb_build_workspace(const gee_csr *csr, int64_t n_lds);
 
-/* Builds the layout of a unit-weight CSR (csr->val must be NULL) with the first n_lds
- * hot slots (0 <= n_lds <= min(n_hot, GEE_PB_MAX_TIER)) in the tier; other hot-slot
- * columns are decoded through hot_ids. Outputs are caller device buffers: col
- * [nnz + 16] (16-byte aligned), ul [nnz + 32 rounded up to 16] (16-byte aligned), cell_start,
- * cell_count and cell_word [gee_pb_cells(n, n_lds)], lds_ids [n_lds] (may be NULL when
- * n_lds = 0). cell_word[rb * n_cb + c] is the first 32-bit word of cell c when the
- * cells of row block rb are read one after another as words (a cell covering
- * ceil(((cell_start mod 4) + cell_count) / 4) of them, none when empty). A column id
- * outside [0, n) stores GEE_EVERTEX in *err. */
+/* Builds the layout of csr with the first n_lds hot slots (0 <= n_lds <=
+ * min(n_hot, GEE_PB_MAX_TIER)) in the tier; other hot-slot columns are decoded through
+ * hot_ids. Outputs are caller device buffers: col [nnz + 16] (16-byte aligned), ul
+ * [nnz + 32 rounded up to 16] (16-byte aligned), cell_start, cell_count and cell_word
+ * [gee_pb_cells(n, n_lds)], lds_ids [n_lds] (may be NULL when n_lds = 0), meta [4];
+ * for a weighted CSR (csr->val != NULL) also val [nnz + 32 rounded up to 16] (16-byte
+ * aligned) and rb_flag [ceil(n / 256)], which must be NULL otherwise. cell_word[rb *
+ * n_cb + c] is the first 32-bit word of cell c when the cells of row block rb are read
+ * one after another as words (a cell covering ceil(((cell_start mod 4) + cell_count) /
+ * 4) of them, none when empty). A column id outside [0, n) stores GEE_EVERTEX in *err. */
 int gee_pb_build(const gee_csr *csr, int64_t n_lds, int32_t *col, uint8_t *ul, int64_t *cell_start,
-                 uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, void *ws, size_t ws_bytes,
-                 int32_t *err, hipStream_t stream);
+                 uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, float *val, uint8_t *rb_flag,
+                 int64_t *meta, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream);
 
 /* Workspace bytes of gee_embed_pb (0 on invalid input); 1 <= K <= 128. */
 size_t gee_embed_pb_workspace(const gee_pb *pb, int32_t K);
 
-/* Algorithm 1, adjacency version, unit weights, over the layout: labels [n] in
- * [0, K] (K <= 128), Z [n * K] FP32 overwritten. Same results and data errors as
- * gee_embed on the CSR the layout was built from. opts->hot_begin / hot_end
- * bracket the two passes (label gathers and row counts); seg_len is unused. */
+/* Algorithm 1, adjacency version, over the layout: labels [n] in [0, K] (K <= 128), Z
+ * [n * K] FP32 overwritten. Same results and data errors as gee_embed on the CSR the
+ * layout was built from (bit for bit with unit weights; with weights within the
+ * rounding described above). opts->hot_begin / hot_end bracket the two passes (label
+ * gathers and row sums); seg_len is unused. */
 int gee_embed_pb(const gee_pb *pb, const int32_t *labels, int32_t K, float *Z, void *ws, size_t ws_bytes,
                  int32_t *err, const gee_embed_opts *opts, hipStream_t stream);
 

@@ -61,7 +61,8 @@ class Pb(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_rb", ctypes.c_int64), ("n_cb", ctypes.c_int32),
                 ("col", ctypes.c_void_p), ("ul", ctypes.c_void_p), ("cell_start", ctypes.c_void_p),
                 ("cell_count", ctypes.c_void_p), ("n_lds", ctypes.c_int64), ("lds_ids", ctypes.c_void_p),
-                ("cell_word", ctypes.c_void_p)]
+                ("cell_word", ctypes.c_void_p), ("val", ctypes.c_void_p), ("rb_flag", ctypes.c_void_p),
+                ("meta", ctypes.c_void_p)]
 
 
 class Batch(ctypes.Structure):
@@ -113,7 +114,7 @@ def load():
         lib.gee_pb_build_workspace.restype = sz
         lib.gee_pb_build_workspace.argtypes = [CsrP, i64]
         lib.gee_pb_build.restype = ci
-        lib.gee_pb_build.argtypes = [CsrP, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp]
+        lib.gee_pb_build.argtypes = [CsrP, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp]
         lib.gee_embed_pb_workspace.restype = sz
         lib.gee_embed_pb_workspace.argtypes = [PbP, i32]
         lib.gee_embed_pb.restype = ci
@@ -379,8 +380,9 @@ PB_MAX_TIER = 1 << 23
 
 @dataclass
 class DevicePb:
-    """Propagation-blocked layout of a unit-weight CSR (entries by 2^21-vertex column
-    block, then by tier slice of 2^17 hot slots; cells of 256-row blocks)."""
+    """Propagation-blocked layout of a CSR (entries by 2^21-vertex column block, then by
+    tier slice of 2^17 hot slots; cells of 256-row blocks), with the entries' weights in
+    layout order for a weighted CSR."""
 
     n: int
     col: torch.Tensor         # [nnz + 16] int32; tier slots packed in 3 bytes from byte 4 H0
@@ -390,6 +392,9 @@ class DevicePb:
     lds_ids: torch.Tensor     # [n_lds]
     cell_word: torch.Tensor   # [n_rb * n_cb]
     nnz: int = 0
+    meta: torch.Tensor | None = None     # [4] int64 fingerprint written by the build
+    val: torch.Tensor | None = None      # [nnz + 32 rounded up to 16] float32, weighted layouts
+    rb_flag: torch.Tensor | None = None  # [n_rb] uint8, weighted layouts
 
     @property
     def n_rb(self) -> int:
@@ -406,7 +411,7 @@ class DevicePb:
     def struct(self) -> Pb:
         return Pb(self.n, self.nnz, self.n_rb, self.n_cb, _ptr(self.col), _ptr(self.ul), _ptr(self.cell_start),
                   _ptr(self.cell_count), self.n_lds, _ptr(self.lds_ids) if self.n_lds else None,
-                  _ptr(self.cell_word))
+                  _ptr(self.cell_word), _ptr(self.val), _ptr(self.rb_flag), _ptr(self.meta))
 
 
 def pb_tier_slots(csr: DeviceCsr, min_per_row_block: int = 4, stream=None) -> int:
@@ -422,8 +427,9 @@ def pb_tier_slots(csr: DeviceCsr, min_per_row_block: int = 4, stream=None) -> in
 
 
 def pb_build(csr: DeviceCsr, tier_slots: int | None = None, stream=None, check: bool = True) -> DevicePb:
-    """Layout for gee_embed_pb from a unit-weight CSR (per-graph preprocessing). The first
-    ``tier_slots`` hot slots are read from LDS; None takes pb_tier_slots(csr)."""
+    """Layout for gee_embed_pb from a CSR (per-graph preprocessing; a weighted CSR gives a
+    weighted layout). The first ``tier_slots`` hot slots are read from LDS; None takes
+    pb_tier_slots(csr)."""
     lib = load()
     rs = csr.struct()
     dev = csr.row_ptr.device
@@ -438,14 +444,19 @@ def pb_build(csr: DeviceCsr, tier_slots: int | None = None, stream=None, check: 
     cell_count = torch.empty(cells, dtype=torch.int32, device=dev)
     cell_word = torch.empty(cells, dtype=torch.int32, device=dev)
     lds_ids = torch.empty(n_lds, dtype=torch.int32, device=dev)
+    meta = torch.empty(4, dtype=torch.int64, device=dev)
+    weighted = csr.val is not None
+    val = torch.empty((csr.nnz + 32 + 15) // 16 * 16, dtype=torch.float32, device=dev) if weighted else None
+    rb_flag = torch.empty((csr.n + PB_ROWS - 1) // PB_ROWS, dtype=torch.uint8, device=dev) if weighted else None
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     err = torch.zeros(1, dtype=torch.int32, device=dev)
     _rc(lib.gee_pb_build(ctypes.byref(rs), n_lds, _ptr(col), _ptr(ul), _ptr(cell_start), _ptr(cell_count),
-                         _ptr(cell_word), _ptr(lds_ids) if n_lds else None, _ptr(ws), wsb, _ptr(err), _stream(stream)), "gee_pb_build")
+                         _ptr(cell_word), _ptr(lds_ids) if n_lds else None, _ptr(val), _ptr(rb_flag), _ptr(meta),
+                         _ptr(ws), wsb, _ptr(err), _stream(stream)), "gee_pb_build")
     if check:
         _check_err(err, "gee_pb_build")
     del ws
-    return DevicePb(csr.n, col, ul, cell_start, cell_count, lds_ids, cell_word, csr.nnz)
+    return DevicePb(csr.n, col, ul, cell_start, cell_count, lds_ids, cell_word, csr.nnz, meta, val, rb_flag)
 
 
 def embed_pb_workspace_bytes(pb: DevicePb, K: int) -> int:
@@ -454,7 +465,7 @@ def embed_pb_workspace_bytes(pb: DevicePb, K: int) -> int:
 
 def embed_pb(labels: torch.Tensor, K: int, pb: DevicePb, Z: torch.Tensor | None = None, ws: torch.Tensor | None = None,
              err: torch.Tensor | None = None, events=None, stream=None, check: bool = True) -> torch.Tensor:
-    """Adjacency-version Z [n, K] of a unit-weight graph from its propagation-blocked layout."""
+    """Adjacency-version Z [n, K] of a graph from its propagation-blocked layout."""
     lib = load()
     dev = pb.cell_start.device
     _need(labels, torch.int32, pb.n, "labels", dev)

@@ -48,6 +48,9 @@ int32_t batch_default_seg_len(int64_t n, int64_t nnz)
 }
 constexpr int32_t kMaxSegLen = 65535; // 16-bit per-segment class counters
 constexpr size_t kWaveLdsBudget = 16384;
+// Real-valued bins (weighted, Laplacian): about 8 KB a wavefront, so four workgroups of
+// four wavefronts share a CU and their label gathers overlap.
+constexpr size_t kWaveLdsBudgetReal = 8448;
 
 inline bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -61,7 +64,8 @@ struct Plan {
     int rw = 0;
     // workspace offsets
     int64_t n_hot = 0;
-    size_t o_counts = 0, o_inv = 0, o_lab = 0, o_deg = 0, o_hot = 0, o_segi = 0, o_sege = 0, o_part = 0, total = 0;
+    size_t o_counts = 0, o_inv = 0, o_lab = 0, o_deg = 0, o_hot = 0, o_segi = 0, o_sege = 0, o_part = 0, o_redo = 0,
+           total = 0;
 };
 
 int check_coo(const gee_coo *g)
@@ -119,7 +123,8 @@ int make_plan(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian, co
             P.rw = o->rows_per_window;
         } else {
             P.rw = 64;
-            while (P.rw > 1 && pull_wave_bytes(K, P.wide, P.rw) > kWaveLdsBudget) --P.rw;
+            const size_t budget = P.wide ? kWaveLdsBudgetReal : kWaveLdsBudget;
+            while (P.rw > 1 && pull_wave_bytes(K, P.wide, P.rw) > budget) --P.rw;
         }
         if (pull_wave_bytes(K, P.wide, P.rw) > 65536) return GEE_EINVAL;
     }
@@ -140,6 +145,7 @@ int make_plan(const gee_coo *g, const gee_csr *csr, int32_t K, int laplacian, co
         P.o_segi = take(4 * (size_t)(P.nseg + 1));
         P.o_sege = take(8 * (size_t)(P.nseg + 1));
         P.o_part = take(8 * 2 * (size_t)P.nseg * (size_t)K);
+        if (P.weighted && !P.lap) P.o_redo = take((size_t)P.nseg);
     }
     P.total = align_up(off, 256);
     *p = P;
@@ -357,8 +363,9 @@ int embed_impl(const gee_coo *g, const gee_csr *csr, const int32_t *labels, int3
     double *part = reinterpret_cast<double *>(w + p.o_part);
     if ((rc = hip_rc(launch_seg_bounds(p.n, p.nnz, csr->row_ptr, p.L, p.nseg, seg_i, seg_e, stream)))) return rc;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_begin, stream)))) return rc;
+    uint8_t *redo = (p.weighted && !p.lap) ? reinterpret_cast<uint8_t *>(w + p.o_redo) : nullptr;
     if ((rc = hip_rc(launch_pull(a, p.nnz, csr->row_ptr, csr->col, csr->val, w + p.o_hot, p.n_hot, seg_i, seg_e,
-                                 p.nseg, p.rw, part, stream))))
+                                 p.nseg, p.rw, part, redo, stream))))
         return rc;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;
     return hip_rc(launch_merge(a, csr->row_ptr, seg_i, seg_e, p.nseg, part, stream));
@@ -535,28 +542,29 @@ int64_t gee_pb_tier_slots(const gee_csr *csr, int64_t min_per_row_block, void *w
 
 size_t gee_pb_build_workspace(const gee_csr *csr, int64_t n_lds)
 {
-    if (check_csr(csr) != GEE_OK || csr->val || csr->nnz > kPbMaxNnz) return 0;
+    if (check_csr(csr) != GEE_OK || csr->nnz > kPbMaxNnz) return 0;
     if (n_lds < 0 || n_lds > (csr->hot_ids ? csr->n_hot : 0) || n_lds > kPbMaxSlices * kPbSlice) return 0;
-    return pb_build_scratch(csr->n, csr->nnz, n_lds);
+    return pb_build_scratch(csr->n, csr->nnz, n_lds, csr->val != nullptr);
 }
 
 int gee_pb_build(const gee_csr *csr, int64_t n_lds, int32_t *col, uint8_t *ul, int64_t *cell_start,
-                 uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, void *ws, size_t ws_bytes, int32_t *err,
-                 hipStream_t stream)
+                 uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, float *val, uint8_t *rb_flag,
+                 int64_t *meta, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream)
 {
     int rc;
     if ((rc = check_csr(csr)) != GEE_OK) return rc;
-    if (csr->val) return GEE_EINVAL; // the layout serves unit-weight graphs
     if (csr->nnz > kPbMaxNnz) return GEE_EOVERFLOW;
     if (n_lds < 0 || n_lds > (csr->hot_ids ? csr->n_hot : 0) || n_lds > kPbMaxSlices * kPbSlice) return GEE_EINVAL;
-    if ((csr->nnz > 0 && (!col || !ul)) || !cell_start || !cell_count || !cell_word || !aligned(col, 16) ||
-        !aligned(ul, 16) ||
-        (n_lds > 0 && !lds_ids))
+    if ((csr->nnz > 0 && (!col || !ul)) || !cell_start || !cell_count || !cell_word || !meta || !aligned(col, 16) ||
+        !aligned(ul, 16) || (n_lds > 0 && !lds_ids))
         return GEE_EINVAL;
-    const size_t need = pb_build_scratch(csr->n, csr->nnz, n_lds);
+    const bool weighted = csr->val != nullptr;
+    if (weighted ? (!rb_flag || (csr->nnz > 0 && !val) || !aligned(val, 16)) : (val || rb_flag)) return GEE_EINVAL;
+    const size_t need = pb_build_scratch(csr->n, csr->nnz, n_lds, weighted);
     if (!ws || !aligned(ws, 256) || ws_bytes < need) return GEE_EWORKSPACE;
-    return hip_rc(launch_pb_build(csr->n, csr->nnz, csr->row_ptr, csr->col, csr->hot_ids, csr->n_hot, n_lds, col, ul,
-                                  cell_start, cell_count, cell_word, lds_ids, ws, err, stream));
+    return hip_rc(launch_pb_build(csr->n, csr->nnz, csr->row_ptr, csr->col, csr->val, csr->hot_ids, csr->n_hot, n_lds,
+                                  col, ul, cell_start, cell_count, cell_word, lds_ids, val, rb_flag, meta, ws, err,
+                                  stream));
 }
 
 } // extern "C"
@@ -571,8 +579,9 @@ int check_pb(const gee_pb *pb)
     const PbLayout L = pb_layout(pb->n, pb->n_lds);
     if (pb->n_rb != L.n_rb || pb->n_cb != L.n_cb) return GEE_EINVAL;
     if ((pb->nnz > 0 && (!pb->col || !pb->ul)) || !pb->cell_start || !pb->cell_count || !pb->cell_word ||
-        !aligned(pb->col, 16) ||
-        !aligned(pb->ul, 16))
+        !pb->meta || !aligned(pb->col, 16) || !aligned(pb->ul, 16))
+        return GEE_EINVAL;
+    if ((pb->val == nullptr) != (pb->rb_flag == nullptr) || !aligned(pb->val, 16) || (pb->nnz > 0 && pb->rb_flag && !pb->val))
         return GEE_EINVAL;
     return GEE_OK;
 }
@@ -629,10 +638,11 @@ int gee_embed_pb(const gee_pb *pb, const int32_t *labels, int32_t K, float *Z, v
     const bool timed = opts && opts->hot_begin && opts->hot_end;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_begin, stream)))) return rc;
     const PbLayout L = pb_layout(pb->n, pb->n_lds);
-    if ((rc = hip_rc(launch_pb_gather(pb->nnz, L, pb->n_lds, pb->cell_start, pb->cell_count, pb->col, pb->lds_ids,
-                                      lab, tab, yv, stream))))
+    if ((rc = hip_rc(launch_pb_gather(pb->n, pb->nnz, L, pb->n_lds, pb->cell_start, pb->cell_count, pb->col,
+                                      pb->lds_ids, pb->meta, pb->val != nullptr, lab, tab, yv, err, stream))))
         return rc;
-    if ((rc = hip_rc(launch_pb_rows(pb->n, K, L, pb->cell_start, pb->cell_count, pb->cell_word, pb->ul, yv, inv, Z, stream))))
+    if ((rc = hip_rc(launch_pb_rows(pb->n, pb->nnz, K, L, pb->cell_start, pb->cell_count, pb->cell_word, pb->ul, yv,
+                                    pb->val, pb->rb_flag, pb->meta, pb->n_lds, inv, Z, err, stream))))
         return rc;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;
     return GEE_OK;

@@ -486,6 +486,30 @@ size_t radix_scratch_bytes(int64_t N, int64_t scan_n, size_t *hist_bytes, size_t
     return *hist_bytes + *offs_bytes + *part_bytes;
 }
 
+hipError_t radix_sort_bits_kv(uint64_t *keys0, uint64_t *keys1, float *vals0, float *vals1, int64_t N, int lo, int hi,
+                              uint32_t *hist, int64_t *offs, int64_t *scan_part, uint64_t **rkeys, float **rvals,
+                              hipStream_t s)
+{
+    uint64_t *kb[2] = {keys0, keys1};
+    float *vb[2] = {vals0, vals1};
+    int cur = 0;
+    const int64_t nt = tiles(N);
+    hipError_t e;
+    for (int sh = lo; N > 0 && sh < hi; sh += 8) {
+        hipLaunchKernelGGL(k_radix_hist<true>, dim3((unsigned)nt), dim3(kT), 0, s, kb[cur], vb[cur], N, sh, false, hist,
+                           nt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = scan(hist, 256 * nt, offs, scan_part, SumOp{}, false, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nt), dim3(kT), 0, s, kb[cur], vb[cur], kb[cur ^ 1],
+                           vb[cur ^ 1], N, sh, false, offs, nt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        cur ^= 1;
+    }
+    *rkeys = kb[cur];
+    *rvals = vb[cur];
+    return hipSuccess;
+}
+
 hipError_t radix_sort_bits(uint64_t *keys0, uint64_t *keys1, int64_t N, int lo, int hi, uint32_t *hist,
                            int64_t *offs, int64_t *scan_part, uint64_t **result, hipStream_t s)
 {

@@ -151,29 +151,79 @@ k_degrees_coo(int64_t n, int64_t ns, const int32_t *__restrict__ src, const int3
 }
 
 // One thread per row: sum the row's stored weights in order (deterministic).
+// Row sums of a CSR: one row per lane, its weights added in stored order with 16-byte
+// loads where the row is aligned for them (the lanes of a wavefront read 64 different
+// rows, so wide loads cut the memory requests fourfold). A row of more than kDegLong
+// entries is summed instead by the whole wavefront (lane l takes entries l, l + 64, ...
+// in order, then a fixed butterfly adds the 64 partial sums), so one long row does not
+// hold a lane for its whole length. Every sum is taken in a fixed order.
+constexpr int64_t kDegLong = 4096;
+
 template <bool W>
 __global__ void __launch_bounds__(kBlock)
 k_degrees_csr(int64_t n, const int64_t *__restrict__ row_ptr, const float *__restrict__ val, int64_t nnz,
-              double *__restrict__ deg, bool check_neg, int32_t *err)
+              double *__restrict__ deg, bool check_neg, bool vec_ok, int32_t *err)
 {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
-        int64_t b = row_ptr[u], e = row_ptr[u + 1];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    bool neg = false;
+    for (int64_t base = ((int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave; base < n;
+         base += waves * kWave) {
+        const int64_t u = base + lane;
+        const bool act = u < n;
+        int64_t b = act ? row_ptr[u] : 0, e = act ? row_ptr[u + 1] : 0;
         b = b < 0 ? 0 : (b > nnz ? nnz : b);
         e = e < b ? b : (e > nnz ? nnz : e);
         if (!W) {
-            deg[u] = (double)(e - b);
+            if (act) deg[u] = (double)(e - b);
             continue;
         }
-        double d = 0.0;
-        bool neg = false;
-        for (int64_t j = b; j < e; ++j) {
-            const float x = val[j];
-            neg |= !(x >= 0.0f);
-            d += (double)x;
+        const bool longrow = act && e - b > kDegLong;
+        if (act && !longrow) {
+            double d = 0.0;
+            int64_t q = b;
+            if (vec_ok) {
+                for (; q < e && (q & 3); ++q) {
+                    const float x = val[q];
+                    neg |= !(x >= 0.0f);
+                    d += (double)x;
+                }
+                for (; q + 4 <= e; q += 4) {
+                    const float4 x = *reinterpret_cast<const float4 *>(val + q);
+                    neg |= !(x.x >= 0.0f) || !(x.y >= 0.0f) || !(x.z >= 0.0f) || !(x.w >= 0.0f);
+                    d += (double)x.x;
+                    d += (double)x.y;
+                    d += (double)x.z;
+                    d += (double)x.w;
+                }
+            }
+            for (; q < e; ++q) {
+                const float x = val[q];
+                neg |= !(x >= 0.0f);
+                d += (double)x;
+            }
+            deg[u] = d;
         }
-        if (check_neg && neg) flag_error(err, GEE_ENEGW);
-        deg[u] = d;
+        // the long rows of these 64, one at a time by the whole wavefront
+        for (uint64_t longs = __ballot(longrow); longs; longs &= longs - 1) {
+            const int l = __builtin_ctzll(longs);
+            const int64_t lb = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l) & 0xffffffffll;
+            const int64_t lb_hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+            const int64_t le_lo = __builtin_amdgcn_readlane((int)(e & 0xffffffff), l) & 0xffffffffll;
+            const int64_t le_hi = __builtin_amdgcn_readlane((int)(e >> 32), l);
+            const int64_t rb = (lb_hi << 32) | lb, re = (le_hi << 32) | le_lo;
+            double d = 0.0;
+            for (int64_t q = rb + lane; q < re; q += kWave) {
+                const float x = val[q];
+                neg |= !(x >= 0.0f);
+                d += (double)x;
+            }
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) d += __shfl_xor(d, o, kWave);
+            if (lane == 0) deg[base + l] = d;
+        }
     }
+    if (check_neg && neg) flag_error(err, GEE_ENEGW);
 }
 
 // Laplacian label records: class in the low word, d^-1/2 rounded to FP32 in the
@@ -368,7 +418,13 @@ __device__ inline int wave_shr1(int x) { return __builtin_amdgcn_update_dpp(-1, 
 //  0: one FP64 sum per class (weighted or Laplacian);
 //  1: unit-weight counts, two classes per 32-bit word (16-bit counters; a segment
 //     holds at most 65535 entries, so they cannot overflow);
-//  2: unit-weight counts, one 32-bit counter per class.
+//  2: unit-weight counts, one 32-bit counter per class;
+//  3: one FP32 sum per class (weighted or Laplacian). A window whose rows all have at
+//     most kF32Terms entries in the segment uses them: no bin then takes more than
+//     kF32Terms terms, and for non-negative terms an FP32 sum of m terms in any order
+//     is within (m - 1) 2^-24 of its exact value, relative. A window with a longer row
+//     takes FP64 bins for half as many rows in the same LDS; a segment with a negative
+//     weight is flagged and computed again with FP64 bins by a second launch.
 template <int BK> struct Bins;
 template <> struct Bins<0> {
     using word = double;
@@ -394,8 +450,20 @@ template <> struct Bins<2> {
     __device__ static void add_masked(word *row, int k, double, bool use) { atomicAdd(&row[k], use ? 1u : 0u); }
     __device__ static double get(const word *row, int k) { return (double)row[k]; }
 };
-// Bin kind of the unit-weight adjacency variant.
+template <> struct Bins<3> {
+    using word = float;
+    __host__ __device__ static int words(int K) { return K; }
+    __device__ static void add(word *row, int k, double x) { atomicAdd(&row[k], (float)x); }
+    __device__ static void add_masked(word *row, int k, double x, bool use)
+    {
+        atomicAdd(&row[k], use ? (float)x : 0.0f);
+    }
+    __device__ static double get(const word *row, int k) { return (double)row[k]; }
+};
+// Bin kind of the unit-weight adjacency variant, and of the others.
 constexpr int kUnitBins = 1;
+constexpr int kRealBins = 3;
+constexpr int kF32Terms = 128; // terms per FP32 bin: (128 - 1) 2^-24 = 7.6e-6 relative at most
 
 constexpr int kPass = 1024;              // entries whose row-start markers are mapped at once
 constexpr int kChunk = 2 * 4 * kWave;    // entries per inner step (two 16-byte loads per lane)
@@ -406,6 +474,7 @@ constexpr int kSinkBytes = kWave * 8;    // one word per lane for masked bin upd
 // and the class weights (K <= 64).
 __host__ __device__ inline size_t pull_bins_bytes(int32_t K, int bk, int rw)
 {
+    if (bk == 3) return align_up((size_t)((rw + 1) / 2) * K * 8, 16); // rw FP32 rows or (rw + 1) / 2 FP64 rows
     const size_t row = bk == 0 ? (size_t)K * 8 : (bk == 1 ? (size_t)(K + 1) / 2 * 4 : (size_t)K * 4);
     return align_up((size_t)rw * row, 16);
 }
@@ -432,33 +501,38 @@ __host__ __device__ inline size_t pull_lds_bytes(int32_t K, int bk, int rw)
 //    row by row with lanes over classes. A row cut by a segment boundary goes to
 //    the FP64 partials instead (head: continues from an earlier segment; tail:
 //    continues into later ones).
+//  - Real-valued bins (kind 3) are FP32 unless a row of the window has more than
+//    kF32Terms entries in the segment; the weighted adjacency version flags a
+//    segment with a negative weight in redo[j] (FP32 sums are only bounded relative
+//    to their own value for terms of one sign), and a second launch with FP64 bins
+//    (kind 0, redo given) recomputes exactly the flagged segments.
 template <int BK, bool LAP, bool W, typename P, bool H6>
 __global__ void __launch_bounds__(kBlock)
 k_pull(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
        const float *__restrict__ val, const P *__restrict__ lab, const P *__restrict__ hotlab, int64_t n_hot,
        const double *__restrict__ inv, int32_t K, const int32_t *__restrict__ seg_i,
        const int64_t *__restrict__ seg_e, int64_t nseg, int RW, uint32_t wave_bytes, bool vec_ok,
-       float *__restrict__ Z, double *__restrict__ part, int32_t *err)
+       float *__restrict__ Z, double *__restrict__ part, uint8_t *__restrict__ redo, int32_t *err)
 {
-    using BT = Bins<BK>;
-    using word = typename BT::word;
+    constexpr bool REAL = BK == 0 || BK == 3;     // sums of weights (and d^-1/2), not counts
+    constexpr bool FLAG_NEG = BK == 3 && W && !LAP; // flags segments with a negative weight
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (j >= nseg) return;
+    if (BK == 0 && redo && !redo[j]) return; // the FP64 pass over flagged segments only
     unsigned char *my = smem + (size_t)wave * wave_bytes;
-    const int KW = BT::words(K);
-    word *bins = (word *)my;
-    int8_t *mark = (int8_t *)(my + pull_bins_bytes(K, BK, RW));
-    word *sink = (word *)(my + pull_bins_bytes(K, BK, RW) + kPass); // one per lane: target of masked adds
-    double *invt = (double *)(my + pull_bins_bytes(K, BK, RW) + kPass + kSinkBytes);
+    const size_t bins_bytes = pull_bins_bytes(K, BK, RW);
+    int8_t *mark = (int8_t *)(my + bins_bytes);
+    unsigned char *sink_bytes = my + bins_bytes + kPass; // one 8-byte word per lane: target of masked adds
+    double *invt = (double *)(my + bins_bytes + kPass + kSinkBytes);
     const bool flat = K <= kFlatFlushMaxK;
 
     const SegInfo sg = seg_info(j, n, row_ptr, seg_i, seg_e);
-    for (int b = lane; b < RW * KW; b += kWave) bins[b] = (word)0;
+    for (int b = lane; b < (int)(bins_bytes / 4); b += kWave) ((uint32_t *)my)[b] = 0u;
     for (int b = lane; b < kPass / 4; b += kWave) ((int32_t *)mark)[b] = -1;
     if (flat && lane < K) invt[lane] = inv[lane + 1];
-    bool bad = false;
+    bool bad = false, neg = false;
     // A segment whose last 16-byte column quad may pass the end of the array takes
     // the guarded loads; every other segment runs branch-free steps, so the loads
     // in flight can be counted statically and the next step's column loads stay
@@ -475,10 +549,9 @@ k_pull(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_
     };
     int64_t rp0, rp1;
     fetch_rows(sg.i0, rp0, rp1);
-    for (int64_t r = sg.i0; r < sg.rend; r += RW) {
-        const int nr = (int)((sg.rend - r) < RW ? (sg.rend - r) : RW);
+    for (int64_t r = sg.i0; r < sg.rend;) {
+        int nr = (int)((sg.rend - r) < RW ? (sg.rend - r) : RW);
         int64_t p0 = rp0, p1 = rp1;
-        fetch_rows(r + RW, rp0, rp1);
         // lane l < nr: clamped start and end of row r + l, relative to e0
         int32_t cs = 0, ce = 0;
         if (lane < nr) {
@@ -487,188 +560,221 @@ k_pull(int64_t n, int64_t nnz, const int64_t *__restrict__ row_ptr, const int32_
             cs = (int32_t)(p0 - sg.e0);
             ce = (int32_t)(p1 - sg.e0);
         }
+        bool wide = false;
+        if constexpr (BK == 3) {
+            // FP32 bins unless one of the window's rows has more than kF32Terms entries here;
+            // then FP64 bins for the first (RW + 1) / 2 rows
+            wide = __ballot(ce - cs > kF32Terms) != 0ull;
+            if (wide && nr > (RW + 1) / 2) {
+                nr = (RW + 1) / 2;
+                if (lane >= nr) cs = ce = 0;
+            }
+        }
+        fetch_rows(r + nr, rp0, rp1);
         const int32_t ws = __builtin_amdgcn_readlane(cs, 0), we = __builtin_amdgcn_readlane(ce, nr - 1);
         // 4-aligned (in absolute entry index) start of the window's steps
         const int32_t base = (int32_t)(((sg.e0 + ws) & ~(int64_t)3) - sg.e0);
         const bool nonempty = lane < nr && cs < ce;
-        int carry = -1;
-        for (int32_t p0 = base; p0 < we; p0 += kPass) {
-            const int32_t p1 = (p0 + kPass < we) ? p0 + kPass : we;
-            const bool mine = nonempty && cs >= p0 && cs < p0 + kPass;
-            if (mine) mark[cs - p0] = (int8_t)lane;
+
+        auto window = [&](auto bins_tag) {
+            using BT = typename decltype(bins_tag)::type;
+            using word = typename BT::word;
+            word *bins = (word *)my;
+            word *sink = (word *)sink_bytes;
+            const int KW = BT::words(K);
+            int carry = -1;
+            for (int32_t p0 = base; p0 < we; p0 += kPass) {
+                const int32_t p1 = (p0 + kPass < we) ? p0 + kPass : we;
+                const bool mine = nonempty && cs >= p0 && cs < p0 + kPass;
+                if (mine) mark[cs - p0] = (int8_t)lane;
+                wave_sync();
+
+                auto pass = [&](auto tail_tag) {
+                    constexpr bool TAIL = decltype(tail_tag)::value;
+                    // column (and weight) quad of a half-step: lane owns entries q .. q+3
+                    auto load = [&](int32_t q, int32_t (&c)[4], float (&x)[4]) {
+                        const bool any = q < p1 && q + 3 >= ws;
+                        if (TAIL) {
+                            const int64_t a = sg.e0 + q;
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) {
+                                const bool in = any && q + t >= ws && q + t < p1;
+                                c[t] = in ? col[a + t] : 0;
+                                if (W) x[t] = in ? val[a + t] : 0.0f;
+                            }
+                        } else {
+                            // lanes outside the pass read the window's first quad (in bounds)
+                            const int64_t a = sg.e0 + (any ? q : base);
+                            const int4 cq = *reinterpret_cast<const int4 *>(col + a);
+                            c[0] = cq.x, c[1] = cq.y, c[2] = cq.z, c[3] = cq.w;
+                            if (W) {
+                                const float4 vq = *reinterpret_cast<const float4 *>(val + a);
+                                x[0] = vq.x, x[1] = vq.y, x[2] = vq.z, x[3] = vq.w;
+                            }
+                        }
+                    };
+                    // row-start marker word of a half-step (-1 outside the pass)
+                    auto marks = [&](int32_t q) -> int32_t {
+                        const bool any = q < p1 && q + 3 >= ws;
+                        int32_t wi = (q - p0) >> 2;
+                        wi = wi < 0 ? 0 : (wi >= kPass / 4 ? kPass / 4 - 1 : wi);
+                        const int32_t mw = ((const int32_t *)mark)[wi];
+                        return any ? mw : -1;
+                    };
+                    int32_t cc[2][4], cn[2][4] = {};
+                    float xc[2][4] = {}, xn[2][4] = {};
+                    int32_t mwc[2], mwn[2] = {-1, -1};
+                    load(p0 + 4 * lane, cc[0], xc[0]);
+                    load(p0 + 4 * kWave + 4 * lane, cc[1], xc[1]);
+                    mwc[0] = marks(p0 + 4 * lane);
+                    mwc[1] = marks(p0 + 4 * kWave + 4 * lane);
+                    for (int32_t q0 = p0; q0 < p1; q0 += kChunk) {
+                        int m[2][4];
+                        bool in[2][4];
+                        P pk[2][4];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int32_t q = q0 + h * 4 * kWave + 4 * lane;
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) {
+                                m[h][t] = (int)(int8_t)(mwc[h] >> (8 * t));
+                                in[h][t] = q + t >= ws && q + t < p1;
+                            }
+                            m[h][1] = imax(m[h][1], m[h][0]);
+                            m[h][2] = imax(m[h][2], m[h][1]);
+                            m[h][3] = imax(m[h][3], m[h][2]);
+                            const int incl = wave_incl_max(m[h][3]);
+                            const int excl = imax(wave_shr1(incl), carry);
+                            carry = imax(carry, __builtin_amdgcn_readlane(incl, kWave - 1));
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) m[h][t] = imax(m[h][t], excl);
+                            // label records, one gather per entry (masked lanes read lab[0]);
+                            // bit 31 of a column selects the hot table
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) {
+                                const int32_t c = cc[h][t];
+                                const bool hot = c < 0;
+                                const uint32_t idx = (uint32_t)c & 0x7fffffffu;
+                                const bool ok = in[h][t] && (hot ? (int64_t)idx < n_hot : (int64_t)idx < n);
+                                bad |= in[h][t] && !ok;
+                                in[h][t] = ok;
+                                if (H6) {
+                                    // one aligned 32-bit gather: a hot slot's 6-bit field in the
+                                    // packed hot table, or the byte of a cold label in its word
+                                    const uint32_t wq = __umulhi(idx, 0xCCCCCCCDu) >> 2; // idx / 5
+                                    const uint32_t *src =
+                                        !ok ? reinterpret_cast<const uint32_t *>(lab)
+                                            : (hot ? reinterpret_cast<const uint32_t *>(hotlab) + wq
+                                                   : reinterpret_cast<const uint32_t *>(lab + (idx & ~3u)));
+                                    const uint32_t word32 = *src;
+                                    const uint32_t sh = hot ? 6u * (idx - 5u * wq) : 8u * (idx & 3u);
+                                    pk[h][t] = ok ? (P)((word32 >> sh) & (hot ? 63u : 255u)) : (P)0;
+                                } else {
+                                    const P *tab = (ok && hot) ? hotlab : lab;
+                                    pk[h][t] = tab[ok ? idx : 0u];
+                                }
+                            }
+                        }
+                        // next step's columns (issued after this step's gathers) and markers
+                        // (read before this step's atomics enter the LDS queue)
+                        const int32_t qn = q0 + kChunk;
+                        load(qn + 4 * lane, cn[0], xn[0]);
+                        load(qn + 4 * kWave + 4 * lane, cn[1], xn[1]);
+                        mwn[0] = marks(qn + 4 * lane);
+                        mwn[1] = marks(qn + 4 * kWave + 4 * lane);
+                        // bin updates; masked entries add nothing to this lane's sink word
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) {
+                                const int y = LabelRec<P>::cls(pk[h][t]);
+                                const bool use = in[h][t] && y > 0 && m[h][t] >= 0;
+                                double add = 1.0;
+                                if (REAL) {
+                                    if (W) add = (double)xc[h][t];
+                                    if (LAP) add *= (double)LabelRec<P>::rsd(pk[h][t]);
+                                }
+                                if (FLAG_NEG) neg |= use && xc[h][t] < 0.0f;
+                                BT::add_masked(use ? &bins[m[h][t] * KW] : &sink[lane], use ? y - 1 : 0, add, use);
+                            }
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            mwc[h] = mwn[h];
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) {
+                                cc[h][t] = cn[h][t];
+                                if (W) xc[h][t] = xn[h][t];
+                            }
+                        }
+                    }
+                };
+                if (tail_seg) pass(std::true_type{});
+                else pass(std::false_type{});
+                wave_sync();
+                if (mine) mark[cs - p0] = -1;
+            }
             wave_sync();
 
-            auto pass = [&](auto tail_tag) {
-                constexpr bool TAIL = decltype(tail_tag)::value;
-                // column (and weight) quad of a half-step: lane owns entries q .. q+3
-                auto load = [&](int32_t q, int32_t (&c)[4], float (&x)[4]) {
-                    const bool any = q < p1 && q + 3 >= ws;
-                    if (TAIL) {
-                        const int64_t a = sg.e0 + q;
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) {
-                            const bool in = any && q + t >= ws && q + t < p1;
-                            c[t] = in ? col[a + t] : 0;
-                            if (W) x[t] = in ? val[a + t] : 0.0f;
-                        }
-                    } else {
-                        // lanes outside the pass read the window's first quad (in bounds)
-                        const int64_t a = sg.e0 + (any ? q : base);
-                        const int4 cq = *reinterpret_cast<const int4 *>(col + a);
-                        c[0] = cq.x, c[1] = cq.y, c[2] = cq.z, c[3] = cq.w;
-                        if (W) {
-                            const float4 vq = *reinterpret_cast<const float4 *>(val + a);
-                            x[0] = vq.x, x[1] = vq.y, x[2] = vq.z, x[3] = vq.w;
-                        }
-                    }
-                };
-                // row-start marker word of a half-step (-1 outside the pass)
-                auto marks = [&](int32_t q) -> int32_t {
-                    const bool any = q < p1 && q + 3 >= ws;
-                    int32_t wi = (q - p0) >> 2;
-                    wi = wi < 0 ? 0 : (wi >= kPass / 4 ? kPass / 4 - 1 : wi);
-                    const int32_t mw = ((const int32_t *)mark)[wi];
-                    return any ? mw : -1;
-                };
-                int32_t cc[2][4], cn[2][4] = {};
-                float xc[2][4] = {}, xn[2][4] = {};
-                int32_t mwc[2], mwn[2] = {-1, -1};
-                load(p0 + 4 * lane, cc[0], xc[0]);
-                load(p0 + 4 * kWave + 4 * lane, cc[1], xc[1]);
-                mwc[0] = marks(p0 + 4 * lane);
-                mwc[1] = marks(p0 + 4 * kWave + 4 * lane);
-                for (int32_t q0 = p0; q0 < p1; q0 += kChunk) {
-                    int m[2][4];
-                    bool in[2][4];
-                    P pk[2][4];
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int32_t q = q0 + h * 4 * kWave + 4 * lane;
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) {
-                            m[h][t] = (int)(int8_t)(mwc[h] >> (8 * t));
-                            in[h][t] = q + t >= ws && q + t < p1;
-                        }
-                        m[h][1] = imax(m[h][1], m[h][0]);
-                        m[h][2] = imax(m[h][2], m[h][1]);
-                        m[h][3] = imax(m[h][3], m[h][2]);
-                        const int incl = wave_incl_max(m[h][3]);
-                        const int excl = imax(wave_shr1(incl), carry);
-                        carry = imax(carry, __builtin_amdgcn_readlane(incl, kWave - 1));
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) m[h][t] = imax(m[h][t], excl);
-                        // label records, one gather per entry (masked lanes read lab[0]);
-                        // bit 31 of a column selects the hot table
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) {
-                            const int32_t c = cc[h][t];
-                            const bool hot = c < 0;
-                            const uint32_t idx = (uint32_t)c & 0x7fffffffu;
-                            const bool ok = in[h][t] && (hot ? (int64_t)idx < n_hot : (int64_t)idx < n);
-                            bad |= in[h][t] && !ok;
-                            in[h][t] = ok;
-                            if (H6) {
-                                // one aligned 32-bit gather: a hot slot's 6-bit field in the
-                                // packed hot table, or the byte of a cold label in its word
-                                const uint32_t wq = __umulhi(idx, 0xCCCCCCCDu) >> 2; // idx / 5
-                                const uint32_t *src =
-                                    !ok ? reinterpret_cast<const uint32_t *>(lab)
-                                        : (hot ? reinterpret_cast<const uint32_t *>(hotlab) + wq
-                                               : reinterpret_cast<const uint32_t *>(lab + (idx & ~3u)));
-                                const uint32_t word = *src;
-                                const uint32_t sh = hot ? 6u * (idx - 5u * wq) : 8u * (idx & 3u);
-                                pk[h][t] = ok ? (P)((word >> sh) & (hot ? 63u : 255u)) : (P)0;
-                            } else {
-                                const P *tab = (ok && hot) ? hotlab : lab;
-                                pk[h][t] = tab[ok ? idx : 0u];
-                            }
+            // ---- write the window's rows
+            const bool head_here = sg.carried && r == sg.i0;
+            const bool tail_here = sg.tail && sg.i1 >= r && sg.i1 < r + nr;
+            if (head_here)
+                for (int k = lane; k < K; k += kWave) part[(2 * j) * K + k] = BT::get(&bins[0], k);
+            if (tail_here)
+                for (int k = lane; k < K; k += kWave) part[(2 * j + 1) * K + k] = BT::get(&bins[(sg.i1 - r) * KW], k);
+            if (flat) {
+                // floats [r K, (r + nr) K) in 64-float blocks aligned to 256 bytes
+                const int64_t f_lo = r * K, f_hi = (r + nr) * K;
+                const int64_t f_start = f_lo & ~(int64_t)(kWave - 1);
+                int64_t f = f_start + lane;
+                const int rel = (int)(f - f_lo); // negative in the first block: floats of earlier rows
+                int l = rel >= 0 ? rel / K : -((-rel + K - 1) / K);
+                int k = rel - l * K;
+                const int dl = kWave / K, dk = kWave % K;
+                for (; f < f_hi; f += kWave) {
+                    if (l >= 0) {
+                        const int64_t u = r + l;
+                        const bool skip = (head_here && l == 0) || (tail_here && u == sg.i1);
+                        if (!skip) {
+                            double sc = invt[k];
+                            if (LAP) sc *= (double)LabelRec<P>::rsd(lab[u]);
+                            __builtin_nontemporal_store((float)(BT::get(&bins[l * KW], k) * sc), &Z[f]);
                         }
                     }
-                    // next step's columns (issued after this step's gathers) and markers
-                    // (read before this step's atomics enter the LDS queue)
-                    const int32_t qn = q0 + kChunk;
-                    load(qn + 4 * lane, cn[0], xn[0]);
-                    load(qn + 4 * kWave + 4 * lane, cn[1], xn[1]);
-                    mwn[0] = marks(qn + 4 * lane);
-                    mwn[1] = marks(qn + 4 * kWave + 4 * lane);
-                    // bin updates; masked entries add nothing to this lane's sink word
-#pragma unroll
-                    for (int h = 0; h < 2; ++h)
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) {
-                            const int y = LabelRec<P>::cls(pk[h][t]);
-                            const bool use = in[h][t] && y > 0 && m[h][t] >= 0;
-                            double add = 1.0;
-                            if (BK == 0) {
-                                if (W) add = (double)xc[h][t];
-                                if (LAP) add *= (double)LabelRec<P>::rsd(pk[h][t]);
-                            }
-                            BT::add_masked(use ? &bins[m[h][t] * KW] : &sink[lane], use ? y - 1 : 0, add, use);
-                        }
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        mwc[h] = mwn[h];
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) {
-                            cc[h][t] = cn[h][t];
-                            if (W) xc[h][t] = xn[h][t];
-                        }
+                    l += dl;
+                    k += dk;
+                    if (k >= K) {
+                        k -= K;
+                        ++l;
                     }
                 }
-            };
-            if (tail_seg) pass(std::true_type{});
-            else pass(std::false_type{});
-            wave_sync();
-            if (mine) mark[cs - p0] = -1;
-        }
-        wave_sync();
-
-        // ---- write the window's rows
-        const bool head_here = sg.carried && r == sg.i0;
-        const bool tail_here = sg.tail && sg.i1 >= r && sg.i1 < r + nr;
-        if (head_here)
-            for (int k = lane; k < K; k += kWave) part[(2 * j) * K + k] = BT::get(&bins[0], k);
-        if (tail_here)
-            for (int k = lane; k < K; k += kWave) part[(2 * j + 1) * K + k] = BT::get(&bins[(sg.i1 - r) * KW], k);
-        if (flat) {
-            // floats [r K, (r + nr) K) in 64-float blocks aligned to 256 bytes
-            const int64_t f_lo = r * K, f_hi = (r + nr) * K;
-            const int64_t f_start = f_lo & ~(int64_t)(kWave - 1);
-            int64_t f = f_start + lane;
-            const int rel = (int)(f - f_lo); // negative in the first block: floats of earlier rows
-            int l = rel >= 0 ? rel / K : -((-rel + K - 1) / K);
-            int k = rel - l * K;
-            const int dl = kWave / K, dk = kWave % K;
-            for (; f < f_hi; f += kWave) {
-                if (l >= 0) {
+            } else {
+                for (int l = 0; l < nr; ++l) {
                     const int64_t u = r + l;
-                    const bool skip = (head_here && l == 0) || (tail_here && u == sg.i1);
-                    if (!skip) {
-                        double sc = invt[k];
-                        if (LAP) sc *= (double)LabelRec<P>::rsd(lab[u]);
-                        __builtin_nontemporal_store((float)(BT::get(&bins[l * KW], k) * sc), &Z[f]);
-                    }
-                }
-                l += dl;
-                k += dk;
-                if (k >= K) {
-                    k -= K;
-                    ++l;
+                    if ((head_here && l == 0) || (tail_here && u == sg.i1)) continue;
+                    const double ru = LAP ? (double)LabelRec<P>::rsd(lab[u]) : 1.0;
+                    for (int k = lane; k < K; k += kWave)
+                        __builtin_nontemporal_store((float)(BT::get(&bins[l * KW], k) * (inv[k + 1] * ru)),
+                                                    &Z[u * K + k]);
                 }
             }
+            wave_sync();
+            for (int b = lane; b < nr * KW; b += kWave) bins[b] = (word)0;
+            wave_sync();
+        };
+        struct Own { using type = Bins<BK>; };
+        if constexpr (BK == 3) {
+            struct F64 { using type = Bins<0>; };
+            if (wide) window(F64{});
+            else window(Own{});
         } else {
-            for (int l = 0; l < nr; ++l) {
-                const int64_t u = r + l;
-                if ((head_here && l == 0) || (tail_here && u == sg.i1)) continue;
-                const double ru = LAP ? (double)LabelRec<P>::rsd(lab[u]) : 1.0;
-                for (int k = lane; k < K; k += kWave)
-                    __builtin_nontemporal_store((float)(BT::get(&bins[l * KW], k) * (inv[k + 1] * ru)),
-                                                &Z[u * K + k]);
-            }
+            window(Own{});
         }
-        wave_sync();
-        for (int b = lane; b < nr * KW; b += kWave) bins[b] = (word)0;
-        wave_sync();
+        r += nr;
+    }
+    if (FLAG_NEG) {
+        const bool any_neg = __ballot(neg) != 0ull;
+        if (lane == 0) redo[j] = any_neg ? 1 : 0;
     }
     if (bad) flag_error(err, GEE_EVERTEX);
 }
@@ -777,8 +883,9 @@ hipError_t launch_degrees_csr(int64_t n, const int64_t *row_ptr, const float *va
                               bool check_neg, int32_t *err, hipStream_t s)
 {
     const dim3 g(grid_for(n, kBlock, 1 << 20)), b(kBlock);
-    if (val) hipLaunchKernelGGL(k_degrees_csr<true>, g, b, 0, s, n, row_ptr, val, nnz, deg, check_neg, err);
-    else hipLaunchKernelGGL(k_degrees_csr<false>, g, b, 0, s, n, row_ptr, val, nnz, deg, check_neg, err);
+    const bool vec_ok = (uintptr_t)val % 16 == 0;
+    if (val) hipLaunchKernelGGL(k_degrees_csr<true>, g, b, 0, s, n, row_ptr, val, nnz, deg, check_neg, vec_ok, err);
+    else hipLaunchKernelGGL(k_degrees_csr<false>, g, b, 0, s, n, row_ptr, val, nnz, deg, check_neg, vec_ok, err);
     return hipGetLastError();
 }
 
@@ -842,12 +949,12 @@ hipError_t launch_seg_bounds(int64_t n, int64_t nnz, const int64_t *row_ptr, int
     return hipGetLastError();
 }
 
-size_t pull_wave_bytes(int32_t K, bool wide_bins, int rw) { return pull_lds_bytes(K, wide_bins ? 0 : kUnitBins, rw); }
+size_t pull_wave_bytes(int32_t K, bool wide_bins, int rw) { return pull_lds_bytes(K, wide_bins ? kRealBins : kUnitBins, rw); }
 
 template <int BK, bool LAP, bool W, typename P, bool H6 = false>
 static hipError_t pull_t(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
                          const float *val, const void *hotlab, int64_t n_hot, const int32_t *seg_i,
-                         const int64_t *seg_e, int64_t nseg, int rw, double *part, hipStream_t s)
+                         const int64_t *seg_e, int64_t nseg, int rw, double *part, uint8_t *redo, hipStream_t s)
 {
     const uint32_t wb = (uint32_t)pull_lds_bytes(a.K, BK, rw);
     int wpb = (int)(65536 / wb);
@@ -856,21 +963,34 @@ static hipError_t pull_t(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr
     const bool vec_ok = ((uintptr_t)col % 16 == 0) && (!val || (uintptr_t)val % 16 == 0);
     hipLaunchKernelGGL((k_pull<BK, LAP, W, P, H6>), dim3((unsigned)blocks), dim3(wpb * kWave), (size_t)wpb * wb, s,
                        a.n, nnz, row_ptr, col, val, static_cast<const P *>(a.lab), static_cast<const P *>(hotlab),
-                       n_hot, a.inv, a.K, seg_i, seg_e, nseg, rw, wb, vec_ok, a.Z, part, a.err);
+                       n_hot, a.inv, a.K, seg_i, seg_e, nseg, rw, wb, vec_ok, a.Z, part, redo, a.err);
     return hipGetLastError();
 }
 
 hipError_t launch_pull(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const float *val,
                        const void *hotlab, int64_t n_hot, const int32_t *seg_i, const int64_t *seg_e, int64_t nseg,
-                       int rw, double *part, hipStream_t s)
+                       int rw, double *part, uint8_t *redo, hipStream_t s)
 {
 #define GEE_PULL(PK, LAP, W, P) \
-    pull_t<PK, LAP, W, P>(a, nnz, row_ptr, col, val, hotlab, n_hot, seg_i, seg_e, nseg, rw, part, s)
-    if (a.laplacian) return val ? GEE_PULL(0, true, true, uint64_t) : GEE_PULL(0, true, false, uint64_t);
-    if (val) return a.pack == Pack::U16 ? GEE_PULL(0, false, true, uint16_t) : GEE_PULL(0, false, true, uint8_t);
+    pull_t<PK, LAP, W, P>(a, nnz, row_ptr, col, val, hotlab, n_hot, seg_i, seg_e, nseg, rw, part, nullptr, s)
+    if (a.laplacian) return val ? GEE_PULL(kRealBins, true, true, uint64_t) : GEE_PULL(kRealBins, true, false, uint64_t);
+    if (val) {
+        // FP32 bins, then FP64 bins over the segments that hold a negative weight
+        if (!redo) return hipErrorInvalidValue;
+        hipError_t e = a.pack == Pack::U16
+                           ? pull_t<kRealBins, false, true, uint16_t>(a, nnz, row_ptr, col, val, hotlab, n_hot, seg_i,
+                                                                      seg_e, nseg, rw, part, redo, s)
+                           : pull_t<kRealBins, false, true, uint8_t>(a, nnz, row_ptr, col, val, hotlab, n_hot, seg_i,
+                                                                     seg_e, nseg, rw, part, redo, s);
+        if (e != hipSuccess) return e;
+        return a.pack == Pack::U16 ? pull_t<0, false, true, uint16_t>(a, nnz, row_ptr, col, val, hotlab, n_hot, seg_i,
+                                                                      seg_e, nseg, rw, part, redo, s)
+                                   : pull_t<0, false, true, uint8_t>(a, nnz, row_ptr, col, val, hotlab, n_hot, seg_i,
+                                                                     seg_e, nseg, rw, part, redo, s);
+    }
     if (a.pack == Pack::U16) return GEE_PULL(kUnitBins, false, false, uint16_t);
     return a.hot6 ? pull_t<kUnitBins, false, false, uint8_t, true>(a, nnz, row_ptr, col, val, hotlab, n_hot, seg_i,
-                                                                  seg_e, nseg, rw, part, s)
+                                                                  seg_e, nseg, rw, part, nullptr, s)
                   : GEE_PULL(kUnitBins, false, false, uint8_t);
 #undef GEE_PULL
 }

@@ -44,11 +44,14 @@ hipError_t launch_push(const EmbedArgs &a, int64_t ns, const int32_t *src, const
 hipError_t launch_scale(const EmbedArgs &a, hipStream_t s);
 hipError_t launch_seg_bounds(int64_t n, int64_t nnz, const int64_t *row_ptr, int64_t L, int64_t nseg,
                              int32_t *seg_i, int64_t *seg_e, hipStream_t s);
-// LDS bytes one wavefront of the pull kernel uses for `rw` rows of K bins.
+// LDS bytes one wavefront of the pull kernel uses for `rw` rows of K bins (wide_bins: the
+// real-valued bins of the weighted and Laplacian versions).
 size_t pull_wave_bytes(int32_t K, bool wide_bins, int rw);
+// redo: [nseg] bytes of scratch, required for weighted adjacency (segments with a negative
+// weight are summed again in FP64), else unused.
 hipError_t launch_pull(const EmbedArgs &a, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
                        const float *val, const void *hotlab, int64_t n_hot, const int32_t *seg_i,
-                       const int64_t *seg_e, int64_t nseg, int rw, double *part, hipStream_t s);
+                       const int64_t *seg_e, int64_t nseg, int rw, double *part, uint8_t *redo, hipStream_t s);
 hipError_t launch_pack_hot(const EmbedArgs &a, const int32_t *hot_ids, int64_t n_hot, void *hotlab, hipStream_t s);
 hipError_t launch_merge(const EmbedArgs &a, const int64_t *row_ptr, const int32_t *seg_i, const int64_t *seg_e,
                         int64_t nseg, const double *part, hipStream_t s);
@@ -116,6 +119,10 @@ size_t radix_scratch_bytes(int64_t N, int64_t scan_n, size_t *hist_bytes, size_t
 // buffers; *result is the buffer that holds the sorted keys.
 hipError_t radix_sort_bits(uint64_t *keys0, uint64_t *keys1, int64_t N, int lo, int hi, uint32_t *hist,
                            int64_t *offs, int64_t *scan_part, uint64_t **result, hipStream_t s);
+// The same with a float carried along with each key.
+hipError_t radix_sort_bits_kv(uint64_t *keys0, uint64_t *keys1, float *vals0, float *vals1, int64_t N, int lo, int hi,
+                              uint32_t *hist, int64_t *offs, int64_t *scan_part, uint64_t **rkeys, float **rvals,
+                              hipStream_t s);
 hipError_t max_scan_i64(const int64_t *in, int64_t N, int64_t *out, int64_t *scan_part, hipStream_t s); // inclusive
 hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t value, hipStream_t s);
 
@@ -137,22 +144,30 @@ struct PbLayout {
     int64_t cells = 0;
 };
 PbLayout pb_layout(int64_t n, int64_t n_lds);
-size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds);
-hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const int32_t *hot_ids,
-                           int64_t n_hot, int64_t n_lds, int32_t *colc, uint8_t *ul, int64_t *cell_start,
-                           uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, void *ws, int32_t *err,
-                           hipStream_t s);
+constexpr int kPbF32Terms = 128; // a weighted row block sums in FP32 when its rows have at most this many entries
+size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds, bool weighted);
+// val (CSR weights) null for a unit-weight layout; then vl and rb_flag are unused.
+hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const float *val,
+                           const int32_t *hot_ids, int64_t n_hot, int64_t n_lds, int32_t *colc, uint8_t *ul,
+                           int64_t *cell_start, uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids,
+                           float *vl, uint8_t *rb_flag, int64_t *meta, void *ws, int32_t *err, hipStream_t s);
 // tab: per-call scratch of (n_lds rounded up to 16) bytes.
-hipError_t launch_pb_gather(int64_t nnz, const PbLayout &L, int64_t n_lds, const int64_t *cell_start,
+// A layout whose fingerprint (meta) disagrees with n, nnz, n_lds and weighted raises
+// GEE_EVERTEX in err and is not read.
+hipError_t launch_pb_gather(int64_t n, int64_t nnz, const PbLayout &L, int64_t n_lds, const int64_t *cell_start,
                             const uint32_t *cell_count, const int32_t *colc, const int32_t *lds_ids,
-                            const uint8_t *lab, uint8_t *tab, uint8_t *yv, hipStream_t s);
+                            const int64_t *meta, bool weighted, const uint8_t *lab, uint8_t *tab, uint8_t *yv,
+                            int32_t *err, hipStream_t s);
 // slice_entries [ceil(n_slots / 2^17)]: entries whose column is a hot slot of that slice.
 hipError_t launch_pb_slice_entries(int64_t n_slots, const int32_t *hot_ids, const int64_t *row_ptr,
                                   int64_t *slice_entries, hipStream_t s);
 // ul and yv: 4-byte aligned, readable up to nnz + 32 (the gap before the tier included).
-hipError_t launch_pb_rows(int64_t n, int32_t K, const PbLayout &L, const int64_t *cell_start,
+// A cell outside the layout's nnz + 15 entries is read as empty and raises GEE_EVERTEX.
+// vl and rb_flag: a weighted layout's weights and row-block flags, else null.
+hipError_t launch_pb_rows(int64_t n, int64_t nnz, int32_t K, const PbLayout &L, const int64_t *cell_start,
                           const uint32_t *cell_count, const uint32_t *cell_word, const uint8_t *ul, const uint8_t *yv,
-                          const double *inv, float *Z, hipStream_t s);
+                          const float *vl, const uint8_t *rb_flag, const int64_t *meta, int64_t n_lds,
+                          const double *inv, float *Z, int32_t *err, hipStream_t s);
 
 // Labels from an embedding: out[u] = 1 + argmax_k Z[u][k] (first maximum; 0 for a row
 // with no positive entry); changed (nullable) is set to the number of rows where out

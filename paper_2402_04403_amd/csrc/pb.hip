@@ -46,6 +46,7 @@ constexpr int64_t kPbRows = (int64_t)1 << kPbRowBits;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 inline int grid_cap(int64_t items, int per_block)
 {
@@ -120,9 +121,9 @@ __global__ void k_pb_tier_start(const uint64_t *__restrict__ keys, int64_t nnz, 
 // is the row within its block; celllast[cell] = o + 1 for a cell's last entry. The gap
 // [h0, H0) gets column 0 and row 0. tier = {h0, H0} (null: no tier, h0 = H0 = nnz).
 __global__ void __launch_bounds__(kT)
-k_pb_finalize(const uint64_t *__restrict__ keys, int64_t nnz, int64_t n_rb, int32_t n_vcb,
-              const int64_t *__restrict__ tier, int32_t *__restrict__ colc, uint8_t *__restrict__ colb,
-              uint8_t *__restrict__ ul, int64_t *__restrict__ celllast)
+k_pb_finalize(const uint64_t *__restrict__ keys, const float *__restrict__ sval, int64_t nnz, int64_t n_rb,
+              int32_t n_vcb, const int64_t *__restrict__ tier, int32_t *__restrict__ colc, uint8_t *__restrict__ colb,
+              uint8_t *__restrict__ ul, float *__restrict__ vl, int64_t *__restrict__ celllast)
 {
     const int64_t h0 = tier ? tier[0] : nnz, H0 = tier ? tier[1] : nnz;
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gs = (int64_t)gridDim.x * blockDim.x;
@@ -130,6 +131,7 @@ k_pb_finalize(const uint64_t *__restrict__ keys, int64_t nnz, int64_t n_rb, int3
         const uint64_t k = keys[i];
         const uint64_t c = k >> 32;
         const int64_t o = i < h0 ? i : i + (H0 - h0);
+        if (vl) vl[o] = sval[i];
         if (i < h0) {
             colc[o] = (int32_t)c;
         } else {
@@ -146,6 +148,37 @@ k_pb_finalize(const uint64_t *__restrict__ keys, int64_t nnz, int64_t n_rb, int3
     for (int64_t i = h0 + gt; i < H0; i += gs) {
         colc[i] = 0;
         ul[i] = 0;
+        if (vl) vl[i] = 0.0f;
+    }
+}
+
+// rb_flag[rb] = 1 when a row of 256-row block rb has more than kPbF32Terms entries or
+// a weight that is not >= 0 (NaN included): such a block sums in FP64. One workgroup
+// per block: thread t checks row 256 rb + t, then the block's entries are scanned with
+// coalesced reads.
+__global__ void __launch_bounds__(kT)
+k_pb_rbflag(int64_t n, int64_t n_rb, const int64_t *__restrict__ row_ptr, const float *__restrict__ val,
+            uint8_t *__restrict__ rb_flag)
+{
+    for (int64_t rb = blockIdx.x; rb < n_rb; rb += gridDim.x) {
+        const int64_t r0 = rb * kPbRows, r1 = r0 + kPbRows < n ? r0 + kPbRows : n;
+        const int64_t u = r0 + threadIdx.x;
+        bool f = u < r1 && row_ptr[u + 1] - row_ptr[u] > kPbF32Terms;
+        for (int64_t e = row_ptr[r0] + threadIdx.x; e < row_ptr[r1]; e += kT) f |= !(val[e] >= 0.0f);
+        f = __syncthreads_or(f) != 0;
+        if (threadIdx.x == 0) rb_flag[rb] = f ? 1 : 0;
+        __syncthreads();
+    }
+}
+
+// The layout's fingerprint: n, nnz, n_lds, weighted.
+__global__ void k_pb_meta(int64_t *meta, int64_t n, int64_t nnz, int64_t n_lds, int64_t weighted)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        meta[0] = n;
+        meta[1] = nnz;
+        meta[2] = n_lds;
+        meta[3] = weighted;
     }
 }
 
@@ -212,14 +245,28 @@ k_pb_words(int64_t n_rb, int32_t n_cb, const int64_t *__restrict__ cell_start, c
 
 __device__ inline int64_t clamp_index(int64_t h, int64_t nnz) { return h < 0 ? 0 : (h > nnz ? nnz : h); }
 
+// The layout's fingerprint (written by its build) against the fields of the gee_pb it
+// came with. A layout built for another graph fails this, and every pass then skips its
+// work and raises GEE_EVERTEX: its columns need not lie in [0, n) of these labels.
+__device__ inline bool layout_matches(const int64_t *__restrict__ meta, int64_t n, int64_t nnz, int64_t n_lds,
+                                      bool weighted, int32_t *err)
+{
+    const bool ok = meta[0] == n && meta[1] == nnz && meta[2] == n_lds && meta[3] == (weighted ? 1 : 0);
+    if (!ok && threadIdx.x == 0 && blockIdx.x == 0) flag_error(err, GEE_EVERTEX);
+    return ok;
+}
+
 // yv[i] = lab[colc[i]] over the entries with vertex columns [0, h0), 32 entries per
 // thread: eight 16-byte loads of columns, their 32 label reads in flight together, and
 // two 16-byte stores of labels (32 entries measured faster than 16 or 64). h0 is the
-// first tier entry (*tier_start), or nnz without a tier (tier_start null).
+// first tier entry (*tier_start), or nnz without a tier (tier_start null). The columns
+// are the layout's own, all in [0, n) once its fingerprint matches.
 __global__ void __launch_bounds__(kT)
-k_pb_gather(int64_t nnz, const int64_t *__restrict__ tier_start, const int32_t *__restrict__ colc,
-            const uint8_t *__restrict__ lab, uint8_t *__restrict__ yv)
+k_pb_gather(int64_t nnz, int64_t n, int64_t n_lds, bool weighted, const int64_t *__restrict__ meta,
+            const int64_t *__restrict__ tier_start, const int32_t *__restrict__ colc, const uint8_t *__restrict__ lab,
+            uint8_t *__restrict__ yv, int32_t *err)
 {
+    if (!layout_matches(meta, n, nnz, n_lds, weighted, err)) return;
     const int64_t h0 = tier_start ? clamp_index(*tier_start, nnz) : nnz;
     const int64_t nvec = h0 / 32;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvec; v += (int64_t)gridDim.x * blockDim.x) {
@@ -241,14 +288,23 @@ k_pb_gather(int64_t nnz, const int64_t *__restrict__ tier_start, const int32_t *
         yv[i] = lab[colc[i]];
 }
 
-// tab[q] = lab[lds_ids[q]] for the n_lds tier slots, zero-padded to a multiple of 16.
+// tab[q] = lab[lds_ids[q]] for the n_lds tier slots, zero-padded to a multiple of 16; a
+// slot whose vertex is outside [0, n) gets label 0 and raises GEE_EVERTEX.
 __global__ void __launch_bounds__(kT)
-k_pb_tier_labels(int64_t n_lds, const int32_t *__restrict__ lds_ids, const uint8_t *__restrict__ lab,
-                 uint8_t *__restrict__ tab)
+k_pb_tier_labels(int64_t n_lds, int64_t n, int64_t nnz, bool weighted, const int64_t *__restrict__ meta,
+                 const int32_t *__restrict__ lds_ids, const uint8_t *__restrict__ lab, uint8_t *__restrict__ tab,
+                 int32_t *err)
 {
+    if (!layout_matches(meta, n, nnz, n_lds, weighted, err)) return;
     const int64_t padded = (n_lds + 15) / 16 * 16;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < padded; i += (int64_t)gridDim.x * blockDim.x)
-        tab[i] = i < n_lds ? lab[lds_ids[i]] : 0;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < padded; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = i < n_lds ? lds_ids[i] : 0;
+        const bool ok = (uint64_t)(uint32_t)v < (uint64_t)n;
+        bad |= !ok;
+        tab[i] = (i < n_lds && ok) ? lab[v] : 0;
+    }
+    if (bad) flag_error(err, GEE_EVERTEX);
 }
 
 // The slot of tier entry i: 3 bytes at colb[4 H0 + 3 (i - H0)].
@@ -266,11 +322,13 @@ __device__ inline uint32_t tier_slot(const uint8_t *colb, int64_t H0, int64_t i)
 // them there. Sixteen entries' slots are three 16-byte loads. Slots are masked to the
 // table, so no LDS read leaves it.
 __global__ void __launch_bounds__(kLdsT)
-k_pb_gather_tier(int64_t nnz, int32_t n_sl, int64_t n_lds, const int64_t *__restrict__ sl_start,
-                 const int64_t *__restrict__ last_start, const uint32_t *__restrict__ last_count,
-                 const uint8_t *__restrict__ colb, const uint8_t *__restrict__ tab, uint8_t *__restrict__ yv)
+k_pb_gather_tier(int64_t nnz, int64_t n, bool weighted, const int64_t *__restrict__ meta, int32_t n_sl, int64_t n_lds,
+                 const int64_t *__restrict__ sl_start, const int64_t *__restrict__ last_start,
+                 const uint32_t *__restrict__ last_count, const uint8_t *__restrict__ colb,
+                 const uint8_t *__restrict__ tab, uint8_t *__restrict__ yv, int32_t *err)
 {
     extern __shared__ __align__(16) uint8_t stab[];
+    if (!layout_matches(meta, n, nnz, n_lds, weighted, err)) return;
     __shared__ int64_t bnd[kPbMaxSlices + 1];
     const int t = threadIdx.x;
     const int64_t lim = nnz + 16; // entries of the layout, gap included, are at most nnz + 15
@@ -294,11 +352,24 @@ k_pb_gather_tier(int64_t nnz, int32_t n_sl, int64_t n_lds, const int64_t *__rest
         for (int i = t; i < (int)((nj + 15) / 16); i += kLdsT) reinterpret_cast<uint4 *>(stab)[i] = src[i];
         __syncthreads();
         const int64_t v0 = (a + 15) / 16, v1 = b / 16;
-        for (int64_t v = v0 + t; v < v1; v += kLdsT) {
-            // entries 16 v .. 16 v + 15: 48 bytes at 4 H0 + 3 (16 v - H0), 16-byte aligned
+        // entries 16 v .. 16 v + 15: 48 bytes at 4 H0 + 3 (16 v - H0), 16-byte aligned. The
+        // slots of a lane's next 16 entries are loaded before its current ones are looked
+        // up, so two loads per lane are in flight while the LDS reads run.
+        auto slots = [&](int64_t v, uint4 (&q)[3]) {
             const uint4 *cp = reinterpret_cast<const uint4 *>(colb + 4 * H0 + 48 * (v - H0 / 16));
-            const uint4 q0 = cp[0], q1 = cp[1], q2 = cp[2];
-            const uint32_t x[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+            q[0] = cp[0];
+            q[1] = cp[1];
+            q[2] = cp[2];
+        };
+        int64_t v = v0 + t;
+        uint4 cur[3] = {};
+        if (v < v1) slots(v, cur);
+        while (v < v1) {
+            const int64_t vn = v + kLdsT;
+            uint4 nxt[3] = {};
+            if (vn < v1) slots(vn, nxt);
+            const uint32_t x[12] = {cur[0].x, cur[0].y, cur[0].z, cur[0].w, cur[1].x, cur[1].y,
+                                    cur[1].z, cur[1].w, cur[2].x, cur[2].y, cur[2].z, cur[2].w};
             uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
@@ -307,6 +378,9 @@ k_pb_gather_tier(int64_t nnz, int32_t n_sl, int64_t n_lds, const int64_t *__rest
                 w[e / 4] |= (uint32_t)stab[slot & mask] << (8 * (e % 4));
             }
             *reinterpret_cast<uint4 *>(yv + v * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) cur[i] = nxt[i];
+            v = vn;
         }
         // entries outside the 16-aligned run: the head [a, 16 v0) and the tail [16 v1, b)
         const int64_t head_end = v0 * 16 < b ? v0 * 16 : b;
@@ -325,18 +399,33 @@ k_pb_gather_tier(int64_t nnz, int32_t n_sl, int64_t n_lds, const int64_t *__rest
 // bins [row][class]; then the rows of Z are written once (count * 1/n_k), four
 // floats at a time when Z is 16-byte aligned (VEC). The word prefix of the cells comes
 // with the layout (cell_word).
-template <bool VEC>
+//
+// HALF (many classes): the bins take half the LDS, so more workgroups share a CU. A
+// unit-weight block of at most 4 * 16383 entries counts into 16-bit halves of 32-bit
+// words (no count can reach 2^16, so none carries into its neighbour); a larger block
+// is counted in two passes over its words, rows 0-127 and then rows 128-255, each into
+// 32-bit bins.
+//
+// WT (weighted layout): the bins hold sums of the entries' weights. A block whose flag
+// is 0 (rows of at most kPbF32Terms entries, no negative weight) sums in FP32; a
+// flagged block in FP64. The bins' LDS holds R rows of either (R = 256 or 128 for FP32,
+// half that for FP64), and the block's rows are taken R at a time, one pass over its
+// words each.
+template <bool VEC, bool HALF, bool WT>
 __global__ void __launch_bounds__(kRowsT)
-k_pb_rows(int64_t n, int32_t K, uint64_t magicK, int32_t n_cb, int32_t top, const int64_t *__restrict__ cell_start,
+k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ meta, int64_t lim, int32_t K,
+          uint64_t magicK, int32_t n_cb, int32_t top, const int64_t *__restrict__ cell_start,
           const uint32_t *__restrict__ cell_count, const uint32_t *__restrict__ cell_word,
-          const uint32_t *__restrict__ ul4, const uint32_t *__restrict__ yv4, const double *__restrict__ inv,
-          float *__restrict__ Z)
+          const uint32_t *__restrict__ ul4, const uint32_t *__restrict__ yv4, const f32x4 *__restrict__ vl4,
+          const uint8_t *__restrict__ rb_flag, const double *__restrict__ inv, float *__restrict__ Z, int32_t *err)
 {
-    // LDS: bins [nb] uint32 (nb = 256 K rounded up to 4), invx [K + 3] double
-    // (invx[i] = 1/n_(i mod K) + 1), per cell: first word [n_cb] int64, word prefix
-    // [n_cb + 1], entry count [n_cb], byte offset of the start in its word [n_cb].
+    // LDS: bins [nb] uint32 (nb = 256 K, or 128 K for HALF, rounded up to 4), invx
+    // [K + 3] double (invx[i] = 1/n_(i mod K) + 1), per cell: first word [n_cb] int64,
+    // word prefix [n_cb + 1], entry count [n_cb], byte offset of the start in its word
+    // [n_cb].
     extern __shared__ __align__(16) uint32_t bins[];
-    const uint32_t nb = (uint32_t)align_up((size_t)kPbRows * K, 4);
+    if (!layout_matches(meta, n, nnz, n_lds, WT, err)) return;
+    const uint32_t nb = (uint32_t)align_up((size_t)(HALF ? kPbRows / 2 : kPbRows) * K, 4);
     double *invx = reinterpret_cast<double *>(bins + nb);
     int64_t *cw0 = reinterpret_cast<int64_t *>(invx + K + 3);
     uint32_t *pre = reinterpret_cast<uint32_t *>(cw0 + n_cb);
@@ -356,8 +445,16 @@ k_pb_rows(int64_t n, int32_t K, uint64_t magicK, int32_t n_cb, int32_t top, cons
     for (uint32_t i = t; i < nb / 4; i += kRowsT) reinterpret_cast<u32x4 *>(bins)[i] = u32x4{0u, 0u, 0u, 0u};
     for (int i = t; i < K + 3; i += kRowsT) invx[i] = inv[1 + i % K];
     for (int c = t; c < n_cb; c += kRowsT) {
-        const int64_t a = cell_start[rb * n_cb + c];
-        const uint32_t m = cell_count[rb * n_cb + c], p = cell_word[rb * n_cb + c];
+        int64_t a = cell_start[rb * n_cb + c];
+        uint32_t m = cell_count[rb * n_cb + c];
+        const uint32_t p = cell_word[rb * n_cb + c];
+        // a cell must lie inside the layout's entries [0, lim): one that does not (a layout
+        // that is not what it claims) is read as empty and raises GEE_EVERTEX
+        if (a < 0 || a > lim || (int64_t)m > lim - a) {
+            flag_error(err, GEE_EVERTEX);
+            a = 0;
+            m = 0u;
+        }
         cw0[c] = a >> 2;
         cm[c] = m;
         coff[c] = (uint32_t)(a & 3);
@@ -366,71 +463,161 @@ k_pb_rows(int64_t n, int32_t K, uint64_t magicK, int32_t n_cb, int32_t top, cons
     }
     __syncthreads();
     const uint32_t T = pre[n_cb];
-    for (uint32_t f0 = (uint32_t)(wave * kWave + lane); f0 < T; f0 += kRowsU * kRowsT) {
-        uint32_t u[kRowsU], y[kRowsU], rel[kRowsU], m[kRowsU];
-        // the cells of the kRowsU words, by binary searches run in step: each step reads
-        // pre[] once per word (an index past the last cell reads pre[n_cb] = T, which
-        // no word reaches), so the reads of one step are in flight together
-        int cs[kRowsU];
+    const int64_t wlim = (lim + 3) / 4; // the last word holding layout entries
+
+    // every entry (ub, yb) of the block's cells with a known class, to add(ub, yb, weight)
+    // (the weight is 1 for a unit-weight layout)
+    auto count = [&](auto add) __attribute__((always_inline)) {
+        for (uint32_t f0 = (uint32_t)(wave * kWave + lane); f0 < T; f0 += kRowsU * kRowsT) {
+            uint32_t u[kRowsU], y[kRowsU], rel[kRowsU], m[kRowsU];
+            f32x4 wq[kRowsU];
+            // the cells of the kRowsU words, by binary searches run in step: each step reads
+            // pre[] once per word (an index past the last cell reads pre[n_cb] = T, which
+            // no word reaches), so the reads of one step are in flight together
+            int cs[kRowsU];
 #pragma unroll
-        for (int j = 0; j < kRowsU; ++j) cs[j] = 0;
-        for (int st = top; st > 0; st >>= 1) {
-            uint32_t p[kRowsU];
+            for (int j = 0; j < kRowsU; ++j) cs[j] = 0;
+            for (int st = top; st > 0; st >>= 1) {
+                uint32_t p[kRowsU];
+#pragma unroll
+                for (int j = 0; j < kRowsU; ++j) {
+                    const int nc = cs[j] + st;
+                    p[j] = pre[nc < n_cb ? nc : n_cb];
+                }
+#pragma unroll
+                for (int j = 0; j < kRowsU; ++j)
+                    cs[j] = p[j] <= f0 + (uint32_t)j * kRowsT ? cs[j] + st : cs[j];
+            }
 #pragma unroll
             for (int j = 0; j < kRowsU; ++j) {
-                const int nc = cs[j] + st;
-                p[j] = pre[nc < n_cb ? nc : n_cb];
+                const uint32_t f = f0 + (uint32_t)j * kRowsT;
+                u[j] = 0u;
+                y[j] = 0u;
+                rel[j] = 0u;
+                m[j] = 0u;
+                wq[j] = f32x4{1.0f, 1.0f, 1.0f, 1.0f};
+                if (f < T) {
+                    const int c = cs[j];
+                    const uint32_t k = f - pre[c];
+                    // the word prefix comes with the layout: a word index it would carry past
+                    // the layout's words (an inconsistent prefix) is clamped into them, and
+                    // the entries it then reads lie outside the cell's count, so none is added
+                    int64_t w = cw0[c] + k;
+                    w = w < wlim ? w : wlim;
+                    u[j] = ul4[w];
+                    y[j] = yv4[w];
+                    if (WT) wq[j] = vl4[w];
+                    rel[j] = 4u * k - coff[c]; // entry index within the cell of the word's byte 0 (mod 2^32)
+                    m[j] = cm[c];
+                }
             }
 #pragma unroll
-            for (int j = 0; j < kRowsU; ++j)
-                cs[j] = p[j] <= f0 + (uint32_t)j * kRowsT ? cs[j] + st : cs[j];
-        }
+            for (int j = 0; j < kRowsU; ++j) {
 #pragma unroll
-        for (int j = 0; j < kRowsU; ++j) {
-            const uint32_t f = f0 + (uint32_t)j * kRowsT;
-            u[j] = 0u;
-            y[j] = 0u;
-            rel[j] = 0u;
-            m[j] = 0u;
-            if (f < T) {
-                const int c = cs[j];
-                const uint32_t k = f - pre[c];
-                const int64_t w = cw0[c] + k;
-                u[j] = ul4[w];
-                y[j] = yv4[w];
-                rel[j] = 4u * k - coff[c]; // entry index within the cell of the word's byte 0 (mod 2^32)
-                m[j] = cm[c];
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t yb = (y[j] >> (8 * b)) & 0xffu;
+                    const uint32_t ub = (u[j] >> (8 * b)) & 0xffu;
+                    if (yb != 0u && rel[j] + (uint32_t)b < m[j]) add(ub, yb, wq[j][b]);
+                }
             }
         }
-#pragma unroll
-        for (int j = 0; j < kRowsU; ++j) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const uint32_t yb = (y[j] >> (8 * b)) & 0xffu;
-                const uint32_t ub = (u[j] >> (8 * b)) & 0xffu;
-                if (yb != 0u && rel[j] + (uint32_t)b < m[j]) atomicAdd(&bins[ub * (uint32_t)K + (yb - 1u)], 1u);
+    };
+    // rows [lo, hi) of the block to Z from the bins, get4(g) giving the four sums of flat
+    // elements g .. g + 3 (g a multiple of 4) and get1(g) one, g counted from row lo;
+    // 16-byte stores when VEC (Z 16-byte aligned and lo K a multiple of 4)
+    auto write = [&](int lo, int hi, auto get4, auto get1) __attribute__((always_inline)) {
+        float *zb = Z + (r0 + lo) * K;
+        const uint32_t total = (uint32_t)(hi - lo) * (uint32_t)K;
+        uint32_t done = 0;
+        if (VEC) {
+            const uint32_t nv = total / 4;
+            for (uint32_t v = t; v < nv; v += kRowsT) {
+                const uint32_t f = 4u * v;
+                const uint32_t k = f - div_small(f, magicK) * (uint32_t)K;
+                const auto c = get4(f);
+                const f32x4 o = {(float)((double)c.x * invx[k]), (float)((double)c.y * invx[k + 1]),
+                                 (float)((double)c.z * invx[k + 2]), (float)((double)c.w * invx[k + 3])};
+                __builtin_nontemporal_store(o, reinterpret_cast<f32x4 *>(zb) + v);
             }
+            done = nv * 4;
         }
-    }
-    __syncthreads();
-    float *zb = Z + r0 * K;
-    const uint32_t total = (uint32_t)nr * (uint32_t)K;
-    uint32_t done = 0;
-    if (VEC) {
-        const uint32_t nv = total / 4;
-        for (uint32_t v = t; v < nv; v += kRowsT) {
-            const uint32_t f = 4u * v;
+        for (uint32_t f = done + t; f < total; f += kRowsT) {
             const uint32_t k = f - div_small(f, magicK) * (uint32_t)K;
-            const u32x4 c = reinterpret_cast<const u32x4 *>(bins)[v];
-            const f32x4 o = {(float)((double)c.x * invx[k]), (float)((double)c.y * invx[k + 1]),
-                             (float)((double)c.z * invx[k + 2]), (float)((double)c.w * invx[k + 3])};
-            __builtin_nontemporal_store(o, reinterpret_cast<f32x4 *>(zb) + v);
+            __builtin_nontemporal_store((float)((double)get1(f) * invx[k]), zb + f);
         }
-        done = nv * 4;
+    };
+    auto zero = [&]() __attribute__((always_inline)) {
+        __syncthreads(); // the previous rows are written
+        for (uint32_t i = t; i < nb / 4; i += kRowsT) reinterpret_cast<u32x4 *>(bins)[i] = u32x4{0u, 0u, 0u, 0u};
+        __syncthreads();
+    };
+    if constexpr (WT) {
+        float *fb = reinterpret_cast<float *>(bins);
+        double *db = reinterpret_cast<double *>(bins);
+        const bool wide = rb_flag[rb] != 0;
+        int R = (int)(nb / (uint32_t)(wide ? 2 * K : K));
+        R = R < kPbRows ? R : kPbRows;
+        for (int lo = 0; lo < nr; lo += R) {
+            if (lo > 0) zero();
+            const int hi = nr < lo + R ? nr : lo + R;
+            if (wide) {
+                count([&](uint32_t ub, uint32_t yb, float w) {
+                    if (ub - (uint32_t)lo < (uint32_t)R)
+                        atomicAdd(&db[(ub - (uint32_t)lo) * (uint32_t)K + (yb - 1u)], (double)w);
+                });
+                __syncthreads();
+                write(
+                    lo, hi,
+                    [&](uint32_t f) {
+                        const double2 a = reinterpret_cast<const double2 *>(db)[f / 2];
+                        const double2 b = reinterpret_cast<const double2 *>(db)[f / 2 + 1];
+                        return f64x4{a.x, a.y, b.x, b.y};
+                    },
+                    [&](uint32_t f) { return db[f]; });
+            } else {
+                count([&](uint32_t ub, uint32_t yb, float w) {
+                    if (ub - (uint32_t)lo < (uint32_t)R) atomicAdd(&fb[(ub - (uint32_t)lo) * (uint32_t)K + (yb - 1u)], w);
+                });
+                __syncthreads();
+                write(
+                    lo, hi, [&](uint32_t f) { return reinterpret_cast<const f32x4 *>(fb)[f / 4]; },
+                    [&](uint32_t f) { return fb[f]; });
+            }
+        }
+        return;
     }
-    for (uint32_t f = done + t; f < total; f += kRowsT) {
-        const uint32_t k = f - div_small(f, magicK) * (uint32_t)K;
-        __builtin_nontemporal_store((float)((double)bins[f] * invx[k]), zb + f);
+    auto get4_32 = [&](uint32_t f) { return reinterpret_cast<const u32x4 *>(bins)[f / 4]; };
+    auto get1_32 = [&](uint32_t f) { return bins[f]; };
+    if (!HALF) {
+        count([&](uint32_t ub, uint32_t yb, float) { atomicAdd(&bins[ub * (uint32_t)K + (yb - 1u)], 1u); });
+        __syncthreads();
+        write(0, nr, get4_32, get1_32);
+        return;
+    }
+    if (T <= 16383u) {
+        // at most 65532 entries: 16-bit counts, element f in half (f & 1) of word f / 2
+        count([&](uint32_t ub, uint32_t yb, float) {
+            const uint32_t f = ub * (uint32_t)K + (yb - 1u);
+            atomicAdd(&bins[f >> 1], 1u << (16u * (f & 1u)));
+        });
+        __syncthreads();
+        write(
+            0, nr,
+            [&](uint32_t f) {
+                const uint2 w = reinterpret_cast<const uint2 *>(bins)[f / 4];
+                return u32x4{w.x & 0xffffu, w.x >> 16, w.y & 0xffffu, w.y >> 16};
+            },
+            [&](uint32_t f) { return (bins[f >> 1] >> (16u * (f & 1u))) & 0xffffu; });
+        return;
+    }
+    for (int h = 0; h < 2 && h * (kPbRows / 2) < nr; ++h) {
+        if (h == 1) zero();
+        count([&](uint32_t ub, uint32_t yb, float) {
+            if ((ub >> 7) == (uint32_t)h) atomicAdd(&bins[(ub & 127u) * (uint32_t)K + (yb - 1u)], 1u);
+        });
+        __syncthreads();
+        const int lo = h * (kPbRows / 2), hi = nr < lo + kPbRows / 2 ? nr : lo + kPbRows / 2;
+        write(lo, hi, get4_32, get1_32);
     }
 }
 
@@ -448,7 +635,7 @@ PbLayout pb_layout(int64_t n, int64_t n_lds)
 }
 
 // Build scratch: two key buffers [nnz], radix histograms, scan partials, two cell arrays.
-size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds)
+size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds, bool weighted)
 {
     const PbLayout L = pb_layout(n, n_lds);
     size_t hb, ob, pbytes;
@@ -466,13 +653,17 @@ size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds)
     take((size_t)L.cells * 8);
     take((size_t)L.cells * 8);
     take(16);
+    if (weighted) {
+        take((size_t)nnz * 4);
+        take((size_t)nnz * 4);
+    }
     return align_up(off, 256);
 }
 
-hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const int32_t *hot_ids,
-                           int64_t n_hot, int64_t n_lds, int32_t *colc, uint8_t *ul, int64_t *cell_start,
-                           uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, void *ws, int32_t *err,
-                           hipStream_t s)
+hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const float *val,
+                           const int32_t *hot_ids, int64_t n_hot, int64_t n_lds, int32_t *colc, uint8_t *ul,
+                           int64_t *cell_start, uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids,
+                           float *vl, uint8_t *rb_flag, int64_t *meta, void *ws, int32_t *err, hipStream_t s)
 {
     const PbLayout L = pb_layout(n, n_lds);
     size_t hb, ob, pbytes;
@@ -493,8 +684,21 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
     int64_t *celllast = (int64_t *)take((size_t)L.cells * 8);
     int64_t *cellend = (int64_t *)take((size_t)L.cells * 8);
     int64_t *tier = L.n_sl > 0 ? (int64_t *)take(16) : nullptr; // {h0, H0}
+    if (!tier) take(16);
+    float *v0 = val ? (float *)take((size_t)nnz * 4) : nullptr;
+    float *v1 = val ? (float *)take((size_t)nnz * 4) : nullptr;
+    float *sval = nullptr; // weights in sorted order
     hipError_t e;
     const dim3 b(kT);
+    hipLaunchKernelGGL(k_pb_meta, dim3(1), dim3(kWave), 0, s, meta, n, nnz, n_lds, (int64_t)(val != nullptr));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (val) {
+        hipLaunchKernelGGL(k_pb_rbflag, dim3(grid_cap(L.n_rb, 1)), b, 0, s, n, L.n_rb, row_ptr, val, rb_flag);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (nnz > 0 && (e = hipMemcpyAsync(v0, val, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            return e;
+        sval = v0;
+    }
     if (n_lds > 0 && (e = hipMemcpyAsync(lds_ids, hot_ids, (size_t)n_lds * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess)
         return e;
     if (nnz > 0) {
@@ -513,16 +717,22 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
         if (L.n_cb > 1) {
             int hi = 32 + kPbColBits;
             while (hi < 64 && ((int64_t)1 << (hi - 32 - kPbColBits)) < L.n_cb) ++hi;
-            if ((e = radix_sort_bits(k0, k1, nnz, 32 + kPbColBits, hi, hist, offs, part, &sorted, s)) != hipSuccess)
+            if (val) {
+                if ((e = radix_sort_bits_kv(k0, k1, v0, v1, nnz, 32 + kPbColBits, hi, hist, offs, part, &sorted, &sval,
+                                            s)) != hipSuccess)
+                    return e;
+            } else if ((e = radix_sort_bits(k0, k1, nnz, 32 + kPbColBits, hi, hist, offs, part, &sorted, s)) !=
+                       hipSuccess) {
                 return e;
+            }
         }
         if ((e = launch_fill_i64(celllast, L.cells, 0, s)) != hipSuccess) return e;
         if (tier) {
             hipLaunchKernelGGL(k_pb_tier_start, dim3(1), dim3(kWave), 0, s, sorted, nnz, L.n_vcb, tier);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(k_pb_finalize, dim3(grid_cap(nnz, kT * 4)), b, 0, s, sorted, nnz, L.n_rb, L.n_vcb, tier,
-                           colc, reinterpret_cast<uint8_t *>(colc), ul, celllast);
+        hipLaunchKernelGGL(k_pb_finalize, dim3(grid_cap(nnz, kT * 4)), b, 0, s, sorted, sval, nnz, L.n_rb, L.n_vcb,
+                           tier, colc, reinterpret_cast<uint8_t *>(colc), ul, vl, celllast);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
         if ((e = launch_fill_i64(celllast, L.cells, 0, s)) != hipSuccess) return e;
@@ -537,18 +747,21 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
     return hipGetLastError();
 }
 
-hipError_t launch_pb_gather(int64_t nnz, const PbLayout &L, int64_t n_lds, const int64_t *cell_start,
+hipError_t launch_pb_gather(int64_t n, int64_t nnz, const PbLayout &L, int64_t n_lds, const int64_t *cell_start,
                             const uint32_t *cell_count, const int32_t *colc, const int32_t *lds_ids,
-                            const uint8_t *lab, uint8_t *tab, uint8_t *yv, hipStream_t s)
+                            const int64_t *meta, bool weighted, const uint8_t *lab, uint8_t *tab, uint8_t *yv,
+                            int32_t *err, hipStream_t s)
 {
     if (nnz <= 0) return hipSuccess;
     const int64_t *sl_start = L.n_sl > 0 ? cell_start + L.n_vcb : nullptr; // cells (0, n_vcb + j)
     // vertex blocks: one workgroup per 8,192 entries, dispatched in order, so the entries
     // in flight stay within one or two column blocks (their labels in L2)
-    hipLaunchKernelGGL(k_pb_gather, dim3(grid_cap(nnz, kT * 32)), dim3(kT), 0, s, nnz, sl_start, colc, lab, yv);
+    hipLaunchKernelGGL(k_pb_gather, dim3(grid_cap(nnz, kT * 32)), dim3(kT), 0, s, nnz, n, n_lds, weighted, meta,
+                       sl_start, colc, lab, yv, err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || L.n_sl == 0) return e;
-    hipLaunchKernelGGL(k_pb_tier_labels, dim3(grid_cap(n_lds, kT * 4)), dim3(kT), 0, s, n_lds, lds_ids, lab, tab);
+    hipLaunchKernelGGL(k_pb_tier_labels, dim3(grid_cap(n_lds, kT * 4)), dim3(kT), 0, s, n_lds, n, nnz, weighted, meta,
+                       lds_ids, lab, tab, err);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
@@ -558,9 +771,9 @@ hipError_t launch_pb_gather(int64_t nnz, const PbLayout &L, int64_t n_lds, const
     if (grid > cus) grid = cus;
     if (grid < 1) grid = 1;
     const int64_t last = L.cells - 1; // the last cell of the column-block-major order
-    hipLaunchKernelGGL(k_pb_gather_tier, dim3((unsigned)grid), dim3(kLdsT), (size_t)kPbSlice, s, nnz, L.n_sl, n_lds,
-                       sl_start, cell_start + last, cell_count + last, reinterpret_cast<const uint8_t *>(colc), tab,
-                       yv);
+    hipLaunchKernelGGL(k_pb_gather_tier, dim3((unsigned)grid), dim3(kLdsT), (size_t)kPbSlice, s, nnz, n, weighted,
+                       meta, L.n_sl, n_lds, sl_start, cell_start + last, cell_count + last,
+                       reinterpret_cast<const uint8_t *>(colc), tab, yv, err);
     return hipGetLastError();
 }
 
@@ -574,28 +787,50 @@ hipError_t launch_pb_slice_entries(int64_t n_slots, const int32_t *hot_ids, cons
     return hipGetLastError();
 }
 
-size_t pb_rows_lds_bytes(int32_t K, int32_t n_cb)
+size_t pb_rows_lds_bytes(int32_t K, int32_t n_cb, bool half)
 {
-    return align_up((size_t)kPbRows * K, 4) * 4 + (size_t)(K + 3) * 8 + (size_t)n_cb * 8 + (size_t)(n_cb + 1) * 4 +
-           (size_t)n_cb * 8;
+    return align_up((size_t)(half ? kPbRows / 2 : kPbRows) * K, 4) * 4 + (size_t)(K + 3) * 8 + (size_t)n_cb * 8 +
+           (size_t)(n_cb + 1) * 4 + (size_t)n_cb * 8;
 }
 
-hipError_t launch_pb_rows(int64_t n, int32_t K, const PbLayout &L, const int64_t *cell_start,
+// 16-bit (HALF) bins when 32-bit bins would leave fewer than three workgroups per CU
+// (160 KB of LDS), as they do from about 52 classes up.
+bool pb_rows_half(int32_t K, int32_t n_cb) { return 3 * pb_rows_lds_bytes(K, n_cb, false) > 160 * 1024; }
+
+hipError_t launch_pb_rows(int64_t n, int64_t nnz, int32_t K, const PbLayout &L, const int64_t *cell_start,
                           const uint32_t *cell_count, const uint32_t *cell_word, const uint8_t *ul, const uint8_t *yv,
-                          const double *inv, float *Z, hipStream_t s)
+                          const float *vl, const uint8_t *rb_flag, const int64_t *meta, int64_t n_lds,
+                          const double *inv, float *Z, int32_t *err, hipStream_t s)
 {
-    const size_t lds = pb_rows_lds_bytes(K, L.n_cb);
+    const int64_t lim = nnz + 15; // layout entries, the gap before the tier included
+    const bool half = pb_rows_half(K, L.n_cb);
+    const size_t lds = pb_rows_lds_bytes(K, L.n_cb, half);
     const uint64_t magic = ((1ull << 32) + (uint64_t)K - 1) / (uint64_t)K;
     int top = 1;
     while (top * 2 <= L.n_cb - 1) top *= 2;
     const uint32_t *ul4 = reinterpret_cast<const uint32_t *>(ul);
     const uint32_t *yv4 = reinterpret_cast<const uint32_t *>(yv);
-    if ((reinterpret_cast<uintptr_t>(Z) & 15) == 0)
-        hipLaunchKernelGGL(k_pb_rows<true>, dim3((unsigned)L.n_rb), dim3(kRowsT), lds, s, n, K, magic, L.n_cb, top,
-                           cell_start, cell_count, cell_word, ul4, yv4, inv, Z);
-    else
-        hipLaunchKernelGGL(k_pb_rows<false>, dim3((unsigned)L.n_rb), dim3(kRowsT), lds, s, n, K, magic, L.n_cb, top,
-                           cell_start, cell_count, cell_word, ul4, yv4, inv, Z);
+    const f32x4 *vl4 = reinterpret_cast<const f32x4 *>(vl);
+    const bool vec = (reinterpret_cast<uintptr_t>(Z) & 15) == 0;
+#define GEE_ROWS(V, H, W)                                                                                            \
+    hipLaunchKernelGGL((k_pb_rows<V, H, W>), dim3((unsigned)L.n_rb), dim3(kRowsT), lds, s, n, nnz, n_lds, meta, lim, \
+                       K, magic, L.n_cb, top, cell_start, cell_count, cell_word, ul4, yv4, vl4, rb_flag, inv, Z, err)
+    if (vl) {
+        if (half) {
+            if (vec) GEE_ROWS(true, true, true);
+            else GEE_ROWS(false, true, true);
+        } else {
+            if (vec) GEE_ROWS(true, false, true);
+            else GEE_ROWS(false, false, true);
+        }
+    } else if (half) {
+        if (vec) GEE_ROWS(true, true, false);
+        else GEE_ROWS(false, true, false);
+    } else {
+        if (vec) GEE_ROWS(true, false, false);
+        else GEE_ROWS(false, false, false);
+    }
+#undef GEE_ROWS
     return hipGetLastError();
 }
 

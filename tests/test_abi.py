@@ -199,38 +199,54 @@ def test_pb_argument_errors(lib):
     assert lib.gee_pb_build_workspace(ctypes.byref(plain), 1) == 0    # no hot slots to put in the tier
     assert lib.gee_pb_build_workspace(ctypes.byref(hot), 700) > 10_000 * 16
     assert lib.gee_pb_build_workspace(ctypes.byref(hot), 701) == 0
-    assert lib.gee_pb_build_workspace(ctypes.byref(weighted), 0) == 0  # unit weights only
+    assert lib.gee_pb_build_workspace(ctypes.byref(weighted), 0) > lib.gee_pb_build_workspace(ctypes.byref(plain), 0)
     assert lib.gee_pb_build_workspace(ctypes.byref(huge), 0) == 0      # 32-bit cell lengths
-    assert lib.gee_pb_build(ctypes.byref(huge), 0, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 40, FAKE, None) == \
-        gee.GEE_EOVERFLOW
-    assert lib.gee_pb_build(ctypes.byref(hot), 700, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, 1 << 40, FAKE,
-                            None) == gee.GEE_EINVAL  # lds_ids needed
-    assert lib.gee_pb_build(ctypes.byref(hot), 701, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 40, FAKE,
-                            None) == gee.GEE_EINVAL  # more tier slots than hot slots
-    assert lib.gee_pb_build(ctypes.byref(plain), 0, FAKE, FAKE + 4, FAKE, FAKE, FAKE, None, FAKE, 1 << 40, FAKE,
-                            None) == gee.GEE_EINVAL  # ul 16-byte aligned
-    assert lib.gee_pb_build(ctypes.byref(plain), 0, FAKE, FAKE, FAKE, FAKE, None, None, FAKE, 1 << 40, FAKE,
-                            None) == gee.GEE_EINVAL  # cell_word needed
+    def build(c, tier, col=FAKE, ul=FAKE, word=FAKE, ids=FAKE, val=None, flag=None, meta=FAKE, wsb=1 << 40):
+        return lib.gee_pb_build(ctypes.byref(c), tier, col, ul, FAKE, FAKE, word, ids, val, flag, meta, FAKE, wsb,
+                                FAKE, None)
+
+    assert build(huge, 0) == gee.GEE_EOVERFLOW
+    assert build(hot, 700, ids=None) == gee.GEE_EINVAL  # lds_ids needed
+    assert build(hot, 701) == gee.GEE_EINVAL  # more tier slots than hot slots
+    assert build(plain, 0, ul=FAKE + 4) == gee.GEE_EINVAL  # ul 16-byte aligned
+    assert build(plain, 0, word=None) == gee.GEE_EINVAL  # cell_word needed
+    assert build(plain, 0, meta=None) == gee.GEE_EINVAL  # the fingerprint is written by every build
+    assert build(plain, 0, val=FAKE, flag=FAKE) == gee.GEE_EINVAL  # no weights to lay out
+    assert build(weighted, 0, val=FAKE, flag=None) == gee.GEE_EINVAL  # row-block flags needed
+    assert build(weighted, 0, val=None, flag=FAKE) == gee.GEE_EINVAL  # weights needed
+    assert build(weighted, 0, val=FAKE + 4, flag=FAKE) == gee.GEE_EINVAL  # weights 16-byte aligned
+    assert build(weighted, 0, val=FAKE, flag=FAKE, wsb=lib.gee_pb_build_workspace(ctypes.byref(weighted), 0) - 1) == \
+        gee.GEE_EWORKSPACE
     # the tier planner: nothing to plan without hot slots; checks before any launch
     assert lib.gee_pb_tier_slots(ctypes.byref(plain), 4, None, 0, None) == 0
     assert lib.gee_pb_tier_slots(ctypes.byref(hot), 4, None, 0, None) == gee.GEE_EWORKSPACE
     assert lib.gee_pb_tier_slots(ctypes.byref(hot), -1, FAKE, 512, None) == gee.GEE_EINVAL
     assert lib.gee_pb_tier_slots(ctypes.byref(hot), 4, FAKE, 256, None) == gee.GEE_EWORKSPACE
     assert lib.gee_pb_tier_slots(None, 4, FAKE, 256, None) == gee.GEE_EINVAL
-    pb = gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 0, None, FAKE)
+    pb = gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 0, None, FAKE, None, None, FAKE)
     assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 128) > 10_000
     assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 129) == 0
     assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 0) == 0
-    tiered = gee.Pb(1000, 10_000, 4, 2, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE)
+    tiered = gee.Pb(1000, 10_000, 4, 2, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, None, None, FAKE)
+    assert lib.gee_embed_pb_workspace(ctypes.byref(tiered), 8) > 10_000
+    weighted_pb = gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 0, None, FAKE, FAKE, FAKE, FAKE)
+    assert lib.gee_embed_pb_workspace(ctypes.byref(weighted_pb), 8) > 10_000
     assert lib.gee_embed_pb_workspace(ctypes.byref(tiered), 8) > 10_000
     o = gee.EmbedOpts(0, 0, None, None)
-    for bad in (gee.Pb(1000, 10_000, 5, 1, FAKE, FAKE, FAKE, FAKE, 0, None, FAKE),  # n_rb does not match n
-                gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE),  # n_cb without the tier slice
-                gee.Pb(1000, 10_000, 4, 2, FAKE, FAKE, FAKE, FAKE, 5, None, FAKE),  # tier slots without ids
-                gee.Pb(1000, 10_000, 4, 66, FAKE, FAKE, FAKE, FAKE, (1 << 23) + 1, FAKE, FAKE),  # tier above 2^23
-                gee.Pb(1000, 10_000, 4, 1, FAKE + 4, FAKE, FAKE, FAKE, 0, None, FAKE),  # col unaligned
-                gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE + 8, FAKE, FAKE, 0, None, FAKE),  # ul unaligned
-                gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 0, None, None)):  # no word prefix
+    def P(n_rb=4, n_cb=1, col=FAKE, ul=FAKE, n_lds=0, ids=None, word=FAKE, val=None, flag=None, meta=FAKE):
+        return gee.Pb(1000, 10_000, n_rb, n_cb, col, ul, FAKE, FAKE, n_lds, ids, word, val, flag, meta)
+
+    for bad in (P(n_rb=5),  # n_rb does not match n
+                P(n_lds=5, ids=FAKE),  # n_cb without the tier slice
+                P(n_cb=2, n_lds=5),  # tier slots without ids
+                P(n_cb=66, n_lds=(1 << 23) + 1, ids=FAKE),  # tier above 2^23
+                P(col=FAKE + 4),  # col unaligned
+                P(ul=FAKE + 8),  # ul unaligned
+                P(word=None),  # no word prefix
+                P(meta=None),  # no fingerprint
+                P(val=FAKE),  # weights without row-block flags
+                P(flag=FAKE),  # row-block flags without weights
+                P(val=FAKE + 4, flag=FAKE)):  # weights unaligned
         assert lib.gee_embed_pb_workspace(ctypes.byref(bad), 8) == 0
         assert lib.gee_embed_pb(ctypes.byref(bad), FAKE, 8, FAKE, FAKE, 1 << 30, FAKE, ctypes.byref(o), None) == \
             gee.GEE_EINVAL

@@ -226,6 +226,32 @@ def test_hubs_split_across_segments(lap, weighted):
             assert np.array_equal(Z.view(np.uint32), ref.view(np.uint32)), name
 
 
+@pytest.mark.parametrize("seg_len", [0, 64])
+def test_negative_weights_pull(seg_len):
+    """Adjacency weights of both signs: the pull form's FP32 bins hold only segments without
+    a negative weight, the others are summed again in FP64. Half of the rows see only
+    positive weights, so both passes run; every row is within the bar, and the result is
+    bit-reproducible."""
+    rng = np.random.default_rng(21)
+    n, s, K = 30_000, 600_000, 17
+    src, dst, _ = random_multigraph(rng, n, s, False)
+    w = ((rng.integers(0, 1 << 24, s) + 1) * 2.0 ** -24).astype(np.float32)
+    neg = (src < n // 2) & (rng.random(s) < 0.3)
+    w[neg] = -w[neg]
+    hub = np.arange(1, 3001, dtype=np.int32)  # a hub row longer than a segment's FP32 window
+    src = np.r_[src, np.full(hub.size, n - 1, np.int32)].astype(np.int32)
+    dst = np.r_[dst, hub].astype(np.int32)
+    w = np.r_[w, np.linspace(0.25, 1.0, hub.size, dtype=np.float32)].astype(np.float32)
+    Y = random_labels(rng, n, K)
+    Zo = oracle.embed(n, src, dst, w, Y, K, False)
+    csr = gee.csr_build(gee.to_device(n, src, dst, w, device=DEV))
+    labels = dev(Y)
+    Z1 = gee.embed(labels, K, csr=csr, seg_len=seg_len).cpu().numpy()
+    assert_parity(Z1, Zo, what=f"negative weights, seg_len={seg_len}")
+    Z2 = gee.embed(labels, K, csr=csr, seg_len=seg_len).cpu().numpy()
+    assert np.array_equal(Z1.view(np.uint32), Z2.view(np.uint32))
+
+
 def test_big_star_exact():
     """m = 2^20 + 3 unit leaves of class 2 around a class-1 centre: Z[centre] = [0, 1] exactly."""
     m = (1 << 20) + 3

@@ -226,7 +226,108 @@ def test_errors():
     with pytest.raises(gee.GeeError) as e:
         gee.embed_pb(Y, 5, pb)
     assert e.value.code == gee.GEE_ELABEL
+    # a weighted layout with unit weights: the same counts as the unit-weight layout (sums
+    # of ones are exact in FP32 and FP64 alike), and the same label error
     w = np.ones(g.s, np.float32)
     wcsr = gee.csr_build(gee.to_device(g.n, g.src, g.dst, w, device=DEV))
-    with pytest.raises(gee.GeeError):
-        gee.pb_build(wcsr)
+    wpb = gee.pb_build(wcsr)
+    with pytest.raises(gee.GeeError) as e:
+        gee.embed_pb(Y, 5, wpb)
+    assert e.value.code == gee.GEE_ELABEL
+    Y[7] = 2
+    _same_bits(gee.embed_pb(Y, 5, wpb), gee.embed_pb(Y, 5, pb))
+    # a layout struct whose weights do not match its fingerprint is skipped with an error
+    mixed = gee.DevicePb(g.n, pb.col, pb.ul, pb.cell_start, pb.cell_count, pb.lds_ids, pb.cell_word, pb.nnz,
+                         wpb.meta)
+    with pytest.raises(gee.GeeError) as e:
+        gee.embed_pb(Y, 5, mixed)
+    assert e.value.code == gee.GEE_EVERTEX
+
+
+def test_layout_of_another_graph_raises_vertex_error():
+    """A layout used with labels of a smaller graph (its n says 2,000, its entries and tier
+    name vertices up to 4,999) is caught by the fingerprint its build wrote: the passes
+    read nothing of it and the call raises GEE_EVERTEX (the layout's arrays are those of
+    the larger graph, so every table the smaller n implies lies inside them anyway)."""
+    rng = np.random.default_rng(41)
+    n_big, s = 5000, 60_000
+    src = rng.integers(0, n_big, s).astype(np.int32)
+    dst = rng.integers(0, n_big, s).astype(np.int32)
+    csr = gee.csr_build(gee.to_device(n_big, src, dst, None, device=DEV), hot_budget=600)
+    pb = gee.pb_build(csr, tier_slots=512)
+    assert pb.n_lds == 512 and int(pb.lds_ids.max()) >= 2000
+    stale = gee.DevicePb(2000, pb.col, pb.ul, pb.cell_start, pb.cell_count, pb.lds_ids, pb.cell_word, pb.nnz,
+                         pb.meta)
+    assert stale.n_cb == pb.n_cb and stale.n_rb < pb.n_rb
+    labels = torch.as_tensor(random_labels(rng, 2000, 5)).to(DEV)
+    with pytest.raises(gee.GeeError) as e:
+        gee.embed_pb(labels, 5, stale)
+    assert e.value.code == gee.GEE_EVERTEX
+    # the layout itself, with labels of its own graph, is fine
+    Yb = torch.as_tensor(random_labels(rng, n_big, 5)).to(DEV)
+    _same_bits(gee.embed_pb(Yb, 5, pb), gee.embed(Yb, 5, csr=csr))
+
+
+def _flags_host(n, src, dst, w):
+    """Row-block flags of a weighted layout, from the records: a row of more than 128
+    entries (of A + A^T) or a weight that is not >= 0 in one of the block's rows."""
+    deg = np.bincount(src, minlength=n) + np.bincount(dst, minlength=n)
+    bad = np.zeros(n, bool)
+    neg = ~(w >= 0)
+    bad[src[neg]] = True
+    bad[dst[neg]] = True
+    rows = (deg > 128) | bad
+    n_rb = (n + 255) // 256
+    return np.array([rows[256 * b: 256 * b + 256].any() for b in range(n_rb)], np.uint8)
+
+
+@pytest.mark.parametrize("K", [5, 50, 100])
+@pytest.mark.parametrize("tier", ["none", "all"])
+def test_weighted_layout_matches_oracle(K, tier):
+    """Weighted propagation-blocked pass: grid weights in (0, 1], plus a star of 400
+    leaves (a row of more than 128 entries) and a few negative weights, so that row blocks
+    take FP32 sums, FP64 sums and, for K = 100, passes over half or a quarter of their
+    rows. Within the bar of the oracle, flags as the records imply, and the same with Z
+    at an offset of one float. The block's wavefronts add weights into shared bins in an
+    order that varies from call to call, so two calls agree within rounding, not bit for
+    bit."""
+    rng = np.random.default_rng(K + (tier == "all"))
+    n, s = 40_000, 500_000
+    src = rng.integers(0, n, s).astype(np.int32)
+    dst = rng.integers(0, n, s).astype(np.int32)
+    hub = np.arange(1, 401, dtype=np.int32) * 37
+    src = np.r_[src, np.full(hub.size, 5000, np.int32)].astype(np.int32)
+    dst = np.r_[dst, hub].astype(np.int32)
+    w = ((rng.integers(0, 1 << 24, src.size) + 1) * 2.0 ** -24).astype(np.float32)
+    w[rng.choice(src.size, 50, replace=False)] *= -1
+    Y = random_labels(rng, n, K, unknown=0.1)
+    coo = gee.to_device(n, src, dst, w, device=DEV)
+    csr = gee.csr_build(coo, hot_budget=n if tier == "all" else 0)
+    pb = gee.pb_build(csr, tier_slots=None if tier == "all" else 0)
+    assert pb.val is not None and (pb.n_lds > 0) == (tier == "all")
+    assert np.array_equal(pb.rb_flag.cpu().numpy(), _flags_host(n, src, dst, w))
+    assert pb.meta.cpu().tolist() == [n, csr.nnz, pb.n_lds, 1]
+    labels = torch.as_tensor(Y).to(DEV)
+    Z = gee.embed_pb(labels, K, pb)
+    Zo = oracle.embed(n, src, dst, w, Y, K, False)
+    Zn = Z.cpu().numpy()
+    assert_parity(Zn, Zo, what=f"weighted layout K={K} tier={tier}")
+    assert_parity(gee.embed_pb(labels, K, pb).cpu().numpy(), Zn.astype(np.float64), what="second call")
+    buf = torch.full((n * K + 2,), -1.0, dtype=torch.float32, device=DEV)
+    Zu = gee.embed_pb(labels, K, pb, Z=buf[1:-1].view(n, K))
+    assert_parity(Zu.cpu().numpy(), Zo, what="Z at an offset of one float")
+    assert buf[0].item() == -1.0 and buf[-1].item() == -1.0
+    assert_parity(Z.cpu().numpy(), gee.embed(labels, K, csr=csr).cpu().numpy().astype(np.float64),
+                  what="weighted layout vs pull")
+
+
+def test_weighted_layout_er_workload_shape():
+    """The weighted Erdos-Renyi workload's shape at 2^20 records (every vertex in the tier)
+    against the oracle."""
+    wl = gen.er_weighted(seed=7, log2n=16, log2s=20, K=50)
+    g = wl.graph
+    csr = gee.csr_build(gee.to_device(g.n, g.src, g.dst, g.w, device=DEV), hot_budget=g.n)
+    pb = gee.pb_build(csr)
+    assert pb.n_lds == g.n
+    Z = gee.embed_pb(torch.as_tensor(wl.labels).to(DEV), wl.K, pb).cpu().numpy()
+    assert_parity(Z, oracle.embed(g.n, g.src, g.dst, g.w, wl.labels, wl.K, False), what="weighted ER layout")
