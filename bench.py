@@ -408,17 +408,25 @@ def er_weighted_leg(a, gee, torch, dev):
     p0, p1 = gee.HipEvent(), gee.HipEvent()
     p0.record()
     csr_hot = gee.csr_build(coo, hot_budget=min(n, 1 << 23), check=False)
-    pb = gee.pb_build(csr_hot, check=False)
+    pbs = {False: gee.pb_build(csr_hot, check=False)}
     p1.record()
     p1.synchronize()
+    out["pb_build_ms"] = round(p0.elapsed_ms(p1), 2)
+    # the Laplacian layout: degrees and every entry's w d_v^-1/2 taken once here, with the
+    # layout (per-graph preprocessing, as the CSR is); its calls skip the degree pass
+    p0.record()
+    pbs[True] = gee.pb_build(csr_hot, laplacian=True, check=False)
+    p1.record()
+    p1.synchronize()
+    out["pb_laplacian_build_ms"] = round(p0.elapsed_ms(p1), 2)
     del csr_hot
     torch.cuda.empty_cache()
-    out["pb_build_ms"] = round(p0.elapsed_ms(p1), 2)
-    out["pb_tier_slots"] = pb.n_lds
-    wsb_pb = gee.embed_pb_workspace_bytes(pb, K)
+    out["pb_tier_slots"] = pbs[False].n_lds
+    wsb_pb = gee.embed_pb_workspace_bytes(pbs[False], K)
     for lap in (False, True):
         ver = "laplacian" if lap else "adjacency"
-        for form in (("pb", "pull", "push") if not lap else ("pull", "push")):
+        pb = pbs[lap]
+        for form in ("pb", "pull", "push"):
             ws = torch.empty(wsb_pb if form == "pb" else
                              max(gee.embed_workspace_bytes(K, coo=coo if form == "push" else None,
                                                            csr=csr if form == "pull" else None, laplacian=lap,
@@ -451,10 +459,14 @@ def er_weighted_leg(a, gee, torch, dev):
                 # records' columns and weights once, row pointers, one read of each label
                 # (Laplacian: an 8-byte record of class and d^-1/2), Z written once, and the
                 # counts kernel's read of the int32 labels; the Laplacian adds the degree pass
-                # (weights and row pointers again, degrees written) and its label records
+                # (weights and row pointers again, degrees written) and its label records.
+                # The layout's Laplacian calls skip the degree pass (warm: degrees of a
+                # resident graph) and are priced without it
                 b_alg = 8 * nnz + 8 * (n + 1) + n + 4 * n * K + 4 * n
-                if lap:
+                if lap and form == "pull":
                     b_alg += 4 * nnz + 8 * (n + 1) + 8 * n + 8 * n
+                elif lap:
+                    b_alg += 4 * n  # warm: each row's d^-1/2 read once, no degree pass
             else:
                 # records once (8 + 4 bytes), two 4-byte atomic read-modify-writes into Z per
                 # record, Z zeroed and scaled, labels read; the Laplacian adds the degree pass
@@ -483,7 +495,7 @@ def er_weighted_leg(a, gee, torch, dev):
                 out[f"{form}_{ver}"]["rows_per_window_sweep_ms"] = sweep
                 log(f"er-weighted {form} {ver}: rows per window {sweep}")
             del ws
-    del Z, csr, coo, pb
+    del Z, csr, coo, pb, pbs
     torch.cuda.empty_cache()
     if not a.no_cpu_baseline:
         for lap in (False, True):

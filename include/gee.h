@@ -183,7 +183,7 @@ int gee_embed_noalloc(const gee_coo *g, const gee_csr *csr, const int32_t *label
                       float *Z, int32_t *err, const gee_embed_opts *opts, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------
- * Propagation-blocked layout of a CSR, and the pull pass over it (adjacency version).
+ * Propagation-blocked layout of a CSR, and the pull pass over it.
  *
  * The pull pass of Algorithm 1 (Section II; Section III's per-vertex edge lists)
  * reads the label of every entry's column at a random address. The adjacency
@@ -201,10 +201,21 @@ int gee_embed_noalloc(const gee_coo *g, const gee_csr *csr, const int32_t *label
  * is bit-identical to gee_embed on the same CSR. With weights the second pass adds
  * them into FP32 sums, which the layout allows only for row blocks whose rows have at
  * most 128 entries and no negative weight (rb_flag 0): such a sum of m terms is within
- * (m - 1) 2^-24 of its value, relative; the other blocks take FP64 sums. Results then
- * agree with gee_embed within rounding, not bit for bit, and since a block's wavefronts
- * add into shared bins in an order that varies, two calls agree within rounding too
- * (the CSR pull form of gee_embed is the bit-reproducible one).
+ * (m - 1) 2^-24 of its value, relative; the other blocks take FP64 sums. When every
+ * positive weight is an integer multiple of one power of two 2^-g and a sum of 128 of
+ * them, scaled by 2^g, stays below 2^32 (the build records g in meta[4]), the unflagged
+ * blocks add the scaled weights in 32-bit integers instead, which is exact (weights on
+ * the 2^-24 grid in (0, 1] qualify). Otherwise results agree with gee_embed within
+ * rounding, not bit for bit, and since a block's wavefronts add into shared bins in an
+ * order that varies, two calls agree within rounding too (the CSR pull form of gee_embed
+ * is the bit-reproducible one).
+ *
+ * A Laplacian layout (gee_pb_build with laplacian != 0) stores, in place of the weights,
+ * each entry's w d_v^-1/2 (its column's factor, FP32: one rounding of the exact product)
+ * and every vertex's d^-1/2 (rsd), the degrees d = (A + A^T) 1 being taken once when the
+ * layout is built, as the CSR is (they depend on the graph only). The pass then adds the
+ * stored terms as a weighted layout does and writes each row scaled by its own d_u^-1/2:
+ * the Laplacian version, within the same rounding bound.
  *
  * Cell (rb, cb) of the layout is the run of column block cb's entries whose rows
  * lie in [256 rb, 256 rb + 256); cell_start[rb * n_cb + cb] is its first index in
@@ -234,9 +245,12 @@ typedef struct gee_pb {
                                   entry; NULL for a unit-weight layout */
     const uint8_t *rb_flag;    /* [n_rb] weighted layouts: 1 where a row of the block has more than 128 entries
                                   or a negative weight (FP64 sums), else 0; NULL for a unit-weight layout */
-    const int64_t *meta;       /* [4] written by gee_pb_build: n, nnz, n_lds and 1 if weighted. A layout whose
-                                  meta disagrees with these fields (one built for another graph) makes
-                                  gee_embed_pb skip its passes and raise GEE_EVERTEX */
+    const int64_t *meta;       /* [8] written by gee_pb_build: n, nnz, n_lds, the kind (0 unit-weight
+                                  adjacency, 1 weighted adjacency, 2 Laplacian), then the weights' grid
+                                  (below). A layout whose meta disagrees with the fields here (one built
+                                  for another graph) makes gee_embed_pb skip its passes and raise
+                                  GEE_EVERTEX */
+    const float *rsd;          /* [n] Laplacian layouts: d^-1/2 of every vertex (0 where d = 0); else NULL */
 } gee_pb;
 
 /* n_rb * n_cb for n vertices and n_lds tier slots (0 on invalid input). */
@@ -253,30 +267,33 @@ int64_t gee_pb_tier_slots(const gee_csr *csr, int64_t min_per_row_block, void *w
 
 /* Scratch bytes gee_pb_build needs (0 on invalid input, more than 2^32 - 65 entries,
  * or n_lds above min(n_hot, GEE_PB_MAX_TIER)). */
-size_t gee_pb_build_workspace(const gee_csr *csr, int64_t n_lds);
+size_t gee_pb_build_workspace(const gee_csr *csr, int64_t n_lds, int laplacian);
 
 /* Builds the layout of csr with the first n_lds hot slots (0 <= n_lds <=
- * min(n_hot, GEE_PB_MAX_TIER)) in the tier; other hot-slot columns are decoded through
- * hot_ids. Outputs are caller device buffers: col [nnz + 16] (16-byte aligned), ul
- * [nnz + 32 rounded up to 16] (16-byte aligned), cell_start, cell_count and cell_word
- * [gee_pb_cells(n, n_lds)], lds_ids [n_lds] (may be NULL when n_lds = 0), meta [4];
- * for a weighted CSR (csr->val != NULL) also val [nnz + 32 rounded up to 16] (16-byte
- * aligned) and rb_flag [ceil(n / 256)], which must be NULL otherwise. cell_word[rb *
- * n_cb + c] is the first 32-bit word of cell c when the cells of row block rb are read
- * one after another as words (a cell covering ceil(((cell_start mod 4) + cell_count) /
- * 4) of them, none when empty). A column id outside [0, n) stores GEE_EVERTEX in *err. */
-int gee_pb_build(const gee_csr *csr, int64_t n_lds, int32_t *col, uint8_t *ul, int64_t *cell_start,
+ * min(n_hot, GEE_PB_MAX_TIER)) in the tier, for the adjacency version (laplacian = 0)
+ * or the Laplacian version; other hot-slot columns are decoded through hot_ids. Outputs
+ * are caller device buffers: col [nnz + 16] (16-byte aligned), ul [nnz + 32 rounded up
+ * to 16] (16-byte aligned), cell_start, cell_count and cell_word [gee_pb_cells(n,
+ * n_lds)], lds_ids [n_lds] (may be NULL when n_lds = 0), meta [8]; for a weighted CSR
+ * (csr->val != NULL) or a Laplacian layout also val [nnz + 32 rounded up to 16]
+ * (16-byte aligned) and rb_flag [ceil(n / 256)], and for a Laplacian layout rsd [n];
+ * each must be NULL when not needed. cell_word[rb * n_cb + c] is the first 32-bit word
+ * of cell c when the cells of row block rb are read one after another as words (a cell
+ * covering ceil(((cell_start mod 4) + cell_count) / 4) of them, none when empty). A
+ * column id outside [0, n) stores GEE_EVERTEX in *err; for a Laplacian layout a
+ * negative or NaN weight stores GEE_ENEGW. */
+int gee_pb_build(const gee_csr *csr, int64_t n_lds, int laplacian, int32_t *col, uint8_t *ul, int64_t *cell_start,
                  uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, float *val, uint8_t *rb_flag,
-                 int64_t *meta, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream);
+                 float *rsd, int64_t *meta, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream);
 
 /* Workspace bytes of gee_embed_pb (0 on invalid input); 1 <= K <= 128. */
 size_t gee_embed_pb_workspace(const gee_pb *pb, int32_t K);
 
-/* Algorithm 1, adjacency version, over the layout: labels [n] in [0, K] (K <= 128), Z
- * [n * K] FP32 overwritten. Same results and data errors as gee_embed on the CSR the
- * layout was built from (bit for bit with unit weights; with weights within the
- * rounding described above). opts->hot_begin / hot_end bracket the two passes (label
- * gathers and row sums); seg_len is unused. */
+/* Algorithm 1 over the layout, in the version the layout was built for: labels [n] in
+ * [0, K] (K <= 128), Z [n * K] FP32 overwritten. Same results and data errors as
+ * gee_embed on the CSR the layout was built from (bit for bit for unit-weight
+ * adjacency; otherwise within the rounding described above). opts->hot_begin / hot_end
+ * bracket the two passes (label gathers and row sums); seg_len is unused. */
 int gee_embed_pb(const gee_pb *pb, const int32_t *labels, int32_t K, float *Z, void *ws, size_t ws_bytes,
                  int32_t *err, const gee_embed_opts *opts, hipStream_t stream);
 

@@ -62,7 +62,7 @@ class Pb(ctypes.Structure):
                 ("col", ctypes.c_void_p), ("ul", ctypes.c_void_p), ("cell_start", ctypes.c_void_p),
                 ("cell_count", ctypes.c_void_p), ("n_lds", ctypes.c_int64), ("lds_ids", ctypes.c_void_p),
                 ("cell_word", ctypes.c_void_p), ("val", ctypes.c_void_p), ("rb_flag", ctypes.c_void_p),
-                ("meta", ctypes.c_void_p)]
+                ("meta", ctypes.c_void_p), ("rsd", ctypes.c_void_p)]
 
 
 class Batch(ctypes.Structure):
@@ -112,9 +112,11 @@ def load():
         lib.gee_pb_tier_slots.restype = i64
         lib.gee_pb_tier_slots.argtypes = [CsrP, i64, vp, sz, vp]
         lib.gee_pb_build_workspace.restype = sz
-        lib.gee_pb_build_workspace.argtypes = [CsrP, i64]
+        lib.gee_pb_build_workspace.argtypes = [CsrP, i64, ci]
         lib.gee_pb_build.restype = ci
-        lib.gee_pb_build.argtypes = [CsrP, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp]
+        # csr, n_lds, laplacian, col, ul, cell_start, cell_count, cell_word, lds_ids, val, rb_flag, rsd,
+        # meta, ws, ws_bytes, err, stream
+        lib.gee_pb_build.argtypes = [CsrP, i64, ci] + [vp] * 11 + [sz, vp, vp]
         lib.gee_embed_pb_workspace.restype = sz
         lib.gee_embed_pb_workspace.argtypes = [PbP, i32]
         lib.gee_embed_pb.restype = ci
@@ -392,9 +394,14 @@ class DevicePb:
     lds_ids: torch.Tensor     # [n_lds]
     cell_word: torch.Tensor   # [n_rb * n_cb]
     nnz: int = 0
-    meta: torch.Tensor | None = None     # [4] int64 fingerprint written by the build
-    val: torch.Tensor | None = None      # [nnz + 32 rounded up to 16] float32, weighted layouts
-    rb_flag: torch.Tensor | None = None  # [n_rb] uint8, weighted layouts
+    meta: torch.Tensor | None = None     # [8] int64 fingerprint (and weight grid) written by the build
+    val: torch.Tensor | None = None      # [nnz + 32 rounded up to 16] float32: w, or w d_v^-1/2 (Laplacian)
+    rb_flag: torch.Tensor | None = None  # [n_rb] uint8, weighted and Laplacian layouts
+    rsd: torch.Tensor | None = None      # [n] float32 d^-1/2, Laplacian layouts
+
+    @property
+    def laplacian(self) -> bool:
+        return self.rsd is not None
 
     @property
     def n_rb(self) -> int:
@@ -411,7 +418,7 @@ class DevicePb:
     def struct(self) -> Pb:
         return Pb(self.n, self.nnz, self.n_rb, self.n_cb, _ptr(self.col), _ptr(self.ul), _ptr(self.cell_start),
                   _ptr(self.cell_count), self.n_lds, _ptr(self.lds_ids) if self.n_lds else None,
-                  _ptr(self.cell_word), _ptr(self.val), _ptr(self.rb_flag), _ptr(self.meta))
+                  _ptr(self.cell_word), _ptr(self.val), _ptr(self.rb_flag), _ptr(self.meta), _ptr(self.rsd))
 
 
 def pb_tier_slots(csr: DeviceCsr, min_per_row_block: int = 4, stream=None) -> int:
@@ -426,16 +433,18 @@ def pb_tier_slots(csr: DeviceCsr, min_per_row_block: int = 4, stream=None) -> in
     return r
 
 
-def pb_build(csr: DeviceCsr, tier_slots: int | None = None, stream=None, check: bool = True) -> DevicePb:
+def pb_build(csr: DeviceCsr, tier_slots: int | None = None, laplacian: bool = False, stream=None,
+             check: bool = True) -> DevicePb:
     """Layout for gee_embed_pb from a CSR (per-graph preprocessing; a weighted CSR gives a
-    weighted layout). The first ``tier_slots`` hot slots are read from LDS; None takes
+    weighted layout; ``laplacian`` a layout of the Laplacian version, with the degrees taken
+    once here). The first ``tier_slots`` hot slots are read from LDS; None takes
     pb_tier_slots(csr)."""
     lib = load()
     rs = csr.struct()
     dev = csr.row_ptr.device
     n_lds = pb_tier_slots(csr, stream=stream) if tier_slots is None else int(tier_slots)
     cells = int(lib.gee_pb_cells(csr.n, n_lds))
-    wsb = int(lib.gee_pb_build_workspace(ctypes.byref(rs), n_lds))
+    wsb = int(lib.gee_pb_build_workspace(ctypes.byref(rs), n_lds, 1 if laplacian else 0))
     if wsb == 0 or cells == 0:
         raise GeeError(GEE_EINVAL, "gee_pb_build_workspace")
     col = torch.empty(csr.nnz + 16, dtype=torch.int32, device=dev)
@@ -444,19 +453,21 @@ def pb_build(csr: DeviceCsr, tier_slots: int | None = None, stream=None, check: 
     cell_count = torch.empty(cells, dtype=torch.int32, device=dev)
     cell_word = torch.empty(cells, dtype=torch.int32, device=dev)
     lds_ids = torch.empty(n_lds, dtype=torch.int32, device=dev)
-    meta = torch.empty(4, dtype=torch.int64, device=dev)
-    weighted = csr.val is not None
-    val = torch.empty((csr.nnz + 32 + 15) // 16 * 16, dtype=torch.float32, device=dev) if weighted else None
-    rb_flag = torch.empty((csr.n + PB_ROWS - 1) // PB_ROWS, dtype=torch.uint8, device=dev) if weighted else None
+    meta = torch.empty(8, dtype=torch.int64, device=dev)
+    carried = csr.val is not None or laplacian
+    val = torch.empty((csr.nnz + 32 + 15) // 16 * 16, dtype=torch.float32, device=dev) if carried else None
+    rb_flag = torch.empty((csr.n + PB_ROWS - 1) // PB_ROWS, dtype=torch.uint8, device=dev) if carried else None
+    rsd = torch.empty(csr.n, dtype=torch.float32, device=dev) if laplacian else None
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     err = torch.zeros(1, dtype=torch.int32, device=dev)
-    _rc(lib.gee_pb_build(ctypes.byref(rs), n_lds, _ptr(col), _ptr(ul), _ptr(cell_start), _ptr(cell_count),
-                         _ptr(cell_word), _ptr(lds_ids) if n_lds else None, _ptr(val), _ptr(rb_flag), _ptr(meta),
-                         _ptr(ws), wsb, _ptr(err), _stream(stream)), "gee_pb_build")
+    _rc(lib.gee_pb_build(ctypes.byref(rs), n_lds, 1 if laplacian else 0, _ptr(col), _ptr(ul), _ptr(cell_start),
+                         _ptr(cell_count), _ptr(cell_word), _ptr(lds_ids) if n_lds else None, _ptr(val),
+                         _ptr(rb_flag), _ptr(rsd), _ptr(meta), _ptr(ws), wsb, _ptr(err), _stream(stream)),
+        "gee_pb_build")
     if check:
         _check_err(err, "gee_pb_build")
     del ws
-    return DevicePb(csr.n, col, ul, cell_start, cell_count, lds_ids, cell_word, csr.nnz, meta, val, rb_flag)
+    return DevicePb(csr.n, col, ul, cell_start, cell_count, lds_ids, cell_word, csr.nnz, meta, val, rb_flag, rsd)
 
 
 def embed_pb_workspace_bytes(pb: DevicePb, K: int) -> int:
@@ -465,7 +476,8 @@ def embed_pb_workspace_bytes(pb: DevicePb, K: int) -> int:
 
 def embed_pb(labels: torch.Tensor, K: int, pb: DevicePb, Z: torch.Tensor | None = None, ws: torch.Tensor | None = None,
              err: torch.Tensor | None = None, events=None, stream=None, check: bool = True) -> torch.Tensor:
-    """Adjacency-version Z [n, K] of a graph from its propagation-blocked layout."""
+    """Z [n, K] of a graph from its propagation-blocked layout, in the version the layout was
+    built for (adjacency, or Laplacian for a layout built with ``laplacian``)."""
     lib = load()
     dev = pb.cell_start.device
     _need(labels, torch.int32, pb.n, "labels", dev)

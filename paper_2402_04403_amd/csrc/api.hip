@@ -540,16 +540,16 @@ int64_t gee_pb_tier_slots(const gee_csr *csr, int64_t min_per_row_block, void *w
     return slices == n_sl ? cap : slices * kPbSlice;
 }
 
-size_t gee_pb_build_workspace(const gee_csr *csr, int64_t n_lds)
+size_t gee_pb_build_workspace(const gee_csr *csr, int64_t n_lds, int laplacian)
 {
     if (check_csr(csr) != GEE_OK || csr->nnz > kPbMaxNnz) return 0;
     if (n_lds < 0 || n_lds > (csr->hot_ids ? csr->n_hot : 0) || n_lds > kPbMaxSlices * kPbSlice) return 0;
-    return pb_build_scratch(csr->n, csr->nnz, n_lds, csr->val != nullptr);
+    return pb_build_scratch(csr->n, csr->nnz, n_lds, csr->val != nullptr, laplacian != 0);
 }
 
-int gee_pb_build(const gee_csr *csr, int64_t n_lds, int32_t *col, uint8_t *ul, int64_t *cell_start,
+int gee_pb_build(const gee_csr *csr, int64_t n_lds, int laplacian, int32_t *col, uint8_t *ul, int64_t *cell_start,
                  uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, float *val, uint8_t *rb_flag,
-                 int64_t *meta, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream)
+                 float *rsd, int64_t *meta, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream)
 {
     int rc;
     if ((rc = check_csr(csr)) != GEE_OK) return rc;
@@ -558,13 +558,15 @@ int gee_pb_build(const gee_csr *csr, int64_t n_lds, int32_t *col, uint8_t *ul, i
     if ((csr->nnz > 0 && (!col || !ul)) || !cell_start || !cell_count || !cell_word || !meta || !aligned(col, 16) ||
         !aligned(ul, 16) || (n_lds > 0 && !lds_ids))
         return GEE_EINVAL;
-    const bool weighted = csr->val != nullptr;
-    if (weighted ? (!rb_flag || (csr->nnz > 0 && !val) || !aligned(val, 16)) : (val || rb_flag)) return GEE_EINVAL;
-    const size_t need = pb_build_scratch(csr->n, csr->nnz, n_lds, weighted);
+    const bool lap = laplacian != 0;
+    const bool carried = csr->val != nullptr || lap; // a value per entry in the layout
+    if (carried ? (!rb_flag || (csr->nnz > 0 && !val) || !aligned(val, 16)) : (val || rb_flag)) return GEE_EINVAL;
+    if (lap ? !rsd : rsd != nullptr) return GEE_EINVAL;
+    const size_t need = pb_build_scratch(csr->n, csr->nnz, n_lds, csr->val != nullptr, lap);
     if (!ws || !aligned(ws, 256) || ws_bytes < need) return GEE_EWORKSPACE;
-    return hip_rc(launch_pb_build(csr->n, csr->nnz, csr->row_ptr, csr->col, csr->val, csr->hot_ids, csr->n_hot, n_lds,
-                                  col, ul, cell_start, cell_count, cell_word, lds_ids, val, rb_flag, meta, ws, err,
-                                  stream));
+    return hip_rc(launch_pb_build(csr->n, csr->nnz, csr->row_ptr, csr->col, csr->val, lap, csr->hot_ids, csr->n_hot,
+                                  n_lds, col, ul, cell_start, cell_count, cell_word, lds_ids, val, rb_flag, rsd, meta,
+                                  ws, err, stream));
 }
 
 } // extern "C"
@@ -581,7 +583,7 @@ int check_pb(const gee_pb *pb)
     if ((pb->nnz > 0 && (!pb->col || !pb->ul)) || !pb->cell_start || !pb->cell_count || !pb->cell_word ||
         !pb->meta || !aligned(pb->col, 16) || !aligned(pb->ul, 16))
         return GEE_EINVAL;
-    if ((pb->val == nullptr) != (pb->rb_flag == nullptr) || !aligned(pb->val, 16) || (pb->nnz > 0 && pb->rb_flag && !pb->val))
+    if ((pb->val == nullptr) != (pb->rb_flag == nullptr) || !aligned(pb->val, 16) || (pb->rsd && !pb->val))
         return GEE_EINVAL;
     return GEE_OK;
 }
@@ -638,11 +640,12 @@ int gee_embed_pb(const gee_pb *pb, const int32_t *labels, int32_t K, float *Z, v
     const bool timed = opts && opts->hot_begin && opts->hot_end;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_begin, stream)))) return rc;
     const PbLayout L = pb_layout(pb->n, pb->n_lds);
+    const int kind = pb->rsd ? 2 : (pb->val ? 1 : 0);
     if ((rc = hip_rc(launch_pb_gather(pb->n, pb->nnz, L, pb->n_lds, pb->cell_start, pb->cell_count, pb->col,
-                                      pb->lds_ids, pb->meta, pb->val != nullptr, lab, tab, yv, err, stream))))
+                                      pb->lds_ids, pb->meta, kind, lab, tab, yv, err, stream))))
         return rc;
     if ((rc = hip_rc(launch_pb_rows(pb->n, pb->nnz, K, L, pb->cell_start, pb->cell_count, pb->cell_word, pb->ul, yv,
-                                    pb->val, pb->rb_flag, pb->meta, pb->n_lds, inv, Z, err, stream))))
+                                    pb->val, pb->rb_flag, pb->rsd, pb->meta, pb->n_lds, inv, Z, err, stream))))
         return rc;
     if (timed && (rc = hip_rc(hipEventRecord(opts->hot_end, stream)))) return rc;
     return GEE_OK;

@@ -145,29 +145,35 @@ struct PbLayout {
 };
 PbLayout pb_layout(int64_t n, int64_t n_lds);
 constexpr int kPbF32Terms = 128; // a weighted row block sums in FP32 when its rows have at most this many entries
-size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds, bool weighted);
-// val (CSR weights) null for a unit-weight layout; then vl and rb_flag are unused.
+// meta[4] of a weighted layout whose weights are not all multiples of one power of two
+// small enough for exact 32-bit sums
+constexpr int64_t kPbNoGrid = -((int64_t)1 << 62);
+size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds, bool weighted, bool laplacian);
+// val (CSR weights) null for unit weights. vl and rb_flag are written for a weighted or a
+// Laplacian layout (vl: w, or w d_v^-1/2), rsd for a Laplacian layout.
 hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const float *val,
-                           const int32_t *hot_ids, int64_t n_hot, int64_t n_lds, int32_t *colc, uint8_t *ul,
-                           int64_t *cell_start, uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids,
-                           float *vl, uint8_t *rb_flag, int64_t *meta, void *ws, int32_t *err, hipStream_t s);
+                           bool laplacian, const int32_t *hot_ids, int64_t n_hot, int64_t n_lds, int32_t *colc,
+                           uint8_t *ul, int64_t *cell_start, uint32_t *cell_count, uint32_t *cell_word,
+                           int32_t *lds_ids, float *vl, uint8_t *rb_flag, float *rsd, int64_t *meta, void *ws,
+                           int32_t *err, hipStream_t s);
 // tab: per-call scratch of (n_lds rounded up to 16) bytes.
-// A layout whose fingerprint (meta) disagrees with n, nnz, n_lds and weighted raises
-// GEE_EVERTEX in err and is not read.
+// A layout whose fingerprint (meta) disagrees with n, nnz, n_lds and its kind (0 unit
+// adjacency, 1 weighted adjacency, 2 Laplacian) raises GEE_EVERTEX in err and is not read.
 hipError_t launch_pb_gather(int64_t n, int64_t nnz, const PbLayout &L, int64_t n_lds, const int64_t *cell_start,
                             const uint32_t *cell_count, const int32_t *colc, const int32_t *lds_ids,
-                            const int64_t *meta, bool weighted, const uint8_t *lab, uint8_t *tab, uint8_t *yv,
+                            const int64_t *meta, int kind, const uint8_t *lab, uint8_t *tab, uint8_t *yv,
                             int32_t *err, hipStream_t s);
 // slice_entries [ceil(n_slots / 2^17)]: entries whose column is a hot slot of that slice.
 hipError_t launch_pb_slice_entries(int64_t n_slots, const int32_t *hot_ids, const int64_t *row_ptr,
                                   int64_t *slice_entries, hipStream_t s);
 // ul and yv: 4-byte aligned, readable up to nnz + 32 (the gap before the tier included).
 // A cell outside the layout's nnz + 15 entries is read as empty and raises GEE_EVERTEX.
-// vl and rb_flag: a weighted layout's weights and row-block flags, else null.
+// vl and rb_flag: a weighted or Laplacian layout's values and row-block flags, else null;
+// rsd: a Laplacian layout's d^-1/2, else null.
 hipError_t launch_pb_rows(int64_t n, int64_t nnz, int32_t K, const PbLayout &L, const int64_t *cell_start,
                           const uint32_t *cell_count, const uint32_t *cell_word, const uint8_t *ul, const uint8_t *yv,
-                          const float *vl, const uint8_t *rb_flag, const int64_t *meta, int64_t n_lds,
-                          const double *inv, float *Z, int32_t *err, hipStream_t s);
+                          const float *vl, const uint8_t *rb_flag, const float *rsd, const int64_t *meta,
+                          int64_t n_lds, const double *inv, float *Z, int32_t *err, hipStream_t s);
 
 // Labels from an embedding: out[u] = 1 + argmax_k Z[u][k] (first maximum; 0 for a row
 // with no positive entry); changed (nullable) is set to the number of rows where out

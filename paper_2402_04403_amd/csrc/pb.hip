@@ -30,6 +30,8 @@
 // Counts are integers, so the result is independent of order and bit-identical to
 // the pull pass.
 
+#include <limits.h>
+
 #include "common.h"
 #include "launch.h"
 
@@ -164,14 +166,16 @@ k_pb_rbflag(int64_t n, int64_t n_rb, const int64_t *__restrict__ row_ptr, const 
         const int64_t r0 = rb * kPbRows, r1 = r0 + kPbRows < n ? r0 + kPbRows : n;
         const int64_t u = r0 + threadIdx.x;
         bool f = u < r1 && row_ptr[u + 1] - row_ptr[u] > kPbF32Terms;
-        for (int64_t e = row_ptr[r0] + threadIdx.x; e < row_ptr[r1]; e += kT) f |= !(val[e] >= 0.0f);
+        if (val)
+            for (int64_t e = row_ptr[r0] + threadIdx.x; e < row_ptr[r1]; e += kT) f |= !(val[e] >= 0.0f);
         f = __syncthreads_or(f) != 0;
         if (threadIdx.x == 0) rb_flag[rb] = f ? 1 : 0;
         __syncthreads();
     }
 }
 
-// The layout's fingerprint: n, nnz, n_lds, weighted.
+// The layout's fingerprint: n, nnz, n_lds, weighted; meta[4] (the weights' grid) is
+// filled in by k_pb_grid_final for a weighted layout.
 __global__ void k_pb_meta(int64_t *meta, int64_t n, int64_t nnz, int64_t n_lds, int64_t weighted)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -179,7 +183,77 @@ __global__ void k_pb_meta(int64_t *meta, int64_t n, int64_t nnz, int64_t n_lds, 
         meta[1] = nnz;
         meta[2] = n_lds;
         meta[3] = weighted;
+        meta[4] = kPbNoGrid;
+        meta[5] = meta[6] = meta[7] = 0;
     }
+}
+
+// The Laplacian layout's term of every CSR entry, in CSR order: w d_v^-1/2 for its column v
+// (a hot-slot column decoded through hot_ids), the exact product of the FP32 weight and
+// the FP32 d^-1/2 rounded once to FP32. A column outside [0, n) gives 0 (k_pb_key flags it).
+__global__ void __launch_bounds__(kT)
+k_pb_lapw(int64_t nnz, int64_t n, const int32_t *__restrict__ col, const float *__restrict__ val,
+          const int32_t *__restrict__ hot_ids, int64_t n_hot, const float *__restrict__ rsd, float *__restrict__ out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c0 = col[e];
+        int64_t v = c0;
+        if (c0 < 0) {
+            const int64_t slot = (int64_t)((uint32_t)c0 & 0x7fffffffu);
+            v = slot < n_hot ? hot_ids[slot] : -1;
+        }
+        const double r = (uint64_t)v < (uint64_t)n ? (double)rsd[v] : 0.0;
+        out[e] = (float)((val ? (double)val[e] : 1.0) * r);
+    }
+}
+
+__global__ void k_pb_grid_init(int32_t *ex)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ex[0] = INT_MAX;
+        ex[1] = INT_MIN;
+    }
+}
+
+// The binary exponents of the lowest and the highest set bit over the positive finite
+// weights: ex[0] = min, ex[1] = max (ex starts at {INT_MAX, INT_MIN}).
+__global__ void __launch_bounds__(kT)
+k_pb_grid_bits(int64_t nnz, const float *__restrict__ val, int32_t *ex)
+{
+    int lo = INT_MAX, hi = INT_MIN;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        const float w = val[e];
+        if (!(w > 0.0f) || !(w < INFINITY)) continue; // zero, negative or not finite: not on the grid's path
+        const uint32_t b = __float_as_uint(w), ef = b >> 23, m = b & 0x7fffffu;
+        const uint32_t sig = ef ? (m | 0x800000u) : m;       // significand as an integer
+        const int e0 = ef ? (int)ef - 150 : -149;            // its unit's exponent
+        lo = min(lo, e0 + __builtin_ctz(sig));
+        hi = max(hi, e0 + 31 - __builtin_clz(sig));
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_down(lo, o, kWave));
+        hi = max(hi, __shfl_down(hi, o, kWave));
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicMin(&ex[0], lo);
+        atomicMax(&ex[1], hi);
+    }
+}
+
+// meta[4] = g when every positive weight is a multiple of 2^-g and a sum of kPbF32Terms of
+// them stays below 2^32 once scaled by 2^g (the row sums of an unflagged block then add
+// exactly in 32-bit integers), else kPbNoGrid.
+__global__ void k_pb_grid_final(const int32_t *ex, int64_t *meta)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int lo = ex[0], hi = ex[1];
+    if (lo == INT_MAX) { // no positive weight: every sum is zero
+        meta[4] = 0;
+        return;
+    }
+    const int g = -lo; // scale 2^g: the lowest bit becomes bit 0
+    const bool fits = g >= -126 && g <= 126 && hi + g + 8 <= 32; // (2^(hi+1) - 1) 2^g 2^7 < 2^32
+    meta[4] = fits ? g : kPbNoGrid;
 }
 
 // Row-block-major table: cell (rb, cb) starts where cell (cb, rb) - 1 of the sorted
@@ -249,9 +323,9 @@ __device__ inline int64_t clamp_index(int64_t h, int64_t nnz) { return h < 0 ? 0
 // came with. A layout built for another graph fails this, and every pass then skips its
 // work and raises GEE_EVERTEX: its columns need not lie in [0, n) of these labels.
 __device__ inline bool layout_matches(const int64_t *__restrict__ meta, int64_t n, int64_t nnz, int64_t n_lds,
-                                      bool weighted, int32_t *err)
+                                      int kind, int32_t *err)
 {
-    const bool ok = meta[0] == n && meta[1] == nnz && meta[2] == n_lds && meta[3] == (weighted ? 1 : 0);
+    const bool ok = meta[0] == n && meta[1] == nnz && meta[2] == n_lds && meta[3] == kind;
     if (!ok && threadIdx.x == 0 && blockIdx.x == 0) flag_error(err, GEE_EVERTEX);
     return ok;
 }
@@ -262,11 +336,11 @@ __device__ inline bool layout_matches(const int64_t *__restrict__ meta, int64_t 
 // first tier entry (*tier_start), or nnz without a tier (tier_start null). The columns
 // are the layout's own, all in [0, n) once its fingerprint matches.
 __global__ void __launch_bounds__(kT)
-k_pb_gather(int64_t nnz, int64_t n, int64_t n_lds, bool weighted, const int64_t *__restrict__ meta,
+k_pb_gather(int64_t nnz, int64_t n, int64_t n_lds, int kind, const int64_t *__restrict__ meta,
             const int64_t *__restrict__ tier_start, const int32_t *__restrict__ colc, const uint8_t *__restrict__ lab,
             uint8_t *__restrict__ yv, int32_t *err)
 {
-    if (!layout_matches(meta, n, nnz, n_lds, weighted, err)) return;
+    if (!layout_matches(meta, n, nnz, n_lds, kind, err)) return;
     const int64_t h0 = tier_start ? clamp_index(*tier_start, nnz) : nnz;
     const int64_t nvec = h0 / 32;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvec; v += (int64_t)gridDim.x * blockDim.x) {
@@ -291,11 +365,11 @@ k_pb_gather(int64_t nnz, int64_t n, int64_t n_lds, bool weighted, const int64_t 
 // tab[q] = lab[lds_ids[q]] for the n_lds tier slots, zero-padded to a multiple of 16; a
 // slot whose vertex is outside [0, n) gets label 0 and raises GEE_EVERTEX.
 __global__ void __launch_bounds__(kT)
-k_pb_tier_labels(int64_t n_lds, int64_t n, int64_t nnz, bool weighted, const int64_t *__restrict__ meta,
+k_pb_tier_labels(int64_t n_lds, int64_t n, int64_t nnz, int kind, const int64_t *__restrict__ meta,
                  const int32_t *__restrict__ lds_ids, const uint8_t *__restrict__ lab, uint8_t *__restrict__ tab,
                  int32_t *err)
 {
-    if (!layout_matches(meta, n, nnz, n_lds, weighted, err)) return;
+    if (!layout_matches(meta, n, nnz, n_lds, kind, err)) return;
     const int64_t padded = (n_lds + 15) / 16 * 16;
     bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < padded; i += (int64_t)gridDim.x * blockDim.x) {
@@ -322,13 +396,13 @@ __device__ inline uint32_t tier_slot(const uint8_t *colb, int64_t H0, int64_t i)
 // them there. Sixteen entries' slots are three 16-byte loads. Slots are masked to the
 // table, so no LDS read leaves it.
 __global__ void __launch_bounds__(kLdsT)
-k_pb_gather_tier(int64_t nnz, int64_t n, bool weighted, const int64_t *__restrict__ meta, int32_t n_sl, int64_t n_lds,
+k_pb_gather_tier(int64_t nnz, int64_t n, int kind, const int64_t *__restrict__ meta, int32_t n_sl, int64_t n_lds,
                  const int64_t *__restrict__ sl_start, const int64_t *__restrict__ last_start,
                  const uint32_t *__restrict__ last_count, const uint8_t *__restrict__ colb,
                  const uint8_t *__restrict__ tab, uint8_t *__restrict__ yv, int32_t *err)
 {
     extern __shared__ __align__(16) uint8_t stab[];
-    if (!layout_matches(meta, n, nnz, n_lds, weighted, err)) return;
+    if (!layout_matches(meta, n, nnz, n_lds, kind, err)) return;
     __shared__ int64_t bnd[kPbMaxSlices + 1];
     const int t = threadIdx.x;
     const int64_t lim = nnz + 16; // entries of the layout, gap included, are at most nnz + 15
@@ -407,8 +481,9 @@ k_pb_gather_tier(int64_t nnz, int64_t n, bool weighted, const int64_t *__restric
 // 32-bit bins.
 //
 // WT (weighted layout): the bins hold sums of the entries' weights. A block whose flag
-// is 0 (rows of at most kPbF32Terms entries, no negative weight) sums in FP32; a
-// flagged block in FP64. The bins' LDS holds R rows of either (R = 256 or 128 for FP32,
+// is 0 (rows of at most kPbF32Terms entries, no negative weight) sums in 32-bit integers
+// when the layout's weights lie on a grid 2^-g (meta[4] = g; the sums are then exact),
+// else in FP32; a flagged block sums in FP64. The bins' LDS holds R rows of either (R = 256 or 128 for FP32,
 // half that for FP64), and the block's rows are taken R at a time, one pass over its
 // words each.
 template <bool VEC, bool HALF, bool WT>
@@ -417,14 +492,15 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
           uint64_t magicK, int32_t n_cb, int32_t top, const int64_t *__restrict__ cell_start,
           const uint32_t *__restrict__ cell_count, const uint32_t *__restrict__ cell_word,
           const uint32_t *__restrict__ ul4, const uint32_t *__restrict__ yv4, const f32x4 *__restrict__ vl4,
-          const uint8_t *__restrict__ rb_flag, const double *__restrict__ inv, float *__restrict__ Z, int32_t *err)
+          const uint8_t *__restrict__ rb_flag, const float *__restrict__ rsd, const double *__restrict__ inv,
+          float *__restrict__ Z, int32_t *err)
 {
     // LDS: bins [nb] uint32 (nb = 256 K, or 128 K for HALF, rounded up to 4), invx
     // [K + 3] double (invx[i] = 1/n_(i mod K) + 1), per cell: first word [n_cb] int64,
     // word prefix [n_cb + 1], entry count [n_cb], byte offset of the start in its word
     // [n_cb].
     extern __shared__ __align__(16) uint32_t bins[];
-    if (!layout_matches(meta, n, nnz, n_lds, WT, err)) return;
+    if (!layout_matches(meta, n, nnz, n_lds, rsd ? 2 : (WT ? 1 : 0), err)) return;
     const uint32_t nb = (uint32_t)align_up((size_t)(HALF ? kPbRows / 2 : kPbRows) * K, 4);
     double *invx = reinterpret_cast<double *>(bins + nb);
     int64_t *cw0 = reinterpret_cast<int64_t *>(invx + K + 3);
@@ -525,7 +601,9 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
     // rows [lo, hi) of the block to Z from the bins, get4(g) giving the four sums of flat
     // elements g .. g + 3 (g a multiple of 4) and get1(g) one, g counted from row lo;
     // 16-byte stores when VEC (Z 16-byte aligned and lo K a multiple of 4)
-    auto write = [&](int lo, int hi, auto get4, auto get1) __attribute__((always_inline)) {
+    // scale(k, g): the factor of element g (class k): 1/n_k, times the row's d^-1/2 for a
+    // Laplacian layout
+    auto write = [&](int lo, int hi, auto get4, auto get1, auto scale) __attribute__((always_inline)) {
         float *zb = Z + (r0 + lo) * K;
         const uint32_t total = (uint32_t)(hi - lo) * (uint32_t)K;
         uint32_t done = 0;
@@ -535,17 +613,18 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
                 const uint32_t f = 4u * v;
                 const uint32_t k = f - div_small(f, magicK) * (uint32_t)K;
                 const auto c = get4(f);
-                const f32x4 o = {(float)((double)c.x * invx[k]), (float)((double)c.y * invx[k + 1]),
-                                 (float)((double)c.z * invx[k + 2]), (float)((double)c.w * invx[k + 3])};
+                const f32x4 o = {(float)((double)c.x * scale(k, f)), (float)((double)c.y * scale(k + 1, f + 1)),
+                                 (float)((double)c.z * scale(k + 2, f + 2)), (float)((double)c.w * scale(k + 3, f + 3))};
                 __builtin_nontemporal_store(o, reinterpret_cast<f32x4 *>(zb) + v);
             }
             done = nv * 4;
         }
         for (uint32_t f = done + t; f < total; f += kRowsT) {
             const uint32_t k = f - div_small(f, magicK) * (uint32_t)K;
-            __builtin_nontemporal_store((float)((double)get1(f) * invx[k]), zb + f);
+            __builtin_nontemporal_store((float)((double)get1(f) * scale(k, f)), zb + f);
         }
     };
+    auto inv_only = [&](uint32_t k, uint32_t) { return invx[k]; };
     auto zero = [&]() __attribute__((always_inline)) {
         __syncthreads(); // the previous rows are written
         for (uint32_t i = t; i < nb / 4; i += kRowsT) reinterpret_cast<u32x4 *>(bins)[i] = u32x4{0u, 0u, 0u, 0u};
@@ -555,33 +634,58 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
         float *fb = reinterpret_cast<float *>(bins);
         double *db = reinterpret_cast<double *>(bins);
         const bool wide = rb_flag[rb] != 0;
+        const int64_t grid = meta[4];
+        int lo_cur = 0; // first row of the current pass (for the row factor)
+        auto lap_scale = [&](uint32_t k, uint32_t g) {
+            return invx[k] * (double)rsd[r0 + lo_cur + (int64_t)div_small(g, magicK)];
+        };
         int R = (int)(nb / (uint32_t)(wide ? 2 * K : K));
         R = R < kPbRows ? R : kPbRows;
         for (int lo = 0; lo < nr; lo += R) {
             if (lo > 0) zero();
             const int hi = nr < lo + R ? nr : lo + R;
+            lo_cur = lo;
             if (wide) {
                 count([&](uint32_t ub, uint32_t yb, float w) {
                     if (ub - (uint32_t)lo < (uint32_t)R)
                         atomicAdd(&db[(ub - (uint32_t)lo) * (uint32_t)K + (yb - 1u)], (double)w);
                 });
                 __syncthreads();
-                write(
-                    lo, hi,
-                    [&](uint32_t f) {
-                        const double2 a = reinterpret_cast<const double2 *>(db)[f / 2];
-                        const double2 b = reinterpret_cast<const double2 *>(db)[f / 2 + 1];
-                        return f64x4{a.x, a.y, b.x, b.y};
-                    },
-                    [&](uint32_t f) { return db[f]; });
+                auto g4 = [&](uint32_t f) {
+                    const double2 a = reinterpret_cast<const double2 *>(db)[f / 2];
+                    const double2 b = reinterpret_cast<const double2 *>(db)[f / 2 + 1];
+                    return f64x4{a.x, a.y, b.x, b.y};
+                };
+                auto g1 = [&](uint32_t f) { return db[f]; };
+                if (rsd) write(lo, hi, g4, g1, lap_scale);
+                else write(lo, hi, g4, g1, inv_only);
+            } else if (grid != kPbNoGrid) {
+                // every weight is an integer multiple of 2^-grid: 32-bit integer sums of the
+                // scaled weights are exact (the build checked that they stay below 2^32), and
+                // the row is written from the exact value, as from FP64 sums
+                const float up = ldexpf(1.0f, (int)grid);
+                const double down = ldexp(1.0, -(int)grid);
+                count([&](uint32_t ub, uint32_t yb, float w) {
+                    if (ub - (uint32_t)lo < (uint32_t)R)
+                        atomicAdd(&bins[(ub - (uint32_t)lo) * (uint32_t)K + (yb - 1u)], (uint32_t)(w * up));
+                });
+                __syncthreads();
+                auto g4 = [&](uint32_t f) {
+                    const u32x4 c = reinterpret_cast<const u32x4 *>(bins)[f / 4];
+                    return f64x4{(double)c.x * down, (double)c.y * down, (double)c.z * down, (double)c.w * down};
+                };
+                auto g1 = [&](uint32_t f) { return (double)bins[f] * down; };
+                if (rsd) write(lo, hi, g4, g1, lap_scale);
+                else write(lo, hi, g4, g1, inv_only);
             } else {
                 count([&](uint32_t ub, uint32_t yb, float w) {
                     if (ub - (uint32_t)lo < (uint32_t)R) atomicAdd(&fb[(ub - (uint32_t)lo) * (uint32_t)K + (yb - 1u)], w);
                 });
                 __syncthreads();
-                write(
-                    lo, hi, [&](uint32_t f) { return reinterpret_cast<const f32x4 *>(fb)[f / 4]; },
-                    [&](uint32_t f) { return fb[f]; });
+                auto g4 = [&](uint32_t f) { return reinterpret_cast<const f32x4 *>(fb)[f / 4]; };
+                auto g1 = [&](uint32_t f) { return fb[f]; };
+                if (rsd) write(lo, hi, g4, g1, lap_scale);
+                else write(lo, hi, g4, g1, inv_only);
             }
         }
         return;
@@ -591,7 +695,7 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
     if (!HALF) {
         count([&](uint32_t ub, uint32_t yb, float) { atomicAdd(&bins[ub * (uint32_t)K + (yb - 1u)], 1u); });
         __syncthreads();
-        write(0, nr, get4_32, get1_32);
+        write(0, nr, get4_32, get1_32, inv_only);
         return;
     }
     if (T <= 16383u) {
@@ -607,7 +711,7 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
                 const uint2 w = reinterpret_cast<const uint2 *>(bins)[f / 4];
                 return u32x4{w.x & 0xffffu, w.x >> 16, w.y & 0xffffu, w.y >> 16};
             },
-            [&](uint32_t f) { return (bins[f >> 1] >> (16u * (f & 1u))) & 0xffffu; });
+            [&](uint32_t f) { return (bins[f >> 1] >> (16u * (f & 1u))) & 0xffffu; }, inv_only);
         return;
     }
     for (int h = 0; h < 2 && h * (kPbRows / 2) < nr; ++h) {
@@ -617,7 +721,7 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
         });
         __syncthreads();
         const int lo = h * (kPbRows / 2), hi = nr < lo + kPbRows / 2 ? nr : lo + kPbRows / 2;
-        write(lo, hi, get4_32, get1_32);
+        write(lo, hi, get4_32, get1_32, inv_only);
     }
 }
 
@@ -635,7 +739,7 @@ PbLayout pb_layout(int64_t n, int64_t n_lds)
 }
 
 // Build scratch: two key buffers [nnz], radix histograms, scan partials, two cell arrays.
-size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds, bool weighted)
+size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds, bool weighted, bool laplacian)
 {
     const PbLayout L = pb_layout(n, n_lds);
     size_t hb, ob, pbytes;
@@ -653,17 +757,20 @@ size_t pb_build_scratch(int64_t n, int64_t nnz, int64_t n_lds, bool weighted)
     take((size_t)L.cells * 8);
     take((size_t)L.cells * 8);
     take(16);
-    if (weighted) {
+    take(16);
+    if (weighted || laplacian) {
         take((size_t)nnz * 4);
         take((size_t)nnz * 4);
     }
+    if (laplacian) take((size_t)n * 8);
     return align_up(off, 256);
 }
 
 hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const float *val,
-                           const int32_t *hot_ids, int64_t n_hot, int64_t n_lds, int32_t *colc, uint8_t *ul,
-                           int64_t *cell_start, uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids,
-                           float *vl, uint8_t *rb_flag, int64_t *meta, void *ws, int32_t *err, hipStream_t s)
+                           bool laplacian, const int32_t *hot_ids, int64_t n_hot, int64_t n_lds, int32_t *colc,
+                           uint8_t *ul, int64_t *cell_start, uint32_t *cell_count, uint32_t *cell_word,
+                           int32_t *lds_ids, float *vl, uint8_t *rb_flag, float *rsd, int64_t *meta, void *ws,
+                           int32_t *err, hipStream_t s)
 {
     const PbLayout L = pb_layout(n, n_lds);
     size_t hb, ob, pbytes;
@@ -683,20 +790,42 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
     int64_t *part = (int64_t *)take(pbytes);
     int64_t *celllast = (int64_t *)take((size_t)L.cells * 8);
     int64_t *cellend = (int64_t *)take((size_t)L.cells * 8);
-    int64_t *tier = L.n_sl > 0 ? (int64_t *)take(16) : nullptr; // {h0, H0}
-    if (!tier) take(16);
-    float *v0 = val ? (float *)take((size_t)nnz * 4) : nullptr;
-    float *v1 = val ? (float *)take((size_t)nnz * 4) : nullptr;
-    float *sval = nullptr; // weights in sorted order
+    int64_t *tier_buf = (int64_t *)take(16);
+    int64_t *tier = L.n_sl > 0 ? tier_buf : nullptr; // {h0, H0}
+    int32_t *ex = (int32_t *)take(16);                // lowest and highest weight bit (weighted)
+    const bool carried = val != nullptr || laplacian; // a value per entry goes with the sort
+    float *v0 = carried ? (float *)take((size_t)nnz * 4) : nullptr;
+    float *v1 = carried ? (float *)take((size_t)nnz * 4) : nullptr;
+    double *deg = laplacian ? (double *)take((size_t)n * 8) : nullptr;
+    float *sval = nullptr; // values in sorted order
     hipError_t e;
     const dim3 b(kT);
-    hipLaunchKernelGGL(k_pb_meta, dim3(1), dim3(kWave), 0, s, meta, n, nnz, n_lds, (int64_t)(val != nullptr));
+    const int64_t kind = laplacian ? 2 : (val ? 1 : 0);
+    hipLaunchKernelGGL(k_pb_meta, dim3(1), dim3(kWave), 0, s, meta, n, nnz, n_lds, kind);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (val) {
+    if (carried) {
         hipLaunchKernelGGL(k_pb_rbflag, dim3(grid_cap(L.n_rb, 1)), b, 0, s, n, L.n_rb, row_ptr, val, rb_flag);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (nnz > 0 && (e = hipMemcpyAsync(v0, val, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        if (laplacian) {
+            // the graph's degrees and d^-1/2, then every entry's term w d_v^-1/2
+            if ((e = launch_degrees_csr(n, row_ptr, val, nnz, deg, true, err, s)) != hipSuccess) return e;
+            if ((e = launch_rsd(deg, n, rsd, s)) != hipSuccess) return e;
+            if (nnz > 0) {
+                hipLaunchKernelGGL(k_pb_lapw, dim3(grid_cap(nnz, kT * 4)), b, 0, s, nnz, n, col, val, hot_ids, n_hot,
+                                   rsd, v0);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
+        } else if (nnz > 0 && (e = hipMemcpyAsync(v0, val, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess) {
             return e;
+        }
+        hipLaunchKernelGGL(k_pb_grid_init, dim3(1), dim3(kWave), 0, s, ex);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (nnz > 0) {
+            hipLaunchKernelGGL(k_pb_grid_bits, dim3(grid_cap(nnz, kT * 16)), b, 0, s, nnz, v0, ex);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_pb_grid_final, dim3(1), dim3(kWave), 0, s, ex, meta);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
         sval = v0;
     }
     if (n_lds > 0 && (e = hipMemcpyAsync(lds_ids, hot_ids, (size_t)n_lds * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess)
@@ -717,7 +846,7 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
         if (L.n_cb > 1) {
             int hi = 32 + kPbColBits;
             while (hi < 64 && ((int64_t)1 << (hi - 32 - kPbColBits)) < L.n_cb) ++hi;
-            if (val) {
+            if (carried) {
                 if ((e = radix_sort_bits_kv(k0, k1, v0, v1, nnz, 32 + kPbColBits, hi, hist, offs, part, &sorted, &sval,
                                             s)) != hipSuccess)
                     return e;
@@ -749,18 +878,18 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
 
 hipError_t launch_pb_gather(int64_t n, int64_t nnz, const PbLayout &L, int64_t n_lds, const int64_t *cell_start,
                             const uint32_t *cell_count, const int32_t *colc, const int32_t *lds_ids,
-                            const int64_t *meta, bool weighted, const uint8_t *lab, uint8_t *tab, uint8_t *yv,
+                            const int64_t *meta, int kind, const uint8_t *lab, uint8_t *tab, uint8_t *yv,
                             int32_t *err, hipStream_t s)
 {
     if (nnz <= 0) return hipSuccess;
     const int64_t *sl_start = L.n_sl > 0 ? cell_start + L.n_vcb : nullptr; // cells (0, n_vcb + j)
     // vertex blocks: one workgroup per 8,192 entries, dispatched in order, so the entries
     // in flight stay within one or two column blocks (their labels in L2)
-    hipLaunchKernelGGL(k_pb_gather, dim3(grid_cap(nnz, kT * 32)), dim3(kT), 0, s, nnz, n, n_lds, weighted, meta,
+    hipLaunchKernelGGL(k_pb_gather, dim3(grid_cap(nnz, kT * 32)), dim3(kT), 0, s, nnz, n, n_lds, kind, meta,
                        sl_start, colc, lab, yv, err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || L.n_sl == 0) return e;
-    hipLaunchKernelGGL(k_pb_tier_labels, dim3(grid_cap(n_lds, kT * 4)), dim3(kT), 0, s, n_lds, n, nnz, weighted, meta,
+    hipLaunchKernelGGL(k_pb_tier_labels, dim3(grid_cap(n_lds, kT * 4)), dim3(kT), 0, s, n_lds, n, nnz, kind, meta,
                        lds_ids, lab, tab, err);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int dev = 0, cus = 0;
@@ -771,7 +900,7 @@ hipError_t launch_pb_gather(int64_t n, int64_t nnz, const PbLayout &L, int64_t n
     if (grid > cus) grid = cus;
     if (grid < 1) grid = 1;
     const int64_t last = L.cells - 1; // the last cell of the column-block-major order
-    hipLaunchKernelGGL(k_pb_gather_tier, dim3((unsigned)grid), dim3(kLdsT), (size_t)kPbSlice, s, nnz, n, weighted,
+    hipLaunchKernelGGL(k_pb_gather_tier, dim3((unsigned)grid), dim3(kLdsT), (size_t)kPbSlice, s, nnz, n, kind,
                        meta, L.n_sl, n_lds, sl_start, cell_start + last, cell_count + last,
                        reinterpret_cast<const uint8_t *>(colc), tab, yv, err);
     return hipGetLastError();
@@ -799,8 +928,8 @@ bool pb_rows_half(int32_t K, int32_t n_cb) { return 3 * pb_rows_lds_bytes(K, n_c
 
 hipError_t launch_pb_rows(int64_t n, int64_t nnz, int32_t K, const PbLayout &L, const int64_t *cell_start,
                           const uint32_t *cell_count, const uint32_t *cell_word, const uint8_t *ul, const uint8_t *yv,
-                          const float *vl, const uint8_t *rb_flag, const int64_t *meta, int64_t n_lds,
-                          const double *inv, float *Z, int32_t *err, hipStream_t s)
+                          const float *vl, const uint8_t *rb_flag, const float *rsd, const int64_t *meta,
+                          int64_t n_lds, const double *inv, float *Z, int32_t *err, hipStream_t s)
 {
     const int64_t lim = nnz + 15; // layout entries, the gap before the tier included
     const bool half = pb_rows_half(K, L.n_cb);
@@ -814,7 +943,8 @@ hipError_t launch_pb_rows(int64_t n, int64_t nnz, int32_t K, const PbLayout &L, 
     const bool vec = (reinterpret_cast<uintptr_t>(Z) & 15) == 0;
 #define GEE_ROWS(V, H, W)                                                                                            \
     hipLaunchKernelGGL((k_pb_rows<V, H, W>), dim3((unsigned)L.n_rb), dim3(kRowsT), lds, s, n, nnz, n_lds, meta, lim, \
-                       K, magic, L.n_cb, top, cell_start, cell_count, cell_word, ul4, yv4, vl4, rb_flag, inv, Z, err)
+                       K, magic, L.n_cb, top, cell_start, cell_count, cell_word, ul4, yv4, vl4, rb_flag, rsd, inv, Z,  \
+                       err)
     if (vl) {
         if (half) {
             if (vec) GEE_ROWS(true, true, true);

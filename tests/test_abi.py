@@ -35,6 +35,28 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, name), f"{name} declared in gee.h but not exported"
 
 
+def declared_arity():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(gee_\w+)\s*\(([^;{()]*)\)\s*;", text, flags=re.S):
+        params = m.group(2).strip()
+        out[m.group(1)] = 0 if params in ("", "void") else len(params.split(","))
+    return out
+
+
+def test_binding_arity_matches_header(lib):
+    """Every ctypes prototype has exactly the header's parameter count. A short list lets
+    ctypes pass the trailing arguments by default conversion (a Python int becomes a 32-bit
+    int whose upper half in a 64-bit slot is undefined), which corrupts a stream handle."""
+    arity = declared_arity()
+    assert set(arity) == set(declared_functions())
+    for name, n in arity.items():
+        at = getattr(lib, name).argtypes
+        assert at is not None, f"{name} has no argtypes"
+        assert len(at) == n, f"{name}: {len(at)} argtypes, {n} parameters in gee.h"
+
+
 def test_strerror(lib):
     for code in range(-7, 1):
         assert lib.gee_strerror(code)
@@ -195,15 +217,18 @@ def test_pb_argument_errors(lib):
     hot = gee.Csr(1000, 10_000, FAKE, FAKE, None, 700, FAKE)
     weighted = gee.Csr(1000, 10_000, FAKE, FAKE, FAKE, 0, None)
     huge = gee.Csr(1000, (1 << 32) - 64, FAKE, FAKE, None, 0, None)
-    assert lib.gee_pb_build_workspace(ctypes.byref(plain), 0) > 10_000 * 16
-    assert lib.gee_pb_build_workspace(ctypes.byref(plain), 1) == 0    # no hot slots to put in the tier
-    assert lib.gee_pb_build_workspace(ctypes.byref(hot), 700) > 10_000 * 16
-    assert lib.gee_pb_build_workspace(ctypes.byref(hot), 701) == 0
-    assert lib.gee_pb_build_workspace(ctypes.byref(weighted), 0) > lib.gee_pb_build_workspace(ctypes.byref(plain), 0)
-    assert lib.gee_pb_build_workspace(ctypes.byref(huge), 0) == 0      # 32-bit cell lengths
-    def build(c, tier, col=FAKE, ul=FAKE, word=FAKE, ids=FAKE, val=None, flag=None, meta=FAKE, wsb=1 << 40):
-        return lib.gee_pb_build(ctypes.byref(c), tier, col, ul, FAKE, FAKE, word, ids, val, flag, meta, FAKE, wsb,
-                                FAKE, None)
+    bw = lambda c, tier, lap=0: lib.gee_pb_build_workspace(ctypes.byref(c), tier, lap)
+    assert bw(plain, 0) > 10_000 * 16
+    assert bw(plain, 1) == 0    # no hot slots to put in the tier
+    assert bw(hot, 700) > 10_000 * 16
+    assert bw(hot, 701) == 0
+    assert bw(weighted, 0) > bw(plain, 0)
+    assert bw(plain, 0, 1) > bw(weighted, 0)  # the terms and the degrees
+    assert bw(huge, 0) == 0      # 32-bit cell lengths
+    def build(c, tier, col=FAKE, ul=FAKE, word=FAKE, ids=FAKE, val=None, flag=None, meta=FAKE, wsb=1 << 40,
+              lap=0, rsd=None):
+        return lib.gee_pb_build(ctypes.byref(c), tier, lap, col, ul, FAKE, FAKE, word, ids, val, flag, rsd, meta,
+                                FAKE, wsb, FAKE, None)
 
     assert build(huge, 0) == gee.GEE_EOVERFLOW
     assert build(hot, 700, ids=None) == gee.GEE_EINVAL  # lds_ids needed
@@ -215,8 +240,11 @@ def test_pb_argument_errors(lib):
     assert build(weighted, 0, val=FAKE, flag=None) == gee.GEE_EINVAL  # row-block flags needed
     assert build(weighted, 0, val=None, flag=FAKE) == gee.GEE_EINVAL  # weights needed
     assert build(weighted, 0, val=FAKE + 4, flag=FAKE) == gee.GEE_EINVAL  # weights 16-byte aligned
-    assert build(weighted, 0, val=FAKE, flag=FAKE, wsb=lib.gee_pb_build_workspace(ctypes.byref(weighted), 0) - 1) == \
-        gee.GEE_EWORKSPACE
+    assert build(weighted, 0, val=FAKE, flag=FAKE, wsb=bw(weighted, 0) - 1) == gee.GEE_EWORKSPACE
+    assert build(plain, 0, lap=1, val=FAKE, flag=FAKE) == gee.GEE_EINVAL  # d^-1/2 output needed
+    assert build(plain, 0, lap=1, rsd=FAKE) == gee.GEE_EINVAL  # Laplacian terms and flags needed
+    assert build(plain, 0, rsd=FAKE) == gee.GEE_EINVAL  # d^-1/2 only for a Laplacian layout
+    assert build(plain, 0, lap=1, val=FAKE, flag=FAKE, rsd=FAKE, wsb=bw(plain, 0, 1) - 1) == gee.GEE_EWORKSPACE
     # the tier planner: nothing to plan without hot slots; checks before any launch
     assert lib.gee_pb_tier_slots(ctypes.byref(plain), 4, None, 0, None) == 0
     assert lib.gee_pb_tier_slots(ctypes.byref(hot), 4, None, 0, None) == gee.GEE_EWORKSPACE
@@ -233,8 +261,8 @@ def test_pb_argument_errors(lib):
     assert lib.gee_embed_pb_workspace(ctypes.byref(weighted_pb), 8) > 10_000
     assert lib.gee_embed_pb_workspace(ctypes.byref(tiered), 8) > 10_000
     o = gee.EmbedOpts(0, 0, None, None)
-    def P(n_rb=4, n_cb=1, col=FAKE, ul=FAKE, n_lds=0, ids=None, word=FAKE, val=None, flag=None, meta=FAKE):
-        return gee.Pb(1000, 10_000, n_rb, n_cb, col, ul, FAKE, FAKE, n_lds, ids, word, val, flag, meta)
+    def P(n_rb=4, n_cb=1, col=FAKE, ul=FAKE, n_lds=0, ids=None, word=FAKE, val=None, flag=None, meta=FAKE, rsd=None):
+        return gee.Pb(1000, 10_000, n_rb, n_cb, col, ul, FAKE, FAKE, n_lds, ids, word, val, flag, meta, rsd)
 
     for bad in (P(n_rb=5),  # n_rb does not match n
                 P(n_lds=5, ids=FAKE),  # n_cb without the tier slice
@@ -246,7 +274,8 @@ def test_pb_argument_errors(lib):
                 P(meta=None),  # no fingerprint
                 P(val=FAKE),  # weights without row-block flags
                 P(flag=FAKE),  # row-block flags without weights
-                P(val=FAKE + 4, flag=FAKE)):  # weights unaligned
+                P(val=FAKE + 4, flag=FAKE),  # weights unaligned
+                P(rsd=FAKE)):  # d^-1/2 without terms
         assert lib.gee_embed_pb_workspace(ctypes.byref(bad), 8) == 0
         assert lib.gee_embed_pb(ctypes.byref(bad), FAKE, 8, FAKE, FAKE, 1 << 30, FAKE, ctypes.byref(o), None) == \
             gee.GEE_EINVAL

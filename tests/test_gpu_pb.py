@@ -288,9 +288,8 @@ def test_weighted_layout_matches_oracle(K, tier):
     leaves (a row of more than 128 entries) and a few negative weights, so that row blocks
     take FP32 sums, FP64 sums and, for K = 100, passes over half or a quarter of their
     rows. Within the bar of the oracle, flags as the records imply, and the same with Z
-    at an offset of one float. The block's wavefronts add weights into shared bins in an
-    order that varies from call to call, so two calls agree within rounding, not bit for
-    bit."""
+    at an offset of one float. The weights lie on the 2^-24 grid, so unflagged blocks add
+    them exactly in 32-bit integers and every call gives the same bits."""
     rng = np.random.default_rng(K + (tier == "all"))
     n, s = 40_000, 500_000
     src = rng.integers(0, n, s).astype(np.int32)
@@ -306,9 +305,12 @@ def test_weighted_layout_matches_oracle(K, tier):
     pb = gee.pb_build(csr, tier_slots=None if tier == "all" else 0)
     assert pb.val is not None and (pb.n_lds > 0) == (tier == "all")
     assert np.array_equal(pb.rb_flag.cpu().numpy(), _flags_host(n, src, dst, w))
-    assert pb.meta.cpu().tolist() == [n, csr.nnz, pb.n_lds, 1]
+    meta = pb.meta.cpu().tolist()
+    assert meta[:4] == [n, csr.nnz, pb.n_lds, 1]
+    assert meta[4] == 24  # weights (r + 1) 2^-24 up to 1: exact 32-bit sums of 2^24 w
     labels = torch.as_tensor(Y).to(DEV)
     Z = gee.embed_pb(labels, K, pb)
+    _same_bits(gee.embed_pb(labels, K, pb), Z)  # integer sums: the same bits on every call
     Zo = oracle.embed(n, src, dst, w, Y, K, False)
     Zn = Z.cpu().numpy()
     assert_parity(Zn, Zo, what=f"weighted layout K={K} tier={tier}")
@@ -331,3 +333,84 @@ def test_weighted_layout_er_workload_shape():
     assert pb.n_lds == g.n
     Z = gee.embed_pb(torch.as_tensor(wl.labels).to(DEV), wl.K, pb).cpu().numpy()
     assert_parity(Z, oracle.embed(g.n, g.src, g.dst, g.w, wl.labels, wl.K, False), what="weighted ER layout")
+
+
+def test_weighted_layout_off_grid():
+    """Weights with no common grid (significands down to 2^-70 and below):
+    the build records no grid, unflagged blocks sum in FP32 (shared bins, so two calls
+    agree within rounding), and the result is within the bar of the oracle."""
+    rng = np.random.default_rng(77)
+    n, s, K = 30_000, 400_000, 20
+    src = rng.integers(0, n, s).astype(np.int32)
+    dst = rng.integers(0, n, s).astype(np.int32)
+    # cubes of uniform doubles, rounded to FP32: exponents down to 2^-50 and beyond with full
+    # significands (uniform FP32 draws would all be multiples of 2^-24)
+    w = (rng.random(s) ** 3).astype(np.float32)
+    w[w == 0] = 0.5
+    Y = random_labels(rng, n, K)
+    csr = gee.csr_build(gee.to_device(n, src, dst, w, device=DEV), hot_budget=n)
+    pb = gee.pb_build(csr)
+    assert pb.meta.cpu().tolist()[4] == -(1 << 62)
+    labels = torch.as_tensor(Y).to(DEV)
+    Z = gee.embed_pb(labels, K, pb).cpu().numpy()
+    assert_parity(Z, oracle.embed(n, src, dst, w, Y, K, False), what="weights off any grid")
+    assert_parity(gee.embed_pb(labels, K, pb).cpu().numpy(), Z.astype(np.float64), what="second call")
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("K", [7, 100])
+def test_laplacian_layout_matches_oracle(weighted, K):
+    """Laplacian layout: the degrees and each entry's w d_v^-1/2 taken at the build, the row's
+    d_u^-1/2 applied when it is written. Unit and grid weights, a hub row (FP64 blocks),
+    isolated vertices (zero rows), with and without the tier; within the bar of the oracle
+    and of the CSR pull form, d^-1/2 as the CSR's degrees give it."""
+    rng = np.random.default_rng(K + 10 * weighted)
+    n, s = 30_000, 300_000
+    src = rng.integers(0, n - 500, s).astype(np.int32)  # the last 500 vertices isolated
+    dst = rng.integers(0, n - 500, s).astype(np.int32)
+    hub = np.arange(1, 301, dtype=np.int32) * 41
+    src = np.r_[src, np.full(hub.size, 777, np.int32)].astype(np.int32)
+    dst = np.r_[dst, hub].astype(np.int32)
+    w = ((rng.integers(0, 1 << 24, src.size) + 1) * 2.0 ** -24).astype(np.float32) if weighted else None
+    Y = random_labels(rng, n, K, unknown=0.2)
+    Zo = oracle.embed(n, src, dst, w, Y, K, True)
+    coo = gee.to_device(n, src, dst, w, device=DEV)
+    labels = torch.as_tensor(Y).to(DEV)
+    for hot in (0, n):
+        csr = gee.csr_build(coo, hot_budget=hot)
+        pb = gee.pb_build(csr, tier_slots=None if hot else 0, laplacian=True)
+        assert pb.laplacian and pb.meta.cpu().tolist()[3] == 2
+        d = oracle.degrees(n, src, dst, w)
+        r = np.where(d > 0, 1.0 / np.sqrt(np.where(d > 0, d, 1.0)), 0.0).astype(np.float32)
+        assert np.array_equal(pb.rsd.cpu().numpy(), r)
+        Z = gee.embed_pb(labels, K, pb).cpu().numpy()
+        assert_parity(Z, Zo, what=f"Laplacian layout K={K} weighted={weighted} hot={hot}")
+        assert not Z[n - 500:].any()
+        Zp = gee.embed(labels, K, csr=csr, laplacian=True).cpu().numpy()
+        assert_parity(Z, Zp.astype(np.float64), what="Laplacian layout vs pull")
+
+
+def test_laplacian_layout_negative_weight_and_mismatch():
+    """A negative weight raises GEE_ENEGW at the Laplacian build; a Laplacian layout struct
+    handed over without its d^-1/2 (read as adjacency) is refused by the fingerprint."""
+    rng = np.random.default_rng(3)
+    n, s = 2000, 10_000
+    src = rng.integers(0, n, s).astype(np.int32)
+    dst = rng.integers(0, n, s).astype(np.int32)
+    w = np.ones(s, np.float32)
+    w[17] = -0.5
+    csr = gee.csr_build(gee.to_device(n, src, dst, w, device=DEV))
+    with pytest.raises(gee.GeeError) as e:
+        gee.pb_build(csr, laplacian=True)
+    assert e.value.code == gee.GEE_ENEGW
+    w[17] = 0.5
+    csr = gee.csr_build(gee.to_device(n, src, dst, w, device=DEV))
+    pb = gee.pb_build(csr, laplacian=True)
+    as_adj = gee.DevicePb(n, pb.col, pb.ul, pb.cell_start, pb.cell_count, pb.lds_ids, pb.cell_word, pb.nnz, pb.meta,
+                          pb.val, pb.rb_flag, None)
+    labels = torch.as_tensor(random_labels(rng, n, 5)).to(DEV)
+    with pytest.raises(gee.GeeError) as e:
+        gee.embed_pb(labels, 5, as_adj)
+    assert e.value.code == gee.GEE_EVERTEX
+    assert_parity(gee.embed_pb(labels, 5, pb).cpu().numpy(),
+                  oracle.embed(n, src, dst, w, labels.cpu().numpy(), 5, True), what="Laplacian layout")
