@@ -211,11 +211,11 @@ int gee_embed_noalloc(const gee_coo *g, const gee_csr *csr, const int32_t *label
  * is the bit-reproducible one).
  *
  * A Laplacian layout (gee_pb_build with laplacian != 0) stores, in place of the weights,
- * each entry's w d_v^-1/2 (its column's factor, FP32: one rounding of the exact product)
- * and every vertex's d^-1/2 (rsd), the degrees d = (A + A^T) 1 being taken once when the
- * layout is built, as the CSR is (they depend on the graph only). The pass then adds the
- * stored terms as a weighted layout does and writes each row scaled by its own d_u^-1/2:
- * the Laplacian version, within the same rounding bound.
+ * each entry's w d_u^-1/2 d_v^-1/2 (both its row's and its column's factor, FP32: one
+ * rounding of the product of the FP32 weight and the two FP32 factors) and every vertex's
+ * d^-1/2 (rsd), the degrees d = (A + A^T) 1 being taken once when the layout is built, as
+ * the CSR is (they depend on the graph only). The pass then adds the stored terms as a
+ * weighted layout does: the Laplacian version, within the same rounding bound.
  *
  * Cell (rb, cb) of the layout is the run of column block cb's entries whose rows
  * lie in [256 rb, 256 rb + 256); cell_start[rb * n_cb + cb] is its first index in

@@ -395,7 +395,7 @@ class DevicePb:
     cell_word: torch.Tensor   # [n_rb * n_cb]
     nnz: int = 0
     meta: torch.Tensor | None = None     # [8] int64 fingerprint (and weight grid) written by the build
-    val: torch.Tensor | None = None      # [nnz + 32 rounded up to 16] float32: w, or w d_v^-1/2 (Laplacian)
+    val: torch.Tensor | None = None      # [nnz + 32 rounded up to 16] float32: w, or w d_u^-1/2 d_v^-1/2 (Laplacian)
     rb_flag: torch.Tensor | None = None  # [n_rb] uint8, weighted and Laplacian layouts
     rsd: torch.Tensor | None = None      # [n] float32 d^-1/2, Laplacian layouts
 

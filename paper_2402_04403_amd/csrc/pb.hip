@@ -188,12 +188,14 @@ __global__ void k_pb_meta(int64_t *meta, int64_t n, int64_t nnz, int64_t n_lds, 
     }
 }
 
-// The Laplacian layout's term of every CSR entry, in CSR order: w d_v^-1/2 for its column v
-// (a hot-slot column decoded through hot_ids), the exact product of the FP32 weight and
-// the FP32 d^-1/2 rounded once to FP32. A column outside [0, n) gives 0 (k_pb_key flags it).
+// The Laplacian layout's term of every CSR entry, in CSR order: w d_u^-1/2 d_v^-1/2 for its
+// row u (the low half of its key) and column v (a hot-slot column decoded through
+// hot_ids), the product of the FP32 weight and the two FP32 factors (exact in FP64)
+// rounded once to FP32. A column outside [0, n) gives 0 (k_pb_key flags it).
 __global__ void __launch_bounds__(kT)
 k_pb_lapw(int64_t nnz, int64_t n, const int32_t *__restrict__ col, const float *__restrict__ val,
-          const int32_t *__restrict__ hot_ids, int64_t n_hot, const float *__restrict__ rsd, float *__restrict__ out)
+          const int32_t *__restrict__ hot_ids, int64_t n_hot, const uint64_t *__restrict__ keys,
+          const float *__restrict__ rsd, float *__restrict__ out)
 {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c0 = col[e];
@@ -202,8 +204,10 @@ k_pb_lapw(int64_t nnz, int64_t n, const int32_t *__restrict__ col, const float *
             const int64_t slot = (int64_t)((uint32_t)c0 & 0x7fffffffu);
             v = slot < n_hot ? hot_ids[slot] : -1;
         }
-        const double r = (uint64_t)v < (uint64_t)n ? (double)rsd[v] : 0.0;
-        out[e] = (float)((val ? (double)val[e] : 1.0) * r);
+        const int64_t u = (int64_t)(keys[e] & 0xffffffffull);
+        const double rv = (uint64_t)v < (uint64_t)n ? (double)rsd[v] : 0.0;
+        const double ru = (uint64_t)u < (uint64_t)n ? (double)rsd[u] : 0.0;
+        out[e] = (float)((val ? (double)val[e] : 1.0) * ru * rv);
     }
 }
 
@@ -489,7 +493,7 @@ k_pb_gather_tier(int64_t nnz, int64_t n, int kind, const int64_t *__restrict__ m
 template <bool VEC, bool HALF, bool WT>
 __global__ void __launch_bounds__(kRowsT)
 k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ meta, int64_t lim, int32_t K,
-          uint64_t magicK, int32_t n_cb, int32_t top, const int64_t *__restrict__ cell_start,
+          uint64_t magicK, int32_t n_cb, int32_t top, int32_t strideq, const int64_t *__restrict__ cell_start,
           const uint32_t *__restrict__ cell_count, const uint32_t *__restrict__ cell_word,
           const uint32_t *__restrict__ ul4, const uint32_t *__restrict__ yv4, const f32x4 *__restrict__ vl4,
           const uint8_t *__restrict__ rb_flag, const float *__restrict__ rsd, const double *__restrict__ inv,
@@ -589,42 +593,46 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
             }
 #pragma unroll
             for (int j = 0; j < kRowsU; ++j) {
+                if (f0 + (uint32_t)j * kRowsT < T) {
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const uint32_t yb = (y[j] >> (8 * b)) & 0xffu;
-                    const uint32_t ub = (u[j] >> (8 * b)) & 0xffu;
-                    if (yb != 0u && rel[j] + (uint32_t)b < m[j]) add(ub, yb, wq[j][b]);
+                    for (int b = 0; b < 4; ++b) {
+                        const uint32_t yb = (y[j] >> (8 * b)) & 0xffu;
+                        const uint32_t ub = (u[j] >> (8 * b)) & 0xffu;
+                        add(ub, yb, wq[j][b], yb != 0u && rel[j] + (uint32_t)b < m[j]);
+                    }
                 }
             }
         }
     };
     // rows [lo, hi) of the block to Z from the bins, get4(g) giving the four sums of flat
-    // elements g .. g + 3 (g a multiple of 4) and get1(g) one, g counted from row lo;
-    // 16-byte stores when VEC (Z 16-byte aligned and lo K a multiple of 4)
-    // scale(k, g): the factor of element g (class k): 1/n_k, times the row's d^-1/2 for a
-    // Laplacian layout
-    auto write = [&](int lo, int hi, auto get4, auto get1, auto scale) __attribute__((always_inline)) {
+    // elements g .. g + 3 (g a multiple of 4) and get1(g) one, g counted from row lo, each
+    // times 1/n_k of its class k (a Laplacian layout's entries carry both d^-1/2 factors).
+    // With 16-byte stores (VEC: Z 16-byte aligned, lo K a multiple of 4) the quads a thread
+    // takes are strideq apart, a multiple of K elements, so all of them start at one class
+    // and its four factors stay in registers.
+    auto write = [&](int lo, int hi, auto get4, auto get1) __attribute__((always_inline)) {
         float *zb = Z + (r0 + lo) * K;
         const uint32_t total = (uint32_t)(hi - lo) * (uint32_t)K;
         uint32_t done = 0;
-        if (VEC) {
+        if (VEC && strideq > 0) {
             const uint32_t nv = total / 4;
-            for (uint32_t v = t; v < nv; v += kRowsT) {
-                const uint32_t f = 4u * v;
-                const uint32_t k = f - div_small(f, magicK) * (uint32_t)K;
-                const auto c = get4(f);
-                const f32x4 o = {(float)((double)c.x * scale(k, f)), (float)((double)c.y * scale(k + 1, f + 1)),
-                                 (float)((double)c.z * scale(k + 2, f + 2)), (float)((double)c.w * scale(k + 3, f + 3))};
-                __builtin_nontemporal_store(o, reinterpret_cast<f32x4 *>(zb) + v);
+            if (t < strideq) {
+                const uint32_t k = (4u * (uint32_t)t) % (uint32_t)K;
+                const double i0 = invx[k], i1 = invx[k + 1], i2 = invx[k + 2], i3 = invx[k + 3];
+                for (uint32_t v = t; v < nv; v += (uint32_t)strideq) {
+                    const auto c = get4(4u * v);
+                    const f32x4 o = {(float)((double)c.x * i0), (float)((double)c.y * i1), (float)((double)c.z * i2),
+                                     (float)((double)c.w * i3)};
+                    __builtin_nontemporal_store(o, reinterpret_cast<f32x4 *>(zb) + v);
+                }
             }
             done = nv * 4;
         }
         for (uint32_t f = done + t; f < total; f += kRowsT) {
             const uint32_t k = f - div_small(f, magicK) * (uint32_t)K;
-            __builtin_nontemporal_store((float)((double)get1(f) * scale(k, f)), zb + f);
+            __builtin_nontemporal_store((float)((double)get1(f) * invx[k]), zb + f);
         }
     };
-    auto inv_only = [&](uint32_t k, uint32_t) { return invx[k]; };
     auto zero = [&]() __attribute__((always_inline)) {
         __syncthreads(); // the previous rows are written
         for (uint32_t i = t; i < nb / 4; i += kRowsT) reinterpret_cast<u32x4 *>(bins)[i] = u32x4{0u, 0u, 0u, 0u};
@@ -635,19 +643,14 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
         double *db = reinterpret_cast<double *>(bins);
         const bool wide = rb_flag[rb] != 0;
         const int64_t grid = meta[4];
-        int lo_cur = 0; // first row of the current pass (for the row factor)
-        auto lap_scale = [&](uint32_t k, uint32_t g) {
-            return invx[k] * (double)rsd[r0 + lo_cur + (int64_t)div_small(g, magicK)];
-        };
         int R = (int)(nb / (uint32_t)(wide ? 2 * K : K));
         R = R < kPbRows ? R : kPbRows;
         for (int lo = 0; lo < nr; lo += R) {
             if (lo > 0) zero();
             const int hi = nr < lo + R ? nr : lo + R;
-            lo_cur = lo;
             if (wide) {
-                count([&](uint32_t ub, uint32_t yb, float w) {
-                    if (ub - (uint32_t)lo < (uint32_t)R)
+                count([&](uint32_t ub, uint32_t yb, float w, bool ok) {
+                    if (ok && ub - (uint32_t)lo < (uint32_t)R)
                         atomicAdd(&db[(ub - (uint32_t)lo) * (uint32_t)K + (yb - 1u)], (double)w);
                 });
                 __syncthreads();
@@ -657,16 +660,15 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
                     return f64x4{a.x, a.y, b.x, b.y};
                 };
                 auto g1 = [&](uint32_t f) { return db[f]; };
-                if (rsd) write(lo, hi, g4, g1, lap_scale);
-                else write(lo, hi, g4, g1, inv_only);
+                write(lo, hi, g4, g1);
             } else if (grid != kPbNoGrid) {
                 // every weight is an integer multiple of 2^-grid: 32-bit integer sums of the
                 // scaled weights are exact (the build checked that they stay below 2^32), and
                 // the row is written from the exact value, as from FP64 sums
                 const float up = ldexpf(1.0f, (int)grid);
                 const double down = ldexp(1.0, -(int)grid);
-                count([&](uint32_t ub, uint32_t yb, float w) {
-                    if (ub - (uint32_t)lo < (uint32_t)R)
+                count([&](uint32_t ub, uint32_t yb, float w, bool ok) {
+                    if (ok && ub - (uint32_t)lo < (uint32_t)R)
                         atomicAdd(&bins[(ub - (uint32_t)lo) * (uint32_t)K + (yb - 1u)], (uint32_t)(w * up));
                 });
                 __syncthreads();
@@ -675,17 +677,15 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
                     return f64x4{(double)c.x * down, (double)c.y * down, (double)c.z * down, (double)c.w * down};
                 };
                 auto g1 = [&](uint32_t f) { return (double)bins[f] * down; };
-                if (rsd) write(lo, hi, g4, g1, lap_scale);
-                else write(lo, hi, g4, g1, inv_only);
+                write(lo, hi, g4, g1);
             } else {
-                count([&](uint32_t ub, uint32_t yb, float w) {
-                    if (ub - (uint32_t)lo < (uint32_t)R) atomicAdd(&fb[(ub - (uint32_t)lo) * (uint32_t)K + (yb - 1u)], w);
+                count([&](uint32_t ub, uint32_t yb, float w, bool ok) {
+                    if (ok && ub - (uint32_t)lo < (uint32_t)R) atomicAdd(&fb[(ub - (uint32_t)lo) * (uint32_t)K + (yb - 1u)], w);
                 });
                 __syncthreads();
                 auto g4 = [&](uint32_t f) { return reinterpret_cast<const f32x4 *>(fb)[f / 4]; };
                 auto g1 = [&](uint32_t f) { return fb[f]; };
-                if (rsd) write(lo, hi, g4, g1, lap_scale);
-                else write(lo, hi, g4, g1, inv_only);
+                write(lo, hi, g4, g1);
             }
         }
         return;
@@ -693,14 +693,18 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
     auto get4_32 = [&](uint32_t f) { return reinterpret_cast<const u32x4 *>(bins)[f / 4]; };
     auto get1_32 = [&](uint32_t f) { return bins[f]; };
     if (!HALF) {
-        count([&](uint32_t ub, uint32_t yb, float) { atomicAdd(&bins[ub * (uint32_t)K + (yb - 1u)], 1u); });
+        // branch-free: an entry outside its cell or without a class adds 0 at a valid bin
+        count([&](uint32_t ub, uint32_t yb, float, bool ok) {
+            atomicAdd(&bins[__umul24(ub, (uint32_t)K) + (yb != 0u ? yb - 1u : 0u)], ok ? 1u : 0u);
+        });
         __syncthreads();
-        write(0, nr, get4_32, get1_32, inv_only);
+        write(0, nr, get4_32, get1_32);
         return;
     }
     if (T <= 16383u) {
         // at most 65532 entries: 16-bit counts, element f in half (f & 1) of word f / 2
-        count([&](uint32_t ub, uint32_t yb, float) {
+        count([&](uint32_t ub, uint32_t yb, float, bool ok) {
+            if (!ok) return;
             const uint32_t f = ub * (uint32_t)K + (yb - 1u);
             atomicAdd(&bins[f >> 1], 1u << (16u * (f & 1u)));
         });
@@ -711,17 +715,17 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
                 const uint2 w = reinterpret_cast<const uint2 *>(bins)[f / 4];
                 return u32x4{w.x & 0xffffu, w.x >> 16, w.y & 0xffffu, w.y >> 16};
             },
-            [&](uint32_t f) { return (bins[f >> 1] >> (16u * (f & 1u))) & 0xffffu; }, inv_only);
+            [&](uint32_t f) { return (bins[f >> 1] >> (16u * (f & 1u))) & 0xffffu; });
         return;
     }
     for (int h = 0; h < 2 && h * (kPbRows / 2) < nr; ++h) {
         if (h == 1) zero();
-        count([&](uint32_t ub, uint32_t yb, float) {
-            if ((ub >> 7) == (uint32_t)h) atomicAdd(&bins[(ub & 127u) * (uint32_t)K + (yb - 1u)], 1u);
+        count([&](uint32_t ub, uint32_t yb, float, bool ok) {
+            if (ok && (ub >> 7) == (uint32_t)h) atomicAdd(&bins[(ub & 127u) * (uint32_t)K + (yb - 1u)], 1u);
         });
         __syncthreads();
         const int lo = h * (kPbRows / 2), hi = nr < lo + kPbRows / 2 ? nr : lo + kPbRows / 2;
-        write(lo, hi, get4_32, get1_32, inv_only);
+        write(lo, hi, get4_32, get1_32);
     }
 }
 
@@ -807,26 +811,12 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
         hipLaunchKernelGGL(k_pb_rbflag, dim3(grid_cap(L.n_rb, 1)), b, 0, s, n, L.n_rb, row_ptr, val, rb_flag);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (laplacian) {
-            // the graph's degrees and d^-1/2, then every entry's term w d_v^-1/2
+            // the graph's degrees and d^-1/2 (the terms follow once every entry has its row)
             if ((e = launch_degrees_csr(n, row_ptr, val, nnz, deg, true, err, s)) != hipSuccess) return e;
             if ((e = launch_rsd(deg, n, rsd, s)) != hipSuccess) return e;
-            if (nnz > 0) {
-                hipLaunchKernelGGL(k_pb_lapw, dim3(grid_cap(nnz, kT * 4)), b, 0, s, nnz, n, col, val, hot_ids, n_hot,
-                                   rsd, v0);
-                if ((e = hipGetLastError()) != hipSuccess) return e;
-            }
         } else if (nnz > 0 && (e = hipMemcpyAsync(v0, val, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess) {
             return e;
         }
-        hipLaunchKernelGGL(k_pb_grid_init, dim3(1), dim3(kWave), 0, s, ex);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (nnz > 0) {
-            hipLaunchKernelGGL(k_pb_grid_bits, dim3(grid_cap(nnz, kT * 16)), b, 0, s, nnz, v0, ex);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        hipLaunchKernelGGL(k_pb_grid_final, dim3(1), dim3(kWave), 0, s, ex, meta);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        sval = v0;
     }
     if (n_lds > 0 && (e = hipMemcpyAsync(lds_ids, hot_ids, (size_t)n_lds * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess)
         return e;
@@ -841,6 +831,22 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
         hipLaunchKernelGGL(k_pb_key, dim3(grid_cap(nnz, kT * 4)), b, 0, s, nnz, n, col, hot_ids, n_hot, n_lds, L.n_vcb,
                            k0, err);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (laplacian) {
+            // every entry's term w d_u^-1/2 d_v^-1/2 (its row u in the key's low half)
+            hipLaunchKernelGGL(k_pb_lapw, dim3(grid_cap(nnz, kT * 4)), b, 0, s, nnz, n, col, val, hot_ids, n_hot, k0,
+                               rsd, v0);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        if (carried) {
+            // the weights' grid (meta[4]), from the values the layout will hold
+            hipLaunchKernelGGL(k_pb_grid_init, dim3(1), dim3(kWave), 0, s, ex);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_pb_grid_bits, dim3(grid_cap(nnz, kT * 16)), b, 0, s, nnz, v0, ex);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_pb_grid_final, dim3(1), dim3(kWave), 0, s, ex, meta);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            sval = v0;
+        }
         // stable sort on the column-block bits (the entries are in row order already)
         uint64_t *sorted = k0;
         if (L.n_cb > 1) {
@@ -866,6 +872,12 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
     } else {
         if ((e = launch_fill_i64(celllast, L.cells, 0, s)) != hipSuccess) return e;
         if (tier && (e = launch_fill_i64(tier, 2, 0, s)) != hipSuccess) return e;
+        if (carried) { // no weights: any grid holds them
+            hipLaunchKernelGGL(k_pb_grid_init, dim3(1), dim3(kWave), 0, s, ex);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_pb_grid_final, dim3(1), dim3(kWave), 0, s, ex, meta);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     if ((e = max_scan_i64(celllast, L.cells, cellend, part, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_pb_table, dim3(grid_cap(L.cells, kT * 4)), b, 0, s, L.n_rb, L.n_cb, L.n_vcb, tier, cellend,
@@ -937,14 +949,17 @@ hipError_t launch_pb_rows(int64_t n, int64_t nnz, int32_t K, const PbLayout &L, 
     const uint64_t magic = ((1ull << 32) + (uint64_t)K - 1) / (uint64_t)K;
     int top = 1;
     while (top * 2 <= L.n_cb - 1) top *= 2;
+    // quad stride of the fixed-class write: the largest multiple of K / gcd(K, 4) up to kRowsT
+    const int kq = K / (K % 4 == 0 ? 4 : (K % 2 == 0 ? 2 : 1));
+    const int strideq = kq <= kRowsT ? (kRowsT / kq) * kq : 0;
     const uint32_t *ul4 = reinterpret_cast<const uint32_t *>(ul);
     const uint32_t *yv4 = reinterpret_cast<const uint32_t *>(yv);
     const f32x4 *vl4 = reinterpret_cast<const f32x4 *>(vl);
     const bool vec = (reinterpret_cast<uintptr_t>(Z) & 15) == 0;
 #define GEE_ROWS(V, H, W)                                                                                            \
     hipLaunchKernelGGL((k_pb_rows<V, H, W>), dim3((unsigned)L.n_rb), dim3(kRowsT), lds, s, n, nnz, n_lds, meta, lim, \
-                       K, magic, L.n_cb, top, cell_start, cell_count, cell_word, ul4, yv4, vl4, rb_flag, rsd, inv, Z,  \
-                       err)
+                       K, magic, L.n_cb, top, strideq, cell_start, cell_count, cell_word, ul4, yv4, vl4, rb_flag, rsd,  \
+                       inv, Z, err)
     if (vl) {
         if (half) {
             if (vec) GEE_ROWS(true, true, true);

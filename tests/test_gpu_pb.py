@@ -360,8 +360,8 @@ def test_weighted_layout_off_grid():
 @pytest.mark.parametrize("weighted", [False, True])
 @pytest.mark.parametrize("K", [7, 100])
 def test_laplacian_layout_matches_oracle(weighted, K):
-    """Laplacian layout: the degrees and each entry's w d_v^-1/2 taken at the build, the row's
-    d_u^-1/2 applied when it is written. Unit and grid weights, a hub row (FP64 blocks),
+    """Laplacian layout: the degrees and each entry's w d_u^-1/2 d_v^-1/2 taken at the build,
+    summed as a weighted layout's terms. Unit and grid weights, a hub row (FP64 blocks),
     isolated vertices (zero rows), with and without the tier; within the bar of the oracle
     and of the CSR pull form, d^-1/2 as the CSR's degrees give it."""
     rng = np.random.default_rng(K + 10 * weighted)
