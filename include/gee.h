@@ -221,8 +221,10 @@ int gee_embed_noalloc(const gee_coo *g, const gee_csr *csr, const int32_t *label
  * lie in [256 rb, 256 rb + 256); cell_start[rb * n_cb + cb] is its first index in
  * the layout and cell_count[...] its length. The tier's entries start at H0, the
  * first multiple of 16 at or after the end of the vertex blocks (the gap before it
- * belongs to no cell); tier entry i keeps its slot in bytes 4 H0 + 3 (i - H0) ..
- * + 2 of col, little-endian. n_rb = ceil(n / 256),
+ * belongs to no cell); with NT tier entries padded to NTp, a multiple of 64, tier entry
+ * i keeps the low 16 bits of its slot in bytes 4 H0 + 2 (i - H0) .. + 1 of col
+ * (little-endian) and its 17th bit as bit (i - H0) mod 8 of byte 4 H0 + 2 NTp +
+ * (i - H0) / 8 (8-byte aligned). n_rb = ceil(n / 256),
  * n_cb = ceil(n / 2^21) + ceil(n_lds / 2^17). The layout holds at most 2^32 - 65
  * entries (GEE_EOVERFLOW beyond).
  * ------------------------------------------------------------------------------ */
@@ -233,8 +235,8 @@ typedef struct gee_pb {
     int64_t n, nnz;            /* vertices, entries (as in the CSR) */
     int64_t n_rb;              /* row blocks */
     int32_t n_cb;              /* column blocks: vertex blocks, then tier slices */
-    const int32_t *col;        /* [nnz + 16] layout order, 16-byte aligned: the column of each vertex-block entry;
-                                  each tier entry's slot within its slice in 3 bytes from byte 4 H0 on */
+    const int32_t *col;        /* [nnz + 64] layout order, 16-byte aligned: the column of each vertex-block entry;
+                                  each tier entry's slot within its slice (17 bits) from byte 4 H0 on */
     const uint8_t *ul;         /* [nnz + 32 rounded up to 16] row within its 256-row block; 16-byte aligned */
     const int64_t *cell_start; /* [n_rb * n_cb] */
     const uint32_t *cell_count; /* [n_rb * n_cb] */
@@ -272,7 +274,7 @@ size_t gee_pb_build_workspace(const gee_csr *csr, int64_t n_lds, int laplacian);
 /* Builds the layout of csr with the first n_lds hot slots (0 <= n_lds <=
  * min(n_hot, GEE_PB_MAX_TIER)) in the tier, for the adjacency version (laplacian = 0)
  * or the Laplacian version; other hot-slot columns are decoded through hot_ids. Outputs
- * are caller device buffers: col [nnz + 16] (16-byte aligned), ul [nnz + 32 rounded up
+ * are caller device buffers: col [nnz + 64] (16-byte aligned), ul [nnz + 32 rounded up
  * to 16] (16-byte aligned), cell_start, cell_count and cell_word [gee_pb_cells(n,
  * n_lds)], lds_ids [n_lds] (may be NULL when n_lds = 0), meta [8]; for a weighted CSR
  * (csr->val != NULL) or a Laplacian layout also val [nnz + 32 rounded up to 16]

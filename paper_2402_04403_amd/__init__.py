@@ -387,7 +387,7 @@ class DevicePb:
     layout order for a weighted CSR."""
 
     n: int
-    col: torch.Tensor         # [nnz + 16] int32; tier slots packed in 3 bytes from byte 4 H0
+    col: torch.Tensor         # [nnz + 64] int32; tier slots (17 bits) packed from byte 4 H0
     ul: torch.Tensor          # [nnz + 32 rounded up to 16]
     cell_start: torch.Tensor
     cell_count: torch.Tensor
@@ -447,7 +447,7 @@ def pb_build(csr: DeviceCsr, tier_slots: int | None = None, laplacian: bool = Fa
     wsb = int(lib.gee_pb_build_workspace(ctypes.byref(rs), n_lds, 1 if laplacian else 0))
     if wsb == 0 or cells == 0:
         raise GeeError(GEE_EINVAL, "gee_pb_build_workspace")
-    col = torch.empty(csr.nnz + 16, dtype=torch.int32, device=dev)
+    col = torch.empty(csr.nnz + 64, dtype=torch.int32, device=dev)
     ul = torch.empty((csr.nnz + 32 + 15) // 16 * 16, dtype=torch.uint8, device=dev)
     cell_start = torch.empty(cells, dtype=torch.int64, device=dev)
     cell_count = torch.empty(cells, dtype=torch.int32, device=dev)

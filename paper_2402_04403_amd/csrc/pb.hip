@@ -14,7 +14,8 @@
 //     and keep their slot within the slice instead of the vertex. A cell is the run of
 //     one column block's entries that belong to one block of 256 rows. Stored: the
 //     column of every vertex-block entry (32 bits), the slot of every tier entry (17
-//     bits in 3 bytes), its row within the 256-row block (8 bits), and for each (row
+//     bits: 16 in place, the 17th in a bit array), its row within the 256-row block (8
+//     bits), and for each (row
 //     block, column block) the cell's start and length. The tier entries start at H0,
 //     the first multiple of 16 at or after the last vertex-block entry; the gap of
 //     fewer than 16 entries before it belongs to no cell (its columns are 0).
@@ -119,7 +120,8 @@ __global__ void k_pb_tier_start(const uint64_t *__restrict__ keys, int64_t nnz, 
 
 // Layout arrays from the sorted keys. Sorted index i goes to o = i before h0 and to
 // i + (H0 - h0) from h0 on. A vertex-block entry stores its column in colc[o]; a tier
-// entry stores its slot within the slice in 3 bytes at colb[4 H0 + 3 (o - H0)]. ul[o]
+// entry stores the low 16 bits of its slot within the slice at colb[4 H0 + 2 (o - H0)]
+// (16-bit, little-endian; the 17th bit is written by k_pb_tier_hi). ul[o]
 // is the row within its block; celllast[cell] = o + 1 for a cell's last entry. The gap
 // [h0, H0) gets column 0 and row 0. tier = {h0, H0} (null: no tier, h0 = H0 = nnz).
 __global__ void __launch_bounds__(kT)
@@ -137,11 +139,8 @@ k_pb_finalize(const uint64_t *__restrict__ keys, const float *__restrict__ sval,
         if (i < h0) {
             colc[o] = (int32_t)c;
         } else {
-            const uint32_t slot = (uint32_t)(c & (kPbSlice - 1));
-            uint8_t *q = colb + 4 * H0 + 3 * (o - H0);
-            q[0] = (uint8_t)slot;
-            q[1] = (uint8_t)(slot >> 8);
-            q[2] = (uint8_t)(slot >> 16);
+            // the slot's low 16 bits (its 17th bit goes to the tier's bit array, k_pb_tier_hi)
+            reinterpret_cast<uint16_t *>(colb + 4 * H0)[o - H0] = (uint16_t)c;
         }
         ul[o] = (uint8_t)(k & (kPbRows - 1));
         const int64_t cell = pb_cell(k, n_rb);
@@ -151,6 +150,27 @@ k_pb_finalize(const uint64_t *__restrict__ keys, const float *__restrict__ sval,
         colc[i] = 0;
         ul[i] = 0;
         if (vl) vl[i] = 0.0f;
+    }
+}
+
+// The tier's bit array: bit r of it is the 17th bit of tier entry H0 + r's slot. The
+// tier's NT = nnz - h0 entries are padded to NTp, a multiple of 64; their low halves take
+// bytes [4 H0, 4 H0 + 2 NTp) of col and the bit array follows (8-byte aligned), NTp / 64
+// words of 64 bits (padding bits 0). One entry per lane, one word per wavefront (ballot).
+__global__ void __launch_bounds__(kT)
+k_pb_tier_hi(const uint64_t *__restrict__ keys, int64_t nnz, const int64_t *__restrict__ tier, uint8_t *colb)
+{
+    const int64_t h0 = tier[0], H0 = tier[1];
+    const int64_t NT = nnz - h0, NTp = (NT + 63) & ~(int64_t)63;
+    uint64_t *bits = reinterpret_cast<uint64_t *>(colb + 4 * H0 + 2 * NTp);
+    const int lane = threadIdx.x % kWave;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t ws = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t q = w0; q < NTp / 64; q += ws) { // uniform per wavefront
+        const int64_t r = 64 * q + lane;
+        const bool bit = r < NT && ((keys[h0 + (r < NT ? r : 0)] >> (32 + 16)) & 1u) != 0;
+        const uint64_t m = __ballot(bit);
+        if (lane == 0) bits[q] = m;
     }
 }
 
@@ -385,11 +405,12 @@ k_pb_tier_labels(int64_t n_lds, int64_t n, int64_t nnz, int kind, const int64_t 
     if (bad) flag_error(err, GEE_EVERTEX);
 }
 
-// The slot of tier entry i: 3 bytes at colb[4 H0 + 3 (i - H0)].
-__device__ inline uint32_t tier_slot(const uint8_t *colb, int64_t H0, int64_t i)
+// The slot of tier entry i: its low 16 bits at colb[4 H0 + 2 (i - H0)], its 17th bit in
+// the bit array at colb[hb] (bit i - H0).
+__device__ inline uint32_t tier_slot(const uint8_t *colb, int64_t H0, const uint8_t *hb, int64_t i)
 {
-    const uint8_t *q = colb + 4 * H0 + 3 * (i - H0);
-    return (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16);
+    const int64_t r = i - H0;
+    return (uint32_t)reinterpret_cast<const uint16_t *>(colb + 4 * H0)[r] | ((uint32_t)((hb[r >> 3] >> (r & 7)) & 1u) << 16);
 }
 
 // yv[i] = (labels of slice j)[slot of i] over the tier entries [H0, E), where slice j's
@@ -397,8 +418,8 @@ __device__ inline uint32_t tier_slot(const uint8_t *colb, int64_t H0, int64_t i)
 // and E = cell_start + cell_count of the last cell. The range is cut into one chunk per
 // workgroup (16-aligned); for every slice its chunk meets, the workgroup copies that
 // slice's labels (at most kPbSlice bytes) into an LDS table of kPbSlice bytes and reads
-// them there. Sixteen entries' slots are three 16-byte loads. Slots are masked to the
-// table, so no LDS read leaves it.
+// them there. Sixteen entries' slots are two 16-byte loads and one 2-byte load. Slots are
+// masked to the table, so no LDS read leaves it.
 __global__ void __launch_bounds__(kLdsT)
 k_pb_gather_tier(int64_t nnz, int64_t n, int kind, const int64_t *__restrict__ meta, int32_t n_sl, int64_t n_lds,
                  const int64_t *__restrict__ sl_start, const int64_t *__restrict__ last_start,
@@ -414,6 +435,9 @@ k_pb_gather_tier(int64_t nnz, int64_t n, int kind, const int64_t *__restrict__ m
     if (t <= n_sl) bnd[t] = t < n_sl ? clamp_index(sl_start[t], E) : E;
     __syncthreads();
     const int64_t H0 = bnd[0] & ~(int64_t)15; // a multiple of 16 by construction
+    // the bit array after the low halves of the tier's E - H0 entries, padded to 64 (every
+    // read stays below 4 (nnz + 16) + 200 bytes, inside col's nnz + 64 words)
+    const uint8_t *hb = colb + 4 * H0 + 2 * ((E - H0 + 63) & ~(int64_t)63);
     const int64_t per = ((E - H0 + gridDim.x - 1) / gridDim.x + 15) & ~(int64_t)15;
     int64_t lo = H0 + (int64_t)blockIdx.x * per;
     const int64_t hi = lo + per < E ? lo + per : E;
@@ -430,41 +454,44 @@ k_pb_gather_tier(int64_t nnz, int64_t n, int kind, const int64_t *__restrict__ m
         for (int i = t; i < (int)((nj + 15) / 16); i += kLdsT) reinterpret_cast<uint4 *>(stab)[i] = src[i];
         __syncthreads();
         const int64_t v0 = (a + 15) / 16, v1 = b / 16;
-        // entries 16 v .. 16 v + 15: 48 bytes at 4 H0 + 3 (16 v - H0), 16-byte aligned. The
-        // slots of a lane's next 16 entries are loaded before its current ones are looked
-        // up, so two loads per lane are in flight while the LDS reads run.
-        auto slots = [&](int64_t v, uint4 (&q)[3]) {
-            const uint4 *cp = reinterpret_cast<const uint4 *>(colb + 4 * H0 + 48 * (v - H0 / 16));
+        // entries 16 v .. 16 v + 15: their low halves, 32 bytes at 4 H0 + 2 (16 v - H0)
+        // (16-byte aligned), and their 17th bits, 2 bytes at hb + 2 (v - H0 / 16). The slots
+        // of a lane's next 16 entries are loaded before its current ones are looked up, so
+        // two loads per lane are in flight while the LDS reads run.
+        auto slots = [&](int64_t v, uint4 (&q)[2], uint32_t &h) {
+            const int64_t g = v - H0 / 16;
+            const uint4 *cp = reinterpret_cast<const uint4 *>(colb + 4 * H0) + 2 * g;
             q[0] = cp[0];
             q[1] = cp[1];
-            q[2] = cp[2];
+            h = reinterpret_cast<const uint16_t *>(hb)[g];
         };
         int64_t v = v0 + t;
-        uint4 cur[3] = {};
-        if (v < v1) slots(v, cur);
+        uint4 cur[2] = {};
+        uint32_t ch = 0u;
+        if (v < v1) slots(v, cur, ch);
         while (v < v1) {
             const int64_t vn = v + kLdsT;
-            uint4 nxt[3] = {};
-            if (vn < v1) slots(vn, nxt);
-            const uint32_t x[12] = {cur[0].x, cur[0].y, cur[0].z, cur[0].w, cur[1].x, cur[1].y,
-                                    cur[1].z, cur[1].w, cur[2].x, cur[2].y, cur[2].z, cur[2].w};
+            uint4 nxt[2] = {};
+            uint32_t nh = 0u;
+            if (vn < v1) slots(vn, nxt, nh);
+            const uint32_t x[8] = {cur[0].x, cur[0].y, cur[0].z, cur[0].w, cur[1].x, cur[1].y, cur[1].z, cur[1].w};
             uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const int bit = 24 * e, wd = bit / 32, sh = bit % 32;
-                const uint32_t slot = sh <= 8 ? (x[wd] >> sh) : ((x[wd] >> sh) | (x[wd + 1] << (32 - sh)));
+                const uint32_t slot = ((x[e / 2] >> (16 * (e % 2))) & 0xffffu) | (((ch >> e) & 1u) << 16);
                 w[e / 4] |= (uint32_t)stab[slot & mask] << (8 * (e % 4));
             }
             *reinterpret_cast<uint4 *>(yv + v * 16) = make_uint4(w[0], w[1], w[2], w[3]);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) cur[i] = nxt[i];
+            for (int i = 0; i < 2; ++i) cur[i] = nxt[i];
+            ch = nh;
             v = vn;
         }
         // entries outside the 16-aligned run: the head [a, 16 v0) and the tail [16 v1, b)
         const int64_t head_end = v0 * 16 < b ? v0 * 16 : b;
-        for (int64_t i = a + t; i < head_end; i += kLdsT) yv[i] = stab[tier_slot(colb, H0, i) & mask];
+        for (int64_t i = a + t; i < head_end; i += kLdsT) yv[i] = stab[tier_slot(colb, H0, hb, i) & mask];
         const int64_t tail_begin = v1 * 16 > head_end ? v1 * 16 : head_end;
-        for (int64_t i = tail_begin + t; i < b; i += kLdsT) yv[i] = stab[tier_slot(colb, H0, i) & mask];
+        for (int64_t i = tail_begin + t; i < b; i += kLdsT) yv[i] = stab[tier_slot(colb, H0, hb, i) & mask];
     }
 }
 
@@ -869,6 +896,11 @@ hipError_t launch_pb_build(int64_t n, int64_t nnz, const int64_t *row_ptr, const
         hipLaunchKernelGGL(k_pb_finalize, dim3(grid_cap(nnz, kT * 4)), b, 0, s, sorted, sval, nnz, L.n_rb, L.n_vcb,
                            tier, colc, reinterpret_cast<uint8_t *>(colc), ul, vl, celllast);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (tier) {
+            hipLaunchKernelGGL(k_pb_tier_hi, dim3(grid_cap(nnz + 64, kT)), b, 0, s, sorted, nnz, tier,
+                               reinterpret_cast<uint8_t *>(colc));
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     } else {
         if ((e = launch_fill_i64(celllast, L.cells, 0, s)) != hipSuccess) return e;
         if (tier && (e = launch_fill_i64(tier, 2, 0, s)) != hipSuccess) return e;

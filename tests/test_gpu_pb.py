@@ -58,13 +58,17 @@ def _check_layout(csr, pb):
     vcol = pcol[idx].copy()
     tier = cb_of >= n_vcb
     assert np.all(vcol[~tier] >> 21 == cb_of[~tier])
-    if tier.any():  # tier slots: 3 bytes each from byte 4 H0, H0 the first tier index (a multiple of 16)
+    if tier.any():  # tier slots: low 16 bits from byte 4 H0, then the 17th bits (H0 a multiple of 16)
         ti = idx[tier]
         H0 = int(ti.min())
         assert H0 % 16 == 0 and int(idx[~tier].max(initial=-1)) < H0
-        off = 4 * H0 + 3 * (ti - H0)
+        r = ti - H0
+        NT = int(tier.sum())
+        assert int(r.max()) == NT - 1  # the tier's entries are contiguous from H0
+        off = 4 * H0 + 2 * r
+        hb = 4 * H0 + 2 * ((NT + 63) // 64 * 64)
         vcol[tier] = (colbytes[off].astype(np.int64) | (colbytes[off + 1].astype(np.int64) << 8)
-                      | (colbytes[off + 2].astype(np.int64) << 16))
+                      | (((colbytes[hb + r // 8] >> (r % 8)) & 1).astype(np.int64) << 16))
     slots = vcol[tier] + ((cb_of[tier] - n_vcb) << 17)  # slot within the slice -> tier slot
     assert np.all((vcol[tier] >= 0) & (vcol[tier] < (1 << 17)) & (slots < max(pb.n_lds, 1)))
     if pb.n_lds:
