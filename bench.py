@@ -84,7 +84,7 @@ def parse():
     p.add_argument("--no-tune", dest="tune", action="store_false",
                    help="batched workload: keep the default segment length instead of the autotuner's choice")
     p.add_argument("--rows-per-window", type=int, default=0)
-    p.add_argument("--hot-budget", type=int, default=-1, help="hot-vertex slots of the CSR (-1: library default)")
+    p.add_argument("--hot-budget", type=int, default=-1, help="hot-vertex slots of the CSR (-1: PB_HOT_BUDGET for the propagation-blocked form, else DEFAULT_HOT_BUDGET)")
     p.add_argument("--push-steps", type=int, default=3, help="timed steps of each other form, reported beside")
     p.add_argument("--cpu-records", type=int, default=400_000_000,
                    help="records of the one-thread oracle's timed prefix (the all-threads run takes every record)")
@@ -193,7 +193,10 @@ def main():
     # per-graph preprocessing: canonical symmetric CSR
     e0, e1 = gee.HipEvent(), gee.HipEvent()
     e0.record()
-    hot_budget = gee.DEFAULT_HOT_BUDGET if a.hot_budget < 0 else a.hot_budget
+    if a.hot_budget >= 0:
+        hot_budget = a.hot_budget
+    else:
+        hot_budget = gee.PB_HOT_BUDGET if a.form == "pb" else gee.DEFAULT_HOT_BUDGET
     csr = gee.csr_build(coo, hot_budget=hot_budget, check=False)
     e1.record()
     e1.synchronize()

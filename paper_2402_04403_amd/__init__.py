@@ -37,6 +37,10 @@ GEE_OK, GEE_EINVAL, GEE_ELABEL, GEE_EVERTEX, GEE_ENEGW, GEE_EOVERFLOW, GEE_EWORK
 # label records in degree-rank order, so the hottest labels share the lines that stay
 # in one XCD's 4 MiB L2 beside the streaming traffic.
 DEFAULT_HOT_BUDGET = 1 << 22
+# Hot slots for a graph embedded through its propagation-blocked layout: as many as the
+# layout's LDS tier takes (GEE_PB_MAX_TIER), so the entries of the 2^23 highest-degree
+# vertices read their labels from LDS.
+PB_HOT_BUDGET = 1 << 23
 
 
 class GeeError(RuntimeError):

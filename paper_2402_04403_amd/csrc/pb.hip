@@ -527,17 +527,15 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
           float *__restrict__ Z, int32_t *err)
 {
     // LDS: bins [nb] uint32 (nb = 256 K, or 128 K for HALF, rounded up to 4), invx
-    // [K + 3] double (invx[i] = 1/n_(i mod K) + 1), per cell: first word [n_cb] int64,
-    // word prefix [n_cb + 1], entry count [n_cb], byte offset of the start in its word
-    // [n_cb].
+    // [K + 3] double (invx[i] = 1/n_(i mod K) + 1), per cell: first entry [n_cb] (its
+    // word and its byte offset in that word), word prefix [n_cb + 1], entry count [n_cb].
     extern __shared__ __align__(16) uint32_t bins[];
     if (!layout_matches(meta, n, nnz, n_lds, rsd ? 2 : (WT ? 1 : 0), err)) return;
     const uint32_t nb = (uint32_t)align_up((size_t)(HALF ? kPbRows / 2 : kPbRows) * K, 4);
     double *invx = reinterpret_cast<double *>(bins + nb);
-    int64_t *cw0 = reinterpret_cast<int64_t *>(invx + K + 3);
-    uint32_t *pre = reinterpret_cast<uint32_t *>(cw0 + n_cb);
+    uint32_t *ca = reinterpret_cast<uint32_t *>(invx + K + 3);
+    uint32_t *pre = ca + n_cb;
     uint32_t *cm = pre + n_cb + 1;
-    uint32_t *coff = cm + n_cb;
     // Workgroups are dealt to the 8 XCDs in turn (i -> XCD i mod 8). Neighbouring row
     // blocks' cells share cache lines (a vertex block's cells are small and adjacent),
     // so each XCD takes one contiguous run of row blocks and the lines are fetched into
@@ -562,9 +560,8 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
             a = 0;
             m = 0u;
         }
-        cw0[c] = a >> 2;
+        ca[c] = (uint32_t)a; // below 2^32: the layout holds fewer than 2^32 entries
         cm[c] = m;
-        coff[c] = (uint32_t)(a & 3);
         pre[c] = p;
         if (c == n_cb - 1) pre[n_cb] = p + (m != 0u ? ((uint32_t)(a & 3) + m + 3u) >> 2 : 0u);
     }
@@ -609,12 +606,13 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
                     // the word prefix comes with the layout: a word index it would carry past
                     // the layout's words (an inconsistent prefix) is clamped into them, and
                     // the entries it then reads lie outside the cell's count, so none is added
-                    int64_t w = cw0[c] + k;
+                    const uint32_t a = ca[c];
+                    int64_t w = (int64_t)(a >> 2) + k;
                     w = w < wlim ? w : wlim;
                     u[j] = ul4[w];
                     y[j] = yv4[w];
                     if (WT) wq[j] = vl4[w];
-                    rel[j] = 4u * k - coff[c]; // entry index within the cell of the word's byte 0 (mod 2^32)
+                    rel[j] = 4u * k - (a & 3u); // entry index within the cell of the word's byte 0 (mod 2^32)
                     m[j] = cm[c];
                 }
             }
@@ -962,13 +960,18 @@ hipError_t launch_pb_slice_entries(int64_t n_slots, const int32_t *hot_ids, cons
 
 size_t pb_rows_lds_bytes(int32_t K, int32_t n_cb, bool half)
 {
-    return align_up((size_t)(half ? kPbRows / 2 : kPbRows) * K, 4) * 4 + (size_t)(K + 3) * 8 + (size_t)n_cb * 8 +
-           (size_t)(n_cb + 1) * 4 + (size_t)n_cb * 8;
+    return align_up((size_t)(half ? kPbRows / 2 : kPbRows) * K, 4) * 4 + (size_t)(K + 3) * 8 +
+           (size_t)(3 * n_cb + 1) * 4;
 }
 
-// 16-bit (HALF) bins when 32-bit bins would leave fewer than three workgroups per CU
-// (160 KB of LDS), as they do from about 52 classes up.
-bool pb_rows_half(int32_t K, int32_t n_cb) { return 3 * pb_rows_lds_bytes(K, n_cb, false) > 160 * 1024; }
+// LDS that three 512-thread workgroups of the rows pass can share on one CU: measured,
+// three of 53,548 bytes run together and three of 53,948 bytes do not (less than the
+// 160 KB the device reports), so a bound between the two.
+constexpr size_t kRowsCuLds = 161280;
+
+// 16-bit (HALF) bins when 32-bit bins would leave fewer than three workgroups per CU,
+// as they do from about 51 classes up.
+bool pb_rows_half(int32_t K, int32_t n_cb) { return 3 * pb_rows_lds_bytes(K, n_cb, false) > kRowsCuLds; }
 
 hipError_t launch_pb_rows(int64_t n, int64_t nnz, int32_t K, const PbLayout &L, const int64_t *cell_start,
                           const uint32_t *cell_count, const uint32_t *cell_word, const uint8_t *ul, const uint8_t *yv,

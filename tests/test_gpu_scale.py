@@ -114,7 +114,7 @@ def test_rmat_paper_scale_sampled_rows():
     announce(f"  generated s={g.s} {time.time() - t0:.1f}s")
     coo = gee.to_device(g.n, g.src, g.dst, device=DEV)
     labels = torch.as_tensor(wl.labels).to(DEV)
-    csr = gee.csr_build(coo, hot_budget=gee.DEFAULT_HOT_BUDGET)  # the configuration the benchmark times
+    csr = gee.csr_build(coo, hot_budget=gee.PB_HOT_BUDGET)  # the configuration the benchmark times
     torch.cuda.synchronize()
     announce(f"  csr built nnz={csr.nnz} {time.time() - t0:.1f}s")
     assert csr.nnz == 2 * g.s
