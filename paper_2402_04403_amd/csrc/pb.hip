@@ -517,8 +517,8 @@ k_pb_gather_tier(int64_t nnz, int64_t n, int kind, const int64_t *__restrict__ m
 // else in FP32; a flagged block sums in FP64. The bins' LDS holds R rows of either (R = 256 or 128 for FP32,
 // half that for FP64), and the block's rows are taken R at a time, one pass over its
 // words each.
-template <bool VEC, bool HALF, bool WT>
-__global__ void __launch_bounds__(kRowsT)
+template <bool VEC, bool HALF, bool WT, int NT>
+__global__ void __launch_bounds__(NT)
 k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ meta, int64_t lim, int32_t K,
           uint64_t magicK, int32_t n_cb, int32_t top, int32_t strideq, const int64_t *__restrict__ cell_start,
           const uint32_t *__restrict__ cell_count, const uint32_t *__restrict__ cell_word,
@@ -547,9 +547,9 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
     const int nr = (int)((n - r0) < kPbRows ? (n - r0) : kPbRows);
     const int t = threadIdx.x, lane = t % kWave;
     const int wave = __builtin_amdgcn_readfirstlane(t / kWave);
-    for (uint32_t i = t; i < nb / 4; i += kRowsT) reinterpret_cast<u32x4 *>(bins)[i] = u32x4{0u, 0u, 0u, 0u};
-    for (int i = t; i < K + 3; i += kRowsT) invx[i] = inv[1 + i % K];
-    for (int c = t; c < n_cb; c += kRowsT) {
+    for (uint32_t i = t; i < nb / 4; i += NT) reinterpret_cast<u32x4 *>(bins)[i] = u32x4{0u, 0u, 0u, 0u};
+    for (int i = t; i < K + 3; i += NT) invx[i] = inv[1 + i % K];
+    for (int c = t; c < n_cb; c += NT) {
         int64_t a = cell_start[rb * n_cb + c];
         uint32_t m = cell_count[rb * n_cb + c];
         const uint32_t p = cell_word[rb * n_cb + c];
@@ -572,7 +572,7 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
     // every entry (ub, yb) of the block's cells with a known class, to add(ub, yb, weight)
     // (the weight is 1 for a unit-weight layout)
     auto count = [&](auto add) __attribute__((always_inline)) {
-        for (uint32_t f0 = (uint32_t)(wave * kWave + lane); f0 < T; f0 += kRowsU * kRowsT) {
+        for (uint32_t f0 = (uint32_t)(wave * kWave + lane); f0 < T; f0 += kRowsU * NT) {
             uint32_t u[kRowsU], y[kRowsU], rel[kRowsU], m[kRowsU];
             f32x4 wq[kRowsU];
             // the cells of the kRowsU words, by binary searches run in step: each step reads
@@ -590,11 +590,11 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
                 }
 #pragma unroll
                 for (int j = 0; j < kRowsU; ++j)
-                    cs[j] = p[j] <= f0 + (uint32_t)j * kRowsT ? cs[j] + st : cs[j];
+                    cs[j] = p[j] <= f0 + (uint32_t)j * NT ? cs[j] + st : cs[j];
             }
 #pragma unroll
             for (int j = 0; j < kRowsU; ++j) {
-                const uint32_t f = f0 + (uint32_t)j * kRowsT;
+                const uint32_t f = f0 + (uint32_t)j * NT;
                 u[j] = 0u;
                 y[j] = 0u;
                 rel[j] = 0u;
@@ -618,7 +618,7 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
             }
 #pragma unroll
             for (int j = 0; j < kRowsU; ++j) {
-                if (f0 + (uint32_t)j * kRowsT < T) {
+                if (f0 + (uint32_t)j * NT < T) {
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
                         const uint32_t yb = (y[j] >> (8 * b)) & 0xffu;
@@ -653,14 +653,14 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
             }
             done = nv * 4;
         }
-        for (uint32_t f = done + t; f < total; f += kRowsT) {
+        for (uint32_t f = done + t; f < total; f += NT) {
             const uint32_t k = f - div_small(f, magicK) * (uint32_t)K;
             __builtin_nontemporal_store((float)((double)get1(f) * invx[k]), zb + f);
         }
     };
     auto zero = [&]() __attribute__((always_inline)) {
         __syncthreads(); // the previous rows are written
-        for (uint32_t i = t; i < nb / 4; i += kRowsT) reinterpret_cast<u32x4 *>(bins)[i] = u32x4{0u, 0u, 0u, 0u};
+        for (uint32_t i = t; i < nb / 4; i += NT) reinterpret_cast<u32x4 *>(bins)[i] = u32x4{0u, 0u, 0u, 0u};
         __syncthreads();
     };
     if constexpr (WT) {
@@ -984,17 +984,26 @@ hipError_t launch_pb_rows(int64_t n, int64_t nnz, int32_t K, const PbLayout &L, 
     const uint64_t magic = ((1ull << 32) + (uint64_t)K - 1) / (uint64_t)K;
     int top = 1;
     while (top * 2 <= L.n_cb - 1) top *= 2;
-    // quad stride of the fixed-class write: the largest multiple of K / gcd(K, 4) up to kRowsT
+    // 1024-thread workgroups when fewer than three of 512 fit in a CU's LDS (two then
+    // still do, with twice the wavefronts per row block)
+    const bool wide_wg = 3 * lds > kRowsCuLds;
+    const int nt = wide_wg ? 2 * kRowsT : kRowsT;
+    // quad stride of the fixed-class write: the largest multiple of K / gcd(K, 4) up to nt
     const int kq = K / (K % 4 == 0 ? 4 : (K % 2 == 0 ? 2 : 1));
-    const int strideq = kq <= kRowsT ? (kRowsT / kq) * kq : 0;
+    const int strideq = kq <= nt ? (nt / kq) * kq : 0;
     const uint32_t *ul4 = reinterpret_cast<const uint32_t *>(ul);
     const uint32_t *yv4 = reinterpret_cast<const uint32_t *>(yv);
     const f32x4 *vl4 = reinterpret_cast<const f32x4 *>(vl);
     const bool vec = (reinterpret_cast<uintptr_t>(Z) & 15) == 0;
-#define GEE_ROWS(V, H, W)                                                                                            \
-    hipLaunchKernelGGL((k_pb_rows<V, H, W>), dim3((unsigned)L.n_rb), dim3(kRowsT), lds, s, n, nnz, n_lds, meta, lim, \
+#define GEE_ROWS_NT(V, H, W, N)                                                                                      \
+    hipLaunchKernelGGL((k_pb_rows<V, H, W, N>), dim3((unsigned)L.n_rb), dim3(N), lds, s, n, nnz, n_lds, meta, lim,   \
                        K, magic, L.n_cb, top, strideq, cell_start, cell_count, cell_word, ul4, yv4, vl4, rb_flag, rsd,  \
                        inv, Z, err)
+#define GEE_ROWS(V, H, W)                                                                                            \
+    do {                                                                                                             \
+        if (wide_wg) GEE_ROWS_NT(V, H, W, 2 * kRowsT);                                                               \
+        else GEE_ROWS_NT(V, H, W, kRowsT);                                                                           \
+    } while (0)
     if (vl) {
         if (half) {
             if (vec) GEE_ROWS(true, true, true);
@@ -1011,6 +1020,7 @@ hipError_t launch_pb_rows(int64_t n, int64_t nnz, int32_t K, const PbLayout &L, 
         else GEE_ROWS(false, false, false);
     }
 #undef GEE_ROWS
+#undef GEE_ROWS_NT
     return hipGetLastError();
 }
 

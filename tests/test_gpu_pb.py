@@ -285,7 +285,7 @@ def _flags_host(n, src, dst, w):
     return np.array([rows[256 * b: 256 * b + 256].any() for b in range(n_rb)], np.uint8)
 
 
-@pytest.mark.parametrize("K", [5, 50, 100])
+@pytest.mark.parametrize("K", [5, 50, 100, 128])
 @pytest.mark.parametrize("tier", ["none", "all"])
 def test_weighted_layout_matches_oracle(K, tier):
     """Weighted propagation-blocked pass: grid weights in (0, 1], plus a star of 400
