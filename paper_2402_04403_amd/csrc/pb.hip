@@ -41,7 +41,7 @@ namespace gee {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kRowsT = 512;    // rows kernel: 8 wavefronts per 256-row block
+constexpr int kRowsT = 512;    // rows kernel: 8 wavefronts per 256-row block (16 when its LDS allows two)
 constexpr int kRowsU = 4;      // words per lane in flight in the rows kernel
 constexpr int kLdsT = 1024;    // LDS-tier gather: 16 wavefronts share one label table
 constexpr uint32_t kXcds = 8;  // accelerator dies, each with its own L2
@@ -495,15 +495,16 @@ k_pb_gather_tier(int64_t nnz, int64_t n, int kind, const int64_t *__restrict__ m
     }
 }
 
-// One workgroup per 256-row block. The block's cells (one run per column block) are
-// read as one flattened sequence of 32-bit words of ul and yv: word f of the sequence
-// is found by a binary search over the cells' word prefix in LDS, and lane i of a
-// wavefront takes words i, i + 64, ... so loads stay coalesced and kRowsU of them per
-// array are in flight per lane. The bytes of a word that lie outside its cell (the
-// cells do not start on word boundaries) are masked. One count per entry into LDS
-// bins [row][class]; then the rows of Z are written once (count * 1/n_k), four
-// floats at a time when Z is 16-byte aligned (VEC). The word prefix of the cells comes
-// with the layout (cell_word).
+// One workgroup of NT threads (512, or 1024 when fewer than three of 512 fit in a CU's
+// LDS) per 256-row block. The block's cells (one run per column block) are read as one
+// flattened sequence of 32-bit words of ul and yv: word f of the sequence is found by a
+// binary search over the cells' word prefix in LDS, and lane i of a wavefront takes words
+// i, i + 64, ... so loads stay coalesced and kRowsU of them per array are in flight per
+// lane. The bytes of a word that lie outside its cell (the cells do not start on word
+// boundaries) are masked. One count per entry into LDS bins [row][class] (unit weights:
+// without a branch, an entry outside its cell or without a class adding 0); then the rows
+// of Z are written once (count * 1/n_k), four floats at a time when Z is 16-byte aligned
+// (VEC). The word prefix of the cells comes with the layout (cell_word).
 //
 // HALF (many classes): the bins take half the LDS, so more workgroups share a CU. A
 // unit-weight block of at most 4 * 16383 entries counts into 16-bit halves of 32-bit
@@ -511,12 +512,13 @@ k_pb_gather_tier(int64_t nnz, int64_t n, int kind, const int64_t *__restrict__ m
 // is counted in two passes over its words, rows 0-127 and then rows 128-255, each into
 // 32-bit bins.
 //
-// WT (weighted layout): the bins hold sums of the entries' weights. A block whose flag
-// is 0 (rows of at most kPbF32Terms entries, no negative weight) sums in 32-bit integers
-// when the layout's weights lie on a grid 2^-g (meta[4] = g; the sums are then exact),
-// else in FP32; a flagged block sums in FP64. The bins' LDS holds R rows of either (R = 256 or 128 for FP32,
-// half that for FP64), and the block's rows are taken R at a time, one pass over its
-// words each.
+// WT (weighted layout): the bins hold sums of the entries' weights (a Laplacian layout's
+// entries carry w d_u^-1/2 d_v^-1/2). A block whose flag is 0 (rows of at most
+// kPbF32Terms entries, no negative weight) sums in 32-bit integers when the layout's
+// weights lie on a grid 2^-g (meta[4] = g; the sums are then exact), else in FP32; a
+// flagged block sums in FP64. The bins' LDS holds R rows of either (R = 256 or 128 for
+// FP32, half that for FP64), and the block's rows are taken R at a time, one pass over
+// its words each.
 template <bool VEC, bool HALF, bool WT, int NT>
 __global__ void __launch_bounds__(NT)
 k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ meta, int64_t lim, int32_t K,
