@@ -199,20 +199,18 @@ int gee_embed_noalloc(const gee_coo *g, const gee_csr *csr, const int32_t *label
  * a second pass counts, per 256-row block, the (row, class) pairs of the block's
  * cells in LDS and writes those rows of Z once. Unit-weight counts are integers: Z
  * is bit-identical to gee_embed on the same CSR. With weights the second pass adds
- * them into FP32 sums, which the layout allows only for row blocks whose rows have at
- * most 128 entries and no negative weight (rb_flag 0): such a sum of m terms is within
- * (m - 1) 2^-24 of its value, relative; the other blocks take FP64 sums. When every
- * positive weight is an integer multiple of one power of two 2^-g and a sum of 128 of
- * them, scaled by 2^g, stays below 2^32 (the build records g in meta[4]), the unflagged
- * blocks add the scaled weights in 32-bit integers instead, which is exact (weights on
- * the 2^-24 grid in (0, 1] qualify). Otherwise results agree with gee_embed within
+ * them into FP64 sums. When every positive weight is an integer multiple of one power of
+ * two 2^-g and a sum of 128 of them, scaled by 2^g, stays below 2^32 (the build records g
+ * in meta[4]), the row blocks whose rows have at most 128 entries and no negative weight
+ * (rb_flag 0) add the scaled weights in 32-bit integers instead, which is exact (weights
+ * on the 2^-24 grid in (0, 1] qualify). Otherwise results agree with gee_embed within
  * rounding, not bit for bit, and since a block's wavefronts add into shared bins in an
  * order that varies, two calls agree within rounding too (the CSR pull form of gee_embed
  * is the bit-reproducible one).
  *
  * A Laplacian layout (gee_pb_build with laplacian != 0) stores, in place of the weights,
- * each entry's w d_u^-1/2 d_v^-1/2 (both its row's and its column's factor, FP32: one
- * rounding of the product of the FP32 weight and the two FP32 factors) and every vertex's
+ * each entry's w d_u^-1/2 d_v^-1/2 (both its row's and its column's factor, FP32: the
+ * product of the FP32 weight and the two FP32 factors rounded once) and every vertex's
  * d^-1/2 (rsd), the degrees d = (A + A^T) 1 being taken once when the layout is built, as
  * the CSR is (they depend on the graph only). The pass then adds the stored terms as a
  * weighted layout does: the Laplacian version, within the same rounding bound.

@@ -210,7 +210,7 @@ __global__ void k_pb_meta(int64_t *meta, int64_t n, int64_t nnz, int64_t n_lds, 
 
 // The Laplacian layout's term of every CSR entry, in CSR order: w d_u^-1/2 d_v^-1/2 for its
 // row u (the low half of its key) and column v (a hot-slot column decoded through
-// hot_ids), the product of the FP32 weight and the two FP32 factors (exact in FP64)
+// hot_ids): the product of the FP32 weight and the two FP32 factors, taken in FP64 and
 // rounded once to FP32. A column outside [0, n) gives 0 (k_pb_key flags it).
 __global__ void __launch_bounds__(kT)
 k_pb_lapw(int64_t nnz, int64_t n, const int32_t *__restrict__ col, const float *__restrict__ val,
@@ -515,10 +515,9 @@ k_pb_gather_tier(int64_t nnz, int64_t n, int kind, const int64_t *__restrict__ m
 // WT (weighted layout): the bins hold sums of the entries' weights (a Laplacian layout's
 // entries carry w d_u^-1/2 d_v^-1/2). A block whose flag is 0 (rows of at most
 // kPbF32Terms entries, no negative weight) sums in 32-bit integers when the layout's
-// weights lie on a grid 2^-g (meta[4] = g; the sums are then exact), else in FP32; a
-// flagged block sums in FP64. The bins' LDS holds R rows of either (R = 256 or 128 for
-// FP32, half that for FP64), and the block's rows are taken R at a time, one pass over
-// its words each.
+// weights lie on a grid 2^-g (meta[4] = g; the sums are then exact); other blocks sum in
+// FP64. The bins' LDS holds R rows of either (R = 256 or 128 for the integers, half that
+// for FP64), and the block's rows are taken R at a time, one pass over its words each.
 template <bool VEC, bool HALF, bool WT, int NT>
 __global__ void __launch_bounds__(NT)
 k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ meta, int64_t lim, int32_t K,
@@ -666,10 +665,12 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
         __syncthreads();
     };
     if constexpr (WT) {
-        float *fb = reinterpret_cast<float *>(bins);
         double *db = reinterpret_cast<double *>(bins);
-        const bool wide = rb_flag[rb] != 0;
+        // exact 32-bit integer sums for a block of grid weights whose flag is 0; FP64 sums
+        // otherwise (FP64 LDS adds measured faster than FP32 ones on MI355X, even with the
+        // block's rows taken in two passes)
         const int64_t grid = meta[4];
+        const bool wide = rb_flag[rb] != 0 || grid == kPbNoGrid;
         int R = (int)(nb / (uint32_t)(wide ? 2 * K : K));
         R = R < kPbRows ? R : kPbRows;
         for (int lo = 0; lo < nr; lo += R) {
@@ -688,7 +689,7 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
                 };
                 auto g1 = [&](uint32_t f) { return db[f]; };
                 write(lo, hi, g4, g1);
-            } else if (grid != kPbNoGrid) {
+            } else {
                 // every weight is an integer multiple of 2^-grid: 32-bit integer sums of the
                 // scaled weights are exact (the build checked that they stay below 2^32), and
                 // the row is written from the exact value, as from FP64 sums
@@ -704,14 +705,6 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
                     return f64x4{(double)c.x * down, (double)c.y * down, (double)c.z * down, (double)c.w * down};
                 };
                 auto g1 = [&](uint32_t f) { return (double)bins[f] * down; };
-                write(lo, hi, g4, g1);
-            } else {
-                count([&](uint32_t ub, uint32_t yb, float w, bool ok) {
-                    if (ok && ub - (uint32_t)lo < (uint32_t)R) atomicAdd(&fb[(ub - (uint32_t)lo) * (uint32_t)K + (yb - 1u)], w);
-                });
-                __syncthreads();
-                auto g4 = [&](uint32_t f) { return reinterpret_cast<const f32x4 *>(fb)[f / 4]; };
-                auto g1 = [&](uint32_t f) { return fb[f]; };
                 write(lo, hi, g4, g1);
             }
         }

@@ -290,7 +290,7 @@ def _flags_host(n, src, dst, w):
 def test_weighted_layout_matches_oracle(K, tier):
     """Weighted propagation-blocked pass: grid weights in (0, 1], plus a star of 400
     leaves (a row of more than 128 entries) and a few negative weights, so that row blocks
-    take FP32 sums, FP64 sums and, for K = 100, passes over half or a quarter of their
+    take exact 32-bit integer sums, FP64 sums and, for K = 100, passes over half or a quarter of their
     rows. Within the bar of the oracle, flags as the records imply, and the same with Z
     at an offset of one float. The weights lie on the 2^-24 grid, so unflagged blocks add
     them exactly in 32-bit integers and every call gives the same bits."""
@@ -341,7 +341,7 @@ def test_weighted_layout_er_workload_shape():
 
 def test_weighted_layout_off_grid():
     """Weights with no common grid (significands down to 2^-70 and below):
-    the build records no grid, unflagged blocks sum in FP32 (shared bins, so two calls
+    the build records no grid, every block sums in FP64 (shared bins, so two calls
     agree within rounding), and the result is within the bar of the oracle."""
     rng = np.random.default_rng(77)
     n, s, K = 30_000, 400_000, 20
