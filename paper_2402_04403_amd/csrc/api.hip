@@ -221,7 +221,9 @@ int make_batch_plan(const gee_csr *csr, const gee_batch *bt, const gee_embed_opt
             ++d.G;
             ++i;
         }
-        d.Gs = (d.G + 7) / 8 * 8;
+        // label row stride: G rounded up to 8, with at least one zero padding column when
+        // G < 64 (lanes without a vector read it)
+        d.Gs = std::min(kGroupMax, (d.G + 1 + 7) / 8 * 8);
         P.groups.push_back(d);
         P.lap.push_back(lap);
         P.Gs_max = std::max(P.Gs_max, d.Gs);

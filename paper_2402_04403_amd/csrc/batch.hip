@@ -16,6 +16,7 @@
 // sums are deterministic. A finished row is scaled and written to Z once. Rows cut
 // by segment boundaries are summed from FP64 partials in segment order.
 
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -183,7 +184,8 @@ k_batch_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__re
              const L *__restrict__ labhot, int Gs, const float *__restrict__ rsd,
              const float *__restrict__ rsdhot, const uint32_t *__restrict__ vmeta, const double *__restrict__ cscale,
              int KT, const int32_t *__restrict__ seg_i, const int64_t *__restrict__ seg_e, int64_t nseg,
-             float *__restrict__ Z, int64_t ldz, int64_t zcol, double *__restrict__ part, int32_t *err)
+             float *__restrict__ Z, int64_t ldz, int64_t zcol, double *__restrict__ part, int32_t *err,
+             const uint8_t *__restrict__ lbase, uint32_t mat_off, uint32_t hot_off)
 {
     extern __shared__ __align__(16) double smem_d[];
     const int KTp = (KT + 1) & ~1; // even, so 16-byte LDS accesses of column pairs stay aligned
@@ -202,10 +204,17 @@ k_batch_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__re
     const bool vvalid = vm != kNoVec;
     const int boff = (int)(vm & 0x7fffffffu) - 1; // bin of class y is boff + y
     const bool vlap = LAP && vvalid && (vm >> 31) != 0;
+    // a lane without a vector reads a zero padding column (label rows are wider than the
+    // group when it has fewer than 64 vectors), so its terms go to its sink
     const int lsrc = lane < Gs ? lane : Gs - 1;
     for (int f = lane; f < KTp + kWave; f += kWave) bins[f] = 0.0;
     const int sink = KTp + lane;
     bool bad = false;
+    // label rows through one buffer resource when both arrays lie within 4 GiB of lbase
+    // (one readlane per entry for its 32-bit offset), else by 64-bit addresses
+    const bool lbuf = lbase != nullptr;
+    const __amdgpu_buffer_rsrc_t lres = __builtin_amdgcn_make_buffer_rsrc((void *)lbase, (short)0, -1, 0x00020000);
+    const uint32_t rowb = (uint32_t)Gs * (uint32_t)sizeof(L), lbyte = (uint32_t)lsrc * (uint32_t)sizeof(L);
 
     // row window: lane i holds the end of row wb + i
     int64_t cu = sg.i0, ce = sg.e0, wb = sg.i0;
@@ -254,24 +263,36 @@ k_batch_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__re
                             float &ru) __attribute__((always_inline)) {
         if (W) ia = wv;
         if (LAP) ru = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rq)));
+        // lanes past the chunk (and invalid ids, flagged) read the zero row n: their terms
+        // go to the sinks, so the adds of a group of 8 need no per-entry test
+        const bool real = lane < m;
         const bool hot = cv < 0;
         const int64_t slot = (int64_t)((uint32_t)cv & 0x7fffffffu);
         const bool ok = hot ? slot < n_hot : cv < n;
-        bad |= !ok;
-        const int32_t c = ok ? cv : (int32_t)n; // the zero row
+        bad |= real && !ok;
+        const bool use = real && ok;
+        const int32_t c = use && !hot ? cv : (int32_t)n; // the zero row
         if (LAP) {
-            const float *rp = !ok ? rsd : (hot ? rsdhot + slot : rsd + c); // one load on every path
+            const float *rp = use && hot ? rsdhot + slot : rsd + (use ? c : 0); // one load on every path
             const float r = *rp;
-            rv = ok ? r : 0.0f;
+            rv = use ? r : 0.0f;
         }
-        // row address per entry (lane j), then per entry one scalar address and one
-        // coalesced load; in groups of 8 under a wave-uniform guard (all of them are
-        // complete by the time the next step's wait for its column ids returns)
-        const L *rowp = hot && ok ? labhot + slot * Gs : labmat + (int64_t)c * Gs;
+        // row offset (or address) per entry (lane j), then per entry one coalesced load; in
+        // groups of 8 under a wave-uniform guard (all of them are complete by the time the
+        // next step's wait for its column ids returns)
+        const L *rowp = use && hot ? labhot + slot * Gs : labmat + (int64_t)c * Gs;
+        const uint32_t off = use && hot ? hot_off + (uint32_t)slot * rowb : mat_off + (uint32_t)c * rowb;
         const uint32_t ralo = (uint32_t)(uintptr_t)rowp, rahi = (uint32_t)((uintptr_t)rowp >> 32);
 #pragma unroll
         for (int q0 = 0; q0 < kCW; q0 += 8) {
-            if (q0 < m) {
+            if (q0 < m && lbuf) {
+#pragma unroll
+                for (int q = q0; q < q0 + 8; ++q) {
+                    const uint32_t so = __builtin_amdgcn_readlane(off, q);
+                    if (sizeof(L) == 1) lab[q] = __builtin_amdgcn_raw_buffer_load_b8(lres, lbyte, so, 0);
+                    else lab[q] = __builtin_amdgcn_raw_buffer_load_b16(lres, lbyte, so, 0);
+                }
+            } else if (q0 < m) {
 #pragma unroll
                 for (int q = q0; q < q0 + 8; ++q) {
                     const uint64_t sa = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(rahi, q) << 32) |
@@ -285,19 +306,24 @@ k_batch_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__re
             }
         }
     };
+    // adds in groups of 8 under one wave-uniform test each: within a group no branch, so
+    // the scheduler interleaves the entries (entries past the chunk carry label 0)
     auto consume = [&](const Chunk &c, const uint16_t (&lab)[kCW], float ia, float rv) __attribute__((always_inline)) {
 #pragma unroll
-        for (int q = 0; q < kCW; ++q) {
-            if (q < c.m) {
-                double inc = 1.0;
-                if (W) inc = (double)readlanef(ia, q);
-                if (LAP) {
-                    const double il = inc * (double)readlanef(rv, q);
-                    inc = vlap ? il : inc;
+        for (int q0 = 0; q0 < kCW; q0 += 8) {
+            if (q0 < c.m) {
+#pragma unroll
+                for (int q = q0; q < q0 + 8; ++q) {
+                    double inc = 1.0;
+                    if (W) inc = (double)readlanef(ia, q);
+                    if (LAP) {
+                        const double il = inc * (double)readlanef(rv, q);
+                        inc = vlap ? il : inc;
+                    }
+                    const uint32_t y = lab[q];
+                    const int at = y != 0 ? boff + (int)y : sink; // no branch, no exec change
+                    atomicAdd(&bins[at], inc);
                 }
-                const uint32_t y = lab[q];
-                const int at = (vvalid && y != 0) ? boff + (int)y : sink; // no branch, no exec change
-                atomicAdd(&bins[at], inc);
             }
         }
     };
@@ -501,13 +527,24 @@ hipError_t launch_pull_group(const GroupArgs &g, hipStream_t s)
 {
     const int nw = batch_waves_per_block(g.KT);
     if (nw < 1) return hipErrorInvalidValue;
+    // both label arrays through one buffer resource: 32-bit byte offsets from the lower
+    // of the two, when they span less than 4 GiB (else 64-bit addresses per entry)
+    const size_t lb = g.u8 ? 1 : 2;
+    const uintptr_t pm = (uintptr_t)g.labmat, ph = (uintptr_t)g.labhot;
+    const uintptr_t lo = g.n_hot > 0 && ph < pm ? ph : pm;
+    const uintptr_t hi = std::max(pm + (size_t)(g.n + 1) * (size_t)g.Gs * lb,
+                                  g.n_hot > 0 ? ph + (size_t)g.n_hot * (size_t)g.Gs * lb : pm);
+    const bool span_ok = hi - lo < ((uint64_t)1 << 32) - 64;
+    const uint8_t *lbase = span_ok ? reinterpret_cast<const uint8_t *>(lo) : nullptr;
+    const uint32_t mat_off = span_ok ? (uint32_t)(pm - lo) : 0u;
+    const uint32_t hot_off = span_ok && g.n_hot > 0 ? (uint32_t)(ph - lo) : 0u;
     const size_t lds = batch_lds_bytes(g.KT, nw);
     const unsigned blocks = (unsigned)((g.nseg + nw - 1) / nw);
 #define GEE_GROUP(W, LAP, L)                                                                                         \
     hipLaunchKernelGGL((k_batch_pull<W, LAP, L>), dim3(blocks), dim3(kWave * nw), lds, s, g.n, g.row_ptr, g.col,     \
                        g.val, g.n_hot, static_cast<const L *>(g.labmat), static_cast<const L *>(g.labhot), g.Gs,     \
                        g.rsd, g.rsdhot, g.vmeta, g.cscale, g.KT, g.seg_i, g.seg_e, g.nseg, g.Z, g.ldz, g.zcol,       \
-                       g.part, g.err)
+                       g.part, g.err, lbase, mat_off, hot_off)
 #define GEE_GROUP_L(W, LAP)                                                                                          \
     do {                                                                                                             \
         if (g.u8) GEE_GROUP(W, LAP, uint8_t);                                                                        \

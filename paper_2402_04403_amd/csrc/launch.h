@@ -66,7 +66,7 @@ constexpr int kBatchMaxKT = 4096;               // classes of one group: KT FP64
 constexpr size_t kBatchLdsBytes = 160 * 1024;   // LDS of one block: column scales + bins of each wavefront
 struct GroupDesc {
     int G = 0;                  // vectors in the group
-    int Gs = 0;                 // label-matrix row stride (G rounded up to 8)
+    int Gs = 0;                 // label-matrix row stride (G + 1 rounded up to 8, at most 64)
     int KT = 0;                 // sum of K over the group
     int32_t vec[kGroupMax];     // index of each vector in the caller's batch
     int32_t K[kGroupMax];       // classes of each vector

@@ -110,8 +110,8 @@ class _Launch:
 def batch_workspace_bound(n: int, nnz: int, n_hot: int, Ks, laps, seg_len: int = 0) -> int:
     """An upper bound, in closed form, on gee_embed_batch's workspace for one graph and
     batch (admission needs a bound per job, and the library's exact query costs a few
-    ctypes objects per call). It takes the widest label row (min(64, B rounded up to 8)
-    vectors) and the most classes of a group (min(sum K, 4096)) for every group-sized
+    ctypes objects per call). It takes the widest label row (min(64, B + 1 rounded up to
+    8) bytes: a group of fewer than 64 vectors keeps a zero padding column) and the most classes of a group (min(sum K, 4096)) for every group-sized
     table, and the library's default segment length (the power of two at or above
     (n + nnz) / 32768 within [512, 16384]) when seg_len is 0."""
     if seg_len:
@@ -122,7 +122,7 @@ def batch_workspace_bound(n: int, nnz: int, n_hot: int, Ks, laps, seg_len: int =
             L *= 2
     nseg = (n + nnz + L - 1) // L
     B, S = len(Ks), int(sum(Ks))
-    gs = min(64, (B + 7) // 8 * 8)
+    gs = min(64, (B + 1 + 7) // 8 * 8)
     kt = min(S, 4096)
     parts = [8 * (S + B), 2 * (n + 1) * gs, 2 * n_hot * gs, 8 * kt, 4 * 64, 4 * (nseg + 1), 8 * (nseg + 1),
              16 * nseg * kt]
