@@ -98,6 +98,29 @@ def test_csr_build_matches_oracle(n, s, weighted):
         assert np.array_equal(csr.val.cpu().numpy().view(np.uint32), val.view(np.uint32))
 
 
+@pytest.mark.parametrize("n,s,weighted", [(1 << 24, 1 << 24, False), (1 << 22, 1 << 23, True)])
+def test_csr_build_matches_oracle_large(n, s, weighted):
+    """Keys of 44 and 48 bits (more radix passes than the small cases) and scans over
+    many blocks."""
+    rng = np.random.default_rng(n + s + 1)
+    src, dst, w = random_multigraph(rng, n, s, weighted)
+    rp, col, val = oracle.csr(n, src, dst, w)
+    csr = gee.csr_build(gee.to_device(n, src, dst, w, device=DEV))
+    assert np.array_equal(csr.row_ptr.cpu().numpy(), rp)
+    assert np.array_equal(csr.col.cpu().numpy(), col)
+    if weighted:
+        assert np.array_equal(csr.val.cpu().numpy().view(np.uint32), val.view(np.uint32))
+
+
+def test_csr_build_rmat_skew_large():
+    """Scale-21 R-MAT (2^24 records), hot slots on: the plain columns match the oracle."""
+    g = gen.rmat(21, 8 << 21, seed=23)
+    rp, col, _ = oracle.csr(g.n, g.src, g.dst)
+    csr = gee.csr_build(gee.to_device(g.n, g.src, g.dst, device=DEV), hot_budget=1 << 16)
+    assert np.array_equal(csr.row_ptr.cpu().numpy(), rp)
+    assert np.array_equal(csr.plain_col().cpu().numpy(), col)
+
+
 def test_csr_build_rmat_skew():
     g = gen.rmat(16, 14 << 16, seed=21)
     rp, col, _ = oracle.csr(g.n, g.src, g.dst)
