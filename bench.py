@@ -65,7 +65,7 @@ def parse():
     p.add_argument("--sweep", default="20,22,24,26,28,30", help="er-sweep: log2 of the record counts")
     p.add_argument("--sweep-records-per-vertex", type=int, default=16)
     p.add_argument("--sweep-hot", type=int, default=0,
-                   help="er-sweep: hot slots of each CSR (0: none; -1: every vertex up to the 2^23-slot tier), so "
+                   help="er-sweep: hot slots of each CSR (0: none; -1: every vertex up to the 2^26-slot tier), so "
                         "that the propagation-blocked form reads those labels from LDS")
     p.add_argument("--sweep-weighted", action="store_true",
                    help="er-sweep: grid weights (no propagation-blocked form then)")
@@ -735,7 +735,7 @@ def main_sweep(a):
         del g, wl
         e0, e1 = gee.HipEvent(), gee.HipEvent()
         e0.record()
-        hot = 0 if a.sweep_hot == 0 else min(n, a.sweep_hot if a.sweep_hot > 0 else 1 << 23)
+        hot = 0 if a.sweep_hot == 0 else min(n, a.sweep_hot if a.sweep_hot > 0 else gee.PB_MAX_TIER)
         csr = gee.csr_build(coo, hot_budget=hot, check=False)
         e1.record()
         e1.synchronize()

@@ -192,7 +192,7 @@ int gee_embed_noalloc(const gee_coo *g, const gee_csr *csr, const int32_t *label
  * (2^21 vertices), each entry keeping its column, its row within a block of 256 rows
  * and, for a weighted CSR, its weight.
  * Entries whose column is one of the CSR's first n_lds hot slots (its highest-degree
- * vertices, n_lds <= 2^23) go instead to "tier slices" of 2^17 slots each, one extra
+ * vertices, n_lds <= 2^26) go instead to "tier slices" of 2^17 slots each, one extra
  * column block per slice after the vertex blocks, and keep their slot within the
  * slice. Per call, one streaming pass writes every entry's label in that order (a
  * vertex block's labels stay in L2; a slice's labels, 128 KB, are read from LDS) and
@@ -227,7 +227,7 @@ int gee_embed_noalloc(const gee_coo *g, const gee_csr *csr, const int32_t *label
  * entries (GEE_EOVERFLOW beyond).
  * ------------------------------------------------------------------------------ */
 #define GEE_PB_SLICE 131072        /* hot slots per tier slice */
-#define GEE_PB_MAX_TIER 8388608    /* at most 64 slices */
+#define GEE_PB_MAX_TIER 67108864   /* at most 512 slices */
 
 typedef struct gee_pb {
     int64_t n, nnz;            /* vertices, entries (as in the CSR) */
@@ -257,10 +257,10 @@ typedef struct gee_pb {
 int64_t gee_pb_cells(int64_t n, int64_t n_lds);
 
 /* A tier size for the layout of csr: the hot slots of the longest run of leading
- * slices (at most 64, of min(n_hot, GEE_PB_MAX_TIER) slots) whose entries average at
+ * slices (at most 512, of min(n_hot, GEE_PB_MAX_TIER) slots) whose entries average at
  * least min_per_row_block per 256-row block, since each slice adds one cell to every
  * row block. Counts each slice's entries on the GPU (row lengths of its vertices) in
- * ws (device, 256-byte aligned, at least 512 bytes) and SYNCHRONIZES the stream.
+ * ws (device, 256-byte aligned, at least 4096 bytes) and SYNCHRONIZES the stream.
  * Returns the slot count (0 for no tier) or a negative status. */
 int64_t gee_pb_tier_slots(const gee_csr *csr, int64_t min_per_row_block, void *ws, size_t ws_bytes,
                           hipStream_t stream);

@@ -37,9 +37,8 @@ GEE_OK, GEE_EINVAL, GEE_ELABEL, GEE_EVERTEX, GEE_ENEGW, GEE_EOVERFLOW, GEE_EWORK
 # label records in degree-rank order, so the hottest labels share the lines that stay
 # in one XCD's 4 MiB L2 beside the streaming traffic.
 DEFAULT_HOT_BUDGET = 1 << 22
-# Hot slots for a graph embedded through its propagation-blocked layout: as many as the
-# layout's LDS tier takes (GEE_PB_MAX_TIER), so the entries of the 2^23 highest-degree
-# vertices read their labels from LDS.
+# Hot slots for a graph embedded through its propagation-blocked layout: the entries of
+# the 2^23 highest-degree vertices read their labels from LDS (64 tier slices).
 PB_HOT_BUDGET = 1 << 23
 
 
@@ -381,7 +380,7 @@ def csr_build(coo: DeviceCoo, hot_budget: int = 0, stream=None, check: bool = Tr
 PB_ROWS = 256
 PB_COLS = 1 << 21
 PB_SLICE = 1 << 17
-PB_MAX_TIER = 1 << 23
+PB_MAX_TIER = 1 << 26
 
 
 @dataclass
@@ -429,7 +428,7 @@ def pb_tier_slots(csr: DeviceCsr, min_per_row_block: int = 4, stream=None) -> in
     """Tier size for pb_build: leading slices of 2^17 hot slots whose entries average at
     least ``min_per_row_block`` per 256-row block (gee_pb_tier_slots; synchronizes)."""
     lib = load()
-    ws = torch.empty(512, dtype=torch.uint8, device=csr.row_ptr.device)
+    ws = torch.empty(8 * 512, dtype=torch.uint8, device=csr.row_ptr.device)  # one count per slice
     r = int(lib.gee_pb_tier_slots(ctypes.byref(csr.struct()), min_per_row_block, _ptr(ws), ws.numel(),
                                   _stream(stream)))
     if r < 0:

@@ -134,7 +134,7 @@ constexpr int kPbColBits = 21;
 constexpr int kPbMaxK = 128;                       // bins of a row block: 256 x K uint32 in LDS
 constexpr int kPbSliceBits = 17;                   // tier slice: 128 KB of 8-bit labels
 constexpr int64_t kPbSlice = (int64_t)1 << kPbSliceBits;
-constexpr int kPbMaxSlices = 64;                   // tier slots <= 2^23
+constexpr int kPbMaxSlices = 512;                  // tier slots <= 2^26
 constexpr int64_t kPbMaxNnz = (int64_t)UINT32_MAX - 64; // cell lengths and word prefixes are 32-bit
 struct PbLayout {
     int64_t n_rb = 0;

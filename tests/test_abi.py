@@ -210,7 +210,8 @@ def test_pb_argument_errors(lib):
     assert lib.gee_pb_cells(256, 1 << 17) == 2
     assert lib.gee_pb_cells(256, (1 << 17) + 1) == 3
     assert lib.gee_pb_cells(256, 1 << 23) == 65
-    assert lib.gee_pb_cells(256, (1 << 23) + 1) == 0
+    assert lib.gee_pb_cells(256, 1 << 26) == 513  # 512 slices, the most
+    assert lib.gee_pb_cells(256, (1 << 26) + 1) == 0
     assert lib.gee_pb_cells(256, -1) == 0
     assert lib.gee_pb_cells((1 << 21) + 1, 0) == 2 * ((((1 << 21) + 1) + 255) // 256)
     plain = gee.Csr(1000, 10_000, FAKE, FAKE, None, 0, None)
@@ -267,7 +268,7 @@ def test_pb_argument_errors(lib):
     for bad in (P(n_rb=5),  # n_rb does not match n
                 P(n_lds=5, ids=FAKE),  # n_cb without the tier slice
                 P(n_cb=2, n_lds=5),  # tier slots without ids
-                P(n_cb=66, n_lds=(1 << 23) + 1, ids=FAKE),  # tier above 2^23
+                P(n_cb=514, n_lds=(1 << 26) + 1, ids=FAKE),  # tier above 2^26
                 P(col=FAKE + 4),  # col unaligned
                 P(ul=FAKE + 8),  # ul unaligned
                 P(word=None),  # no word prefix

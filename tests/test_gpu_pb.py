@@ -118,6 +118,20 @@ def test_several_column_blocks(hot, tier, K):
     _same_bits(gee.embed_pb(Y, K, pb), gee.embed(Y, K, csr=csr))
 
 
+@pytest.mark.parametrize("K", [7, 50])
+def test_tier_beyond_64_slices(K):
+    """Every vertex of an Erdős–Rényi graph on 2^24 - 1000 vertices in the tier: 128 slices,
+    the last one partial (more slices than the scale-27 R-MAT's 64), bit-identical to
+    the pull form."""
+    n = (1 << 24) - 1000
+    g = gen.er(n, 4 * n, seed=11, weighted=False)
+    csr = gee.csr_build(gee.to_device(n, g.src, g.dst, None, device=DEV), hot_budget=n)
+    pb = gee.pb_build(csr, tier_slots=n)
+    assert pb.n_lds == n and pb.n_cb == 8 + 128
+    Y = torch.as_tensor(random_labels(np.random.default_rng(K), n, K, unknown=0.2)).to(DEV)
+    _same_bits(gee.embed_pb(Y, K, pb), gee.embed(Y, K, csr=csr))
+
+
 @pytest.mark.parametrize("hot", [0, 1000, 150_000])
 def test_layout_of_two_column_blocks(hot):
     n = (1 << 21) + 300
