@@ -96,6 +96,32 @@ def test_large_group_of_64_and_hot_slot_csr():
         assert_parity(Zn[:, zoff[b]:zoff[b] + Ks[b]], Zo, what=f"vector {b}")
 
 
+def test_label_rows_beyond_4gib():
+    """64 vectors with 16-bit labels on 2^25 vertices: the label rows span (2^25 + 1) x 128
+    bytes, past 4 GiB, so the pass addresses them by 64-bit pointers instead of 32-bit
+    buffer offsets. Adjacency vectors equal their single calls bit for bit, a Laplacian one
+    matches the oracle on sampled rows."""
+    n = 1 << 25
+    g = gen.er(n, 1 << 25, seed=57, weighted=False)
+    Ks = [2] * 62 + [256, 3]
+    laps = [False] * 63 + [True]
+    coo = gee.to_device(n, g.src, g.dst, None, device=DEV)
+    csr = gee.csr_build(coo, hot_budget=1000)
+    v = torch.arange(n, device=DEV, dtype=torch.int64)
+    Y = torch.stack([((v * (2 * b + 1) + b) % (k + 1)).to(torch.int32) for b, k in enumerate(Ks)])
+    Z, zoff = gee.embed_batch(Y, Ks, laps, csr)
+    sample = torch.randint(0, n, (1 << 20,), device=DEV, generator=torch.Generator(device=DEV).manual_seed(4))
+    for b in (0, 61, 62):  # on 2^20 sampled rows (vector 62's whole block would be 34 GB)
+        Zs = gee.embed(Y[b], Ks[b], csr=csr)
+        got = Z[sample, zoff[b]:zoff[b] + Ks[b]]
+        assert torch.equal(got.view(torch.int32), Zs[sample].view(torch.int32)), b
+        del Zs
+    rows = np.unique(np.random.default_rng(3).choice(n, 2000, replace=False)).astype(np.int64)
+    Zo = oracle.embed_rows(n, g.src, g.dst, None, Y[63].cpu().numpy(), 3, True, rows)
+    got = Z[torch.as_tensor(rows, device=DEV), zoff[63]:zoff[63] + 3].cpu().numpy()
+    assert_parity(got, Zo, what="Laplacian vector beside 16-bit label rows past 4 GiB")
+
+
 def test_batch_is_bit_reproducible():
     n, src, dst, w = _graph(True, seed=54)
     rng = np.random.default_rng(10)
