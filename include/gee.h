@@ -286,11 +286,11 @@ int gee_pb_build(const gee_csr *csr, int64_t n_lds, int laplacian, int32_t *col,
                  uint32_t *cell_count, uint32_t *cell_word, int32_t *lds_ids, float *val, uint8_t *rb_flag,
                  float *rsd, int64_t *meta, void *ws, size_t ws_bytes, int32_t *err, hipStream_t stream);
 
-/* Workspace bytes of gee_embed_pb (0 on invalid input); 1 <= K <= 128. */
+/* Workspace bytes of gee_embed_pb (0 on invalid input); 1 <= K <= 255. */
 size_t gee_embed_pb_workspace(const gee_pb *pb, int32_t K);
 
 /* Algorithm 1 over the layout, in the version the layout was built for: labels [n] in
- * [0, K] (K <= 128), Z [n * K] FP32 overwritten. Same results and data errors as
+ * [0, K] (K <= 255), Z [n * K] FP32 overwritten. Same results and data errors as
  * gee_embed on the CSR the layout was built from (bit for bit for unit-weight
  * adjacency; otherwise within the rounding described above). opts->hot_begin / hot_end
  * bracket the two passes (label gathers and row sums); seg_len is unused. */

@@ -131,7 +131,7 @@ hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t value, hipStream_t
 // of 2^17 hot slots each whose labels are read from LDS.
 constexpr int kPbRowBits = 8;
 constexpr int kPbColBits = 21;
-constexpr int kPbMaxK = 128;                       // bins of a row block: 256 x K uint32 in LDS
+constexpr int kPbMaxK = 255;                       // 8-bit labels; above 128 classes the bins are 16-bit (or two passes)
 constexpr int kPbSliceBits = 17;                   // tier slice: 128 KB of 8-bit labels
 constexpr int64_t kPbSlice = (int64_t)1 << kPbSliceBits;
 constexpr int kPbMaxSlices = 512;                  // tier slots <= 2^26

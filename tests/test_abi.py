@@ -253,8 +253,8 @@ def test_pb_argument_errors(lib):
     assert lib.gee_pb_tier_slots(ctypes.byref(hot), 4, FAKE, 256, None) == gee.GEE_EWORKSPACE
     assert lib.gee_pb_tier_slots(None, 4, FAKE, 256, None) == gee.GEE_EINVAL
     pb = gee.Pb(1000, 10_000, 4, 1, FAKE, FAKE, FAKE, FAKE, 0, None, FAKE, None, None, FAKE)
-    assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 128) > 10_000
-    assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 129) == 0
+    assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 255) > 10_000
+    assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 256) == 0
     assert lib.gee_embed_pb_workspace(ctypes.byref(pb), 0) == 0
     tiered = gee.Pb(1000, 10_000, 4, 2, FAKE, FAKE, FAKE, FAKE, 5, FAKE, FAKE, None, None, FAKE)
     assert lib.gee_embed_pb_workspace(ctypes.byref(tiered), 8) > 10_000

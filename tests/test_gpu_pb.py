@@ -181,9 +181,10 @@ def test_unaligned_z_and_ragged_entries():
             assert buf[0].item() == -1.0
 
 
-@pytest.mark.parametrize("K", [65, 66, 100, 127, 128])
+@pytest.mark.parametrize("K", [65, 66, 100, 127, 128, 129, 200, 255])
 def test_large_K(K):
-    """Above 64 classes a row block's bins take more than 64 KB of LDS: class counts that
+    """Above 64 classes a row block's bins take more than 64 KB of LDS (above 128, 16-bit
+    counts or two passes of 128 rows, one workgroup per CU): class counts that
     are not a multiple of 4, with Z aligned (four-float stores when K is a multiple of 4)
     and at an offset of one float (scalar stores), nothing written outside Z."""
     rng = np.random.default_rng(K)
@@ -203,7 +204,7 @@ def test_large_K(K):
 
 
 @pytest.mark.parametrize("tier", [0, 500])
-@pytest.mark.parametrize("K", [3, 50, 100, 128])
+@pytest.mark.parametrize("K", [3, 50, 100, 128, 255])
 def test_hub_row_blocks(tier, K):
     """Row blocks with 2^16 entries or more take two passes (one per half of their rows,
     32-bit bins): hubs in the first half, the second half, and in a partial last block
@@ -299,7 +300,7 @@ def _flags_host(n, src, dst, w):
     return np.array([rows[256 * b: 256 * b + 256].any() for b in range(n_rb)], np.uint8)
 
 
-@pytest.mark.parametrize("K", [5, 50, 100, 128])
+@pytest.mark.parametrize("K", [5, 50, 100, 128, 255])
 @pytest.mark.parametrize("tier", ["none", "all"])
 def test_weighted_layout_matches_oracle(K, tier):
     """Weighted propagation-blocked pass: grid weights in (0, 1], plus a star of 400
@@ -376,7 +377,7 @@ def test_weighted_layout_off_grid():
 
 
 @pytest.mark.parametrize("weighted", [False, True])
-@pytest.mark.parametrize("K", [7, 100])
+@pytest.mark.parametrize("K", [7, 100, 255])
 def test_laplacian_layout_matches_oracle(weighted, K):
     """Laplacian layout: the degrees and each entry's w d_u^-1/2 d_v^-1/2 taken at the build,
     summed as a weighted layout's terms. Unit and grid weights, a hub row (FP64 blocks),
