@@ -44,33 +44,54 @@ inline int grid_cap(int64_t items, int per_block)
 // labmat[v * Gs + b] = label of vertex v in vector b of the group (0 for a label
 // outside [0, K_b] and for the padding columns b >= G); row n is all zeros and is
 // where invalid column ids point. Labels are 8-bit (L = uint8_t) when every vector
-// of the group has K <= 255, else 16-bit. A 64 x 64 tile goes through LDS so both the
-// read (along v) and the write (along b) are coalesced.
+// of the group has K <= 255, else 16-bit. A tile of 256 vertices x Gs vectors goes
+// through LDS so both the read (along v) and the write (along b, four labels per
+// thread) are coalesced.
 template <typename L>
 __global__ void __launch_bounds__(kBT)
 k_pack_group(const int32_t *__restrict__ labels, int64_t n, GroupDesc d, L *__restrict__ labmat, int32_t *err)
 {
-    __shared__ uint16_t tile[64][65];
-    const int64_t v0 = (int64_t)blockIdx.x * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    // 256 vertices x 64 vectors; 136-byte rows, so four labels are one aligned 8-byte read
+    __shared__ __align__(16) uint16_t tile[kBT][68];
+    const int64_t v0 = (int64_t)blockIdx.x * kBT;
+    const int t = threadIdx.x;
+    const int64_t v = v0 + t;
     bool bad = false;
-    for (int b = ty; b < d.Gs; b += kBT / 64) {
-        const int64_t v = v0 + tx;
-        uint16_t y = 0;
-        if (v < n && b < d.G) {
-            const int32_t x = labels[(int64_t)d.vec[b] * n + v];
-            const bool ok = (uint32_t)x <= (uint32_t)d.K[b];
-            bad |= !ok;
-            y = ok ? (uint16_t)x : 0;
+    // 1 KB of each vector per block, coalesced along v; 16 vectors' loads in flight at once
+    for (int b0 = 0; b0 < d.Gs; b0 += 16) {
+        int32_t x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int b = b0 + i;
+            x[i] = v < n && b < d.G ? labels[(int64_t)d.vec[b] * n + v] : 0;
         }
-        tile[tx][b] = y;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int b = b0 + i;
+            if (b < d.Gs) {
+                const bool ok = b >= d.G || (uint32_t)x[i] <= (uint32_t)d.K[b];
+                bad |= !ok;
+                tile[t][b] = ok ? (uint16_t)x[i] : 0;
+            }
+        }
     }
     __syncthreads();
-    for (int r = ty; r < 64; r += kBT / 64) {
-        const int64_t v = v0 + r;
-        if (v < n && tx < d.Gs) labmat[v * d.Gs + tx] = (L)tile[r][tx];
+    // Gs is a multiple of 8, so a row holds Gs / 4 quads, each 4- (8-bit) or 8-byte
+    // (16-bit) aligned
+    const int qpr = d.Gs / 4;
+    for (int i = t; i < kBT * qpr; i += kBT) {
+        const int r = i / qpr, q = i - r * qpr;
+        const int64_t u = v0 + r;
+        if (u < n) {
+            const uint2 w = *reinterpret_cast<const uint2 *>(&tile[r][4 * q]);
+            if (sizeof(L) == 1)
+                reinterpret_cast<uint32_t *>(labmat + u * d.Gs)[q] =
+                    (w.x & 0xffu) | ((w.x >> 8) & 0xff00u) | ((w.y & 0xffu) << 16) | ((w.y >> 16) << 24);
+            else
+                reinterpret_cast<uint2 *>(labmat + u * d.Gs)[q] = w;
+        }
     }
-    if (blockIdx.x == 0 && threadIdx.x < d.Gs) labmat[n * d.Gs + threadIdx.x] = (L)0;
+    if (blockIdx.x == 0 && t < d.Gs) labmat[n * d.Gs + t] = (L)0;
     if (bad) flag_error(err, GEE_ELABEL);
 }
 
@@ -486,7 +507,7 @@ size_t batch_lds_bytes(int KT, int nw)
 hipError_t launch_pack_group(const int32_t *labels, int64_t n, const GroupDesc &d, void *labmat, bool u8,
                              int32_t *err, hipStream_t s)
 {
-    const dim3 g((unsigned)((n + 63) / 64)), b(kBT);
+    const dim3 g((unsigned)((n + kBT - 1) / kBT)), b(kBT);
     if (u8)
         hipLaunchKernelGGL(k_pack_group<uint8_t>, g, b, 0, s, labels, n, d, static_cast<uint8_t *>(labmat), err);
     else
