@@ -27,7 +27,7 @@ namespace gee {
 namespace {
 
 constexpr int kBT = 256;      // threads per block of the helper kernels
-constexpr int kCW = 32;       // entries per chunk (a chunk never spans two rows)
+constexpr int kCW = 48;       // entries per chunk (a chunk never spans two rows; measured faster than 32 and 64)
 constexpr int kMaxWavesPerBlock = 8;
 constexpr uint32_t kNoVec = 0xffffffffu;
 typedef __attribute__((address_space(1))) const uint16_t global_u16;
