@@ -232,7 +232,9 @@ k_batch_pull(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__re
     const int sink = KTp + lane;
     bool bad = false;
     // label rows through one buffer resource when both arrays lie within 4 GiB of lbase
-    // (one readlane per entry for its 32-bit offset), else by 64-bit addresses
+    // (one readlane per entry for its 32-bit offset), else by 64-bit addresses. The
+    // resource is raw (stride 0, no record limit; word 3 0x20000: 32-bit data, no
+    // swizzle), so its bounds are the caller's check of the span.
     const bool lbuf = lbase != nullptr;
     const __amdgpu_buffer_rsrc_t lres = __builtin_amdgcn_make_buffer_rsrc((void *)lbase, (short)0, -1, 0x00020000);
     const uint32_t rowb = (uint32_t)Gs * (uint32_t)sizeof(L), lbyte = (uint32_t)lsrc * (uint32_t)sizeof(L);
