@@ -548,12 +548,24 @@ k_pb_rows(int64_t n, int64_t nnz, int64_t n_lds, const int64_t *__restrict__ met
     const int nr = (int)((n - r0) < kPbRows ? (n - r0) : kPbRows);
     const int t = threadIdx.x, lane = t % kWave;
     const int wave = __builtin_amdgcn_readfirstlane(t / kWave);
+    // the block's global reads first (its first NT cells and the class factors; K + 3 <=
+    // NT), then the bins are zeroed while they are in flight
+    int64_t a1 = 0;
+    uint32_t m1 = 0u, p1 = 0u;
+    double v1 = 0.0;
+    if (t < n_cb) {
+        a1 = cell_start[rb * n_cb + t];
+        m1 = cell_count[rb * n_cb + t];
+        p1 = cell_word[rb * n_cb + t];
+    }
+    if (t < K + 3) v1 = inv[1 + t % K];
     for (uint32_t i = t; i < nb / 4; i += NT) reinterpret_cast<u32x4 *>(bins)[i] = u32x4{0u, 0u, 0u, 0u};
-    for (int i = t; i < K + 3; i += NT) invx[i] = inv[1 + i % K];
+    if (t < K + 3) invx[t] = v1;
     for (int c = t; c < n_cb; c += NT) {
-        int64_t a = cell_start[rb * n_cb + c];
-        uint32_t m = cell_count[rb * n_cb + c];
-        const uint32_t p = cell_word[rb * n_cb + c];
+        const bool first = c == t;
+        int64_t a = first ? a1 : cell_start[rb * n_cb + c];
+        uint32_t m = first ? m1 : cell_count[rb * n_cb + c];
+        const uint32_t p = first ? p1 : cell_word[rb * n_cb + c];
         // a cell must lie inside the layout's entries [0, lim): one that does not (a layout
         // that is not what it claims) is read as empty and raises GEE_EVERTEX
         if (a < 0 || a > lim || (int64_t)m > lim - a) {
