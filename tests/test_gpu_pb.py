@@ -132,6 +132,20 @@ def test_tier_beyond_64_slices(K):
     _same_bits(gee.embed_pb(Y, K, pb), gee.embed(Y, K, csr=csr))
 
 
+@pytest.mark.parametrize("K", [7, 50])
+def test_cells_beyond_one_per_thread(K):
+    """Every vertex of a sparse Erdős–Rényi graph on 2^26 vertices in the tier: 512 slices
+    and 32 vertex blocks, 544 cells per row block, more than the rows pass's 512 threads
+    (each thread takes a second cell), bit-identical to the pull form."""
+    n = 1 << 26
+    g = gen.er(n, 2 * n, seed=5, weighted=False)
+    csr = gee.csr_build(gee.to_device(n, g.src, g.dst, None, device=DEV), hot_budget=n)
+    pb = gee.pb_build(csr, tier_slots=n)
+    assert pb.n_lds == n and pb.n_cb == 32 + 512
+    Y = torch.as_tensor(random_labels(np.random.default_rng(K + 1), n, K, unknown=0.2)).to(DEV)
+    _same_bits(gee.embed_pb(Y, K, pb), gee.embed(Y, K, csr=csr))
+
+
 @pytest.mark.parametrize("hot", [0, 1000, 150_000])
 def test_layout_of_two_column_blocks(hot):
     n = (1 << 21) + 300
