@@ -43,6 +43,24 @@ def test_counter_traffic_only_for_its_kernel_and_workload(tmp_path):
     assert bench.counters_traffic(1000, str(tmp_path / "missing.json"), str(src)) == (None, None)
 
 
+def test_counter_summaries_are_keyed_on_the_bench_lines_bytes():
+    """Each committed counter summary carries the algorithmic bytes per launch that the
+    committed bench line of its workload prints for the kernel the counters cover (the
+    edge pass for the single-vector forms, the whole group loop for the batched one), so
+    the bench's traffic lookup finds it."""
+    prof = os.path.join(ROOT, "profiles")
+
+    def load(name):
+        with open(os.path.join(prof, name)) as f:
+            return json.load(f)
+
+    pairs = [("k_pb_rmat27_counters.json", load("bench_rmat27_pb.json")["roofline"]["edge_pass"]),
+             ("k_pull_rmat27_counters.json", load("bench_rmat27_pull.json")["roofline"]["edge_pass"]),
+             ("k_batch_pull_rmat24_b64_counters.json", load("bench_rmat24_b64_batched.json")["roofline"])]
+    for summary, line in pairs:
+        assert load(summary)["bytes_alg_per_launch"] == line["bytes_alg_per_launch"], summary
+
+
 def _pool(sizes):
     return {gid: (n, np.zeros(s, np.int32), np.zeros(s, np.int32)) for gid, (n, s) in enumerate(sizes)}
 
